@@ -1,0 +1,165 @@
+"""Pins of the oracle's numbering, element matrices and index sets against what
+the paper prints or what the mathematics fixes (CPU only)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import element, mesh, sparse
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --- element matrices -------------------------------------------------------
+def _printed(name, dim, nu):
+    g = np.loadtxt(os.path.join(GOLD, name))
+    if dim == 2:   # App. B, block PRE.2: Ke = (c1 + nu c2) / (24 (1 - nu^2))
+        return (g[:, 0] + nu * g[:, 1]) / (24.0 * (1.0 - nu * nu))
+    # App. C, block PRE.2: Ke = (k1 + nu k2) / ((1 + nu)(2 nu - 1) 144)
+    return (g[:, 0] + nu * g[:, 1]) / ((1.0 + nu) * (2.0 * nu - 1.0) * 144.0)
+
+
+@pytest.mark.parametrize("nu", [0.3, 0.0, 0.25, 0.45])
+def test_ke_q4_matches_printed_coefficients(nu):
+    v = element.lower_vector(element.ke_q4(nu))
+    assert v.shape == (36,)
+    np.testing.assert_allclose(v, _printed("ke2d_q4_printed.txt", 2, nu), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("nu", [0.3, 0.1, 0.4])
+def test_ke_h8_matches_printed_coefficients(nu):
+    v = element.lower_vector(element.ke_h8(nu))
+    assert v.shape == (300,)
+    np.testing.assert_allclose(v, _printed("ke3d_h8_printed.txt", 3, nu), rtol=0, atol=1e-15)
+
+
+def _rigid_modes(dim):
+    """Rigid-body modes from the corner coordinates of Fig. 1b."""
+    if dim == 2:
+        xy = np.array([(0, 0), (1, 0), (1, 1), (0, 1)], float)
+        modes = [np.tile([1, 0], 4), np.tile([0, 1], 4),
+                 np.column_stack([-xy[:, 1], xy[:, 0]]).reshape(-1)]
+        return np.array(modes, float).T
+    c = np.array([(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0),
+                  (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)], float)
+    modes = [np.tile(np.eye(3)[k], 8) for k in range(3)]
+    for axis in range(3):
+        w = np.zeros(3)
+        w[axis] = 1.0
+        modes.append(np.cross(w, c).reshape(-1))
+    return np.array(modes).T
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_ke_symmetric_psd_nullspace_is_rigid_modes(dim):
+    K = element.element_matrix(dim, 0.3)
+    np.testing.assert_allclose(K, K.T, atol=1e-16)
+    ev = np.linalg.eigvalsh(K)
+    nzero = 3 if dim == 2 else 6
+    assert np.all(ev[:nzero] < 1e-14 * ev[-1])
+    assert ev[nzero] > 1e-3
+    R = _rigid_modes(dim)
+    assert np.linalg.matrix_rank(R) == nzero
+    assert np.abs(K @ R).max() < 1e-14
+
+
+def test_lower_vector_roundtrip():
+    K = element.ke_h8(0.3)
+    np.testing.assert_allclose(element.from_lower_vector(element.lower_vector(K), 24), K, rtol=0, atol=1e-16)
+
+
+# --- numbering and connectivity -------------------------------------------
+@pytest.mark.parametrize("nelx,nely", [(4, 2), (5, 3), (60, 20)])
+def test_cmat_2d_matches_paper_offsets(nelx, nely):
+    """Block PRE.2 of the 2D code builds C from 1-based node numbers N(iy,ix):
+    first DOF 2N+1, offsets [0, 1, 2nely+2, 2nely+3, 2nely, 2nely+1, -2, -1]."""
+    M = mesh.Mesh(nelx, nely)
+    N1 = np.array([[iy + 1 + (nely + 1) * ix for ix in range(nelx)] for iy in range(nely)])
+    cvec = (2 * N1 + 1).reshape(-1, order="F")
+    off = np.array([0, 1, 2 * nely + 2, 2 * nely + 3, 2 * nely, 2 * nely + 1, -2, -1])
+    np.testing.assert_array_equal(M.cmat(), cvec[:, None] + off[None, :] - 1)
+
+
+@pytest.mark.parametrize("nelx,nely,nelz", [(2, 3, 2), (4, 2, 3)])
+def test_cmat_3d_matches_paper_offsets(nelx, nely, nelz):
+    """Block PRE.2 of the 3D code: first DOF 3N+1 with N(iy,iz,ix) 1-based."""
+    M = mesh.Mesh(nelx, nely, nelz)
+    cvec = np.zeros(M.m, int)
+    for ix in range(nelx):
+        for iz in range(nelz):
+            for iy in range(nely):
+                N = iy + 1 + (nely + 1) * iz + (nely + 1) * (nelz + 1) * ix
+                cvec[iy + nely * (iz + nelz * ix)] = 3 * N + 1
+    a, b = 3 * (nely + 1) * (nelz + 1), 3 * (nely + 1)
+    c = 3 * (nely + 1) * (nelz + 2)
+    off = np.array([0, 1, 2, a, a + 1, a + 2, a - 3, a - 2, a - 1, -3, -2, -1,
+                    b, b + 1, b + 2, c, c + 1, c + 2, c - 3, c - 2, c - 1, b - 3, b - 2, b - 1])
+    np.testing.assert_array_equal(M.cmat(), cvec[:, None] + off[None, :] - 1)
+
+
+def test_corner_nodes_are_cell_corners_3d():
+    M = mesh.Mesh(3, 2, 2)
+    iy, ix, iz = M.element_grid()
+    nodes = M.corner_nodes()
+    ny1, nz1 = M.nely + 1, M.nelz + 1
+    ny_, rest = nodes % ny1, nodes // ny1
+    nz_, nx_ = rest % nz1, rest // nz1
+    # physical coordinates (x = ix, y = -iy, z = iz) relative to the cell
+    rel = np.stack([nx_ - ix[:, None], iy[:, None] + 1 - ny_, nz_ - iz[:, None]], -1)
+    expect = np.array([(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0),
+                       (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)])
+    assert np.all(rel == expect[None])
+
+
+# --- reduced index set and CSR --------------------------------------------
+@pytest.mark.parametrize("side,expected", [(120, 1_036_800), (240, 4_147_200)])
+def test_ir_size_table1_2d(side, expected):
+    """Table 1 (H strategy) lists the entries of the two-column array I_r:
+    2 m d(d+1)/2.  (eq. (14)'s printed d~ is wrong; the loops give d(d+1)/2.)"""
+    M = mesh.Mesh(side, side)
+    assert 2 * sparse.reduced_index_set(M.cmat()).shape[0] == expected
+
+
+@pytest.mark.parametrize("side,expected", [(8, 307_200), (16, 2_457_600)])
+def test_ir_size_table1_3d(side, expected):
+    """Table 1, 3D.  The 16^3 entry is printed as 2,457,200: a typo for
+    2 * 4096 * 300 = 2,457,600 (the memory column, 19.7 MB, agrees with it)."""
+    M = mesh.Mesh(side, side, side)
+    assert 2 * sparse.reduced_index_set(M.cmat()).shape[0] == expected
+
+
+@pytest.mark.parametrize("dims", [(4, 2), (5, 3), (2, 2, 3)])
+def test_csr_and_perm_brute_force(dims):
+    M = mesh.Mesh(*dims)
+    C = M.cmat()
+    ir = sparse.reduced_index_set(C)
+    # brute force: the pattern of tril(sum_e A_e^T 1 A_e)
+    P = np.zeros((M.n, M.n), bool)
+    for e in range(M.m):
+        P[np.ix_(C[e], C[e])] = True
+    P = np.tril(P)
+    row_ptr, col_idx, perm, seg_ptr = sparse.csr_pattern(ir, M.n)
+    assert row_ptr[-1] == P.sum() == len(col_idx) == len(seg_ptr) - 1
+    for r in range(M.n):
+        np.testing.assert_array_equal(col_idx[row_ptr[r]:row_ptr[r + 1]], np.nonzero(P[r])[0])
+    # every pair sits in the slot of its (row, col), in ascending pair order
+    slot_of = {}
+    for s in range(len(col_idx)):
+        r = np.searchsorted(row_ptr, s, side="right") - 1
+        slot_of[(r, col_idx[s])] = s
+    members = {s: [] for s in range(len(col_idx))}
+    for t, (r, c) in enumerate(ir):
+        assert r >= c
+        members[slot_of[(r, c)]].append(t)
+    for s in range(len(col_idx)):
+        np.testing.assert_array_equal(perm[seg_ptr[s]:seg_ptr[s + 1]], members[s])
+
+
+def test_nnz_closed_form_60x20():
+    M = mesh.Mesh(60, 20)
+    _, col_idx, _, _ = sparse.csr_pattern(sparse.reduced_index_set(M.cmat()), M.n)
+    # lower triangle: 3 per node (2x2 diagonal block) + 4 per node-pair that
+    # shares an element; node pairs: horizontal, vertical, 2 diagonals
+    nx, ny = M.nelx, M.nely
+    pairs = nx * (ny + 1) + (nx + 1) * ny + 2 * nx * ny
+    assert len(col_idx) == 3 * M.nnode + 4 * pairs == 23_363

@@ -1,0 +1,120 @@
+"""Seeded synthetic workloads shared by the tests, the smoke check and the
+benchmark.  This module holds problem *parameters* and random draws only --
+none of the method's arithmetic -- so that the oracle and the GPU library can
+both be fed from it without sharing any code path.
+
+The problems are the textbook ones the paper defines (half MBB beam, Sec. 3;
+3D cantilever, Sec. 4) at the sizes of the paper's timing runs
+(3e4 to 4.8e5 elements in 2D, 2.2e5 in 3D); no dataset is involved.
+"""
+from dataclasses import dataclass, field, replace
+from typing import Optional, Tuple
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Config:
+    name: str
+    kind: str                 # 'mbb' | 'cantilever2d' | 'cantilever3d'
+    nelx: int
+    nely: int
+    nelz: int = 0             # 0 -> 2D
+    volfrac: float = 0.5
+    penal: float = 3.0
+    rmin: float = 2.0
+    ft: int = 1               # 1 density filter, 2 projection fixed eta, 3 volume-preserving eta
+    bc: str = "D"             # filter boundary rule 'D' | 'N'
+    eta: float = 0.5
+    beta: float = 1.0
+    move: float = 0.2
+    E0: float = 1.0
+    Emin: float = 1e-9
+    nu: float = 0.3
+    iterations: int = 50
+    precision: str = "f64"    # 'f64' | 'f32' (FP32 fields, FP64 solve vectors and sums)
+    # continuation (istart, maxPar, isteps, delta, 'add' | 'mul'); None = off
+    penal_sched: Optional[Tuple] = None
+    beta_sched: Optional[Tuple] = None
+    load: int = 0             # load node: MBB column / cantilever row
+
+    @property
+    def dim(self):
+        return 3 if self.nelz else 2
+
+    @property
+    def m(self):
+        return self.nelx * self.nely * (self.nelz or 1)
+
+
+# Small FP64 case: MBB 60 x 20, density filter only, 50 iterations.
+C0 = Config("mbb60x20", "mbb", 60, 20, rmin=2.0, ft=1, bc="D", iterations=50)
+
+
+def c1(nelx):
+    """MBB at 300x100 / 600x200 / 1200x400: rmin = 2 nelx / 60, volume-
+    preserving projection with beta 1 -> 32 (x2 every 25 iterations) and
+    penal 1 -> 3 (+0.25 every 25 iterations), FP32 fields, 200 iterations."""
+    return Config(f"mbb{nelx}x{nelx // 3}", "mbb", nelx, nelx // 3, rmin=2.0 * nelx / 60.0,
+                  penal=1.0, ft=3, bc="D", eta=0.5, beta=1.0, iterations=200,
+                  precision="f32", penal_sched=(1, 3.0, 25, 0.25, "add"),
+                  beta_sched=(1, 32.0, 25, 2.0, "mul"))
+
+
+C1 = {n: c1(n) for n in (300, 600, 1200)}
+
+# 3D cantilever 96 x 48 x 48, rmin = sqrt(3), mirror filter boundary.
+C2 = Config("cantilever96x48x48", "cantilever3d", 96, 48, 48, volfrac=0.12, penal=3.0,
+            rmin=float(np.sqrt(3.0)), ft=3, bc="N", eta=0.5, beta=2.0, iterations=100)
+
+# A 3D case small enough for the oracle to finish in seconds.
+C2_SMALL = replace(C2, name="cantilever12x6x6", nelx=12, nely=6, nelz=6, iterations=10)
+
+
+def batch_configs(count=64, seed=0):
+    """Ragged batch: per instance (drawn in this order) the problem type
+    (cantilever or MBB, 1/2 each), nelx uniform over even integers in
+    [100, 400] with nely = nelx / 2, the load position on the free edge,
+    volfrac ~ U[0.3, 0.5], rmin ~ U[1.5, 4]; ft = 3, beta = 2, p = 3, 'D'."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        kind = "cantilever2d" if rng.random() < 0.5 else "mbb"
+        nelx = 2 * int(rng.integers(50, 201))
+        nely = nelx // 2
+        load = int(rng.integers(0, nely + 1)) if kind == "cantilever2d" else int(rng.integers(0, nelx))
+        vf = float(rng.uniform(0.3, 0.5))
+        rmin = float(rng.uniform(1.5, 4.0))
+        out.append(Config(f"batch{i}", kind, nelx, nely, volfrac=vf, rmin=rmin, ft=3, bc="D",
+                          beta=2.0, penal=3.0, iterations=100, precision="f32", load=load))
+    return out
+
+
+# --- random fields for kernel-level parity and microbenchmarks ---------------
+def design_field(m, seed, lo=0.0, hi=1.0):
+    return np.random.default_rng(seed).uniform(lo, hi, m)
+
+
+def smooth_design(cfg, seed):
+    """A smooth design in [0.02, 0.98] on the element grid (a few random
+    Fourier modes): closer to mid-run designs than white noise."""
+    rng = np.random.default_rng(seed)
+    shape = (cfg.nely, cfg.nelz, cfg.nelx) if cfg.nelz else (cfg.nely, cfg.nelx)
+    grids = np.meshgrid(*[np.linspace(0, 1, s) for s in shape], indexing="ij")
+    v = np.full(shape, cfg.volfrac)
+    for _ in range(6):
+        k = rng.integers(1, 5, len(shape))
+        ph = rng.uniform(0, 2 * np.pi, len(shape))
+        term = np.ones(shape)
+        for g, kk, p in zip(grids, k, ph):
+            term = term * np.cos(np.pi * kk * g + p)
+        v = v + 0.15 * term
+    return np.clip(v, 0.02, 0.98).reshape(-1, order="F")
+
+
+def displacement_field(n, seed):
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+def sensitivity_field(m, seed):
+    return -np.random.default_rng(seed).uniform(0.0, 1.0, m)
