@@ -1,0 +1,280 @@
+/*
+ * topt.h -- C ABI of the MI355X (gfx950) SIMP minimum-compliance hot path.
+ *
+ * Method: F. Ferrari and O. Sigmund, "A new generation 99 line Matlab code for
+ * compliance Topology Optimization and its extension to 3D" (arXiv:2005.05436).
+ * Equations are cited by their number in order of appearance as typeset:
+ * (1) projection, (2) filter, (5) state equation, (6) SIMP, (7)-(8)
+ * sensitivities, (9) projection derivative, (10)-(11) OC rule, (14) reduced
+ * index set, (15) full-matrix recovery, (17) volume-preserving threshold,
+ * (19) multiplier estimate.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named d_* or documented as "device" are device addresses (e.g. a
+ *    torch tensor's data_ptr()); pointers named h_* are host addresses.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Every
+ *    call except to_plan_create and to_plan_export only enqueues work on it and
+ *    never synchronises the host.
+ *  - The library allocates no device memory.  Plan data and every scratch
+ *    buffer live in one caller-owned device workspace whose size
+ *    to_plan_query reports.  One plan must not be used by two streams at once
+ *    (its scratch buffers would race).
+ *  - Numbering (0-based, y fastest):  element e = iy + nely*ix (2D),
+ *    e = iy + nely*(iz + nelz*ix) (3D); node n = iy + (nely+1)*ix (2D),
+ *    n = iy + (nely+1)*(iz + (nelz+1)*ix) (3D); DOF = dim*n + component.
+ *    Row iy = 0 is the top edge (physical y points to smaller iy).
+ *  - Field dtype: TO_F64 fields are double, TO_F32 fields are float.  The
+ *    displacement u and the load f are always double.  Reductions are always
+ *    accumulated in double in a fixed order (results are bitwise repeatable).
+ *  - Argument errors return TO_EINVAL before anything is enqueued; HIP runtime
+ *    failures return TO_EHIP; details in to_last_error() (thread-local).
+ *    Data-dependent outcomes (CG not converged, Newton or bisection cap hit,
+ *    non-finite values) are never errors: they are flags in the device stats.
+ *  - No C++ exception ever crosses this interface.
+ */
+#ifndef TOPT_H
+#define TOPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TO_OK = 0,
+    TO_EINVAL = 1,        /* bad argument (null pointer, size, mode) */
+    TO_EHIP = 2,          /* HIP runtime error */
+    TO_EWORKSPACE = 3,    /* workspace too small or misaligned (256 B) */
+    TO_EUNSUPPORTED = 4   /* valid request this build does not implement */
+} to_status;
+
+typedef enum { TO_F32 = 0, TO_F64 = 1 } to_dtype;
+
+/* Passive element codes (Sec. 2: active set A, passive solid P1, void P0). */
+enum { TO_ACTIVE = 0, TO_SOLID = 1, TO_VOID = 2 };
+
+/* Mesh and material description (Sec. 3, blocks PRE.1-PRE.3 of both codes). */
+typedef struct {
+    int32_t dim;                 /* 2 (Q4 plane stress) or 3 (Hex8) */
+    int32_t nelx, nely, nelz;    /* elements per axis; nelz ignored in 2D */
+    double E0, Emin, nu;         /* solid / void Young moduli, Poisson ratio */
+    double rmin;                 /* filter radius in element widths, > 0 */
+    char bc;                     /* filter boundary rule: 'D' zero padding, 'N' mirror */
+    const uint8_t* h_passive;    /* host, m codes TO_ACTIVE/SOLID/VOID, or NULL (all active) */
+    const int32_t* h_fixed;      /* host, fixed DOFs (any order, duplicates allowed) */
+    int64_t n_fixed;
+} to_mesh_desc;
+
+typedef struct to_plan to_plan;   /* opaque: host header + views into the workspace */
+
+/* Sizes of a plan (host copy). */
+typedef struct {
+    int32_t dim, d, dtilde;      /* element DOFs d = 8 | 24, d~ = d(d+1)/2 */
+    int64_t m, nnode, n;         /* elements, nodes, DOFs */
+    int64_t n_pairs;             /* |I_r| = m d~  (eq. (14)) */
+    int64_t nnz_lower;           /* non-zeros of K^(s) incl. diagonal */
+    int64_t n_active, n_solid, n_void, n_free;
+    int32_t filter_radius;       /* R = ceil(rmin) - 1 */
+    int32_t coop_blocks;         /* blocks of the persistent kernels */
+    size_t workspace_bytes;
+} to_plan_info;
+
+/* Workspace size for a mesh.  The workspace must be 256-byte aligned.
+ * Returns TO_EINVAL for a bad description (dim not 2/3, non-positive sizes,
+ * rmin <= 0, bc not 'D'/'N', fixed DOF out of range, more than 2^31-1 index
+ * pairs). */
+to_status to_plan_query(const to_mesh_desc* desc, size_t* ws_bytes);
+
+/* Builds the plan (Sec. 3, blocks PRE.2 and PRE.5): connectivity, the reduced
+ * index set I_r of eq. (14), the lower-triangular CSR pattern of K^(s) with
+ * every DOF kept (row_ptr, col_idx ascending within a row), the stable
+ * (row, col)-sort permutation of I_r that assembly reduces through (seg_ptr
+ * delimits each slot's pairs, in ascending pair order), the element matrix
+ * Ke by Gauss quadrature, the cone filter table and its weights Hs.  Uploads
+ * them into `ws` on `stream` and synchronises that stream before returning.
+ * The plan header is host memory owned by the library until to_plan_destroy;
+ * `ws` must outlive the plan. */
+to_status to_plan_create(const to_mesh_desc* desc, void* ws, size_t ws_bytes, void* stream,
+                         to_plan** out);
+void to_plan_destroy(to_plan* plan);
+to_status to_plan_get_info(const to_plan* plan, to_plan_info* out);
+
+/* Copies one plan array to host memory `h_dst` (synchronous on `stream`):
+ *   TO_X_PAIRS   int32 [n_pairs][2]  I_r as (row, col), row >= col
+ *   TO_X_PERM    int32 [n_pairs]     stable sort permutation of I_r
+ *   TO_X_SEGPTR  int32 [nnz_lower+1]
+ *   TO_X_ROWPTR  int32 [n+1]
+ *   TO_X_COLIDX  int32 [nnz_lower]
+ *   TO_X_HS      double [m]          filter weights Hs = h * 1 (eq. (2))
+ *   TO_X_KE      double [d~]         lower triangle of Ke, column by column
+ *   TO_X_FREE    uint8 [n]           1 = free DOF
+ *   TO_X_KERNEL  double [(2R+1)^dim] cone weights h, y fastest */
+enum { TO_X_PAIRS = 0, TO_X_PERM, TO_X_SEGPTR, TO_X_ROWPTR, TO_X_COLIDX, TO_X_HS, TO_X_KE,
+       TO_X_FREE, TO_X_KERNEL };
+to_status to_plan_export(const to_plan* plan, int what, void* h_dst, size_t dst_bytes,
+                         void* stream);
+
+/* Builds one of the arrays above on the host, without a device, with the same
+ * host code to_plan_create runs (for checks on machines without a GPU).
+ * TO_X_HS is device-computed: TO_EUNSUPPORTED. */
+to_status to_plan_build_host(const to_mesh_desc* desc, int what, void* h_dst, size_t dst_bytes);
+
+const char* to_status_string(to_status s);
+const char* to_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * to_filter -- density filter, eq. (2), and its adjoint, eq. (8) read as the
+ * chain rule (the 2D code's back-filter).
+ *   mode TO_FILTER_FWD:  out = (h * in) / Hs                         (s unused)
+ *   mode TO_FILTER_ADJ:  out = h * (in . s / Hs)   = H^T (s . in)   (s NULL -> 1)
+ *   mode TO_FILTER_ADJ2: two adjoints sharing one pass: out = h*(in.s/Hs) and
+ *                        out2 = h*(in2.s/Hs)
+ * in, in2, s, out, out2: device, m values of `dtype`, element order.  `out`
+ * may not alias an input. */
+enum { TO_FILTER_FWD = 0, TO_FILTER_ADJ = 1, TO_FILTER_ADJ2 = 2 };
+to_status to_filter(const to_plan* plan, to_dtype dtype, int mode, const void* in,
+                    const void* in2, const void* s, void* out, void* out2, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * to_project -- physical density (block RL.1): eq. (1) projection, eq. (9)
+ * derivative, eq. (17) volume-preserving threshold by Newton (ft = 3).
+ *   xpre  = xtilde on active elements, 1 on passive solid, 0 on passive void;
+ *   ft = 1: xphys = xpre, dprj = 1;  ft = 2: projection at the given eta;
+ *   ft = 3: Newton on g(eta) = mean(prj(xpre, eta)) - target from *d_eta until
+ *           |g| <= 1e-6 (at most 50 steps), target = `target`, or mean(xtilde)
+ *           when target is NaN;
+ *   xphys = prj(xpre, eta, beta); dprj = d prj/d x at xtilde.
+ * d_eta: device double, in/out.  xphys_old: device, nullable; when given,
+ * ch = |xphys - xphys_old|_2 / sqrt(m).  d_stats: device to_project_stats. */
+typedef struct {
+    double eta, g, ch, vol;      /* final eta, residual g, change, mean(xphys) */
+    int32_t n_newton, converged; /* Newton steps; 1 if |g| <= 1e-6 */
+    int32_t pad[2];
+} to_project_stats;
+to_status to_project(const to_plan* plan, to_dtype dtype, int ft, const void* xtilde,
+                     const void* x, void* xphys, void* dprj, double beta, double* d_eta,
+                     double target, const void* xphys_old, to_project_stats* d_stats,
+                     void* stream);
+
+/* ---------------------------------------------------------------------------
+ * to_assemble -- K^(s) values (block RL.2, eq. (6) and (14)):
+ *   E_e = Emin + xphys_e^penal (E0 - Emin);  sK[e d~ + k] = Ke[k] E_e;
+ *   kval[s] = sum of sK[perm[t]] for t = seg_ptr[s] .. seg_ptr[s+1]-1, ascending.
+ * xphys: device, m; kval: device, nnz_lower (CSR order of the plan). */
+to_status to_assemble(const to_plan* plan, to_dtype dtype, const void* xphys, double penal,
+                      void* kval, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * to_solve -- K(free, free) u = f (eq. (5)) by Jacobi-preconditioned CG.
+ * Fixed DOFs hold u = 0.  The stop test is on the 2-norm over free DOFs:
+ * |f - K u| <= rtol |f|, checked on the recursive residual and confirmed on a
+ * recomputed one (CG restarts from the recomputed residual otherwise).
+ *   dtype TO_F64: plain FP64 PCG with the operator chosen by `op`.
+ *   dtype TO_F32: mixed precision -- outer FP64 residual r = f - K64 u from
+ *                 the element moduli (matrix-free, FP64), inner FP32 PCG on the
+ *                 FP32 assembled kval to relative tolerance inner_rtol, u += d;
+ *                 if the outer loop has not converged after max_outer passes,
+ *                 or stagnates, it falls back to FP64 matrix-free PCG from the
+ *                 current u (flagged in the stats).
+ * kval: device, nnz_lower values of dtype (needed for op TO_OP_ASSEMBLED and
+ * for TO_F32); xphys: device m values of dtype (moduli for the matrix-free
+ * operator); f, u: device double n; u holds the initial guess on entry. */
+enum { TO_OP_ASSEMBLED = 0, TO_OP_MATFREE = 1 };
+typedef struct {
+    double rtol;                 /* default 1e-8 */
+    double inner_rtol;           /* mixed precision inner tolerance, default 1e-4 */
+    int32_t maxit;               /* total CG iteration cap, default 200000 */
+    int32_t max_outer;           /* mixed precision refinement passes, default 30 */
+    int32_t op;                  /* TO_OP_ASSEMBLED | TO_OP_MATFREE (FP64 mode) */
+    int32_t zero_x0;             /* 1: ignore u on entry, start from 0 */
+} to_solve_opts;
+typedef struct {
+    double residual;             /* final true relative residual (FP64) */
+    double bnorm;                /* |f_free|_2 */
+    int32_t iterations;          /* CG iterations (inner + fallback) */
+    int32_t outer;               /* refinement passes (mixed) */
+    int32_t converged;           /* 1 if residual <= rtol */
+    int32_t fallback;            /* 1 if the FP64 fallback ran */
+    int32_t restarts;            /* residual-replacement restarts */
+    int32_t pad;
+} to_solve_stats;
+to_status to_solve(const to_plan* plan, to_dtype dtype, const void* kval, const void* xphys,
+                   double penal, const double* f, double* u, const to_solve_opts* h_opts,
+                   to_solve_stats* d_stats, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * to_sensitivity -- eq. (7): dc_e = -penal (E0 - Emin) xphys_e^(penal-1)
+ * u_e^T Ke u_e on active elements, 0 on passive ones; and the compliance
+ * c = f^T u written to d_compliance (device double).  f may be NULL (then c
+ * is not written). */
+to_status to_sensitivity(const to_plan* plan, to_dtype dtype, const void* xphys,
+                         const double* u, const double* f, double penal, void* dc,
+                         double* d_compliance, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * to_oc_update -- OC rule eq. (10)-(11) with bisection on sqrt(lambda) over
+ * [0, sqrt(lambda#)] of eq. (19) (block RL.4 of the 2D code):
+ *   ocP = x sqrt(max(0, -dc/dv)) on active elements;
+ *   l1 = 0, l2 = mean_active(ocP)/volfrac;
+ *   while (l2-l1)/(l2+l1) > 1e-4 (at most 200 steps):
+ *       lmid = (l1+l2)/2; x_act = clamp(ocP/lmid, max(0, x-move), min(1, x+move));
+ *       mean_all(x) > volfrac ? l1 = lmid : l2 = lmid.
+ * The volume sums are double-double, so the decisions match an exactly
+ * rounded sum.  The GPU evaluates 15 bisection candidates per pass (the next
+ * four levels of the bisection tree) and follows the same decision path.
+ * x: device, m, in/out; dc, dv: device, m (already back-filtered). */
+typedef struct {
+    double lmid, l1, l2, vol;    /* last midpoint, final bracket, final mean(x) */
+    int32_t n_bs, capped;        /* bisection steps, 1 if the 200 cap was hit */
+    int32_t passes, pad;         /* device passes over the design */
+} to_oc_stats;
+to_status to_oc_update(const to_plan* plan, to_dtype dtype, void* x, const void* dc,
+                       const void* dv, double volfrac, double move, to_oc_stats* d_stats,
+                       void* stream);
+
+/* ---------------------------------------------------------------------------
+ * to_step -- one redesign iteration (blocks RL.1-RL.4): filter, projection,
+ * change, assembly, solve, sensitivities + compliance, back-filter of dc and
+ * dV, OC, then parameter continuation.  All buffers are device memory of
+ * `dtype` unless noted; the caller allocates them (m or n entries).  The
+ * host-side fields of to_step_state (penal, beta, loop) are updated. */
+typedef struct {
+    int32_t istart, isteps;      /* continuation starts at loop istart, every isteps */
+    double maxpar, delta;        /* up to maxpar, by +delta (mul = 0) or *delta (mul = 1) */
+    int32_t mul, enabled;
+} to_sched;
+typedef struct {
+    double volfrac, move;
+    int32_t ft;                  /* 1, 2 or 3 */
+    int32_t pad;
+    double target;               /* Newton target; NaN -> volfrac (the codes' choice) */
+    to_sched penal_sched, beta_sched;
+    to_solve_opts solve;
+} to_step_params;
+typedef struct {
+    void *x, *xtilde, *xphys, *xphys_old, *dprj, *dc, *dcf, *dv, *dv0, *kval;
+    double* u;                   /* n, warm start in / solution out */
+    const double* f;             /* n */
+    double* eta;                 /* device scalar */
+    double* compliance;          /* device scalar */
+    to_project_stats* pstats;    /* device */
+    to_solve_stats* sstats;      /* device */
+    to_oc_stats* ostats;         /* device */
+    double penal, beta;          /* host: current continuation parameters */
+    int32_t loop;                /* host: iterations done */
+    int32_t pad;
+} to_step_state;
+to_status to_step(const to_plan* plan, to_dtype dtype, to_step_state* h_state,
+                  const to_step_params* h_params, void* stream);
+
+/* Continuation rule of Sec. 3 (host scalar): par grows by delta (or times
+ * delta) after iteration `loop` when loop >= istart, par < maxpar and
+ * loop % isteps == 0. */
+double to_continuation(double par, const to_sched* sched, int32_t loop);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TOPT_H */

@@ -84,3 +84,23 @@ def lower_to_full(row_ptr, col_idx, vals, n):
     import scipy.sparse as sp
     L = sp.csr_matrix((vals, col_idx, row_ptr), shape=(n, n))
     return (L + L.T - sp.diags(L.diagonal())).tocsr()
+
+
+def assemble_entry(cmat, ke_lower, E, row, col):
+    """One value of K^(s) computed from its definition: every (element,
+    local pair) whose sorted global pair is (row, col), summed in ascending
+    (element, pair) order.  Cost O(elements containing both DOFs) after a
+    scan of the connectivity; meant for sampled checks on large meshes."""
+    d = cmat.shape[1]
+    has_r = np.any(cmat == row, axis=1)
+    has_c = np.any(cmat == col, axis=1)
+    acc = 0.0
+    for e in np.flatnonzero(has_r & has_c):
+        k = 0
+        for j in range(d):
+            for i in range(j, d):
+                a, b = cmat[e, i], cmat[e, j]
+                if max(a, b) == row and min(a, b) == col:
+                    acc += ke_lower[k] * E[e]
+                k += 1
+    return acc

@@ -1,0 +1,219 @@
+"""ctypes binding of include/topt.h: argument marshalling only.
+
+Every function keeps the C name.  Tensor arguments may be torch tensors
+(their data_ptr() is passed) or plain integers (device addresses); host
+arrays are numpy arrays.  A non-OK status raises ToError with the library's
+own message.  There is no fallback: without the built library every call
+fails loudly.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtopt.so")
+
+TO_OK, TO_EINVAL, TO_EHIP, TO_EWORKSPACE, TO_EUNSUPPORTED = range(5)
+TO_F32, TO_F64 = 0, 1
+TO_ACTIVE, TO_SOLID, TO_VOID = 0, 1, 2
+(TO_X_PAIRS, TO_X_PERM, TO_X_SEGPTR, TO_X_ROWPTR, TO_X_COLIDX, TO_X_HS, TO_X_KE, TO_X_FREE,
+ TO_X_KERNEL) = range(9)
+TO_FILTER_FWD, TO_FILTER_ADJ, TO_FILTER_ADJ2 = 0, 1, 2
+TO_OP_ASSEMBLED, TO_OP_MATFREE = 0, 1
+
+EXPORTED = ["to_plan_query", "to_plan_create", "to_plan_destroy", "to_plan_get_info", "to_plan_export",
+            "to_plan_build_host",
+            "to_status_string", "to_last_error", "to_filter", "to_project", "to_assemble", "to_solve",
+            "to_sensitivity", "to_oc_update", "to_step", "to_continuation"]
+
+
+class ToError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"topt status {status}: {msg}")
+        self.status = status
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nelx", C.c_int32), ("nely", C.c_int32), ("nelz", C.c_int32),
+                ("E0", C.c_double), ("Emin", C.c_double), ("nu", C.c_double), ("rmin", C.c_double),
+                ("bc", C.c_char), ("h_passive", C.c_void_p), ("h_fixed", C.c_void_p), ("n_fixed", C.c_int64)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("d", C.c_int32), ("dtilde", C.c_int32),
+                ("m", C.c_int64), ("nnode", C.c_int64), ("n", C.c_int64), ("n_pairs", C.c_int64),
+                ("nnz_lower", C.c_int64), ("n_active", C.c_int64), ("n_solid", C.c_int64),
+                ("n_void", C.c_int64), ("n_free", C.c_int64), ("filter_radius", C.c_int32),
+                ("coop_blocks", C.c_int32), ("workspace_bytes", C.c_size_t)]
+
+
+class ProjectStats(C.Structure):
+    _fields_ = [("eta", C.c_double), ("g", C.c_double), ("ch", C.c_double), ("vol", C.c_double),
+                ("n_newton", C.c_int32), ("converged", C.c_int32), ("pad", C.c_int32 * 2)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("inner_rtol", C.c_double), ("maxit", C.c_int32),
+                ("max_outer", C.c_int32), ("op", C.c_int32), ("zero_x0", C.c_int32)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("residual", C.c_double), ("bnorm", C.c_double), ("iterations", C.c_int32),
+                ("outer", C.c_int32), ("converged", C.c_int32), ("fallback", C.c_int32),
+                ("restarts", C.c_int32), ("pad", C.c_int32)]
+
+
+class OcStats(C.Structure):
+    _fields_ = [("lmid", C.c_double), ("l1", C.c_double), ("l2", C.c_double), ("vol", C.c_double),
+                ("n_bs", C.c_int32), ("capped", C.c_int32), ("passes", C.c_int32), ("pad", C.c_int32)]
+
+
+class Sched(C.Structure):
+    _fields_ = [("istart", C.c_int32), ("isteps", C.c_int32), ("maxpar", C.c_double),
+                ("delta", C.c_double), ("mul", C.c_int32), ("enabled", C.c_int32)]
+
+
+class StepParams(C.Structure):
+    _fields_ = [("volfrac", C.c_double), ("move", C.c_double), ("ft", C.c_int32), ("pad", C.c_int32),
+                ("target", C.c_double), ("penal_sched", Sched), ("beta_sched", Sched), ("solve", SolveOpts)]
+
+
+class StepState(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("x", "xtilde", "xphys", "xphys_old", "dprj", "dc", "dcf", "dv",
+                                          "dv0", "kval", "u", "f", "eta", "compliance", "pstats", "sstats",
+                                          "ostats")] + \
+               [("penal", C.c_double), ("beta", C.c_double), ("loop", C.c_int32), ("pad", C.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Loads libtopt.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(python -m paper_2005_05436_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    P, S = C.c_void_p, C.c_int
+    sig = {
+        "to_plan_query": (S, [C.POINTER(MeshDesc), C.POINTER(C.c_size_t)]),
+        "to_plan_create": (S, [C.POINTER(MeshDesc), P, C.c_size_t, P, C.POINTER(P)]),
+        "to_plan_destroy": (None, [P]),
+        "to_plan_get_info": (S, [P, C.POINTER(PlanInfo)]),
+        "to_plan_export": (S, [P, C.c_int, P, C.c_size_t, P]),
+        "to_plan_build_host": (S, [C.POINTER(MeshDesc), C.c_int, P, C.c_size_t]),
+        "to_status_string": (C.c_char_p, [S]),
+        "to_last_error": (C.c_char_p, []),
+        "to_filter": (S, [P, S, C.c_int, P, P, P, P, P, P]),
+        "to_project": (S, [P, S, C.c_int, P, P, P, P, C.c_double, P, C.c_double, P, P, P]),
+        "to_assemble": (S, [P, S, P, C.c_double, P, P]),
+        "to_solve": (S, [P, S, P, P, C.c_double, P, P, C.POINTER(SolveOpts), P, P]),
+        "to_sensitivity": (S, [P, S, P, P, P, C.c_double, P, P, P]),
+        "to_oc_update": (S, [P, S, P, P, P, C.c_double, C.c_double, P, P]),
+        "to_step": (S, [P, S, C.POINTER(StepState), C.POINTER(StepParams), P]),
+        "to_continuation": (C.c_double, [C.c_double, C.POINTER(Sched), C.c_int32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def ptr(t):
+    """Device/host address of a torch tensor, numpy array or int (None -> NULL)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    raise TypeError(f"cannot take the address of {type(t)}")
+
+
+def check(status):
+    if status != TO_OK:
+        lib = load()
+        raise ToError(status, lib.to_last_error().decode())
+
+
+def stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+# --- same-name wrappers ------------------------------------------------------
+def to_plan_query(desc):
+    n = C.c_size_t(0)
+    check(load().to_plan_query(C.byref(desc), C.byref(n)))
+    return n.value
+
+
+def to_plan_create(desc, ws, ws_bytes, stream=None):
+    out = C.c_void_p()
+    check(load().to_plan_create(C.byref(desc), ptr(ws), ws_bytes, stream_ptr(stream), C.byref(out)))
+    return out.value
+
+
+def to_plan_destroy(plan):
+    load().to_plan_destroy(plan)
+
+
+def to_plan_get_info(plan):
+    info = PlanInfo()
+    check(load().to_plan_get_info(plan, C.byref(info)))
+    return info
+
+
+def to_plan_export(plan, what, dst, stream=None):
+    check(load().to_plan_export(plan, what, ptr(dst), dst.nbytes, stream_ptr(stream)))
+    return dst
+
+
+def to_plan_build_host(desc, what, dst):
+    check(load().to_plan_build_host(C.byref(desc), what, ptr(dst), dst.nbytes))
+    return dst
+
+
+def to_filter(plan, dtype, mode, inp, in2, s, out, out2, stream=None):
+    check(load().to_filter(plan, dtype, mode, ptr(inp), ptr(in2), ptr(s), ptr(out), ptr(out2), stream_ptr(stream)))
+
+
+def to_project(plan, dtype, ft, xtilde, x, xphys, dprj, beta, d_eta, target, xphys_old, d_stats, stream=None):
+    check(load().to_project(plan, dtype, ft, ptr(xtilde), ptr(x), ptr(xphys), ptr(dprj), beta, ptr(d_eta),
+                            target, ptr(xphys_old), ptr(d_stats), stream_ptr(stream)))
+
+
+def to_assemble(plan, dtype, xphys, penal, kval, stream=None):
+    check(load().to_assemble(plan, dtype, ptr(xphys), penal, ptr(kval), stream_ptr(stream)))
+
+
+def to_solve(plan, dtype, kval, xphys, penal, f, u, opts, d_stats, stream=None):
+    check(load().to_solve(plan, dtype, ptr(kval), ptr(xphys), penal, ptr(f), ptr(u),
+                          C.byref(opts) if opts is not None else None, ptr(d_stats), stream_ptr(stream)))
+
+
+def to_sensitivity(plan, dtype, xphys, u, f, penal, dc, d_compliance, stream=None):
+    check(load().to_sensitivity(plan, dtype, ptr(xphys), ptr(u), ptr(f), penal, ptr(dc), ptr(d_compliance),
+                                stream_ptr(stream)))
+
+
+def to_oc_update(plan, dtype, x, dc, dv, volfrac, move, d_stats, stream=None):
+    check(load().to_oc_update(plan, dtype, ptr(x), ptr(dc), ptr(dv), volfrac, move, ptr(d_stats),
+                              stream_ptr(stream)))
+
+
+def to_step(plan, dtype, state, params, stream=None):
+    check(load().to_step(plan, dtype, C.byref(state), C.byref(params), stream_ptr(stream)))
+
+
+def to_continuation(par, sched, loop):
+    return load().to_continuation(par, C.byref(sched), loop)

@@ -1,0 +1,166 @@
+// Physical density (block RL.1): Heaviside projection eq. (1), its derivative
+// eq. (9), and the volume-preserving threshold of eq. (17) by Newton's method
+// with the closed-form d prj / d eta of the codes.
+//
+// One persistent, cooperatively launched kernel does the whole block: each
+// Newton step is one sweep that accumulates sum prj and sum d prj/d eta in
+// FP64, a grid barrier, and an identical fixed-order reduction in every block
+// (so every block takes the same Newton decision).  A final sweep writes
+// xphys and dprj and accumulates the change and the volume.
+#include <cmath>
+
+#include "common.h"
+
+namespace topt {
+
+struct ProjCoef {
+    double beta, eta, den, tbe, csch;
+    __device__ void set(double b, double e) {
+        beta = b; eta = e;
+        tbe = tanh(b * e);
+        den = tbe + tanh(b * (1.0 - e));
+        csch = 1.0 / sinh(b);
+    }
+    __device__ double prj(double v) const { return (tbe + tanh(beta * (v - eta))) / den; }
+    __device__ double dprj(double v) const {
+        double t = tanh(beta * (v - eta));
+        return beta * (1.0 - t * t) / den;
+    }
+    __device__ double deta(double v) const {
+        double c = cosh(beta * (v - eta));
+        return -beta * csch / (c * c) * sinh(v * beta) * sinh((1.0 - v) * beta);
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ double pre_value(const T* xt, const T* x, const uint8_t* pas, int64_t e) {
+    uint8_t c = pas[e];
+    if (c == TO_ACTIVE) return (double)xt[e];
+    if (x) return (double)x[e];
+    return c == TO_SOLID ? 1.0 : 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void project_kernel(
+    int64_t m, int ft, const T* __restrict__ xt, const T* __restrict__ x, const uint8_t* __restrict__ pas,
+    T* __restrict__ xphys, T* __restrict__ dprj, double beta, double* d_eta, double target,
+    int mean_target, const T* __restrict__ xold, to_project_stats* st, double* partial, unsigned* bar) {
+    __shared__ double sh[kWaves];
+    __shared__ double red[4];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double eta = *d_eta;
+    bool alive = true;
+
+    if (ft == 3 && mean_target) {                     // eq. (17): target = volume of the pre-projection field
+        double s = 0.0;
+        for (int64_t e = i0; e < m; e += stride) s += pre_value(xt, x, pas, e);
+        s = block_sum(s, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x * kPartialWidth] = s;
+        alive = grid_sync(bar);
+        grid_reduce<1>(partial, red, sh);
+        target = red[0] / (double)m;
+        alive = alive && grid_sync(bar);              // partial buffer is reused below
+    }
+
+    int steps = 0;
+    double g = 0.0;
+    ProjCoef P;
+    if (ft == 3) {
+        for (;;) {
+            P.set(beta, eta);
+            double sp = 0.0, sd = 0.0;
+            if (alive)
+                for (int64_t e = i0; e < m; e += stride) {
+                    double v = pre_value(xt, x, pas, e);
+                    sp += P.prj(v);
+                    sd += P.deta(v);
+                }
+            sp = block_sum(sp, sh);
+            sd = block_sum(sd, sh);
+            if (threadIdx.x == 0) {
+                partial[blockIdx.x * kPartialWidth + 0] = sp;
+                partial[blockIdx.x * kPartialWidth + 1] = sd;
+            }
+            alive = grid_sync(bar) && alive;
+            grid_reduce<2>(partial, red, sh);
+            g = red[0] / (double)m - target;
+            if (!(fabs(g) > 1e-6) || steps >= 50 || !alive) break;
+            eta = eta - g / (red[1] / (double)m);
+            ++steps;
+            alive = grid_sync(bar) && alive;          // everyone has read the partials
+        }
+        alive = grid_sync(bar) && alive;
+    }
+    P.set(beta, eta);
+    double sc = 0.0, sv = 0.0;
+    if (alive)
+        for (int64_t e = i0; e < m; e += stride) {
+            double v = pre_value(xt, x, pas, e);
+            double xp = ft >= 2 ? P.prj(v) : v;
+            double dp = ft >= 2 ? P.dprj((double)xt[e]) : 1.0;
+            T xpT = (T)xp;
+            xphys[e] = xpT;
+            dprj[e] = (T)dp;
+            if (xold) {
+                double dlt = (double)xpT - (double)xold[e];
+                sc += dlt * dlt;
+            }
+            sv += (double)xpT;
+        }
+    sc = block_sum(sc, sh);
+    sv = block_sum(sv, sh);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x * kPartialWidth + 0] = sc;
+        partial[blockIdx.x * kPartialWidth + 1] = sv;
+    }
+    alive = grid_sync(bar) && alive;
+    if (blockIdx.x == 0) {
+        grid_reduce<2>(partial, red, sh);
+        if (threadIdx.x == 0) {
+            to_project_stats s;
+            s.eta = eta;
+            s.g = g;
+            s.ch = xold ? sqrt(red[0]) / sqrt((double)m) : NAN;
+            s.vol = red[1] / (double)m;
+            s.n_newton = steps;
+            s.converged = (ft != 3 || fabs(g) <= 1e-6) && alive ? 1 : 0;
+            s.pad[0] = s.pad[1] = 0;
+            *st = s;
+            *d_eta = eta;
+        }
+    }
+}
+
+int coop_blocks_for(const void* kernel, int block, size_t smem, int num_cu) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, smem) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return std::min(kMaxCoopBlocks, per_cu * num_cu);
+}
+
+template <typename T>
+static to_status run_project(Plan* p, int ft, const void* xt, const void* x, void* xphys, void* dprj,
+                             double beta, double* d_eta, double target, const void* xold,
+                             to_project_stats* st, hipStream_t s) {
+    auto k = project_kernel<T>;
+    int64_t m = p->info.m;
+    int maxb = coop_blocks_for((const void*)k, kBlock, 0, p->num_cu);
+    int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(maxb, (m + kBlock - 1) / kBlock));
+    int mean_target = std::isnan(target) ? 1 : 0;
+    const T* a = (const T*)xt; const T* b = (const T*)x; const uint8_t* pas = p->passive;
+    T* c = (T*)xphys; T* dp = (T*)dprj; const T* xo = (const T*)xold;
+    double* partial = p->partial; unsigned* bar = p->bar;
+    void* args[] = {&m, &ft, &a, &b, &pas, &c, &dp, &beta, &d_eta, &target, &mean_target, &xo, &st, &partial, &bar};
+    TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(kBlock), args, 0, s));
+    return TO_OK;
+}
+
+to_status launch_project(Plan* p, to_dtype dt, int ft, const void* xt, const void* x, void* xphys,
+                         void* dprj, double beta, double* d_eta, double target, const void* xold,
+                         to_project_stats* st, hipStream_t s) {
+    if (dt == TO_F64) return run_project<double>(p, ft, xt, x, xphys, dprj, beta, d_eta, target, xold, st, s);
+    return run_project<float>(p, ft, xt, x, xphys, dprj, beta, d_eta, target, xold, st, s);
+}
+
+}  // namespace topt

@@ -1,0 +1,154 @@
+"""Plan and optimisation-loop objects around the C ABI.  PyTorch supplies
+device memory and the stream; every step of the method runs in libtopt's
+kernels (to_step and the single-step entry points)."""
+import ctypes as C
+import math
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import problems
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        raise RuntimeError("libtopt needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def _struct_tensor(ctype, device):
+    return torch.zeros(C.sizeof(ctype), dtype=torch.uint8, device=device)
+
+
+def read_struct(t, ctype):
+    """Copies a device stats struct to the host (synchronising)."""
+    raw = t.cpu().numpy().tobytes()
+    return ctype.from_buffer_copy(raw)
+
+
+def struct_dict(s):
+    return {k: getattr(s, k) for k, _ in s._fields_ if k != "pad"}
+
+
+class Plan:
+    """Owns the plan header and its device workspace."""
+
+    def __init__(self, dim, nelx, nely, nelz=1, rmin=2.0, bc="D", fixed=(), passive=None,
+                 E0=1.0, Emin=1e-9, nu=0.3, stream=None):
+        self.device = _dev()
+        self.fixed = np.ascontiguousarray(np.asarray(fixed, dtype=np.int32))
+        self.passive = None if passive is None else np.ascontiguousarray(np.asarray(passive, dtype=np.uint8))
+        self.desc = L.MeshDesc(dim, nelx, nely, nelz if dim == 3 else 1, E0, Emin, nu, rmin, bc.encode(),
+                               L.ptr(self.passive), L.ptr(self.fixed), len(self.fixed))
+        self.ws_bytes = L.to_plan_query(self.desc)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) & ~255
+        self.handle = L.to_plan_create(self.desc, self.ws_ptr, self.ws_bytes, stream)
+        self.info = L.to_plan_get_info(self.handle)
+        self.dim, self.nelx, self.nely, self.nelz = dim, nelx, nely, nelz if dim == 3 else 1
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.to_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def export(self, what):
+        I = self.info
+        shapes = {L.TO_X_PAIRS: (np.int32, (I.n_pairs, 2)), L.TO_X_PERM: (np.int32, (I.n_pairs,)),
+                  L.TO_X_SEGPTR: (np.int32, (I.nnz_lower + 1,)), L.TO_X_ROWPTR: (np.int32, (I.n + 1,)),
+                  L.TO_X_COLIDX: (np.int32, (I.nnz_lower,)), L.TO_X_HS: (np.float64, (I.m,)),
+                  L.TO_X_KE: (np.float64, (I.dtilde,)), L.TO_X_FREE: (np.uint8, (I.n,)),
+                  L.TO_X_KERNEL: (np.float64, ((2 * I.filter_radius + 1) ** I.dim,))}
+        dt, shape = shapes[what]
+        out = np.empty(shape, dtype=dt)
+        return L.to_plan_export(self.handle, what, out)
+
+
+def plan_for_config(cfg, passive=None):
+    f, fixed = problems.from_config(cfg)
+    p = Plan(cfg.dim, cfg.nelx, cfg.nely, cfg.nelz or 1, cfg.rmin, cfg.bc, fixed, passive,
+             cfg.E0, cfg.Emin, cfg.nu)
+    return p, f
+
+
+def _sched(s):
+    if s is None:
+        return L.Sched(0, 1, 0.0, 0.0, 0, 0)
+    istart, maxpar, isteps, delta, mode = s
+    return L.Sched(istart, isteps, maxpar, delta, 1 if mode == "mul" else 0, 1)
+
+
+class TopOpt:
+    """The redesign loop on the GPU: state buffers + to_step."""
+
+    def __init__(self, cfg, op=L.TO_OP_ASSEMBLED, rtol=1e-8, inner_rtol=1e-4, maxit=200000,
+                 precision=None, passive=None):
+        self.cfg = cfg
+        self.plan, f = plan_for_config(cfg, passive)
+        dev = self.plan.device
+        I = self.plan.info
+        prec = precision or cfg.precision
+        self.dtype = L.TO_F64 if prec == "f64" else L.TO_F32
+        tdt = torch.float64 if self.dtype == L.TO_F64 else torch.float32
+        m, n = I.m, I.n
+        code = np.zeros(m, np.uint8) if passive is None else np.asarray(passive, np.uint8)
+        act = code == L.TO_ACTIVE
+        x0 = np.zeros(m)
+        x0[act] = (cfg.volfrac * (m - np.sum(code == L.TO_VOID)) - np.sum(code == L.TO_SOLID)) / np.sum(act)
+        x0[code == L.TO_SOLID] = 1.0
+        dv = np.zeros(m)
+        dv[act] = 1.0 / m / cfg.volfrac
+        mk = lambda a=None: (torch.zeros(m, dtype=tdt, device=dev) if a is None
+                             else torch.as_tensor(a, dtype=tdt).to(dev))
+        self.x, self.xtilde, self.xphys = mk(x0), mk(), mk(x0)
+        self.xphys_old = torch.ones(m, dtype=tdt, device=dev)
+        self.dprj, self.dc, self.dcf, self.dv, self.dv0 = mk(), mk(), mk(dv), mk(dv), mk()
+        self.kval = torch.zeros(I.nnz_lower, dtype=tdt, device=dev)
+        self.u = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.f = torch.as_tensor(f, dtype=torch.float64).to(dev)
+        self.eta = torch.tensor([cfg.eta], dtype=torch.float64, device=dev)
+        self.c = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.pst = _struct_tensor(L.ProjectStats, dev)
+        self.sst = _struct_tensor(L.SolveStats, dev)
+        self.ost = _struct_tensor(L.OcStats, dev)
+        self.state = L.StepState(*[L.ptr(t) for t in (self.x, self.xtilde, self.xphys, self.xphys_old,
+                                                      self.dprj, self.dc, self.dcf, self.dv, self.dv0,
+                                                      self.kval, self.u, self.f, self.eta, self.c,
+                                                      self.pst, self.sst, self.ost)],
+                                 cfg.penal, cfg.beta, 0, 0)
+        self.params = L.StepParams(cfg.volfrac, cfg.move, cfg.ft, 0, math.nan, _sched(cfg.penal_sched),
+                                   _sched(cfg.beta_sched), L.SolveOpts(rtol, inner_rtol, maxit, 30, op, 0))
+
+    @property
+    def loop(self):
+        return self.state.loop
+
+    def step(self, stream=None):
+        """Enqueues one redesign iteration (no host synchronisation)."""
+        L.to_step(self.plan.handle, self.dtype, self.state, self.params, stream)
+
+    def stats(self):
+        """Synchronising read of the last iteration's device statistics."""
+        p = read_struct(self.pst, L.ProjectStats)
+        s = read_struct(self.sst, L.SolveStats)
+        o = read_struct(self.ost, L.OcStats)
+        return dict(loop=self.state.loop, c=float(self.c.item()), vol=p.vol, ch=p.ch, eta=p.eta,
+                    n_newton=p.n_newton, newton_ok=bool(p.converged), n_bs=o.n_bs, lmid=o.lmid,
+                    oc_passes=o.passes, cg_it=s.iterations, residual=s.residual, solve_ok=bool(s.converged),
+                    fallback=s.fallback, outer=s.outer, penal=self.state.penal, beta=self.state.beta)
+
+    def run(self, iterations, log=False):
+        out = []
+        for _ in range(iterations):
+            self.step()
+            if log:
+                out.append(self.stats())
+        return out

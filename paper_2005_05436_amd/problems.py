@@ -1,0 +1,56 @@
+"""Problem definitions on the GPU-library side (block PRE.3 of the paper's
+codes): load vectors and fixed DOFs in the library's numbering
+(node n = iy + (nely+1) ix [+ (nely+1)(nelz+1)-strided z], DOF = dim n + c,
+row iy = 0 on top).  Host numpy only; these are inputs of the C ABI.
+"""
+import numpy as np
+
+
+def _node2(nely, iy, ix):
+    return iy + (nely + 1) * ix
+
+
+def _node3(nely, nelz, iy, ix, iz):
+    return iy + (nely + 1) * (iz + (nelz + 1) * ix)
+
+
+def mbb(nelx, nely, load_ix=0):
+    """Half MBB beam: unit downward load at the top node of column load_ix,
+    x-DOFs of the left edge and the y-DOF of the bottom-right node fixed."""
+    n = 2 * (nelx + 1) * (nely + 1)
+    f = np.zeros(n)
+    f[2 * _node2(nely, 0, load_ix) + 1] = -1.0
+    fixed = np.array([2 * _node2(nely, iy, 0) for iy in range(nely + 1)]
+                     + [2 * _node2(nely, nely, nelx) + 1], dtype=np.int32)
+    return f, np.unique(fixed)
+
+
+def cantilever2d(nelx, nely, load_iy):
+    """Left edge clamped, unit downward load on node (load_iy, nelx)."""
+    n = 2 * (nelx + 1) * (nely + 1)
+    f = np.zeros(n)
+    f[2 * _node2(nely, load_iy, nelx) + 1] = -1.0
+    iy = np.arange(nely + 1)
+    fixed = np.concatenate([2 * _node2(nely, iy, 0), 2 * _node2(nely, iy, 0) + 1]).astype(np.int32)
+    return f, np.unique(fixed)
+
+
+def cantilever3d(nelx, nely, nelz):
+    """Face x = 0 clamped; downward line load sin(pi iy / nely) on u_z along
+    the bottom edge (iz = 0) of the end x = nelx."""
+    n = 3 * (nelx + 1) * (nely + 1) * (nelz + 1)
+    f = np.zeros(n)
+    iy = np.arange(nely + 1)
+    f[3 * _node3(nely, nelz, iy, nelx, 0) + 2] = -np.sin(np.pi * iy / nely)
+    nodes = np.arange((nely + 1) * (nelz + 1))          # ix = 0 face: the first nodes
+    fixed = (3 * nodes[:, None] + np.arange(3)[None, :]).reshape(-1).astype(np.int32)
+    return f, fixed
+
+
+def from_config(cfg):
+    """(f, fixed) for a workloads.Config."""
+    if cfg.nelz:
+        return cantilever3d(cfg.nelx, cfg.nely, cfg.nelz)
+    if cfg.kind == "mbb":
+        return mbb(cfg.nelx, cfg.nely, cfg.load)
+    return cantilever2d(cfg.nelx, cfg.nely, cfg.load)

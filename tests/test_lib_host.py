@@ -1,0 +1,175 @@
+"""Host-side checks of libtopt.so (no GPU needed): every symbol of the header is
+exported, argument validation, and the plan builder's integer arrays
+(I_r, perm, seg_ptr, row_ptr, col_idx) are bit-exact against the oracle."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import continuation as ocont
+from oracle import element as oel
+from oracle import filt as ofilt
+from oracle import mesh as omesh
+from oracle import sparse as osp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+L = pytest.importorskip("paper_2005_05436_amd._lib")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    try:
+        return L.load()
+    except ImportError as e:
+        pytest.skip(str(e))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "topt.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(to_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(L.EXPORTED)
+
+
+def _desc(dim, nelx, nely, nelz=1, rmin=2.0, bc="D", fixed=None, passive=None, nu=0.3):
+    fixed = np.zeros(0, np.int32) if fixed is None else np.ascontiguousarray(fixed, np.int32)
+    d = L.MeshDesc(dim, nelx, nely, nelz, 1.0, 1e-9, nu, rmin, bc.encode(), L.ptr(passive), L.ptr(fixed), len(fixed))
+    d._keep = (fixed, passive)
+    return d
+
+
+def test_plan_query_and_validation(lib):
+    assert L.to_plan_query(_desc(2, 60, 20)) > 0
+    for bad in (_desc(4, 6, 2), _desc(2, 0, 2), _desc(2, 6, 2, rmin=-1.0), _desc(2, 6, 2, bc="X"),
+                _desc(2, 6, 2, fixed=np.array([10 ** 6])), _desc(2, 6, 2, nu=0.5)):
+        with pytest.raises(L.ToError) as ei:
+            L.to_plan_query(bad)
+        assert ei.value.status == L.TO_EINVAL
+    n = C.c_size_t()
+    assert lib.to_plan_query(None, C.byref(n)) == L.TO_EINVAL
+    assert b"NULL" in lib.to_last_error()
+    assert lib.to_status_string(L.TO_EHIP) == b"HIP runtime error"
+
+
+def _host(desc, what, dtype, count):
+    out = np.empty(count, dtype=dtype)
+    return L.to_plan_build_host(desc, what, out)
+
+
+def _mesh_of(dims):
+    return omesh.Mesh(*dims)
+
+
+@pytest.mark.parametrize("dims", [(4, 2), (5, 3), (60, 20), (300, 100), (2, 3, 2), (5, 4, 3), (12, 6, 6)])
+def test_plan_integer_arrays_bit_exact(lib, dims):
+    M = _mesh_of(dims)
+    desc = _desc(M.dim, M.nelx, M.nely, M.nelz)
+    ir = osp.reduced_index_set(M.cmat())
+    row_ptr, col_idx, perm, seg_ptr = osp.csr_pattern(ir, M.n)
+    np.testing.assert_array_equal(_host(desc, L.TO_X_PAIRS, np.int32, 2 * len(ir)).reshape(-1, 2), ir)
+    np.testing.assert_array_equal(_host(desc, L.TO_X_ROWPTR, np.int32, M.n + 1), row_ptr)
+    np.testing.assert_array_equal(_host(desc, L.TO_X_COLIDX, np.int32, len(col_idx)), col_idx)
+    np.testing.assert_array_equal(_host(desc, L.TO_X_PERM, np.int32, len(perm)), perm)
+    np.testing.assert_array_equal(_host(desc, L.TO_X_SEGPTR, np.int32, len(seg_ptr)), seg_ptr)
+
+
+def test_plan_perm_full_2d_size(lib):
+    """The 1200 x 400 mesh (17.28 M index pairs): bit-exact."""
+    M = omesh.Mesh(1200, 400)
+    desc = _desc(2, 1200, 400)
+    ir = osp.reduced_index_set(M.cmat())
+    _, _, perm, seg_ptr = osp.csr_pattern(ir, M.n)
+    np.testing.assert_array_equal(_host(desc, L.TO_X_PERM, np.int32, len(perm)), perm)
+    np.testing.assert_array_equal(_host(desc, L.TO_X_SEGPTR, np.int32, len(seg_ptr)), seg_ptr)
+
+
+def test_plan_perm_full_3d_size_properties(lib):
+    """96 x 48 x 48 (66.4 M pairs): perm is a permutation that sorts I_r by
+    (row, col) stably, seg_ptr delimits equal keys, nnz matches."""
+    M = omesh.Mesh(96, 48, 48)
+    desc = _desc(3, 96, 48, 48)
+    npairs = M.m * 300
+    perm = _host(desc, L.TO_X_PERM, np.int32, npairs).astype(np.int64)
+    pairs = _host(desc, L.TO_X_PAIRS, np.int32, 2 * npairs).reshape(-1, 2)
+    key = pairs[:, 0].astype(np.int64) * M.n + pairs[:, 1]
+    del pairs
+    sk = key[perm]
+    d = np.diff(sk)
+    assert np.all(d >= 0)
+    tie = d == 0
+    assert np.all(np.diff(perm)[tie] > 0)
+    assert np.bincount(perm, minlength=npairs).max() == 1
+    starts = np.flatnonzero(np.concatenate([[True], d != 0]))
+    nnz = len(starts)
+    assert nnz == 27_692_358
+    seg = _host(desc, L.TO_X_SEGPTR, np.int32, nnz + 1)
+    np.testing.assert_array_equal(seg[:-1], starts)
+    assert seg[-1] == npairs
+
+
+@pytest.mark.parametrize("nu", [0.3, 0.2])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_plan_element_matrix(lib, dim, nu):
+    desc = _desc(dim, 3, 2, 2, nu=nu)
+    ke = _host(desc, L.TO_X_KE, np.float64, 36 if dim == 2 else 300)
+    np.testing.assert_allclose(ke, oel.lower_vector(oel.element_matrix(dim, nu)), rtol=0, atol=2e-16)
+
+
+@pytest.mark.parametrize("dim,rmin", [(2, 2.0), (2, 10.0), (2, 3.3), (3, np.sqrt(3.0)), (3, 2.5)])
+def test_plan_filter_table(lib, dim, rmin):
+    desc = _desc(dim, 9, 7, 5, rmin=rmin)
+    h, R = ofilt.kernel(rmin, dim)
+    w = 2 * R + 1
+    got = _host(desc, L.TO_X_KERNEL, np.float64, w ** dim)
+    # library layout: y fastest, then z, then x; oracle h is indexed [y, x] / [y, z, x]
+    ref = h.transpose(1, 0).reshape(-1) if dim == 2 else h.transpose(2, 1, 0).reshape(-1)
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_plan_free_mask(lib):
+    M = omesh.Mesh(6, 3)
+    f, fixed = omesh.mbb(M)
+    desc = _desc(2, 6, 3, fixed=fixed.astype(np.int32))
+    fm = _host(desc, L.TO_X_FREE, np.uint8, M.n)
+    ref = np.ones(M.n, np.uint8)
+    ref[fixed] = 0
+    np.testing.assert_array_equal(fm, ref)
+
+
+def test_continuation_matches_oracle(lib):
+    for sched in [(1, 3.0, 25, 0.25, "add"), (1, 32.0, 25, 2.0, "mul"), (10, 5.0, 7, 1.5, "add")]:
+        s = L.Sched(sched[0], sched[2], sched[1], sched[3], 1 if sched[4] == "mul" else 0, 1)
+        a = b = 1.0
+        for loop in range(1, 260):
+            a = L.to_continuation(a, s, loop)
+            b = ocont.cnt(b, sched, loop)
+            assert a == b
+
+
+def test_problem_definitions_match_oracle():
+    from paper_2005_05436_amd import problems
+    for nelx, nely, load in [(60, 20, 0), (30, 15, 7)]:
+        M = omesh.Mesh(nelx, nely)
+        f1, x1 = problems.mbb(nelx, nely, load)
+        f2, x2 = omesh.mbb(M, load)
+        np.testing.assert_array_equal(f1, f2)
+        np.testing.assert_array_equal(x1, x2)
+        f1, x1 = problems.cantilever2d(nelx, nely, load % (nely + 1))
+        f2, x2 = omesh.cantilever2d(M, load % (nely + 1))
+        np.testing.assert_array_equal(f1, f2)
+        np.testing.assert_array_equal(x1, x2)
+    M = omesh.Mesh(6, 4, 3)
+    f1, x1 = problems.cantilever3d(6, 4, 3)
+    f2, x2 = omesh.cantilever3d(M)
+    np.testing.assert_array_equal(f1, f2)
+    np.testing.assert_array_equal(x1, x2)
