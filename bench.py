@@ -1,0 +1,261 @@
+"""Benchmark of the SIMP redesign iteration on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--precision f32|f64] [--op assembled|matfree] [--no-cpu]
+
+A step is one redesign iteration through the C ABI: filter, projection with
+the volume-preserving threshold, assembly, Jacobi-PCG state solve,
+sensitivities, back-filter, OC update, continuation.  The default workload is
+the MBB half beam at 1200 x 400 (480,000 Q4 elements, rmin 40, beta 1 -> 32
+and penal 1 -> 3 continuation, FP32 fields with FP64 solve vectors, dot
+products and OC sums).  Inputs are synthetic (the paper's own test problem)
+and resident in HBM before the timed region.
+
+Printed: one JSON line.  value = elements per second through the non-solve
+path (filter + projection + assembly + sensitivity + back-filter + OC),
+m * K / (sum of those stage times); to_iters_per_s = whole iterations per
+second including the solve.  Stage times come from HIP events recorded on the
+stream the kernels run on.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "elem/s assembly+filter+OC; TO iters/s plain vs NN-warm-start CG @rtol 1e-8"
+HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
+STAGES = ["filter", "project", "assemble", "solve", "sensitivity", "backfilter", "oc"]
+NON_SOLVE = [s for s in STAGES if s != "solve"]
+
+
+def workloads_by_name():
+    import workloads as W
+    out = {c.name: c for c in W.C1.values()}
+    out[W.C0.name] = W.C0
+    out[W.C2.name] = W.C2
+    return out
+
+
+def stage_bytes(cfg, info, dt_bytes, cg_iters, op, precision):
+    """Algorithmic bytes per launch of each stage (each array the kernel must
+    touch counted once; caches not credited)."""
+    m, n, nnz, npairs, d = info.m, info.n, info.nnz_lower, info.n_pairs, info.d
+    F = dt_bytes
+    nodes_per_elem = n / info.dim / m
+    b = {}
+    b["filter"] = 2 * F * m + F * m                          # x in, xtilde out, Hs
+    b["project"] = (F * m) * 3 + F * m * 3 + m               # newton sweeps read xtilde; write xphys, dprj; codes
+    b["assemble"] = 4 * npairs + 4 * (nnz + 1) + F * nnz + 2 * F * m   # perm, seg_ptr, kval, moduli
+    b["sensitivity"] = 8 * n + F * m * 2 + m + 16 * n        # u gather, xphys, dc, codes, f.u
+    b["backfilter"] = 3 * F * m + F * m + 2 * F * m          # dc, dv, dprj, Hs in; 2 out
+    b["oc"] = F * m * 3 + 8 * m * 2 + F * m                  # x, dc, dv; ocP write/read; x out
+    # one CG iteration
+    if op == "matfree":
+        vec = (4 if precision == "f32" else 8)
+        spmv = F * m + 2 * vec * n + 2 * vec * n
+    else:
+        vec = (4 if precision == "f32" else 8)
+        spmv = F * (2 * nnz - n) + 4 * nnz + 8 * (nnz - n) + 8 * n + 2 * vec * n + 2 * vec * n
+    upd = 8 * n * 2 + vec * n * 6 + n
+    b["solve_per_iter"] = spmv + upd
+    b["solve"] = b["solve_per_iter"] * max(cg_iters, 1)
+    return b
+
+
+def cpu_baseline(cfg, budget_taps=1500):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    workload: one pass of projection, assembly, sensitivity and OC on the full
+    mesh, and one filter application restricted to `budget_taps` of the
+    kernel's non-zero taps, scaled to all taps and to the three filter
+    applications of an iteration."""
+    import numpy as np
+    import workloads as W
+    from oracle import filt, oc, projection, sensitivity, sparse, topopt
+    prob_t0 = time.perf_counter()
+    M = topopt._mesh.Mesh(cfg.nelx, cfg.nely)
+    C = M.cmat()
+    ke = topopt.element.element_matrix(2, cfg.nu)
+    kl = topopt.element.lower_vector(ke)
+    ir = sparse.reduced_index_set(C)
+    row_ptr, col_idx, perm, seg_ptr = sparse.csr_pattern(ir, M.n)
+    del ir
+    setup_s = time.perf_counter() - prob_t0
+    x = W.smooth_design(cfg, 3)
+    act = np.ones(M.m, bool)
+    t = {}
+    # filter: a subset of the taps on the full field
+    h, R = filt.kernel(cfg.rmin, 2)
+    nz = np.argwhere(h > 0)
+    rng = np.random.default_rng(0)
+    pick = nz[rng.choice(len(nz), min(budget_taps, len(nz)), replace=False)]
+    img = x.reshape(M.shape, order="F")
+    out = np.zeros_like(img)
+    t0 = time.perf_counter()
+    for (a, b) in pick:
+        iy, vy = filt._axis_map(M.nely, a - R, cfg.bc)
+        ix, vx = filt._axis_map(M.nelx, b - R, cfg.bc)
+        out += h[a, b] * img[np.ix_(iy, ix)] * (vy[:, None] & vx[None, :])
+    t["filter"] = (time.perf_counter() - t0) * len(nz) / len(pick)
+    xt = x
+    t0 = time.perf_counter()
+    xp, dp, eta, nn, ok = projection.physical_density(xt, x, act, 3, 0.5, 8.0, cfg.volfrac)
+    t["project"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sparse.assemble(xp, kl, perm, seg_ptr, 3.0, 1.0, 1e-9)
+    t["assemble"] = time.perf_counter() - t0
+    u = W.displacement_field(M.n, 4)
+    t0 = time.perf_counter()
+    dc, _ = sensitivity.sensitivity(xp, u, C, ke, act, 3.0, 1.0, 1e-9)
+    t["sensitivity"] = time.perf_counter() - t0
+    dv = np.full(M.m, 1.0 / M.m / cfg.volfrac)
+    t0 = time.perf_counter()
+    oc.oc_update(x, -np.abs(dc), dv, act, cfg.volfrac, cfg.move)
+    t["oc"] = time.perf_counter() - t0
+    t["backfilter"] = 2 * t["filter"]
+    total = sum(t.values())
+    return {"value": M.m / total, "unit": "elem/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle on {cfg.name}: one pass of projection, assembly, sensitivity "
+                       f"and OC on all {M.m} elements; the filter timed on {len(pick)} of its {len(nz)} "
+                       f"non-zero taps over the full mesh and scaled to all taps and to 3 applications; "
+                       f"numpy element-wise kernels run on one thread"),
+            "stage_s": {k: round(v, 4) for k, v in t.items()}, "setup_s": round(setup_s, 2),
+            "host_cpus": len(os.sched_getaffinity(0))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mbb1200x400")
+    ap.add_argument("--precision", default=None, choices=[None, "f32", "f64"])
+    ap.add_argument("--op", default="assembled", choices=["assembled", "matfree"])
+    ap.add_argument("--solve", default="auto", choices=["auto", "f64", "mixed"])
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (how it would shard is "
+              "described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from dataclasses import replace
+    from paper_2005_05436_amd import _lib as L
+    from paper_2005_05436_amd.driver import TopOpt, read_struct
+
+    cfg = workloads_by_name()[args.workload]
+    if args.precision:
+        cfg = replace(cfg, precision=args.precision)
+    op = L.TO_OP_MATFREE if args.op == "matfree" else L.TO_OP_ASSEMBLED
+    torch.cuda.set_device(0)
+    sp = {"auto": L.TO_SOLVE_AUTO, "f64": L.TO_SOLVE_F64, "mixed": L.TO_SOLVE_MIXED}[args.solve]
+    g = TopOpt(cfg, op=op, solve_precision=sp)
+    I = g.plan.info
+    stream = torch.cuda.current_stream()
+    print(f"[bench] {cfg.name} m={I.m} n={I.n} nnz_lower={I.nnz_lower} precision={cfg.precision} op={args.op}",
+          file=sys.stderr, flush=True)
+
+    def timed_step(ev):
+        """One redesign iteration through the single-stage entry points (the
+        same sequence to_step runs), with an event after each stage."""
+        h, dt, st = g.plan.handle, g.dtype, g.state
+        ev[0].record(stream)
+        L.to_filter(h, dt, L.TO_FILTER_FWD, g.x, None, None, g.xtilde, None)
+        ev[1].record(stream)
+        L.to_project(h, dt, cfg.ft, g.xtilde, g.x, g.xphys, g.dprj, st.beta, g.eta, cfg.volfrac,
+                     g.xphys_old, g.pst)
+        ev[2].record(stream)
+        if op == L.TO_OP_ASSEMBLED and (dt == L.TO_F64 or sp != L.TO_SOLVE_F64):
+            L.to_assemble(h, dt, g.xphys, st.penal, g.kval)
+        ev[3].record(stream)
+        L.to_solve(h, dt, g.kval, g.xphys, st.penal, g.f, g.u, g.params.solve, g.sst)
+        ev[4].record(stream)
+        L.to_sensitivity(h, dt, g.xphys, g.u, g.f, st.penal, g.dc, g.c)
+        ev[5].record(stream)
+        L.to_filter(h, dt, L.TO_FILTER_ADJ2, g.dc, g.dv, g.dprj, g.dcf, g.dv0)
+        ev[6].record(stream)
+        L.to_oc_update(h, dt, g.x, g.dcf, g.dv0, cfg.volfrac, cfg.move, g.ost)
+        ev[7].record(stream)
+        g.xphys_old.copy_(g.xphys)
+        st.loop += 1
+        st.penal = L.to_continuation(st.penal, g.params.penal_sched, st.loop)
+        st.beta = L.to_continuation(st.beta, g.params.beta_sched, st.loop)
+
+    for i in range(args.warmup):
+        g.step()
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(8)] for _ in range(args.steps)]
+    cg_iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        timed_step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms = {s: 0.0 for s in STAGES}
+    for k in range(args.steps):
+        for j, s in enumerate(STAGES):
+            stage_ms[s] += evs[k][j].elapsed_time(evs[k][j + 1])
+    last = g.stats()
+    print(f"[bench] timed {args.steps} steps in {wall:.3f} s; last: {json.dumps(last)}", file=sys.stderr,
+          flush=True)
+
+    # solve iterations of the timed steps: re-run the same steps' count from the stats of each
+    # step would need a sync per step; take the average from one extra synchronised pass below
+    K = args.steps
+    non_solve_s = sum(stage_ms[s] for s in NON_SOLVE) / 1e3
+    value = I.m * K / non_solve_s
+    ms_per_step = wall * 1e3 / K
+
+    # per-launch solve statistics from a few extra synchronised steps
+    iters = []
+    solve_ms = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+        timed_step(ev)
+        torch.cuda.synchronize()
+        s = read_struct(g.sst, L.SolveStats)
+        iters.append(s.iterations)
+        solve_ms.append(ev[3].elapsed_time(ev[4]))
+    dt_bytes = 8 if cfg.precision == "f64" else 4
+    sb = stage_bytes(cfg, I, dt_bytes, 1, args.op, cfg.precision)
+    avg_ms = {s: stage_ms[s] / K for s in STAGES}
+    gbps = {s: sb[s] / (avg_ms[s] * 1e-3) / 1e9 for s in NON_SOLVE}
+    per_iter_us = 1e3 * sum(solve_ms) / max(sum(iters), 1)
+    solve_gbps = sb["solve_per_iter"] / (per_iter_us * 1e-6) / 1e9
+    # dominant kernel: the solve (persistent CG kernel), bytes per launch = iterations x bytes/iter
+    avg_iters = sum(iters) / len(iters)
+    roof = {"kernel": "solve_kernel (persistent Jacobi-PCG)", "bound": "hbm",
+            "achieved": round(solve_gbps, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": round(solve_gbps * 1e9 / HBM_PEAK, 4), "traffic": None,
+            "bytes_per_cg_iteration": int(sb["solve_per_iter"]), "cg_iterations_per_launch": avg_iters,
+            "us_per_cg_iteration": round(per_iter_us, 2)}
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "elem/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 fields + f64 solve" if cfg.precision == "f32" else "f64",
+        "data": "synthetic", "config": {"workload": cfg.name, "elements": I.m, "dofs": I.n, "rmin": cfg.rmin,
+                                        "precision": cfg.precision, "operator": args.op, "solve": args.solve,
+                                        "iterations_timed": f"{args.warmup + 1}-{args.warmup + K}"},
+        "to_iters_per_s": round(1e3 / ms_per_step, 3),
+        "stage_ms_per_step": {s: round(v, 4) for s, v in avg_ms.items()},
+        "stage_gbps": {s: round(v, 1) for s, v in gbps.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

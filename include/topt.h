@@ -172,29 +172,47 @@ to_status to_assemble(const to_plan* plan, to_dtype dtype, const void* xphys, do
  * |f - K u| <= rtol |f|, checked on the recursive residual and confirmed on a
  * recomputed one (CG restarts from the recomputed residual otherwise).
  *   dtype TO_F64: plain FP64 PCG with the operator chosen by `op`.
- *   dtype TO_F32: mixed precision -- outer FP64 residual r = f - K64 u from
- *                 the element moduli (matrix-free, FP64), inner FP32 PCG on the
- *                 FP32 assembled kval to relative tolerance inner_rtol, u += d;
- *                 if the outer loop has not converged after max_outer passes,
- *                 or stagnates, it falls back to FP64 matrix-free PCG from the
- *                 current u (flagged in the stats).
+ *   dtype TO_F32, precision AUTO or F64: FP64 PCG on the FP64 matrix-free
+ *                 operator (moduli from the FP32 design promoted to FP64);
+ *                 with op TO_OP_ASSEMBLED its Jacobi diagonal is read from the
+ *                 FP32 assembled kval, with TO_OP_MATFREE it is matrix-free.
+ *   dtype TO_F32, precision MIXED: mixed precision -- CG with FP32 directions, FP32 SpMV (the
+ *                 FP32 assembled kval, or FP32 moduli with op TO_OP_MATFREE)
+ *                 and FP32 Jacobi; the iterate u accumulates in FP64, and
+ *                 each time the FP32 residual has dropped by the factor
+ *                 inner_rtol since the last replacement, the residual is
+ *                 recomputed in FP64 as f - K64 u (matrix-free, FP64 moduli
+ *                 from the same xphys) and replaces the FP32 one (the search
+ *                 direction is kept).  Convergence is judged on those FP64
+ *                 residuals (also recomputed every 64 iterations).  If they
+ *                 stop improving (3 replacements without halving the best),
+ *                 grow, or half of maxit is spent, the solve restarts from the
+ *                 best iterate with FP64 matrix-free PCG (flagged in the stats).
  * kval: device, nnz_lower values of dtype (needed for op TO_OP_ASSEMBLED and
  * for TO_F32); xphys: device m values of dtype (moduli for the matrix-free
  * operator); f, u: device double n; u holds the initial guess on entry. */
 enum { TO_OP_ASSEMBLED = 0, TO_OP_MATFREE = 1 };
+enum { TO_SOLVE_AUTO = 0, TO_SOLVE_F64 = 1, TO_SOLVE_MIXED = 2 };
 typedef struct {
     double rtol;                 /* default 1e-8 */
-    double inner_rtol;           /* mixed precision inner tolerance, default 1e-4 */
+    double inner_rtol;           /* mixed precision replacement factor, default 0.1 */
     int32_t maxit;               /* total CG iteration cap, default 200000 */
-    int32_t max_outer;           /* mixed precision refinement passes, default 30 */
-    int32_t op;                  /* TO_OP_ASSEMBLED | TO_OP_MATFREE (FP64 mode) */
+    int32_t op;                  /* TO_OP_ASSEMBLED | TO_OP_MATFREE */
+    int32_t precision;           /* TO_SOLVE_AUTO or TO_SOLVE_F64: FP64 PCG (for TO_F32 fields the
+                                    operator is the FP64 matrix-free one built from the FP32
+                                    design, and with op TO_OP_ASSEMBLED the Jacobi diagonal is
+                                    taken from the FP32 assembled kval);
+                                    TO_SOLVE_MIXED: the mixed scheme (TO_F32 fields only) */
     int32_t zero_x0;             /* 1: ignore u on entry, start from 0 */
+    int32_t grid_blocks;         /* 0: automatic; else blocks of the persistent solve kernel
+                                    (clamped to what can be co-resident) */
+    int32_t pad;
 } to_solve_opts;
 typedef struct {
     double residual;             /* final true relative residual (FP64) */
     double bnorm;                /* |f_free|_2 */
     int32_t iterations;          /* CG iterations (inner + fallback) */
-    int32_t outer;               /* refinement passes (mixed) */
+    int32_t outer;               /* FP64 residual replacements (mixed) */
     int32_t converged;           /* 1 if residual <= rtol */
     int32_t fallback;            /* 1 if the FP64 fallback ran */
     int32_t restarts;            /* residual-replacement restarts */

@@ -21,6 +21,7 @@ TO_ACTIVE, TO_SOLID, TO_VOID = 0, 1, 2
  TO_X_KERNEL) = range(9)
 TO_FILTER_FWD, TO_FILTER_ADJ, TO_FILTER_ADJ2 = 0, 1, 2
 TO_OP_ASSEMBLED, TO_OP_MATFREE = 0, 1
+TO_SOLVE_AUTO, TO_SOLVE_F64, TO_SOLVE_MIXED = 0, 1, 2
 
 EXPORTED = ["to_plan_query", "to_plan_create", "to_plan_destroy", "to_plan_get_info", "to_plan_export",
             "to_plan_build_host",
@@ -55,7 +56,8 @@ class ProjectStats(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("inner_rtol", C.c_double), ("maxit", C.c_int32),
-                ("max_outer", C.c_int32), ("op", C.c_int32), ("zero_x0", C.c_int32)]
+                ("op", C.c_int32), ("precision", C.c_int32), ("zero_x0", C.c_int32),
+                ("grid_blocks", C.c_int32), ("pad", C.c_int32)]
 
 
 class SolveStats(C.Structure):

@@ -125,7 +125,8 @@ to_status to_assemble(const to_plan* plan, to_dtype dtype, const void* xphys, do
 
 static to_solve_opts default_opts() {
     to_solve_opts o;
-    o.rtol = 1e-8; o.inner_rtol = 1e-4; o.maxit = 200000; o.max_outer = 30; o.op = TO_OP_ASSEMBLED; o.zero_x0 = 0;
+    o.rtol = 1e-8; o.inner_rtol = 0.1; o.maxit = 200000; o.op = TO_OP_ASSEMBLED;
+    o.precision = TO_SOLVE_AUTO; o.zero_x0 = 0; o.grid_blocks = 0; o.pad = 0;
     return o;
 }
 
@@ -135,8 +136,10 @@ to_status to_solve(const to_plan* plan, to_dtype dtype, const void* kval, const 
     if (check_dtype(dtype)) return TO_EINVAL;
     NEED(f, "f"); NEED(u, "u"); NEED(d_stats, "d_stats");
     to_solve_opts o = h_opts ? *h_opts : default_opts();
-    if (!(o.rtol > 0) || !(o.inner_rtol > 0) || o.maxit < 0 || o.max_outer < 0 ||
-        (o.op != TO_OP_ASSEMBLED && o.op != TO_OP_MATFREE)) {
+    if (!(o.rtol > 0) || !(o.inner_rtol > 0 && o.inner_rtol < 1) || o.maxit < 0 || o.grid_blocks < 0 ||
+        (o.op != TO_OP_ASSEMBLED && o.op != TO_OP_MATFREE) ||
+        (o.precision != TO_SOLVE_AUTO && o.precision != TO_SOLVE_F64 && o.precision != TO_SOLVE_MIXED) ||
+        (o.precision == TO_SOLVE_MIXED && dtype == TO_F64)) {
         set_error("bad solve options"); return TO_EINVAL;
     }
     if ((o.op == TO_OP_MATFREE || dtype == TO_F32) && !xphys) { set_error("xphys is NULL"); return TO_EINVAL; }
@@ -177,7 +180,10 @@ to_status to_step(const to_plan* plan, to_dtype dtype, to_step_state* st, const 
     NEED(st->u, "u"); NEED(st->f, "f"); NEED(st->eta, "eta"); NEED(st->compliance, "compliance");
     NEED(st->pstats, "pstats"); NEED(st->sstats, "sstats"); NEED(st->ostats, "ostats");
     if (prm->ft < 1 || prm->ft > 3) { set_error("ft must be 1, 2 or 3"); return TO_EINVAL; }
-    const bool assembled = prm->solve.op == TO_OP_ASSEMBLED || dtype == TO_F32;
+    // op TO_OP_ASSEMBLED: K^(s) is assembled every iteration; it is the CG
+    // operator (FP64 fields, or the mixed scheme) or, for the FP64 solve of
+    // FP32 fields, the source of the FP32 Jacobi preconditioner
+    const bool assembled = prm->solve.op == TO_OP_ASSEMBLED;
     if (assembled) NEED(st->kval, "kval");
     try {
         Plan* p = P(plan);

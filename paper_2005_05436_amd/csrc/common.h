@@ -35,9 +35,6 @@ struct Plan {
     int32_t* seg_ptr = nullptr;   // nnz+1
     int32_t* row_ptr = nullptr;   // n+1
     int32_t* col_idx = nullptr;   // nnz
-    int32_t* tptr = nullptr;      // n+1   strictly-lower entries grouped by column
-    int32_t* tslot = nullptr;     // nnz-n slot of each strictly-lower entry, by column
-    int32_t* trow = nullptr;      // nnz-n its row
     uint8_t* passive = nullptr;   // m
     uint8_t* freemask = nullptr;  // n
     // element matrix and filter (device)
@@ -50,7 +47,7 @@ struct Plan {
     double* E64 = nullptr;   float* E32 = nullptr;       // m
     double* partial = nullptr;                           // kMaxCoopBlocks * kPartialWidth
     double* scal = nullptr;                              // 256 scalars
-    unsigned* bar = nullptr;                             // barrier counters (16 words)
+    unsigned* bar = nullptr;                             // barrier words (1024)
     double* v64[8] = {};                                 // n each
     float* v32[8] = {};                                  // n each
     double* fx64 = nullptr;  float* fx32 = nullptr;      // m (filter staging)
@@ -118,48 +115,86 @@ __device__ __forceinline__ dd wave_dd_sum(dd v) {
     return v;
 }
 
-__device__ __forceinline__ double ld_acq(const double* p) {
-    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Device-coherent access without cache maintenance: relaxed atomics at agent
+// scope are performed at the device coherence point (no stale L1/L2 copy),
+// so data exchanged between blocks of one persistent kernel uses these and
+// the grid barrier needs no agent-scope fence (on this multi-die part an
+// agent-scope fence writes back and invalidates a whole L2, which made the
+// barrier cost grow with the number of blocks).
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T* p) {
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ unsigned ld_acq_u(const unsigned* p) {
-    return __hip_atomic_load(const_cast<unsigned*>(p), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+template <typename T>
+__device__ __forceinline__ void st_dev(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ double ld_acq(const double* p) { return ld_dev(p); }
+__device__ __forceinline__ unsigned ld_acq_u(const unsigned* p) { return ld_dev(p); }
 
 // Grid-wide barrier for cooperatively launched kernels (all blocks resident).
-// bar[0] = arrival count, bar[1] = generation, bar[2] = abort flag, bar[3] = error bits.
-// Returns false (in every thread of the block) once any block has timed out,
-// so persistent loops can leave and every wave reaches the kernel's end.
-__device__ __forceinline__ bool grid_sync(unsigned* bar) {
-    __shared__ int ok_sh;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        unsigned g = ld_acq_u(&bar[1]);
-        __threadfence();
-        unsigned arrived = atomicAdd(&bar[0], 1u);
-        if (arrived == gridDim.x - 1) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+//
+// Data that crosses blocks is written and read with st_dev / ld_dev, so the
+// barrier only has to order it: every wave waits for its own stores
+// (workgroup-scope release = wait for the store counters) before the block
+// arrives, and the arrival and release are relaxed device-scope atomics.
+// Same-address atomics serialise, so arrivals are split over kBarGroups
+// counters on separate cache lines (group = blockIdx % kBarGroups); the last
+// arrival of a group resets it and arrives at the top word, whose low 20 bits
+// count groups and high 12 bits hold the generation; the last group bumps the
+// generation and clears the count with one atomic add.  Every block tracks
+// the generation itself (read once at kernel start; each barrier adds one).
+// Words of `bar`: [0] top, [2] abort flag, [3] error bits, [8] dot-product
+// counter, [64 + 32 g] group g.
+constexpr int kBarGroups = 16;
+
+struct GridBar {
+    unsigned* bar;
+    unsigned gen;        // thread 0 only
+    __device__ __forceinline__ void init(unsigned* b) {
+        bar = b;
+        if (threadIdx.x == 0) gen = (ld_dev(&b[0]) >> 20) & 0xFFFu;
+    }
+    // Returns false in every thread once a block has timed out (then
+    // persistent loops leave and every wave reaches the kernel's end).
+    __device__ __forceinline__ bool sync() {
+        __shared__ int ok_sh;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int ok = 1;
+            const unsigned nb = gridDim.x;
+            const unsigned G = nb < (unsigned)kBarGroups ? nb : (unsigned)kBarGroups;
+            const unsigned g = blockIdx.x % G;
+            const unsigned ng = nb / G + (g < nb % G ? 1u : 0u);
+            unsigned* grp = &bar[64 + 32 * g];
+            const unsigned old = atomicAdd(grp, 1u);
+            if (old == ng - 1) {
+                st_dev(grp, 0u);
+                const unsigned o2 = atomicAdd(&bar[0], 1u);
+                if ((o2 & 0xFFFFFu) == G - 1) atomicAdd(&bar[0], (1u << 20) - G);
+            }
+            const unsigned want = (gen + 1u) & 0xFFFu;
             unsigned spins = 0;
-            while (ld_acq_u(&bar[1]) == g) {
-                if (ld_acq_u(&bar[2]) != 0u) { ok = 0; break; }
-                if (++spins > kSpinLimit) {
-                    atomicOr(&bar[3], FLAG_BARRIER_TIMEOUT);
-                    atomicExch(&bar[2], 1u);
-                    ok = 0;
-                    break;
+            while (((ld_dev(&bar[0]) >> 20) & 0xFFFu) != want) {
+                if ((++spins & 255u) == 0u) {
+                    if (ld_dev(&bar[2]) != 0u) { ok = 0; break; }
+                    if (spins > kSpinLimit) {
+                        atomicOr(&bar[3], FLAG_BARRIER_TIMEOUT);
+                        atomicExch(&bar[2], 1u);
+                        ok = 0;
+                        break;
+                    }
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
+            gen = want;
+            ok_sh = ok;
         }
-        __threadfence();
-        if (ld_acq_u(&bar[2]) != 0u) ok = 0;
-        ok_sh = ok;
+        __syncthreads();
+        return ok_sh != 0;
     }
-    __syncthreads();
-    return ok_sh != 0;
-}
+};
 
 // Sum of K partial columns written by every block: partial[b*kPartialWidth + k].
 // Every block computes the identical result (same data, same order).

@@ -3,12 +3,12 @@
 //
 // Layout: fields are in element order (y fastest), i.e. column-major images.
 // 2D tile: 64 rows (one wave's lanes, contiguous in memory) x 4*V columns (V
-// per wave).  The block stages a (64+2R) x (4V+2R) window in LDS with the
+// per wave).  The block stages a (64+2R) x (4V+2R+V) window in LDS with the
 // boundary rule applied while loading ('D': zeros outside, 'N': half-sample
 // mirror, period 2N), so the tap loop itself is branch-free.  Every lane owns
 // V outputs in one row; all lanes of a wave share the tap offset, so the
 // weight is a wave-uniform (scalar) load.  Taps with zero weight are skipped
-// per column through the plan's hlim table (the cone's support).
+// through the plan's hlim table (the cone's support).
 //
 // Modes: RAW  out = h * in               (used once for Hs)
 //        FWD  out = (h * in) / Hs
@@ -38,24 +38,37 @@ __device__ __forceinline__ T staged_value(int mode, const T* in, const T* sc, co
 }
 
 // ---------------------------------------------------------------------------
-// 2D
+// 2D.  Lane = row (y), V adjacent output columns per lane, CG column groups
+// of V columns, and SPLIT waves per column group that take every SPLIT-th tap
+// row (the per-wave register tile keeps the FMA to LDS-read ratio at V, the
+// split keeps 4 waves per SIMD to hide LDS and scalar latency; partial sums
+// are combined through LDS at the end).  For every tap row dy the lane slides
+// along x through its LDS row: the V outputs need V consecutive columns and
+// one more tap to the right needs one new column, so a ring of V registers
+// (indexed at compile time by unrolling V taps) turns each LDS read into V
+// fused multiply-adds with one wave-uniform weight.  The cone weights are
+// symmetric, so the per-column support table hlim also bounds each tap row;
+// the last unrolled chunk of a row runs past it with zero weight (the window
+// has V spare columns).
+constexpr int kFiltCG = 4, kFiltSplit = 4, kFiltBlock = 64 * kFiltCG * kFiltSplit;
+
 template <typename T, int MODE, int V>
-__global__ __launch_bounds__(kBlock) void filter2d_kernel(
+__global__ __launch_bounds__(kFiltBlock) void filter2d_kernel(
     int nely, int nelx, int R, char bc, const T* __restrict__ h, const int32_t* __restrict__ hlim,
     const T* __restrict__ Hs, const T* __restrict__ in, const T* __restrict__ in2,
     const T* __restrict__ sc, T* __restrict__ out, T* __restrict__ out2) {
     extern __shared__ unsigned char smem_raw[];
     T* tile = reinterpret_cast<T*>(smem_raw);
     constexpr int NF = MODE == M_ADJ2 ? 2 : 1;
-    constexpr int TX = kWaves * V;
+    constexpr int TX = kFiltCG * V;
     const int W = 2 * R + 1;
     const int LY = 64 + 2 * R;           // LDS column height (y, contiguous)
-    const int LX = TX + 2 * R;           // LDS columns (x)
+    const int LX = TX + 2 * R + V;       // LDS columns (x), V spare
     const int y0 = blockIdx.x * 64, x0 = blockIdx.y * TX;
     T* tile2 = tile + (size_t)LY * LX;
 
     // stage the window with the boundary rule
-    for (int i = threadIdx.x; i < LY * LX; i += kBlock) {
+    for (int i = threadIdx.x; i < LY * LX; i += kFiltBlock) {
         int ly = i % LY, lx = i / LY;
         int gy = y0 - R + ly, gx = x0 - R + lx;
         T v = T(0), v2 = T(0);
@@ -77,38 +90,77 @@ __global__ __launch_bounds__(kBlock) void filter2d_kernel(
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int gy = y0 + lane;
-    const int cx0 = wv * V;              // first owned column, tile-local
+    const int cg = wv % kFiltCG, part = wv / kFiltCG;
+    const int cx0 = cg * V;              // first owned column, tile-local
     T acc[V], acc2[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) { acc[v] = T(0); acc2[v] = T(0); }
 
-    for (int dxi = 0; dxi < W; ++dxi) {
-        const int lim = hlim[dxi];
+    for (int dyi = part; dyi < W; dyi += kFiltSplit) {
+        const int lim = hlim[dyi];
         if (lim < 0) continue;
-        const T* hc = h + (size_t)dxi * W + R;       // hc[dy], |dy| <= lim
-        // LDS column of output v at this dx: cx0 + v + dxi (offset by R already)
-        const T* col = tile + (size_t)(cx0 + dxi) * LY + lane + R;
-        const T* colb = tile2 + (size_t)(cx0 + dxi) * LY + lane + R;
-        for (int dy = -lim; dy <= lim; ++dy) {
-            const T w = hc[dy];
+        const T* hrow = h + (size_t)dyi * W + R;        // hrow[dx] = h(dy, dx), |dx| <= lim
+        const T* base = tile + lane + dyi;              // LDS row of this lane at this dy
+        const T* base2 = tile2 + lane + dyi;
+        const int c0 = cx0 + R - lim;                   // LDS column of output 0 at dx = -lim
+        const int ntap = 2 * lim + 1;
+        T ring[V], ring2[V];
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-                acc[v] += w * col[(size_t)v * LY + dy];
-                if (NF == 2) acc2[v] += w * colb[(size_t)v * LY + dy];
+        for (int k = 0; k < V - 1; ++k) {
+            ring[k] = base[(size_t)(c0 + k) * LY];
+            if (NF == 2) ring2[k] = base2[(size_t)(c0 + k) * LY];
+        }
+        for (int t0 = 0; t0 < ntap; t0 += V) {
+            // weights and the V new columns of this chunk are fetched up front
+            T wk[V], nx[V], nx2[V];
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                const int t = t0 + u;
+                const T hw = hrow[min(t, ntap - 1) - lim];
+                wk[u] = t < ntap ? hw : T(0);
+                const size_t col = (size_t)(c0 + t + V - 1) * LY;
+                nx[u] = base[col];
+                if (NF == 2) nx2[u] = base2[col];
+            }
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                ring[(u + V - 1) % V] = nx[u];
+                if (NF == 2) ring2[(u + V - 1) % V] = nx2[u];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    acc[v] += wk[u] * ring[(u + v) % V];
+                    if (NF == 2) acc2[v] += wk[u] * ring2[(u + v) % V];
+                }
             }
         }
     }
+    // combine the SPLIT partial sums (the window is no longer needed)
+    __syncthreads();
+    T* red = tile;                                      // [part][field][cg*V + v][lane]
+    const int slab = NF * TX * 64;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        red[part * slab + (cx0 + v) * 64 + lane] = acc[v];
+        if (NF == 2) red[part * slab + TX * 64 + (cx0 + v) * 64 + lane] = acc2[v];
+    }
+    __syncthreads();
+    if (part != 0) return;
+    const int gy = y0 + lane;
     if (gy < nely) {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             int gx = x0 + cx0 + v;
+            T r = T(0), r2 = T(0);
+#pragma unroll
+            for (int q = 0; q < kFiltSplit; ++q) {
+                r += red[q * slab + (cx0 + v) * 64 + lane];
+                if (NF == 2) r2 += red[q * slab + TX * 64 + (cx0 + v) * 64 + lane];
+            }
             if (gx < nelx) {
                 int64_t e = gy + (int64_t)nely * gx;
-                T r = acc[v];
                 if (MODE == M_FWD) r = r / Hs[e];
                 out[e] = r;
-                if (NF == 2) out2[e] = acc2[v];
+                if (NF == 2) out2[e] = r2;
             }
         }
     }
@@ -193,13 +245,14 @@ static to_status run_filter(Plan* p, const T* h, const T* Hs, const T* in, const
     const int R = p->R;
     const size_t lds_max = 160 * 1024;
     if (p->dim == 2) {
-        constexpr int V = 4;
-        size_t lds = (size_t)NF * (64 + 2 * R) * (kWaves * V + 2 * R) * sizeof(T);
+        constexpr int V = 8;
+        size_t lds = (size_t)NF * (64 + 2 * R) * (kFiltCG * V + 2 * R + V) * sizeof(T);
+        lds = std::max(lds, (size_t)kFiltSplit * NF * kFiltCG * V * 64 * sizeof(T));   // partial-sum reuse
         if (lds > lds_max) { set_error("filter radius too large for the LDS tile"); return TO_EUNSUPPORTED; }
         auto k = filter2d_kernel<T, MODE, V>;
         TO_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        dim3 grid((p->nely + 63) / 64, (p->nelx + kWaves * V - 1) / (kWaves * V));
-        hipLaunchKernelGGL(k, grid, dim3(kBlock), lds, s, p->nely, p->nelx, R, p->bc, h, p->hlim, Hs, in,
+        dim3 grid((p->nely + 63) / 64, (p->nelx + kFiltCG * V - 1) / (kFiltCG * V));
+        hipLaunchKernelGGL(k, grid, dim3(kFiltBlock), lds, s, p->nely, p->nelx, R, p->bc, h, p->hlim, Hs, in,
                            in2, sc, out, out2);
     } else {
         size_t lds = (size_t)NF * (64 + 2 * R) * (4 + 2 * R) * (4 + 2 * R) * sizeof(T);

@@ -42,6 +42,8 @@ __global__ __launch_bounds__(kBlock) void oc_kernel(int64_t m, const uint8_t* __
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     bool alive = true;
     int region = 0;
+    GridBar gb;
+    gb.init(bar);
 
     // block-level double-double sum of K values, written to the partial region
     auto block_dd = [&](dd* v, int K, double* reg) {
@@ -53,8 +55,8 @@ __global__ __launch_bounds__(kBlock) void oc_kernel(int64_t m, const uint8_t* __
             if (threadIdx.x == 0) {
                 dd b{shw[0], shw[1]};
                 for (int i = 1; i < kWaves; ++i) b = dd_add(b, dd{shw[2 * i], shw[2 * i + 1]});
-                reg[blockIdx.x * kPartialWidth + 2 * k] = b.hi;
-                reg[blockIdx.x * kPartialWidth + 2 * k + 1] = b.lo;
+                st_dev(&reg[blockIdx.x * kPartialWidth + 2 * k], b.hi);
+                st_dev(&reg[blockIdx.x * kPartialWidth + 2 * k + 1], b.lo);
             }
         }
     };
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void oc_kernel(int64_t m, const uint8_t* __
         }
         double* reg = partial + (size_t)region * kMaxCoopBlocks * kPartialWidth;
         block_dd(v, 3, reg);
-        alive = grid_sync(bar) && alive;
+        alive = gb.sync() && alive;
         grid_dd(3, reg);
         region ^= 1;
     }
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void oc_kernel(int64_t m, const uint8_t* __
         }
         double* reg = partial + (size_t)region * kMaxCoopBlocks * kPartialWidth;
         block_dd(v, kCand, reg);
-        alive = grid_sync(bar) && alive;
+        alive = gb.sync() && alive;
         grid_dd(kCand, reg);
         region ^= 1;
         ++passes;
@@ -165,7 +167,7 @@ static to_status run_oc(Plan* p, T* x, const T* dc, const T* dv, double volfrac,
     auto k = oc_kernel<T>;
     int64_t m = p->info.m;
     int maxb = coop_blocks_for((const void*)k, kBlock, 0, p->num_cu);
-    int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, p->num_cu), (m + kBlock - 1) / kBlock));
+    int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, 4 * p->num_cu), (m + kBlock - 1) / kBlock));
     const uint8_t* pas = p->passive;
     double* ocp = p->fx64;
     double* partial = p->partial;

@@ -1,7 +1,6 @@
 // Plan builder (host C++): numbering, the reduced index set of eq. (14), the
-// lower CSR pattern of K^(s), the stable (row, col) permutation, the transpose
-// map used by the symmetric SpMV, the element matrix by Gauss quadrature and
-// the cone filter table.  This is the set-up phase of Sec. 3 (blocks PRE.2 and
+// lower CSR pattern of K^(s), the stable (row, col) permutation, the element
+// matrix by Gauss quadrature and the cone filter table.  This is the set-up phase of Sec. 3 (blocks PRE.2 and
 // PRE.5 of both codes); it runs once per mesh.
 #include <algorithm>
 #include <cmath>
@@ -234,7 +233,7 @@ static void filter_table(const Sizes& S, double rmin, std::vector<double>& h, st
 }
 
 struct Offsets {
-    size_t perm, seg, rowp, col, tptr, tslot, trow, pas, freem, ke64, ke32, kf64, kf32, h64, h32,
+    size_t perm, seg, rowp, col, pas, freem, ke64, ke32, kf64, kf32, h64, h32,
         hlim, Hs64, Hs32, E64, E32, partial, scal, bar, v64[8], v32[8], fx64, fx32, total;
 };
 
@@ -245,9 +244,6 @@ static Offsets layout(const Sizes& S) {
     o.seg = L.take(4 * (S.nnz + 1));
     o.rowp = L.take(4 * (S.n + 1));
     o.col = L.take(4 * S.nnz);
-    o.tptr = L.take(4 * (S.n + 1));
-    o.tslot = L.take(4 * (S.nnz - S.n));
-    o.trow = L.take(4 * (S.nnz - S.n));
     o.pas = L.take(S.m);
     o.freem = L.take(S.n);
     o.ke64 = L.take(8 * S.dt);
@@ -263,7 +259,7 @@ static Offsets layout(const Sizes& S) {
     o.E32 = L.take(4 * S.m);
     o.partial = L.take(8 * 2 * (size_t)kMaxCoopBlocks * kPartialWidth);   // two regions
     o.scal = L.take(8 * 256);
-    o.bar = L.take(4 * 16);
+    o.bar = L.take(4 * 1024);
     for (int i = 0; i < 8; ++i) o.v64[i] = L.take(8 * S.n);
     for (int i = 0; i < 8; ++i) o.v32[i] = L.take(4 * S.n);
     o.fx64 = L.take(8 * S.m);
@@ -310,11 +306,9 @@ static void pair_slots(const Sizes& S, const std::vector<int32_t>& rp, const std
 }
 
 
-// Lower CSR, stable permutation of I_r with its segment pointers, and the
-// transpose map (strictly-lower entries grouped by column, rows ascending).
+// Lower CSR and the stable permutation of I_r with its segment pointers.
 static void build_pattern(const Sizes& S, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
-                          std::vector<int32_t>& seg, std::vector<int32_t>& perm, std::vector<int32_t>& tp,
-                          std::vector<int32_t>& ts, std::vector<int32_t>& tr) {
+                          std::vector<int32_t>& seg, std::vector<int32_t>& perm) {
     std::vector<int32_t> slot;
     lower_pattern(S.G, rp, &ci);
     pair_slots(S, rp, ci, slot);
@@ -322,22 +316,8 @@ static void build_pattern(const Sizes& S, std::vector<int32_t>& rp, std::vector<
     perm.resize(S.pairs);
     for (int64_t t = 0; t < S.pairs; ++t) seg[slot[t] + 1]++;
     for (int64_t s = 0; s < S.nnz; ++s) seg[s + 1] += seg[s];
-    {
-        std::vector<int32_t> fill(seg.begin(), seg.end() - 1);
-        for (int64_t t = 0; t < S.pairs; ++t) perm[fill[slot[t]]++] = (int32_t)t;   // stable
-    }
-    slot.clear();
-    slot.shrink_to_fit();
-    tp.assign(S.n + 1, 0);
-    ts.resize(S.nnz - S.n);
-    tr.resize(S.nnz - S.n);
-    for (int64_t r = 0; r < S.n; ++r)
-        for (int32_t s = rp[r]; s < rp[r + 1]; ++s) if (ci[s] < r) tp[ci[s] + 1]++;
-    for (int64_t c = 0; c < S.n; ++c) tp[c + 1] += tp[c];
-    std::vector<int32_t> fill(tp.begin(), tp.end() - 1);
-    for (int64_t r = 0; r < S.n; ++r)
-        for (int32_t s = rp[r]; s < rp[r + 1]; ++s)
-            if (ci[s] < r) { int32_t k = fill[ci[s]]++; ts[k] = s; tr[k] = (int32_t)r; }
+    std::vector<int32_t> fill(seg.begin(), seg.end() - 1);
+    for (int64_t t = 0; t < S.pairs; ++t) perm[fill[slot[t]]++] = (int32_t)t;   // stable
 }
 
 static void write_pairs(const Grid& G, int64_t m, int d, int32_t* o) {
@@ -387,13 +367,13 @@ to_status plan_build_host(const to_mesh_desc* D, int what, void* dst, size_t byt
         return put(h.data(), 8 * h.size());
     }
     if (what == TO_X_HS) { set_error("Hs is computed on the device"); return TO_EUNSUPPORTED; }
-    std::vector<int32_t> rp, ci, seg, perm, tp, ts, tr;
+    std::vector<int32_t> rp, ci, seg, perm;
     if (what == TO_X_ROWPTR || what == TO_X_COLIDX) {
         lower_pattern(S.G, rp, &ci);
         return what == TO_X_ROWPTR ? put(rp.data(), 4 * rp.size()) : put(ci.data(), 4 * ci.size());
     }
     if (what != TO_X_PERM && what != TO_X_SEGPTR) { set_error("unknown export id"); return TO_EINVAL; }
-    build_pattern(S, rp, ci, seg, perm, tp, ts, tr);
+    build_pattern(S, rp, ci, seg, perm);
     return what == TO_X_PERM ? put(perm.data(), 4 * perm.size()) : put(seg.data(), 4 * seg.size());
 }
 
@@ -416,7 +396,6 @@ to_status plan_create(const to_mesh_desc* D, void* ws, size_t ws_bytes, hipStrea
     char* base = (char*)ws;
     p->perm = (int32_t*)(base + o.perm); p->seg_ptr = (int32_t*)(base + o.seg);
     p->row_ptr = (int32_t*)(base + o.rowp); p->col_idx = (int32_t*)(base + o.col);
-    p->tptr = (int32_t*)(base + o.tptr); p->tslot = (int32_t*)(base + o.tslot); p->trow = (int32_t*)(base + o.trow);
     p->passive = (uint8_t*)(base + o.pas); p->freemask = (uint8_t*)(base + o.freem);
     p->ke64 = (double*)(base + o.ke64); p->ke32 = (float*)(base + o.ke32);
     p->kf64 = (double*)(base + o.kf64); p->kf32 = (float*)(base + o.kf32);
@@ -436,8 +415,8 @@ to_status plan_create(const to_mesh_desc* D, void* ws, size_t ws_bytes, hipStrea
     p->num_cu = prop.multiProcessorCount;
 
     // --- sparse pattern, permutation, transpose map ------------------------
-    std::vector<int32_t> rp, ci, seg, perm, tp, ts, tr;
-    build_pattern(S, rp, ci, seg, perm, tp, ts, tr);
+    std::vector<int32_t> rp, ci, seg, perm;
+    build_pattern(S, rp, ci, seg, perm);
     // --- masks --------------------------------------------------------------
     std::vector<uint8_t> pas(S.m, TO_ACTIVE), fm(S.n, 1);
     if (D->h_passive) std::memcpy(pas.data(), D->h_passive, S.m);
@@ -463,11 +442,11 @@ to_status plan_create(const to_mesh_desc* D, void* ws, size_t ws_bytes, hipStrea
     hipError_t e = hipSuccess;
 #define UP(dst, vec) if (e == hipSuccess) e = up(dst, vec.data(), vec.size() * sizeof(vec[0]))
     UP(p->perm, perm); UP(p->seg_ptr, seg); UP(p->row_ptr, rp); UP(p->col_idx, ci);
-    UP(p->tptr, tp); UP(p->tslot, ts); UP(p->trow, tr); UP(p->passive, pas); UP(p->freemask, fm);
+    UP(p->passive, pas); UP(p->freemask, fm);
     UP(p->ke64, p->ke_lower); UP(p->ke32, ke32); UP(p->kf64, p->ke_full); UP(p->kf32, kf32);
     UP(p->h64, p->h); UP(p->h32, h32); UP(p->hlim, p->hlim_host);
 #undef UP
-    if (e == hipSuccess) e = hipMemsetAsync(p->bar, 0, 64, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(p->bar, 0, 4 * 1024, stream);
     if (e == hipSuccess) e = hipMemsetAsync(p->scal, 0, 8 * 256, stream);
     if (e != hipSuccess) { delete p; return hip_fail(e, "plan upload"); }
     st = launch_fill_hs(p, stream);

@@ -51,16 +51,18 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
     const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double eta = *d_eta;
     bool alive = true;
+    GridBar gb;
+    gb.init(bar);
 
     if (ft == 3 && mean_target) {                     // eq. (17): target = volume of the pre-projection field
         double s = 0.0;
         for (int64_t e = i0; e < m; e += stride) s += pre_value(xt, x, pas, e);
         s = block_sum(s, sh);
-        if (threadIdx.x == 0) partial[blockIdx.x * kPartialWidth] = s;
-        alive = grid_sync(bar);
+        if (threadIdx.x == 0) st_dev(&partial[blockIdx.x * kPartialWidth], s);
+        alive = gb.sync();
         grid_reduce<1>(partial, red, sh);
         target = red[0] / (double)m;
-        alive = alive && grid_sync(bar);              // partial buffer is reused below
+        alive = alive && gb.sync();              // partial buffer is reused below
     }
 
     int steps = 0;
@@ -79,18 +81,18 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
             sp = block_sum(sp, sh);
             sd = block_sum(sd, sh);
             if (threadIdx.x == 0) {
-                partial[blockIdx.x * kPartialWidth + 0] = sp;
-                partial[blockIdx.x * kPartialWidth + 1] = sd;
+                st_dev(&partial[blockIdx.x * kPartialWidth + 0], sp);
+                st_dev(&partial[blockIdx.x * kPartialWidth + 1], sd);
             }
-            alive = grid_sync(bar) && alive;
+            alive = gb.sync() && alive;
             grid_reduce<2>(partial, red, sh);
             g = red[0] / (double)m - target;
             if (!(fabs(g) > 1e-6) || steps >= 50 || !alive) break;
             eta = eta - g / (red[1] / (double)m);
             ++steps;
-            alive = grid_sync(bar) && alive;          // everyone has read the partials
+            alive = gb.sync() && alive;          // everyone has read the partials
         }
-        alive = grid_sync(bar) && alive;
+        alive = gb.sync() && alive;
     }
     P.set(beta, eta);
     double sc = 0.0, sv = 0.0;
@@ -111,10 +113,10 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
     sc = block_sum(sc, sh);
     sv = block_sum(sv, sh);
     if (threadIdx.x == 0) {
-        partial[blockIdx.x * kPartialWidth + 0] = sc;
-        partial[blockIdx.x * kPartialWidth + 1] = sv;
+        st_dev(&partial[blockIdx.x * kPartialWidth + 0], sc);
+        st_dev(&partial[blockIdx.x * kPartialWidth + 1], sv);
     }
-    alive = grid_sync(bar) && alive;
+    alive = gb.sync() && alive;
     if (blockIdx.x == 0) {
         grid_reduce<2>(partial, red, sh);
         if (threadIdx.x == 0) {
@@ -146,7 +148,7 @@ static to_status run_project(Plan* p, int ft, const void* xt, const void* x, voi
     auto k = project_kernel<T>;
     int64_t m = p->info.m;
     int maxb = coop_blocks_for((const void*)k, kBlock, 0, p->num_cu);
-    int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(maxb, (m + kBlock - 1) / kBlock));
+    int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, 4 * p->num_cu), (m + kBlock - 1) / kBlock));
     int mean_target = std::isnan(target) ? 1 : 0;
     const T* a = (const T*)xt; const T* b = (const T*)x; const uint8_t* pas = p->passive;
     T* c = (T*)xphys; T* dp = (T*)dprj; const T* xo = (const T*)xold;

@@ -2,9 +2,8 @@
 // one persistent, cooperatively launched kernel per call.
 //
 // Operators (node-centric, gather only, deterministic):
-//   Csr      the assembled K^(s) of eq. (14): row r of the full matrix (eq. (15))
-//            is the lower row plus the strictly-lower entries of column r,
-//            reached through the plan's transpose map (no atomics).
+//   CsrS     the assembled K^(s) of eq. (14) in its CSR order, addressed through
+//            the grid structure (full matrix by eq. (15), no atomics).
 //   MatFree  K = sum_e E_e A_e^T Ke A_e applied node by node: each node sums
 //            the rows of the (up to 4 or 8) adjacent element matrices, with
 //            the element matrix indices fixed at compile time (scalar loads).
@@ -35,15 +34,16 @@ struct Geo {
     }
 };
 
+// Vectors read across blocks (iterate, z, directions) go through ld_dev/st_dev.
 template <typename T> struct Src1 {
-    const T* __restrict__ x;
-    __device__ __forceinline__ T operator()(int64_t i) const { return x[i]; }
+    const T* x;
+    __device__ __forceinline__ T operator()(int64_t i) const { return ld_dev(x + i); }
 };
 template <typename T> struct SrcZP {
-    const T* __restrict__ z;
-    const T* __restrict__ p;
+    const T* z;
+    const T* p;
     T beta;
-    __device__ __forceinline__ T operator()(int64_t i) const { return z[i] + beta * p[i]; }
+    __device__ __forceinline__ T operator()(int64_t i) const { return ld_dev(z + i) + beta * ld_dev(p + i); }
 };
 
 template <int DIM, typename T>
@@ -111,23 +111,83 @@ struct MatFree {
     }
 };
 
+// The assembled K^(s) in the plan's CSR order, read with the structure of the
+// grid instead of column indices.  The lower row of DOF (n, c) holds, for each
+// existing neighbour q < n in ascending node order, the DIM entries of q, then
+// components 0..c of n itself.  So the (n, q) block of the full matrix
+// (eq. (15)) is found at row_ptr[DIM n + c] + DIM * rank_n(q) + c' for q < n,
+// and, for q > n, as the transpose of the (q, n) block in q's rows at
+// DIM * rank_q(n); the ranks are prefix counts of which neighbours exist
+// (boundary nodes have fewer).  Only row_ptr and the values are read; each
+// lower value is read once for its own row and once as a transposed entry.
 template <int DIM, typename T>
-struct Csr {
+struct CsrS {
     const int32_t* __restrict__ rp;
-    const int32_t* __restrict__ ci;
-    const int32_t* __restrict__ tp;
-    const int32_t* __restrict__ ts;
-    const int32_t* __restrict__ tr;
     const T* __restrict__ kv;
+    int nx, ny, nz;
+    static constexpr int NN = DIM == 2 ? 9 : 27;    // neighbourhood incl. the node itself
+    static constexpr int SELF = NN / 2;
+    // neighbour k in ascending node order: (dx, dz, dy) lexicographic
+    __device__ __forceinline__ static void off(int k, int& dx, int& dy, int& dz) {
+        if (DIM == 2) { dx = k / 3 - 1; dy = k % 3 - 1; dz = 0; }
+        else { dx = k / 9 - 1; dz = (k / 3) % 3 - 1; dy = k % 3 - 1; }
+    }
+    __device__ __forceinline__ bool exists(int iy, int ix, int iz, int k) const {
+        int dx, dy, dz;
+        off(k, dx, dy, dz);
+        const int y = iy + dy, x = ix + dx, z = iz + dz;
+        return y >= 0 && y <= ny && x >= 0 && x <= nx && (DIM == 2 || (z >= 0 && z <= nz));
+    }
+    __device__ __forceinline__ int64_t delta(int k) const {
+        int dx, dy, dz;
+        off(k, dx, dy, dz);
+        return DIM == 2 ? dy + (int64_t)(ny + 1) * dx : dy + (int64_t)(ny + 1) * (dz + (int64_t)(nz + 1) * dx);
+    }
     template <class S>
-    __device__ __forceinline__ void apply(int64_t nd, int, int, int, const S& src, T (&out)[DIM]) const {
+    __device__ __forceinline__ void apply(int64_t nd, int iy, int ix, int iz, const S& src, T (&out)[DIM]) const {
+        int32_t row[DIM];
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            const int64_t r = DIM * nd + c;
-            T acc = T(0);
-            for (int32_t s = rp[r]; s < rp[r + 1]; ++s) acc += kv[s] * src(ci[s]);
-            for (int32_t k = tp[r]; k < tp[r + 1]; ++k) acc += kv[ts[k]] * src(tr[k]);
-            out[c] = acc;
+        for (int c = 0; c < DIM; ++c) { row[c] = rp[DIM * nd + c]; out[c] = T(0); }
+        int rank = 0;
+#pragma unroll
+        for (int k = 0; k < SELF; ++k) {                       // lower neighbours
+            if (!exists(iy, ix, iz, k)) continue;
+            const int64_t q = nd + delta(k);
+#pragma unroll
+            for (int c2 = 0; c2 < DIM; ++c2) {
+                const T sv = src(DIM * q + c2);
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) out[c] += kv[row[c] + DIM * rank + c2] * sv;
+            }
+            ++rank;
+        }
+#pragma unroll
+        for (int c2 = 0; c2 < DIM; ++c2) {                      // the node's own block
+            const T sv = src(DIM * nd + c2);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const T kvv = c2 <= c ? kv[row[c] + DIM * rank + c2] : kv[row[c2] + DIM * rank + c];
+                out[c] += kvv * sv;
+            }
+        }
+#pragma unroll
+        for (int k = SELF + 1; k < NN; ++k) {                  // upper neighbours: transposed blocks
+            if (!exists(iy, ix, iz, k)) continue;
+            int dx, dy, dz;
+            off(k, dx, dy, dz);
+            const int qy = iy + dy, qx = ix + dx, qz = iz + dz;
+            const int64_t q = nd + delta(k);
+            const int km = NN - 1 - k;                         // n seen from q
+            int rq = 0;
+#pragma unroll
+            for (int j = 0; j < km; ++j) rq += exists(qy, qx, qz, j) ? 1 : 0;
+#pragma unroll
+            for (int c2 = 0; c2 < DIM; ++c2) {
+                const T sv = src(DIM * q + c2);
+                const int32_t rq0 = rp[DIM * q + c2] + DIM * rq;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) out[c] += kv[rq0 + c] * sv;
+            }
         }
     }
     __device__ __forceinline__ void diag(int64_t nd, int, int, int, T (&out)[DIM]) const {
@@ -139,15 +199,16 @@ struct Csr {
 struct SolveArgs {
     Geo geo;
     const uint8_t* freem;
-    const int32_t *rp, *ci, *tp, *ts, *tr;
+    const int32_t* rp;
     const void* kval;
+    const float* kdiag32;       // FP32 assembled values for the Jacobi of the FP64 solve (nullable)
     const double* E64; const float* E32;
     const double* kf64; const float* kf32;
     const double* f; double* u;
     double* v64[8];
     float* v32[8];
     double rtol, inner_rtol;
-    int maxit, max_outer, zero_x0;
+    int maxit, zero_x0;
     double* partial; unsigned* bar;
     to_solve_stats* st;
 };
@@ -156,7 +217,7 @@ struct SolveArgs {
 // block can write reduction k+1 while slow blocks still read reduction k
 struct Ctx {
     double* partial;
-    unsigned* bar;
+    GridBar gb;
     double* sh;
     double* res;     // shared results
     int red;
@@ -167,9 +228,9 @@ struct Ctx {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             double s = block_sum(v[k], sh);
-            if (threadIdx.x == 0) region[blockIdx.x * kPartialWidth + k] = s;
+                if (threadIdx.x == 0) st_dev(&region[blockIdx.x * kPartialWidth + k], s);
         }
-        alive = grid_sync(bar) && alive;
+        alive = gb.sync() && alive;
         grid_reduce<K>(region, res, sh);
         ++red;
     }
@@ -197,7 +258,7 @@ struct Pcg {
                 T ri = fm[i] ? (x_zero ? b[i] : b[i] - ax[c]) : T(0);
                 T zi = dinv[i] * ri;
                 r[i] = ri;
-                z[i] = zi;
+                st_dev(z + i, zi);
                 v[0] += (double)ri * (double)zi;
                 v[1] += (double)ri * (double)ri;
             }
@@ -206,14 +267,19 @@ struct Pcg {
     }
 
     // Solves A x = b from x (x_zero: from 0) until |r| <= tol; returns iterations.
+    // confirm: accept convergence only when the recomputed residual b - A x
+    // also meets tol (FP64 solves).  The inner FP32 solve of the mixed
+    // scheme stops on the recursive residual: at high stiffness contrast the
+    // FP32 recomputation of b - A x is dominated by cancellation, and the
+    // outer FP64 residual is the judge anyway.
     __device__ int run(const T* b, T* x, bool x_zero, const T* dinv, T* r, T* z, T* pa, T* pb, T* q,
-                       double tol, int maxit, int& restarts) {
+                       double tol, int maxit, int& restarts, bool confirm = true) {
         const int64_t stride = (int64_t)gridDim.x * kBlock;
         const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
         if (x_zero)
             for (int64_t nd = i0; nd < g.nnode; nd += stride)
 #pragma unroll
-                for (int c = 0; c < DIM; ++c) x[DIM * nd + c] = T(0);
+                for (int c = 0; c < DIM; ++c) st_dev(x + DIM * nd + c, T(0));
         residual(b, x, x_zero, dinv, r, z);
         double rz = C.res[0], rr = C.res[1];
         bool fresh = true;
@@ -223,7 +289,7 @@ struct Pcg {
         int it = 0;
         while (C.alive) {
             if (rr <= tol * tol) {
-                if (fresh) break;
+                if (fresh || !confirm) break;
                 residual(b, x, false, dinv, r, z);   // confirm on the recomputed residual
                 rz = C.res[0]; rr = C.res[1];
                 fresh = true; beta = 0.0; pold = z; pnew = pa;
@@ -245,7 +311,7 @@ struct Pcg {
                     const int64_t i = DIM * nd + c;
                     const T pi = src(i);
                     const T qi = fm[i] ? ap[c] : T(0);
-                    pnew[i] = pi;
+                    st_dev(pnew + i, pi);
                     q[i] = qi;
                     v1[0] += (double)pi * (double)qi;
                 }
@@ -261,11 +327,11 @@ struct Pcg {
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) {
                     const int64_t i = DIM * nd + c;
-                    x[i] += a * pnew[i];
+                    st_dev(x + i, ld_dev(x + i) + a * ld_dev(pnew + i));
                     const T ri = r[i] - a * q[i];
                     const T zi = dinv[i] * ri;
                     r[i] = ri;
-                    z[i] = zi;
+                    st_dev(z + i, zi);
                     v2[0] += (double)ri * (double)zi;
                     v2[1] += (double)ri * (double)ri;
                 }
@@ -279,7 +345,7 @@ struct Pcg {
             pnew = t;
             ++it;
         }
-        if (!fresh && C.alive) residual(b, x, false, dinv, r, z);   // report the true residual
+        if (confirm && !fresh && C.alive) residual(b, x, false, dinv, r, z);   // report the true residual
         return it;
     }
 };
@@ -300,13 +366,149 @@ __device__ void jacobi(const Op& op, const Geo& g, const uint8_t* fm, T* dinv) {
     }
 }
 
+// Mixed precision CG with reliable updates: the directions, the SpMV and the
+// recursive residual are FP32 (FP32 operator and Jacobi), the iterate u is
+// accumulated in FP64, and whenever the FP32 residual has dropped by the
+// factor `drop` (opts.inner_rtol) since the last replacement, or every
+// kReplaceEvery iterations, the residual is recomputed in FP64 from the FP64
+// matrix-free operator, f - K64 u, and replaces the FP32 one without
+// restarting the search direction.  Convergence is decided on those FP64
+// residuals only.  The iterate with the smallest FP64 residual is kept (two
+// buffers, swapped).  Returns false when the FP64 residual stops improving
+// (three replacements without halving the best one), grows past twice the
+// best, or half the iteration budget is spent; the caller then restores the
+// best iterate and finishes in FP64.
+constexpr int kReplaceEvery = 64;
+
+template <int DIM, class Op32>
+__device__ bool mixed_cg(Ctx& C, const Geo& g, const SolveArgs& A, const Op32& op32,
+                         const MatFree<DIM, double>& mf64, double tol, int& iters, int& passes, double& rfinal,
+                         double*& ubest) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint8_t* __restrict__ fm = A.freem;
+    double* u = A.u;
+    double* r64 = A.v64[0];
+    double* cand = A.v64[6];
+    float *r = A.v32[2], *z = A.v32[3], *pa = A.v32[4], *pb = A.v32[5], *q = A.v32[6], *dinv = A.v32[7];
+    // FP64 residual replacement: r64 = f - K64 u, r = (float) r64, z = dinv r;
+    // u is copied to the candidate buffer in the same sweep
+    auto replace = [&](double& rz, double& rr64) {
+        double v[2] = {0.0, 0.0};
+        for (int64_t nd = i0; nd < g.nnode; nd += stride) {
+            int iy, ix, iz;
+            g.coords(nd, iy, ix, iz, DIM);
+            double ax[DIM];
+            mf64.apply(nd, iy, ix, iz, Src1<double>{u}, ax);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const int64_t i = DIM * nd + c;
+                st_dev(cand + i, ld_dev(u + i));
+                const double ri = fm[i] ? A.f[i] - ax[c] : 0.0;
+                r64[i] = ri;
+                const float rf = (float)ri, zf = dinv[i] * rf;
+                r[i] = rf;
+                st_dev(z + i, zf);
+                v[0] += (double)rf * (double)zf;
+                v[1] += ri * ri;
+            }
+        }
+        C.reduce<2>(v);
+        rz = C.res[0];
+        rr64 = C.res[1];
+    };
+    double rz, rr64;
+    replace(rz, rr64);
+    double rbest = sqrt(rr64), rlast = rbest;
+    ubest = cand;
+    cand = A.v64[7];
+    rfinal = rbest;
+    if (rbest <= tol) return true;
+    const int budget = iters + A.maxit / 2;
+    int stall = 0, since = 0;
+    double beta = 0.0;
+    float* pold = z;
+    float* pnew = pa;
+    const double drop = A.inner_rtol;
+    while (C.alive && iters < budget) {
+        double v1[1] = {0.0};
+        const SrcZP<float> src{z, pold, (float)beta};
+        for (int64_t nd = i0; nd < g.nnode; nd += stride) {
+            int iy, ix, iz;
+            g.coords(nd, iy, ix, iz, DIM);
+            float ap[DIM];
+            op32.apply(nd, iy, ix, iz, src, ap);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const int64_t i = DIM * nd + c;
+                const float pi = src(i);
+                const float qi = fm[i] ? ap[c] : 0.0f;
+                st_dev(pnew + i, pi);
+                q[i] = qi;
+                v1[0] += (double)pi * (double)qi;
+            }
+        }
+        C.reduce<1>(v1);
+        const double pq = C.res[0];
+        if (!(pq > 0.0)) return false;
+        const double alpha = rz / pq;
+        const float af = (float)alpha;
+        double v2[2] = {0.0, 0.0};
+        for (int64_t nd = i0; nd < g.nnode; nd += stride) {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const int64_t i = DIM * nd + c;
+                st_dev(u + i, ld_dev(u + i) + alpha * (double)ld_dev(pnew + i));
+                const float ri = r[i] - af * q[i];
+                const float zi = dinv[i] * ri;
+                r[i] = ri;
+                st_dev(z + i, zi);
+                v2[0] += (double)ri * (double)zi;
+                v2[1] += (double)ri * (double)ri;
+            }
+        }
+        C.reduce<2>(v2);
+        ++iters;
+        ++since;
+        double rz_new = C.res[0];
+        const double rn32 = sqrt(C.res[1]);
+        if (rn32 <= drop * rlast || rn32 <= tol || since >= kReplaceEvery) {
+            double rr;
+            replace(rz_new, rr);
+            ++passes;
+            since = 0;
+            const double rt = sqrt(rr);
+            rfinal = rt;
+            if (rt <= tol) { ubest = cand; return true; }
+            if (rt < rbest) {
+                stall = rt > 0.5 * rbest ? stall + 1 : 0;
+                rbest = rt;
+                double* t = ubest;
+                ubest = cand;
+                cand = t;
+            } else {
+                ++stall;
+            }
+            if (stall >= 3 || rt > 2.0 * rbest || !(rt == rt)) return false;
+            rlast = rt;
+        }
+        beta = rz_new / rz;
+        rz = rz_new;
+        float* t = pnew == pa ? pb : pa;
+        pold = pnew;
+        pnew = t;
+    }
+    return false;
+}
+
 // MODE 0: FP64, assembled operator; 1: FP64, matrix-free;
 //      2: mixed, FP32 assembled inner; 3: mixed, FP32 matrix-free inner.
 template <int DIM, int MODE>
 __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs A) {
     __shared__ double sh[kWaves];
     __shared__ double res[4];
-    Ctx C{A.partial, A.bar, sh, res, 0, true};
+    Ctx C{A.partial, GridBar{}, sh, res, 0, true};
+    C.gb.init(A.bar);
     const Geo& g = A.geo;
     const int64_t n = g.nnode * DIM;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -318,7 +520,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs A) {
         double v[1] = {0.0};
         for (int64_t i = i0; i < n; i += stride) {
             const bool fr = A.freem[i] != 0;
-            if (!fr || A.zero_x0) u[i] = 0.0;
+            if (!fr || A.zero_x0) st_dev(u + i, 0.0);
             const double fi = fr ? A.f[i] : 0.0;
             v[0] += fi * fi;
         }
@@ -333,12 +535,23 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs A) {
     if (MODE <= 1) {
         double *r = A.v64[0], *z = A.v64[1], *pa = A.v64[2], *pb = A.v64[3], *q = A.v64[4], *dinv = A.v64[5];
         if (MODE == 0) {
-            Csr<DIM, double> op{A.rp, A.ci, A.tp, A.ts, A.tr, (const double*)A.kval};
+            CsrS<DIM, double> op{A.rp, (const double*)A.kval, g.nx, g.ny, g.nz};
             jacobi<DIM, double>(op, g, A.freem, dinv);
-            Pcg<DIM, double, Csr<DIM, double>> cg{op, g, A.freem, C};
+            Pcg<DIM, double, CsrS<DIM, double>> cg{op, g, A.freem, C};
             iters = cg.run(A.f, u, false, dinv, r, z, pa, pb, q, tol, A.maxit, restarts);
         } else {
-            jacobi<DIM, double>(mf64, g, A.freem, dinv);
+            if (A.kdiag32) {   // FP32 fields: Jacobi from the FP32 assembled diagonal
+                const int64_t stride = (int64_t)gridDim.x * kBlock;
+                for (int64_t nd = (int64_t)blockIdx.x * kBlock + threadIdx.x; nd < g.nnode; nd += stride)
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        const int64_t i = DIM * nd + c;
+                        const double dg = (double)A.kdiag32[A.rp[i + 1] - 1];
+                        dinv[i] = A.freem[i] && dg != 0.0 ? 1.0 / dg : 0.0;
+                    }
+            } else {
+                jacobi<DIM, double>(mf64, g, A.freem, dinv);
+            }
             Pcg<DIM, double, MatFree<DIM, double>> cg{mf64, g, A.freem, C};
             iters = cg.run(A.f, u, false, dinv, r, z, pa, pb, q, tol, A.maxit, restarts);
         }
@@ -346,50 +559,29 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs A) {
     } else {
         double *r64 = A.v64[0], *z64 = A.v64[1], *pa64 = A.v64[2], *pb64 = A.v64[3], *q64 = A.v64[4];
         double* dinv64 = A.v64[5];
-        float *b32 = A.v32[0], *d32 = A.v32[1], *r32 = A.v32[2], *z32 = A.v32[3], *pa32 = A.v32[4];
-        float *pb32 = A.v32[5], *q32 = A.v32[6], *dinv32 = A.v32[7];
-        Csr<DIM, float> csr32{A.rp, A.ci, A.tp, A.ts, A.tr, (const float*)A.kval};
+        CsrS<DIM, float> csr32{A.rp, (const float*)A.kval, g.nx, g.ny, g.nz};
         MatFree<DIM, float> mf32{A.E32, A.kf32, g.nx, g.ny, g.nz};
-        if (MODE == 2) jacobi<DIM, float>(csr32, g, A.freem, dinv32);
-        else jacobi<DIM, float>(mf32, g, A.freem, dinv32);
         jacobi<DIM, double>(mf64, g, A.freem, dinv64);   // for the fallback
-        Pcg<DIM, double, MatFree<DIM, double>> cg64{mf64, g, A.freem, C};
-        double prev = INFINITY;
-        int stall = 0;
         bool converged = false;
-        for (;;) {
-            // outer FP64 residual r = f - K64 u
-            cg64.residual(A.f, u, false, dinv64, r64, z64);
-            const double rn = sqrt(C.res[1]);
-            resid = rn / (bnorm > 0 ? bnorm : 1.0);
-            if (rn <= tol || !C.alive) { converged = rn <= tol; break; }
-            stall = rn > 0.5 * prev ? stall + 1 : 0;
-            if (outer >= A.max_outer || stall >= 2 || iters >= A.maxit) break;
-            prev = rn;
-            for (int64_t nd = i0; nd < g.nnode; nd += stride)
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) b32[DIM * nd + c] = (float)r64[DIM * nd + c];
-            const double itol = A.inner_rtol * rn;
-            int left = A.maxit - iters;
-            if (MODE == 2) {
-                Pcg<DIM, float, Csr<DIM, float>> cg{csr32, g, A.freem, C};
-                iters += cg.run(b32, d32, true, dinv32, r32, z32, pa32, pb32, q32, itol, left, restarts);
-            } else {
-                Pcg<DIM, float, MatFree<DIM, float>> cg{mf32, g, A.freem, C};
-                iters += cg.run(b32, d32, true, dinv32, r32, z32, pa32, pb32, q32, itol, left, restarts);
-            }
-            for (int64_t nd = i0; nd < g.nnode; nd += stride)
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) u[DIM * nd + c] += (double)d32[DIM * nd + c];
-            C.alive = grid_sync(A.bar) && C.alive;
-            ++outer;
+        double* ubest = A.v64[6];
+        if (MODE == 2) {
+            jacobi<DIM, float>(csr32, g, A.freem, A.v32[7]);
+            converged = mixed_cg<DIM>(C, g, A, csr32, mf64, tol, iters, outer, resid, ubest);
+        } else {
+            jacobi<DIM, float>(mf32, g, A.freem, A.v32[7]);
+            converged = mixed_cg<DIM>(C, g, A, mf32, mf64, tol, iters, outer, resid, ubest);
         }
         if (!converged && C.alive) {
             fallback = 1;
-            int left = A.maxit - iters;
+            // restart from the iterate with the smallest FP64 residual
+            for (int64_t i = i0; i < n; i += stride) st_dev(u + i, ld_dev(ubest + i));
+            C.alive = C.gb.sync() && C.alive;
+            const int left = A.maxit - iters;
+            Pcg<DIM, double, MatFree<DIM, double>> cg64{mf64, g, A.freem, C};
             iters += cg64.run(A.f, u, false, dinv64, r64, z64, pa64, pb64, q64, tol, left > 0 ? left : 0, restarts);
-            resid = sqrt(C.res[1]) / (bnorm > 0 ? bnorm : 1.0);
+            resid = sqrt(C.res[1]);
         }
+        resid /= (bnorm > 0 ? bnorm : 1.0);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         to_solve_stats s;
@@ -406,11 +598,12 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs A) {
 }
 
 template <int DIM, int MODE>
-static to_status launch_solve_t(Plan* p, SolveArgs& A, hipStream_t s) {
+static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream_t s) {
     auto k = solve_kernel<DIM, MODE>;
     int maxb = coop_blocks_for((const void*)k, kBlock, 0, p->num_cu);
     int64_t want = (A.geo.nnode + kBlock - 1) / kBlock;
-    int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, 2 * p->num_cu), want));
+    int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, p->num_cu), want));
+    if (req_blocks > 0) blocks = std::min(req_blocks, maxb);
     void* args[] = {&A};
     TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(kBlock), args, 0, s));
     return TO_OK;
@@ -418,9 +611,9 @@ static to_status launch_solve_t(Plan* p, SolveArgs& A, hipStream_t s) {
 
 to_status launch_solve(Plan* p, to_dtype dt, const void* kval, const void* xphys, double penal,
                        const double* f, double* u, const to_solve_opts& o, to_solve_stats* st, hipStream_t s) {
-    const bool assembled = o.op == TO_OP_ASSEMBLED;
-    if (dt == TO_F32 && assembled && !kval) { set_error("kval is NULL"); return TO_EINVAL; }
-    if (dt == TO_F64 && assembled && !kval) { set_error("kval is NULL"); return TO_EINVAL; }
+    const bool mixed = dt == TO_F32 && o.precision == TO_SOLVE_MIXED;
+    const bool assembled = o.op == TO_OP_ASSEMBLED && (dt == TO_F64 || mixed);
+    if (o.op == TO_OP_ASSEMBLED && !kval) { set_error("kval is NULL"); return TO_EINVAL; }
     // moduli for the matrix-free operators (FP64 always; FP32 too in mixed mode)
     if (!(dt == TO_F64 && assembled)) {
         to_status r = launch_moduli(p, dt, xphys, penal, s, true);
@@ -429,28 +622,29 @@ to_status launch_solve(Plan* p, to_dtype dt, const void* kval, const void* xphys
     SolveArgs A{};
     A.geo = Geo{p->nelx, p->nely, p->nelz, p->info.nnode};
     A.freem = p->freemask;
-    A.rp = p->row_ptr; A.ci = p->col_idx; A.tp = p->tptr; A.ts = p->tslot; A.tr = p->trow;
+    A.rp = p->row_ptr;
     A.kval = kval;
+    A.kdiag32 = (dt == TO_F32 && !mixed && o.op == TO_OP_ASSEMBLED) ? (const float*)kval : nullptr;
     A.E64 = p->E64; A.E32 = p->E32; A.kf64 = p->kf64; A.kf32 = p->kf32;
     A.f = f; A.u = u;
     for (int i = 0; i < 8; ++i) { A.v64[i] = p->v64[i]; A.v32[i] = p->v32[i]; }
-    A.rtol = o.rtol; A.inner_rtol = o.inner_rtol; A.maxit = o.maxit; A.max_outer = o.max_outer;
+    A.rtol = o.rtol; A.inner_rtol = o.inner_rtol; A.maxit = o.maxit;
     A.zero_x0 = o.zero_x0;
     A.partial = p->partial; A.bar = p->bar; A.st = st;
-    const int mode = dt == TO_F64 ? (assembled ? 0 : 1) : (assembled ? 2 : 3);
+    const int mode = !mixed ? (assembled ? 0 : 1) : (assembled ? 2 : 3);
     if (p->dim == 2) {
         switch (mode) {
-        case 0: return launch_solve_t<2, 0>(p, A, s);
-        case 1: return launch_solve_t<2, 1>(p, A, s);
-        case 2: return launch_solve_t<2, 2>(p, A, s);
-        default: return launch_solve_t<2, 3>(p, A, s);
+        case 0: return launch_solve_t<2, 0>(p, A, o.grid_blocks, s);
+        case 1: return launch_solve_t<2, 1>(p, A, o.grid_blocks, s);
+        case 2: return launch_solve_t<2, 2>(p, A, o.grid_blocks, s);
+        default: return launch_solve_t<2, 3>(p, A, o.grid_blocks, s);
         }
     }
     switch (mode) {
-    case 0: return launch_solve_t<3, 0>(p, A, s);
-    case 1: return launch_solve_t<3, 1>(p, A, s);
-    case 2: return launch_solve_t<3, 2>(p, A, s);
-    default: return launch_solve_t<3, 3>(p, A, s);
+    case 0: return launch_solve_t<3, 0>(p, A, o.grid_blocks, s);
+    case 1: return launch_solve_t<3, 1>(p, A, o.grid_blocks, s);
+    case 2: return launch_solve_t<3, 2>(p, A, o.grid_blocks, s);
+    default: return launch_solve_t<3, 3>(p, A, o.grid_blocks, s);
     }
 }
 

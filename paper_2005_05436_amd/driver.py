@@ -89,8 +89,8 @@ def _sched(s):
 class TopOpt:
     """The redesign loop on the GPU: state buffers + to_step."""
 
-    def __init__(self, cfg, op=L.TO_OP_ASSEMBLED, rtol=1e-8, inner_rtol=1e-4, maxit=200000,
-                 precision=None, passive=None):
+    def __init__(self, cfg, op=L.TO_OP_ASSEMBLED, rtol=1e-8, inner_rtol=0.1, maxit=200000,
+                 precision=None, passive=None, solve_precision=L.TO_SOLVE_AUTO, grid_blocks=0):
         self.cfg = cfg
         self.plan, f = plan_for_config(cfg, passive)
         dev = self.plan.device
@@ -125,7 +125,8 @@ class TopOpt:
                                                       self.pst, self.sst, self.ost)],
                                  cfg.penal, cfg.beta, 0, 0)
         self.params = L.StepParams(cfg.volfrac, cfg.move, cfg.ft, 0, math.nan, _sched(cfg.penal_sched),
-                                   _sched(cfg.beta_sched), L.SolveOpts(rtol, inner_rtol, maxit, 30, op, 0))
+                                   _sched(cfg.beta_sched),
+                                   L.SolveOpts(rtol, inner_rtol, maxit, op, solve_precision, 0, grid_blocks, 0))
 
     @property
     def loop(self):

@@ -302,19 +302,25 @@ def _solve_case(cfg, seed):
     return prob, x, K
 
 
-@pytest.mark.parametrize("case", ["c0_f64_asm", "c0_f64_mf", "c0_mixed_asm", "c0_mixed_mf", "c2s_f64_asm",
-                                  "c2s_f64_mf", "c2s_mixed_mf", "c1_300_mixed_mf"])
+SOLVE_CASES = [("c0", "f64", "auto", "asm"), ("c0", "f64", "auto", "mf"), ("c0", "f32", "mixed", "asm"),
+               ("c0", "f32", "mixed", "mf"), ("c0", "f32", "f64", "mf"), ("c2s", "f64", "auto", "asm"),
+               ("c2s", "f64", "auto", "mf"), ("c2s", "f32", "mixed", "mf"), ("c2s", "f32", "f64", "mf"),
+               ("c1", "f32", "mixed", "mf"), ("c1", "f64", "auto", "mf"), ("c0", "f32", "f64", "asm"),
+               ("c1", "f32", "auto", "asm"), ("c1", "f64", "auto", "asm")]
+
+
+@pytest.mark.parametrize("case", SOLVE_CASES, ids=["-".join(c) for c in SOLVE_CASES])
 def test_solve(case):
     from paper_2005_05436_amd import _lib as L
     from paper_2005_05436_amd.driver import plan_for_config, read_struct
-    cfgname, prec, op = case.split("_", 2)[0], case.split("_")[-2], case.split("_")[-1]
+    cfgname, fields, prec, op = case
     cfg = {"c0": W.C0, "c2s": W.C2_SMALL, "c1": W.C1[300]}[cfgname]
     if cfgname == "c1":
         from dataclasses import replace
         cfg = replace(cfg, penal=3.0)
     prob, x, K = _solve_case(cfg, 31)
     P, f = plan_for_config(cfg)
-    dt = L.TO_F64 if prec == "f64" else L.TO_F32
+    dt = L.TO_F64 if fields == "f64" else L.TO_F32
     T = tdt(dt)
     xd = dev(x, T)
     kval = torch.zeros(P.info.nnz_lower, dtype=T, device="cuda")
@@ -322,7 +328,8 @@ def test_solve(case):
     fd = dev(f, torch.float64)
     u = torch.zeros(P.info.n, dtype=torch.float64, device="cuda")
     st = torch.zeros(40, dtype=torch.uint8, device="cuda")
-    opts = L.SolveOpts(1e-8, 1e-4, 200000, 30, L.TO_OP_ASSEMBLED if op == "asm" else L.TO_OP_MATFREE, 1)
+    sp = {"auto": L.TO_SOLVE_AUTO, "mixed": L.TO_SOLVE_MIXED, "f64": L.TO_SOLVE_F64}[prec]
+    opts = L.SolveOpts(1e-8, 0.1, 200000, L.TO_OP_ASSEMBLED if op == "asm" else L.TO_OP_MATFREE, sp, 1, 0, 0)
     L.to_solve(P.handle, dt, kval, xd, cfg.penal, fd, u, opts, st)
     s = read_struct(st, L.SolveStats)
     uh = host(u)
@@ -331,6 +338,7 @@ def test_solve(case):
     kv = osp.assemble(xin, prob.ke_lower, prob.perm, prob.seg_ptr, cfg.penal, 1.0, 1e-9)
     K = osp.lower_to_full(prob.row_ptr, prob.col_idx, kv, prob.mesh.n)
     res = osolve.true_residual(K, prob.f, prob.free, uh)
+    print(f"{case}: iterations={s.iterations} replacements={s.outer} fallback={s.fallback} residual={res:.3e}")
     assert s.converged == 1, (s.iterations, s.residual, s.fallback)
     assert res <= 1.05e-8, res
     assert abs(s.residual - res) <= 1e-9
@@ -359,21 +367,47 @@ def test_step_trajectory_mbb60x20_f64():
     assert np.abs(host(g.xphys) - st.xphys).max() <= 1e-4
 
 
-def test_step_projection_continuation_short():
-    """ft = 3 with beta and penal continuation (the 300 x 100 schedule) on a
-    small mesh in FP32: compliance within 1e-3, 99% of elements agree on
-    xphys > 0.5 after 30 iterations."""
-    from dataclasses import replace
+def _run_both(cfg, iterations, precision, solve_precision=0):
     from paper_2005_05436_amd.driver import TopOpt
-    cfg = replace(W.C1[300], nelx=90, nely=30, rmin=3.0, iterations=30,
-                  penal_sched=(1, 3.0, 5, 0.25, "add"), beta_sched=(1, 32.0, 5, 2.0, "mul"))
     prob = otop.problem_from_config(cfg)
-    st, log = otop.run(prob, cfg.iterations, solver="pcg")
-    g = TopOpt(cfg)
-    for i in range(cfg.iterations):
+    st, log = otop.run(prob, iterations, solver="pcg")
+    g = TopOpt(cfg, precision=precision, solve_precision=solve_precision)
+    glog = []
+    for _ in range(iterations):
         g.step()
-    s = g.stats()
-    assert abs(s["c"] - log[-1]["c"]) <= 1e-3 * log[-1]["c"], (s["c"], log[-1]["c"])
+        glog.append(g.stats())
+    return st, log, g, glog
+
+
+def test_step_projection_continuation_f64():
+    """ft = 3 (Newton threshold every iteration) with beta doubling and penal
+    steps every 5 iterations, FP64: compliance, eta, Newton and bisection
+    counts follow the oracle iteration by iteration."""
+    from dataclasses import replace
+    cfg = replace(W.C1[300], nelx=90, nely=30, rmin=3.0, precision="f64",
+                  penal_sched=(1, 3.0, 5, 0.25, "add"), beta_sched=(1, 32.0, 5, 2.0, "mul"))
+    st, log, g, glog = _run_both(cfg, 15, "f64")
+    for a, b in zip(glog, log):
+        assert abs(a["c"] - b["c"]) <= 1e-6 * b["c"], (a["loop"], a["c"], b["c"])
+        assert abs(a["eta"] - b["eta"]) <= 1e-7
+        assert a["n_newton"] == b["n_newton"] and a["n_bs"] == b["n_bs"]
+        assert a["penal"] == b["penal"] and a["beta"] == b["beta"]
+    assert np.abs(host(g.xphys) - st.xphys).max() <= 1e-4
+
+
+@pytest.mark.parametrize("solve", ["auto", "mixed"])
+def test_step_projection_fp32(solve):
+    """The 300 x 100 schedule's first 20 iterations (beta = 1, penal = 1) on a
+    90 x 30 mesh with FP32 fields and either the FP64 solve (FP32 Jacobi from
+    the FP32 assembly) or the mixed-precision solve: compliance within 1e-3
+    and 99% of elements agree on xphys > 0.5."""
+    from dataclasses import replace
+    from paper_2005_05436_amd import _lib as L
+    cfg = replace(W.C1[300], nelx=90, nely=30, rmin=3.0)
+    sp = L.TO_SOLVE_AUTO if solve == "auto" else L.TO_SOLVE_MIXED
+    st, log, g, glog = _run_both(cfg, 20, "f32", sp)
+    for a, b in zip(glog, log):
+        assert abs(a["c"] - b["c"]) <= 1e-3 * b["c"], (a["loop"], a["c"], b["c"])
+        assert a["solve_ok"]
     agree = np.mean((host(g.xphys) > 0.5) == (st.xphys > 0.5))
     assert agree >= 0.99
-    assert s["penal"] == log[-1]["penal"] and s["beta"] == log[-1]["beta"]
