@@ -14,6 +14,7 @@ namespace topt {
 
 constexpr int kBlock = 256;             // threads per block (4 wave64)
 constexpr int kWaves = kBlock / 64;
+constexpr int kBigBlock = 1024;         // persistent design-field kernels (16 wave64)
 constexpr int kMaxCoopBlocks = 4096;    // partial-sum slots reserved per reduction
 constexpr int kPartialWidth = 32;       // doubles per block in the partial buffer
 constexpr unsigned kSpinLimit = 1u << 27;   // grid-barrier spin cap (~several seconds)
@@ -42,6 +43,8 @@ struct Plan {
     double* kf64 = nullptr;  float* kf32 = nullptr;      // d x d full
     double* h64 = nullptr;   float* h32 = nullptr;       // (2R+1)^dim, y fastest
     int32_t* hlim = nullptr;                             // per (x[,z]) column: max |dy| with h > 0
+    double* hp64 = nullptr;  float* hp32 = nullptr;      // 2D: row dy of non-zero taps, zero padded
+    int hp_stride = 0;
     double* Hs64 = nullptr;  float* Hs32 = nullptr;      // m
     // scratch (device)
     double* E64 = nullptr;   float* E32 = nullptr;       // m
@@ -82,7 +85,8 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Deterministic block sum; result valid in every thread.  `sh` holds kWaves doubles.
+// Deterministic block sum; result valid in every thread.  `sh` holds NB/64 doubles.
+template <int NB = kBlock>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     v = wave_sum(v);
@@ -91,7 +95,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     __syncthreads();
     double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < kWaves; ++i) s += sh[i];
+    for (int i = 0; i < NB / 64; ++i) s += sh[i];
     return s;
 }
 
@@ -198,12 +202,22 @@ struct GridBar {
 
 // Sum of K partial columns written by every block: partial[b*kPartialWidth + k].
 // Every block computes the identical result (same data, same order).
-template <int K>
+// All loads are issued before the additions (one memory latency per
+// reduction, not one per block); gridDim.x <= 4 * NB.
+template <int K, int NB = kBlock>
 __device__ __forceinline__ void grid_reduce(const double* partial, double* out_sh, double* sh) {
+    double v[K][4];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int b = threadIdx.x + q * NB;
+            v[k][q] = b < (int)gridDim.x ? ld_acq(&partial[b * kPartialWidth + k]) : 0.0;
+        }
+#pragma unroll
     for (int k = 0; k < K; ++k) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) s += ld_acq(&partial[b * kPartialWidth + k]);
-        out_sh[k] = block_sum(s, sh);
+        const double s = ((v[k][0] + v[k][1]) + v[k][2]) + v[k][3];
+        out_sh[k] = block_sum<NB>(s, sh);
     }
 }
 

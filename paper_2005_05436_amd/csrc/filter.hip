@@ -38,130 +38,142 @@ __device__ __forceinline__ T staged_value(int mode, const T* in, const T* sc, co
 }
 
 // ---------------------------------------------------------------------------
-// 2D.  Lane = row (y), V adjacent output columns per lane, CG column groups
-// of V columns, and SPLIT waves per column group that take every SPLIT-th tap
-// row (the per-wave register tile keeps the FMA to LDS-read ratio at V, the
-// split keeps 4 waves per SIMD to hide LDS and scalar latency; partial sums
-// are combined through LDS at the end).  For every tap row dy the lane slides
-// along x through its LDS row: the V outputs need V consecutive columns and
-// one more tap to the right needs one new column, so a ring of V registers
-// (indexed at compile time by unrolling V taps) turns each LDS read into V
-// fused multiply-adds with one wave-uniform weight.  The cone weights are
-// symmetric, so the per-column support table hlim also bounds each tap row;
-// the last unrolled chunk of a row runs past it with zero weight (the window
-// has V spare columns).
-constexpr int kFiltCG = 4, kFiltSplit = 4, kFiltBlock = 64 * kFiltCG * kFiltSplit;
+// 2D.  Work is cut into tiles of 64 rows (a wave's lanes, contiguous in memory)
+// by V columns; the blocks are persistent (a few per CU) and take tiles from
+// an atomic counter, so the ALU-bound large-radius case stays balanced over
+// the CUs whatever the mesh size.  A block stages the tile's (64+2R) x
+// (V+2R+V) window in LDS with the boundary rule applied while loading, then
+// its `parts` waves split the tap rows dy (every parts-th row).  For a tap row
+// a lane slides along x through its LDS row: the V outputs need V consecutive
+// columns and one more tap to the right needs one new column, so a ring of V
+// registers (indexed at compile time by unrolling V taps) turns each LDS read
+// into V fused multiply-adds with one wave-uniform weight.  The cone weights
+// are symmetric, so the per-column support table hlim also bounds each tap
+// row; the last unrolled chunk of a row runs past it into the zero padding of
+// the plan's padded row table (8 consecutive weights per scalar load) and the
+// V spare window columns.  Partial sums of the parts are added through LDS.
+constexpr int kFiltV = 8, kFiltMaxParts = 16;
 
 template <typename T, int MODE, int V>
-__global__ __launch_bounds__(kFiltBlock) void filter2d_kernel(
-    int nely, int nelx, int R, char bc, const T* __restrict__ h, const int32_t* __restrict__ hlim,
+__global__ __launch_bounds__(64 * kFiltMaxParts) void filter2d_kernel(
+    int nely, int nelx, int R, char bc, const T* __restrict__ hp, int hps, const int32_t* __restrict__ hlim,
     const T* __restrict__ Hs, const T* __restrict__ in, const T* __restrict__ in2,
-    const T* __restrict__ sc, T* __restrict__ out, T* __restrict__ out2) {
+    const T* __restrict__ sc, T* __restrict__ out, T* __restrict__ out2, unsigned* ctr) {
     extern __shared__ unsigned char smem_raw[];
+    __shared__ int tile_sh;
     T* tile = reinterpret_cast<T*>(smem_raw);
     constexpr int NF = MODE == M_ADJ2 ? 2 : 1;
-    constexpr int TX = kFiltCG * V;
     const int W = 2 * R + 1;
     const int LY = 64 + 2 * R;           // LDS column height (y, contiguous)
-    const int LX = TX + 2 * R + V;       // LDS columns (x), V spare
-    const int y0 = blockIdx.x * 64, x0 = blockIdx.y * TX;
+    const int LX = V + 2 * R + V;        // LDS columns (x), V spare
+    const int nty = (nely + 63) / 64, ntiles = nty * ((nelx + V - 1) / V);
+    const int lane = threadIdx.x & 63;
+    // wave index made provably wave-uniform, so the tap loop's bounds and
+    // weights are scalar loads (SGPRs) rather than per-lane loads
+    const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int parts = blockDim.x >> 6;
     T* tile2 = tile + (size_t)LY * LX;
 
-    // stage the window with the boundary rule
-    for (int i = threadIdx.x; i < LY * LX; i += kFiltBlock) {
-        int ly = i % LY, lx = i / LY;
-        int gy = y0 - R + ly, gx = x0 - R + lx;
-        T v = T(0), v2 = T(0);
-        bool inside = gy >= 0 && gy < nely && gx >= 0 && gx < nelx;
-        if (bc == 'N' && !inside) {
-            gy = mirror_idx(gy, nely);
-            gx = mirror_idx(gx, nelx);
-            inside = true;
-        }
-        if (inside) {
-            int64_t e = gy + (int64_t)nely * gx;
-            if (MODE == M_RAW) v = T(1);
-            else v = staged_value<T>(MODE, in, sc, Hs, e);
-            if (NF == 2) v2 = staged_value<T>(MODE, in2, sc, Hs, e);
-        }
-        tile[i] = v;
-        if (NF == 2) tile2[i] = v2;
-    }
-    __syncthreads();
-
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int cg = wv % kFiltCG, part = wv / kFiltCG;
-    const int cx0 = cg * V;              // first owned column, tile-local
-    T acc[V], acc2[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) { acc[v] = T(0); acc2[v] = T(0); }
-
-    for (int dyi = part; dyi < W; dyi += kFiltSplit) {
-        const int lim = hlim[dyi];
-        if (lim < 0) continue;
-        const T* hrow = h + (size_t)dyi * W + R;        // hrow[dx] = h(dy, dx), |dx| <= lim
-        const T* base = tile + lane + dyi;              // LDS row of this lane at this dy
-        const T* base2 = tile2 + lane + dyi;
-        const int c0 = cx0 + R - lim;                   // LDS column of output 0 at dx = -lim
-        const int ntap = 2 * lim + 1;
-        T ring[V], ring2[V];
-#pragma unroll
-        for (int k = 0; k < V - 1; ++k) {
-            ring[k] = base[(size_t)(c0 + k) * LY];
-            if (NF == 2) ring2[k] = base2[(size_t)(c0 + k) * LY];
-        }
-        for (int t0 = 0; t0 < ntap; t0 += V) {
-            // weights and the V new columns of this chunk are fetched up front
-            T wk[V], nx[V], nx2[V];
-#pragma unroll
-            for (int u = 0; u < V; ++u) {
-                const int t = t0 + u;
-                const T hw = hrow[min(t, ntap - 1) - lim];
-                wk[u] = t < ntap ? hw : T(0);
-                const size_t col = (size_t)(c0 + t + V - 1) * LY;
-                nx[u] = base[col];
-                if (NF == 2) nx2[u] = base2[col];
+    for (;;) {
+        if (threadIdx.x == 0) tile_sh = (int)atomicAdd(&ctr[0], 1u);
+        __syncthreads();
+        const int t = tile_sh;
+        if (t >= ntiles) break;
+        const int y0 = (t % nty) * 64, x0 = (t / nty) * V;
+        // stage the window with the boundary rule
+        for (int i = threadIdx.x; i < LY * LX; i += blockDim.x) {
+            const int ly = i % LY, lx = i / LY;
+            int gy = y0 - R + ly, gx = x0 - R + lx;
+            T v = T(0), v2 = T(0);
+            bool inside = gy >= 0 && gy < nely && gx >= 0 && gx < nelx;
+            if (bc == 'N' && !inside) {
+                gy = mirror_idx(gy, nely);
+                gx = mirror_idx(gx, nelx);
+                inside = true;
             }
+            if (inside) {
+                const int64_t e = gy + (int64_t)nely * gx;
+                if (MODE == M_RAW) v = T(1);
+                else v = staged_value<T>(MODE, in, sc, Hs, e);
+                if (NF == 2) v2 = staged_value<T>(MODE, in2, sc, Hs, e);
+            }
+            tile[i] = v;
+            if (NF == 2) tile2[i] = v2;
+        }
+        __syncthreads();
+
+        T acc[V], acc2[V];
 #pragma unroll
-            for (int u = 0; u < V; ++u) {
-                ring[(u + V - 1) % V] = nx[u];
-                if (NF == 2) ring2[(u + V - 1) % V] = nx2[u];
+        for (int v = 0; v < V; ++v) { acc[v] = T(0); acc2[v] = T(0); }
+        for (int dyi = part; dyi < W; dyi += parts) {
+            const int lim = hlim[dyi];
+            if (lim < 0) continue;
+            const T* hrow = hp + (size_t)dyi * hps;         // hrow[t] = h(dy, t - lim), zero past 2 lim
+            const T* base = tile + lane + dyi;              // LDS row of this lane at this dy
+            const T* base2 = tile2 + lane + dyi;
+            const int c0 = R - lim;                         // LDS column of output 0 at dx = -lim
+            const int ntap = 2 * lim + 1;
+            T ring[V], ring2[V];
 #pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    acc[v] += wk[u] * ring[(u + v) % V];
-                    if (NF == 2) acc2[v] += wk[u] * ring2[(u + v) % V];
+            for (int k = 0; k < V - 1; ++k) {
+                ring[k] = base[(size_t)(c0 + k) * LY];
+                if (NF == 2) ring2[k] = base2[(size_t)(c0 + k) * LY];
+            }
+            for (int t0 = 0; t0 < ntap; t0 += V) {
+                // weights and the V new columns of this chunk are fetched up front
+                T wk[V], nx[V], nx2[V];
+#pragma unroll
+                for (int u = 0; u < V; ++u) {
+                    wk[u] = hrow[t0 + u];
+                    const size_t col = (size_t)(c0 + t0 + u + V - 1) * LY;
+                    nx[u] = base[col];
+                    if (NF == 2) nx2[u] = base2[col];
+                }
+#pragma unroll
+                for (int u = 0; u < V; ++u) {
+                    ring[(u + V - 1) % V] = nx[u];
+                    if (NF == 2) ring2[(u + V - 1) % V] = nx2[u];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        acc[v] += wk[u] * ring[(u + v) % V];
+                        if (NF == 2) acc2[v] += wk[u] * ring2[(u + v) % V];
+                    }
                 }
             }
         }
-    }
-    // combine the SPLIT partial sums (the window is no longer needed)
-    __syncthreads();
-    T* red = tile;                                      // [part][field][cg*V + v][lane]
-    const int slab = NF * TX * 64;
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        red[part * slab + (cx0 + v) * 64 + lane] = acc[v];
-        if (NF == 2) red[part * slab + TX * 64 + (cx0 + v) * 64 + lane] = acc2[v];
-    }
-    __syncthreads();
-    if (part != 0) return;
-    const int gy = y0 + lane;
-    if (gy < nely) {
+        // combine the parts' partial sums (the window is no longer needed)
+        __syncthreads();
+        T* red = tile;                                      // [part][field][v][lane]
+        const int slab = NF * V * 64;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            int gx = x0 + cx0 + v;
+            red[part * slab + v * 64 + lane] = acc[v];
+            if (NF == 2) red[part * slab + V * 64 + v * 64 + lane] = acc2[v];
+        }
+        __syncthreads();
+        // wave q finishes output column q of the tile (q < V)
+        if (part < V) {
+            const int gy = y0 + lane, gx = x0 + part;
             T r = T(0), r2 = T(0);
-#pragma unroll
-            for (int q = 0; q < kFiltSplit; ++q) {
-                r += red[q * slab + (cx0 + v) * 64 + lane];
-                if (NF == 2) r2 += red[q * slab + TX * 64 + (cx0 + v) * 64 + lane];
+            for (int q = 0; q < parts; ++q) {
+                r += red[q * slab + part * 64 + lane];
+                if (NF == 2) r2 += red[q * slab + V * 64 + part * 64 + lane];
             }
-            if (gx < nelx) {
-                int64_t e = gy + (int64_t)nely * gx;
+            if (gy < nely && gx < nelx) {
+                const int64_t e = gy + (int64_t)nely * gx;
                 if (MODE == M_FWD) r = r / Hs[e];
                 out[e] = r;
                 if (NF == 2) out2[e] = r2;
             }
+        }
+        __syncthreads();
+    }
+    // the last block to finish resets the tile counter for the next launch
+    if (threadIdx.x == 0) {
+        const unsigned done = atomicAdd(&ctr[1], 1u);
+        if (done == gridDim.x - 1) {
+            st_dev(&ctr[0], 0u);
+            st_dev(&ctr[1], 0u);
         }
     }
 }
@@ -239,21 +251,30 @@ __global__ __launch_bounds__(kBlock) void filter3d_kernel(
 
 // ---------------------------------------------------------------------------
 template <typename T, int MODE>
-static to_status run_filter(Plan* p, const T* h, const T* Hs, const T* in, const T* in2, const T* sc,
+static to_status run_filter(Plan* p, const T* h, const T* hp, const T* Hs, const T* in, const T* in2, const T* sc,
                             T* out, T* out2, hipStream_t s) {
     constexpr int NF = MODE == M_ADJ2 ? 2 : 1;
     const int R = p->R;
     const size_t lds_max = 160 * 1024;
     if (p->dim == 2) {
-        constexpr int V = 8;
-        size_t lds = (size_t)NF * (64 + 2 * R) * (kFiltCG * V + 2 * R + V) * sizeof(T);
-        lds = std::max(lds, (size_t)kFiltSplit * NF * kFiltCG * V * 64 * sizeof(T));   // partial-sum reuse
+        constexpr int V = kFiltV;
+        const int W = 2 * R + 1;
+        // waves per block: at least V (wave q finishes output column q), 16
+        // when there are enough tap rows to split
+        const int parts = W >= 16 ? kFiltMaxParts : V;
+        size_t lds = (size_t)NF * (64 + 2 * R) * (V + 2 * R + V) * sizeof(T);
+        lds = std::max(lds, (size_t)parts * NF * V * 64 * sizeof(T));   // partial-sum reuse
         if (lds > lds_max) { set_error("filter radius too large for the LDS tile"); return TO_EUNSUPPORTED; }
         auto k = filter2d_kernel<T, MODE, V>;
         TO_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        dim3 grid((p->nely + 63) / 64, (p->nelx + kFiltCG * V - 1) / (kFiltCG * V));
-        hipLaunchKernelGGL(k, grid, dim3(kFiltBlock), lds, s, p->nely, p->nelx, R, p->bc, h, p->hlim, Hs, in,
-                           in2, sc, out, out2);
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, 64 * parts, lds) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        const int ntiles = ((p->nely + 63) / 64) * ((p->nelx + V - 1) / V);
+        const int blocks = std::max(1, std::min(ntiles, per_cu * p->num_cu));
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * parts), lds, s, p->nely, p->nelx, R, p->bc, hp,
+                           p->hp_stride, p->hlim, Hs, in, in2, sc, out, out2, p->bar + 16);
     } else {
         size_t lds = (size_t)NF * (64 + 2 * R) * (4 + 2 * R) * (4 + 2 * R) * sizeof(T);
         if (lds > lds_max) { set_error("3D filter radius too large for the LDS tile"); return TO_EUNSUPPORTED; }
@@ -274,7 +295,7 @@ __global__ void cast_f64_to_f32(const double* __restrict__ a, float* __restrict_
 }
 
 to_status launch_fill_hs(Plan* p, hipStream_t s) {
-    to_status st = run_filter<double, M_RAW>(p, p->h64, nullptr, nullptr, nullptr, nullptr, p->Hs64, nullptr, s);
+    to_status st = run_filter<double, M_RAW>(p, p->h64, p->hp64, nullptr, nullptr, nullptr, nullptr, p->Hs64, nullptr, s);
     if (st != TO_OK) return st;
     int64_t m = p->info.m ? p->info.m : (int64_t)p->nelx * p->nely * (p->dim == 3 ? p->nelz : 1);
     hipLaunchKernelGGL(cast_f64_to_f32, dim3(256), dim3(kBlock), 0, s, p->Hs64, p->Hs32, m);
@@ -287,23 +308,23 @@ to_status launch_filter(Plan* p, to_dtype dt, int mode, const void* in, const vo
     if (dt == TO_F64) {
         auto a = (const double*)in; auto b = (const double*)in2; auto c = (const double*)sc;
         auto o = (double*)out; auto o2 = (double*)out2;
-        if (mode == TO_FILTER_FWD) return run_filter<double, M_FWD>(p, p->h64, p->Hs64, a, b, c, o, o2, s);
-        if (mode == TO_FILTER_ADJ) return run_filter<double, M_ADJ>(p, p->h64, p->Hs64, a, b, c, o, o2, s);
-        to_status st = run_filter<double, M_ADJ2>(p, p->h64, p->Hs64, a, b, c, o, o2, s);
+        if (mode == TO_FILTER_FWD) return run_filter<double, M_FWD>(p, p->h64, p->hp64, p->Hs64, a, b, c, o, o2, s);
+        if (mode == TO_FILTER_ADJ) return run_filter<double, M_ADJ>(p, p->h64, p->hp64, p->Hs64, a, b, c, o, o2, s);
+        to_status st = run_filter<double, M_ADJ2>(p, p->h64, p->hp64, p->Hs64, a, b, c, o, o2, s);
         if (st == TO_EUNSUPPORTED) {   // two fields do not fit the LDS: two passes
-            st = run_filter<double, M_ADJ>(p, p->h64, p->Hs64, a, nullptr, c, o, nullptr, s);
-            if (st == TO_OK) st = run_filter<double, M_ADJ>(p, p->h64, p->Hs64, b, nullptr, c, o2, nullptr, s);
+            st = run_filter<double, M_ADJ>(p, p->h64, p->hp64, p->Hs64, a, nullptr, c, o, nullptr, s);
+            if (st == TO_OK) st = run_filter<double, M_ADJ>(p, p->h64, p->hp64, p->Hs64, b, nullptr, c, o2, nullptr, s);
         }
         return st;
     }
     auto a = (const float*)in; auto b = (const float*)in2; auto c = (const float*)sc;
     auto o = (float*)out; auto o2 = (float*)out2;
-    if (mode == TO_FILTER_FWD) return run_filter<float, M_FWD>(p, p->h32, p->Hs32, a, b, c, o, o2, s);
-    if (mode == TO_FILTER_ADJ) return run_filter<float, M_ADJ>(p, p->h32, p->Hs32, a, b, c, o, o2, s);
-    to_status st = run_filter<float, M_ADJ2>(p, p->h32, p->Hs32, a, b, c, o, o2, s);
+    if (mode == TO_FILTER_FWD) return run_filter<float, M_FWD>(p, p->h32, p->hp32, p->Hs32, a, b, c, o, o2, s);
+    if (mode == TO_FILTER_ADJ) return run_filter<float, M_ADJ>(p, p->h32, p->hp32, p->Hs32, a, b, c, o, o2, s);
+    to_status st = run_filter<float, M_ADJ2>(p, p->h32, p->hp32, p->Hs32, a, b, c, o, o2, s);
     if (st == TO_EUNSUPPORTED) {
-        st = run_filter<float, M_ADJ>(p, p->h32, p->Hs32, a, nullptr, c, o, nullptr, s);
-        if (st == TO_OK) st = run_filter<float, M_ADJ>(p, p->h32, p->Hs32, b, nullptr, c, o2, nullptr, s);
+        st = run_filter<float, M_ADJ>(p, p->h32, p->hp32, p->Hs32, a, nullptr, c, o, nullptr, s);
+        if (st == TO_OK) st = run_filter<float, M_ADJ>(p, p->h32, p->hp32, p->Hs32, b, nullptr, c, o2, nullptr, s);
     }
     return st;
 }

@@ -12,6 +12,7 @@
 // four times fewer grid barriers.  Volume sums are double-double, so every
 // decision agrees with an exactly rounded sum except in exact ties.
 #include <cmath>
+#include <type_traits>
 
 #include "common.h"
 
@@ -30,54 +31,80 @@ __device__ __forceinline__ double oc_clamp(double ocp, double lm, double x, doub
     return v;
 }
 
+constexpr int kOcBlock = 512;   // 15 double-double accumulators per lane need the register room
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void oc_kernel(int64_t m, const uint8_t* __restrict__ pas, T* __restrict__ x,
+__global__ __launch_bounds__(kOcBlock) void oc_kernel(int64_t m, const uint8_t* __restrict__ pas, T* __restrict__ x,
                                                      const T* __restrict__ dc, const T* __restrict__ dv,
                                                      double volfrac, double move, double* __restrict__ ocp_buf,
                                                      to_oc_stats* st, double* partial, unsigned* bar) {
-    __shared__ double shw[kWaves * 2];
+    constexpr int NB = kOcBlock, NW = NB / 64;
+    __shared__ double wsum[NW * kCand * 2];
+    __shared__ double gsum[NB * 2];
     __shared__ double tot[2 * kCand];
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * NB;
+    const int64_t i0 = (int64_t)blockIdx.x * NB + threadIdx.x;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     bool alive = true;
     int region = 0;
     GridBar gb;
     gb.init(bar);
 
-    // block-level double-double sum of K values, written to the partial region
-    auto block_dd = [&](dd* v, int K, double* reg) {
+    // Block-level double-double sums of K values (K compile-time, unrolled so
+    // v stays in registers): every wave reduces all K with shuffles, one
+    // barrier, then thread k combines the NW wave results of value k in wave
+    // order and writes the block's partial.
+    auto block_dd = [&](auto& v, auto kconst, double* reg) {
+        constexpr int K = decltype(kconst)::value;
+#pragma unroll
         for (int k = 0; k < K; ++k) {
-            dd s = wave_dd_sum(v[k]);
-            __syncthreads();
-            if (lane == 0) { shw[2 * w] = s.hi; shw[2 * w + 1] = s.lo; }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                dd b{shw[0], shw[1]};
-                for (int i = 1; i < kWaves; ++i) b = dd_add(b, dd{shw[2 * i], shw[2 * i + 1]});
-                st_dev(&reg[blockIdx.x * kPartialWidth + 2 * k], b.hi);
-                st_dev(&reg[blockIdx.x * kPartialWidth + 2 * k + 1], b.lo);
-            }
+            const dd s = wave_dd_sum(v[k]);
+            if (lane == 0) { wsum[(w * K + k) * 2] = s.hi; wsum[(w * K + k) * 2 + 1] = s.lo; }
         }
+        __syncthreads();
+        if (threadIdx.x < K) {
+            const int k = threadIdx.x;
+            dd b{wsum[k * 2], wsum[k * 2 + 1]};
+            for (int i = 1; i < NW; ++i) b = dd_add(b, dd{wsum[(i * K + k) * 2], wsum[(i * K + k) * 2 + 1]});
+            st_dev(&reg[blockIdx.x * kPartialWidth + 2 * k], b.hi);
+            st_dev(&reg[blockIdx.x * kPartialWidth + 2 * k + 1], b.lo);
+        }
+        __syncthreads();
     };
-    // identical fixed-order sum of the block partials in every block
-    auto grid_dd = [&](int K, const double* reg) {
-        for (int k = 0; k < K; ++k) {
-            dd s{0.0, 0.0};
-            for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
-                s = dd_add(s, dd{ld_acq(&reg[b * kPartialWidth + 2 * k]), ld_acq(&reg[b * kPartialWidth + 2 * k + 1])});
-            s = wave_dd_sum(s);
-            __syncthreads();
-            if (lane == 0) { shw[2 * w] = s.hi; shw[2 * w + 1] = s.lo; }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                dd b{shw[0], shw[1]};
-                for (int i = 1; i < kWaves; ++i) b = dd_add(b, dd{shw[2 * i], shw[2 * i + 1]});
-                tot[2 * k] = b.hi;
-                tot[2 * k + 1] = b.lo;
+    // Identical fixed-order sum of the block partials in every block: thread
+    // (k, j) with j < S = NB / K sums blocks j, j + S, ... of value k, then
+    // thread k combines its S partial sums in order.
+    auto grid_dd = [&](auto kconst, const double* reg) {
+        constexpr int K = decltype(kconst)::value;
+        constexpr int S = NB / K;
+        if (threadIdx.x < K * S) {
+            const int k = threadIdx.x / S, j = threadIdx.x % S;
+            // all loads issued before the (dependent) additions: one memory
+            // latency instead of one per block (at most kMaxPer blocks each)
+            constexpr int kMaxPer = 32;
+            double hv[kMaxPer], lv[kMaxPer];
+#pragma unroll
+            for (int q = 0; q < kMaxPer; ++q) {
+                const int b = j + q * S;
+                const bool ok = b < (int)gridDim.x;
+                hv[q] = ok ? ld_dev(&reg[b * kPartialWidth + 2 * k]) : 0.0;
+                lv[q] = ok ? ld_dev(&reg[b * kPartialWidth + 2 * k + 1]) : 0.0;
             }
-            __syncthreads();
+            dd a{0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < kMaxPer; ++q) a = dd_add(a, dd{hv[q], lv[q]});
+            gsum[(k * S + j) * 2] = a.hi;
+            gsum[(k * S + j) * 2 + 1] = a.lo;
         }
+        __syncthreads();
+        if (threadIdx.x < K) {
+            const int k = threadIdx.x;
+            dd b{gsum[k * S * 2], gsum[k * S * 2 + 1]};
+            for (int j = 1; j < S; ++j) b = dd_add(b, dd{gsum[(k * S + j) * 2], gsum[(k * S + j) * 2 + 1]});
+            tot[2 * k] = b.hi;
+            tot[2 * k + 1] = b.lo;
+        }
+        __syncthreads();
     };
 
     // sweep 0: ocP on the active set, sum ocP, count active, sum passive x
@@ -95,9 +122,9 @@ __global__ __launch_bounds__(kBlock) void oc_kernel(int64_t m, const uint8_t* __
             }
         }
         double* reg = partial + (size_t)region * kMaxCoopBlocks * kPartialWidth;
-        block_dd(v, 3, reg);
+        block_dd(v, std::integral_constant<int, 3>{}, reg);
         alive = gb.sync() && alive;
-        grid_dd(3, reg);
+        grid_dd(std::integral_constant<int, 3>{}, reg);
         region ^= 1;
     }
     const double n_act = tot[2] + tot[3];
@@ -130,15 +157,15 @@ __global__ __launch_bounds__(kBlock) void oc_kernel(int64_t m, const uint8_t* __
             for (int j = 0; j < kCand; ++j) v[j] = dd_add1(v[j], oc_clamp(q, mid[j], xe, move));
         }
         double* reg = partial + (size_t)region * kMaxCoopBlocks * kPartialWidth;
-        block_dd(v, kCand, reg);
+        block_dd(v, std::integral_constant<int, kCand>{}, reg);
         alive = gb.sync() && alive;
-        grid_dd(kCand, reg);
+        grid_dd(std::integral_constant<int, kCand>{}, reg);
         region ^= 1;
         ++passes;
         // walk the tree exactly as the serial loop would
         int j = 0;
         for (int lev = 0; lev < kLevels && more(); ++lev) {
-            lmid = mid[j];
+            lmid = 0.5 * (l1 + l2);        // equals mid[j]: the same operands, the same rounding
             const dd s = dd_add(dd{tot[2 * j], tot[2 * j + 1]}, pas_sum);
             const double vol = (s.hi + s.lo) / (double)m;
             vol_last = vol;
@@ -166,14 +193,17 @@ static to_status run_oc(Plan* p, T* x, const T* dc, const T* dv, double volfrac,
                         hipStream_t s) {
     auto k = oc_kernel<T>;
     int64_t m = p->info.m;
-    int maxb = coop_blocks_for((const void*)k, kBlock, 0, p->num_cu);
-    int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, 4 * p->num_cu), (m + kBlock - 1) / kBlock));
+    int maxb = coop_blocks_for((const void*)k, kOcBlock, 0, p->num_cu);
+    // blocks <= (kOcBlock / 15) * 32 = 1088 keeps every block partial within the
+    // unrolled gather of the grid reduction
+    int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, 2 * p->num_cu), (m + kOcBlock - 1) / kOcBlock));
+    blocks = std::min(blocks, 1024);
     const uint8_t* pas = p->passive;
     double* ocp = p->fx64;
     double* partial = p->partial;
     unsigned* bar = p->bar;
     void* args[] = {&m, &pas, &x, &dc, &dv, &volfrac, &move, &ocp, &st, &partial, &bar};
-    TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(kBlock), args, 0, s));
+    TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(kOcBlock), args, 0, s));
     return TO_OK;
 }
 

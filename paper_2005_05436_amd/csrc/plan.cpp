@@ -181,6 +181,11 @@ struct Sizes {
     int d = 0, dt = 0, R = 0, taps = 0, cols = 0;
 };
 
+// Row stride of the padded 2D tap table: the non-zero taps of a row followed
+// by zeros, so the filter's unrolled chunks of 8 taps read 8 consecutive
+// weights without bounds tests.
+static int pad_stride(int R) { return ((2 * R + 1 + 8) + 7) / 8 * 8; }
+
 static to_status check_desc(const to_mesh_desc* D, Sizes& S) {
     if (!D) { set_error("desc is NULL"); return TO_EINVAL; }
     if (D->dim != 2 && D->dim != 3) { set_error("dim must be 2 or 3"); return TO_EINVAL; }
@@ -234,7 +239,7 @@ static void filter_table(const Sizes& S, double rmin, std::vector<double>& h, st
 
 struct Offsets {
     size_t perm, seg, rowp, col, pas, freem, ke64, ke32, kf64, kf32, h64, h32,
-        hlim, Hs64, Hs32, E64, E32, partial, scal, bar, v64[8], v32[8], fx64, fx32, total;
+        hlim, hp64, hp32, Hs64, Hs32, E64, E32, partial, scal, bar, v64[8], v32[8], fx64, fx32, total;
 };
 
 static Offsets layout(const Sizes& S) {
@@ -253,6 +258,8 @@ static Offsets layout(const Sizes& S) {
     o.h64 = L.take(8 * S.taps);
     o.h32 = L.take(4 * S.taps);
     o.hlim = L.take(4 * S.cols);
+    o.hp64 = L.take(8 * (size_t)(2 * S.R + 1) * pad_stride(S.R));
+    o.hp32 = L.take(4 * (size_t)(2 * S.R + 1) * pad_stride(S.R));
     o.Hs64 = L.take(8 * S.m);
     o.Hs32 = L.take(4 * S.m);
     o.E64 = L.take(8 * S.m);
@@ -400,6 +407,7 @@ to_status plan_create(const to_mesh_desc* D, void* ws, size_t ws_bytes, hipStrea
     p->ke64 = (double*)(base + o.ke64); p->ke32 = (float*)(base + o.ke32);
     p->kf64 = (double*)(base + o.kf64); p->kf32 = (float*)(base + o.kf32);
     p->h64 = (double*)(base + o.h64); p->h32 = (float*)(base + o.h32); p->hlim = (int32_t*)(base + o.hlim);
+    p->hp64 = (double*)(base + o.hp64); p->hp32 = (float*)(base + o.hp32); p->hp_stride = pad_stride(S.R);
     p->Hs64 = (double*)(base + o.Hs64); p->Hs32 = (float*)(base + o.Hs32);
     p->E64 = (double*)(base + o.E64); p->E32 = (float*)(base + o.E32);
     p->partial = (double*)(base + o.partial); p->scal = (double*)(base + o.scal);
@@ -434,6 +442,17 @@ to_status plan_create(const to_mesh_desc* D, void* ws, size_t ws_bytes, hipStrea
     // --- filter table --------------------------------------------------------
     filter_table(S, D->rmin, p->h, p->hlim_host);
     std::vector<float> h32(p->h.begin(), p->h.end());
+    // padded rows: hp[dyi][t] = h(dy, t - lim(dy)) for t <= 2 lim(dy), else 0
+    // (the cone is symmetric, so lim of column dy bounds row dy)
+    const int W2 = 2 * S.R + 1, WP = pad_stride(S.R);
+    std::vector<double> hp(S.G.dim == 2 ? (size_t)W2 * WP : 1, 0.0);
+    if (S.G.dim == 2)
+        for (int dyi = 0; dyi < W2; ++dyi) {
+            const int lim = p->hlim_host[dyi];
+            for (int t = 0; t <= 2 * lim; ++t)
+                hp[(size_t)dyi * WP + t] = p->h[(size_t)dyi * W2 + S.R + (t - lim)];
+        }
+    std::vector<float> hp32v(hp.begin(), hp.end());
 
     // --- upload ------------------------------------------------------------------
     auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
@@ -445,6 +464,7 @@ to_status plan_create(const to_mesh_desc* D, void* ws, size_t ws_bytes, hipStrea
     UP(p->passive, pas); UP(p->freemask, fm);
     UP(p->ke64, p->ke_lower); UP(p->ke32, ke32); UP(p->kf64, p->ke_full); UP(p->kf32, kf32);
     UP(p->h64, p->h); UP(p->h32, h32); UP(p->hlim, p->hlim_host);
+    UP(p->hp64, hp); UP(p->hp32, hp32v);
 #undef UP
     if (e == hipSuccess) e = hipMemsetAsync(p->bar, 0, 4 * 1024, stream);
     if (e == hipSuccess) e = hipMemsetAsync(p->scal, 0, 8 * 256, stream);

@@ -41,14 +41,15 @@ __device__ __forceinline__ double pre_value(const T* xt, const T* x, const uint8
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void project_kernel(
+__global__ __launch_bounds__(kBigBlock) void project_kernel(
     int64_t m, int ft, const T* __restrict__ xt, const T* __restrict__ x, const uint8_t* __restrict__ pas,
     T* __restrict__ xphys, T* __restrict__ dprj, double beta, double* d_eta, double target,
     int mean_target, const T* __restrict__ xold, to_project_stats* st, double* partial, unsigned* bar) {
-    __shared__ double sh[kWaves];
+    constexpr int NB = kBigBlock;
+    __shared__ double sh[NB / 64];
     __shared__ double red[4];
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * NB;
+    const int64_t i0 = (int64_t)blockIdx.x * NB + threadIdx.x;
     double eta = *d_eta;
     bool alive = true;
     GridBar gb;
@@ -57,10 +58,10 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
     if (ft == 3 && mean_target) {                     // eq. (17): target = volume of the pre-projection field
         double s = 0.0;
         for (int64_t e = i0; e < m; e += stride) s += pre_value(xt, x, pas, e);
-        s = block_sum(s, sh);
+        s = block_sum<NB>(s, sh);
         if (threadIdx.x == 0) st_dev(&partial[blockIdx.x * kPartialWidth], s);
         alive = gb.sync();
-        grid_reduce<1>(partial, red, sh);
+        grid_reduce<1, NB>(partial, red, sh);
         target = red[0] / (double)m;
         alive = alive && gb.sync();              // partial buffer is reused below
     }
@@ -78,14 +79,14 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
                     sp += P.prj(v);
                     sd += P.deta(v);
                 }
-            sp = block_sum(sp, sh);
-            sd = block_sum(sd, sh);
+            sp = block_sum<NB>(sp, sh);
+            sd = block_sum<NB>(sd, sh);
             if (threadIdx.x == 0) {
                 st_dev(&partial[blockIdx.x * kPartialWidth + 0], sp);
                 st_dev(&partial[blockIdx.x * kPartialWidth + 1], sd);
             }
             alive = gb.sync() && alive;
-            grid_reduce<2>(partial, red, sh);
+            grid_reduce<2, NB>(partial, red, sh);
             g = red[0] / (double)m - target;
             if (!(fabs(g) > 1e-6) || steps >= 50 || !alive) break;
             eta = eta - g / (red[1] / (double)m);
@@ -110,15 +111,15 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
             }
             sv += (double)xpT;
         }
-    sc = block_sum(sc, sh);
-    sv = block_sum(sv, sh);
+    sc = block_sum<NB>(sc, sh);
+    sv = block_sum<NB>(sv, sh);
     if (threadIdx.x == 0) {
         st_dev(&partial[blockIdx.x * kPartialWidth + 0], sc);
         st_dev(&partial[blockIdx.x * kPartialWidth + 1], sv);
     }
     alive = gb.sync() && alive;
     if (blockIdx.x == 0) {
-        grid_reduce<2>(partial, red, sh);
+        grid_reduce<2, NB>(partial, red, sh);
         if (threadIdx.x == 0) {
             to_project_stats s;
             s.eta = eta;
@@ -147,14 +148,14 @@ static to_status run_project(Plan* p, int ft, const void* xt, const void* x, voi
                              to_project_stats* st, hipStream_t s) {
     auto k = project_kernel<T>;
     int64_t m = p->info.m;
-    int maxb = coop_blocks_for((const void*)k, kBlock, 0, p->num_cu);
-    int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, 4 * p->num_cu), (m + kBlock - 1) / kBlock));
+    int maxb = coop_blocks_for((const void*)k, kBigBlock, 0, p->num_cu);
+    int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, p->num_cu), (m + kBigBlock - 1) / kBigBlock));
     int mean_target = std::isnan(target) ? 1 : 0;
     const T* a = (const T*)xt; const T* b = (const T*)x; const uint8_t* pas = p->passive;
     T* c = (T*)xphys; T* dp = (T*)dprj; const T* xo = (const T*)xold;
     double* partial = p->partial; unsigned* bar = p->bar;
     void* args[] = {&m, &ft, &a, &b, &pas, &c, &dp, &beta, &d_eta, &target, &mean_target, &xo, &st, &partial, &bar};
-    TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(kBlock), args, 0, s));
+    TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(kBigBlock), args, 0, s));
     return TO_OK;
 }
 

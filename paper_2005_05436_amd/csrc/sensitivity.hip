@@ -58,12 +58,13 @@ __global__ __launch_bounds__(kBlock) void dot_kernel(int64_t n, const double* __
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
         s += a[i] * b[i];
     s = block_sum(s, sh);
+    // partials are exchanged with device-coherent accesses, so the arrival
+    // needs only the block's own stores to have completed (no L2 writeback)
     if (threadIdx.x == 0) {
-        partial[blockIdx.x] = s;
-        __threadfence();
+        st_dev(&partial[blockIdx.x], s);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         unsigned done = atomicAdd(counter, 1u);
         last = done == gridDim.x - 1;
-        if (last) __threadfence();
     }
     __syncthreads();
     if (last) {
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void dot_kernel(int64_t n, const double* __
         t = block_sum(t, sh);
         if (threadIdx.x == 0) {
             *out = t;
-            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st_dev(counter, 0u);
         }
     }
 }

@@ -14,9 +14,15 @@
 // buffered), so no separate direction update phase is needed.  All dot
 // products are FP64, reduced in a fixed order identical in every block.
 //
-// Mixed precision (FP32 fields): outer FP64 residual from the FP64 matrix-free
-// operator, inner FP32 PCG, u += d; FP64 PCG fallback when the refinement
-// stalls.
+// Work split: block b owns the contiguous node range [lo, hi).  Vectors
+// written by the owner and read by a neighbour node in another block (the
+// iterate, z and the directions) are stored device-coherently (st_dev) only
+// in the band of nodes within one neighbourhood of the range ends, and read
+// device-coherently (ld_dev) only when the node is not the block's own; all
+// other accesses are ordinary cached loads and stores.
+//
+// Mixed precision (FP32 fields): FP32 CG with FP64 residual replacement from
+// the FP64 matrix-free operator; FP64 PCG fallback when it stalls.
 #include <cmath>
 
 #include "common.h"
@@ -34,16 +40,35 @@ struct Geo {
     }
 };
 
-// Vectors read across blocks (iterate, z, directions) go through ld_dev/st_dev.
-template <typename T> struct Src1 {
-    const T* x;
-    __device__ __forceinline__ T operator()(int64_t i) const { return ld_dev(x + i); }
+// The block's node range and its halo band (the largest node-index distance
+// between two nodes of one element).
+struct Own {
+    int64_t lo, hi, band;
+    __device__ __forceinline__ bool mine(int64_t q) const { return q >= lo && q < hi; }
+    __device__ __forceinline__ bool edge(int64_t nd) const { return nd < lo + band || nd >= hi - band; }
+    template <typename T>
+    __device__ __forceinline__ T ld(const T* p, int64_t q, int64_t i) const { return mine(q) ? p[i] : ld_dev(p + i); }
+    template <typename T>
+    __device__ __forceinline__ void st(T* p, int64_t nd, int64_t i, T v) const {
+        if (edge(nd)) st_dev(p + i, v);
+        else p[i] = v;
+    }
 };
-template <typename T> struct SrcZP {
+
+// Source vectors of the operators, read by node and component.
+template <int DIM, typename T> struct Src1 {
+    const T* x;
+    Own o;
+    __device__ __forceinline__ T operator()(int64_t q, int c) const { return o.ld(x, q, DIM * q + c); }
+};
+template <int DIM, typename T> struct SrcZP {
     const T* z;
     const T* p;
     T beta;
-    __device__ __forceinline__ T operator()(int64_t i) const { return ld_dev(z + i) + beta * ld_dev(p + i); }
+    Own o;
+    __device__ __forceinline__ T operator()(int64_t q, int c) const {
+        return o.ld(z, q, DIM * q + c) + beta * o.ld(p, q, DIM * q + c);
+    }
 };
 
 template <int DIM, typename T>
@@ -80,7 +105,7 @@ struct MatFree {
             for (int b = 0; b < NC; ++b) {
                 const int64_t q = node(ey + CY[b], ex + CX[b], DIM == 2 ? 0 : ez + CZ[b]);
 #pragma unroll
-                for (int c2 = 0; c2 < DIM; ++c2) sv[b * DIM + c2] = src(DIM * q + c2);
+                for (int c2 = 0; c2 < DIM; ++c2) sv[b * DIM + c2] = src(q, c2);
             }
             const T* kr = ke + (size_t)a * DIM * D;
 #pragma unroll
@@ -155,7 +180,7 @@ struct CsrS {
             const int64_t q = nd + delta(k);
 #pragma unroll
             for (int c2 = 0; c2 < DIM; ++c2) {
-                const T sv = src(DIM * q + c2);
+                const T sv = src(q, c2);
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) out[c] += kv[row[c] + DIM * rank + c2] * sv;
             }
@@ -163,7 +188,7 @@ struct CsrS {
         }
 #pragma unroll
         for (int c2 = 0; c2 < DIM; ++c2) {                      // the node's own block
-            const T sv = src(DIM * nd + c2);
+            const T sv = src(nd, c2);
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
                 const T kvv = c2 <= c ? kv[row[c] + DIM * rank + c2] : kv[row[c2] + DIM * rank + c];
@@ -183,7 +208,7 @@ struct CsrS {
             for (int j = 0; j < km; ++j) rq += exists(qy, qx, qz, j) ? 1 : 0;
 #pragma unroll
             for (int c2 = 0; c2 < DIM; ++c2) {
-                const T sv = src(DIM * q + c2);
+                const T sv = src(q, c2);
                 const int32_t rq0 = rp[DIM * q + c2] + DIM * rq;
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) out[c] += kv[rq0 + c] * sv;
@@ -222,6 +247,7 @@ struct Ctx {
     double* res;     // shared results
     int red;
     bool alive;
+    Own o;
     template <int K>
     __device__ __forceinline__ void reduce(const double (&v)[K]) {
         double* region = partial + (size_t)(red & 1) * kMaxCoopBlocks * kPartialWidth;
@@ -246,19 +272,19 @@ struct Pcg {
     // r = b - A x (x = 0: r = b), z = dinv r; returns (r.z, r.r) in C.res
     __device__ void residual(const T* b, const T* x, bool x_zero, const T* dinv, T* r, T* z) {
         double v[2] = {0.0, 0.0};
-        const int64_t stride = (int64_t)gridDim.x * kBlock;
-        for (int64_t nd = (int64_t)blockIdx.x * kBlock + threadIdx.x; nd < g.nnode; nd += stride) {
+        const Own& o = C.o;
+        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock) {
             int iy, ix, iz;
             g.coords(nd, iy, ix, iz, DIM);
             T ax[DIM];
-            if (!x_zero) op.apply(nd, iy, ix, iz, Src1<T>{x}, ax);
+            if (!x_zero) op.apply(nd, iy, ix, iz, Src1<DIM, T>{x, o}, ax);
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
                 const int64_t i = DIM * nd + c;
                 T ri = fm[i] ? (x_zero ? b[i] : b[i] - ax[c]) : T(0);
                 T zi = dinv[i] * ri;
                 r[i] = ri;
-                st_dev(z + i, zi);
+                o.st(z, nd, i, zi);
                 v[0] += (double)ri * (double)zi;
                 v[1] += (double)ri * (double)ri;
             }
@@ -274,12 +300,11 @@ struct Pcg {
     // outer FP64 residual is the judge anyway.
     __device__ int run(const T* b, T* x, bool x_zero, const T* dinv, T* r, T* z, T* pa, T* pb, T* q,
                        double tol, int maxit, int& restarts, bool confirm = true) {
-        const int64_t stride = (int64_t)gridDim.x * kBlock;
-        const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+        const Own& o = C.o;
         if (x_zero)
-            for (int64_t nd = i0; nd < g.nnode; nd += stride)
+            for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock)
 #pragma unroll
-                for (int c = 0; c < DIM; ++c) st_dev(x + DIM * nd + c, T(0));
+                for (int c = 0; c < DIM; ++c) o.st(x, nd, DIM * nd + c, T(0));
         residual(b, x, x_zero, dinv, r, z);
         double rz = C.res[0], rr = C.res[1];
         bool fresh = true;
@@ -300,8 +325,8 @@ struct Pcg {
             fresh = false;
             // phase A: pnew = z + beta pold; q = A pnew
             double v1[1] = {0.0};
-            const SrcZP<T> src{z, pold, (T)beta};
-            for (int64_t nd = i0; nd < g.nnode; nd += stride) {
+            const SrcZP<DIM, T> src{z, pold, (T)beta, o};
+            for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock) {
                 int iy, ix, iz;
                 g.coords(nd, iy, ix, iz, DIM);
                 T ap[DIM];
@@ -309,9 +334,9 @@ struct Pcg {
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) {
                     const int64_t i = DIM * nd + c;
-                    const T pi = src(i);
+                    const T pi = src(nd, c);
                     const T qi = fm[i] ? ap[c] : T(0);
-                    st_dev(pnew + i, pi);
+                    o.st(pnew, nd, i, pi);
                     q[i] = qi;
                     v1[0] += (double)pi * (double)qi;
                 }
@@ -323,15 +348,15 @@ struct Pcg {
             // phase B: x += alpha p; r -= alpha q; z = dinv r
             double v2[2] = {0.0, 0.0};
             const T a = (T)alpha;
-            for (int64_t nd = i0; nd < g.nnode; nd += stride) {
+            for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock) {
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) {
                     const int64_t i = DIM * nd + c;
-                    st_dev(x + i, ld_dev(x + i) + a * ld_dev(pnew + i));
+                    o.st(x, nd, i, x[i] + a * pnew[i]);
                     const T ri = r[i] - a * q[i];
                     const T zi = dinv[i] * ri;
                     r[i] = ri;
-                    st_dev(z + i, zi);
+                    o.st(z, nd, i, zi);
                     v2[0] += (double)ri * (double)zi;
                     v2[1] += (double)ri * (double)ri;
                 }
@@ -351,9 +376,8 @@ struct Pcg {
 };
 
 template <int DIM, typename T, class Op>
-__device__ void jacobi(const Op& op, const Geo& g, const uint8_t* fm, T* dinv) {
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t nd = (int64_t)blockIdx.x * kBlock + threadIdx.x; nd < g.nnode; nd += stride) {
+__device__ void jacobi(const Op& op, const Geo& g, const Own& o, const uint8_t* fm, T* dinv) {
+    for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock) {
         int iy, ix, iz;
         g.coords(nd, iy, ix, iz, DIM);
         T dg[DIM];
@@ -384,8 +408,7 @@ template <int DIM, class Op32>
 __device__ bool mixed_cg(Ctx& C, const Geo& g, const SolveArgs& A, const Op32& op32,
                          const MatFree<DIM, double>& mf64, double tol, int& iters, int& passes, double& rfinal,
                          double*& ubest) {
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const Own& o = C.o;
     const uint8_t* __restrict__ fm = A.freem;
     double* u = A.u;
     double* r64 = A.v64[0];
@@ -395,20 +418,20 @@ __device__ bool mixed_cg(Ctx& C, const Geo& g, const SolveArgs& A, const Op32& o
     // u is copied to the candidate buffer in the same sweep
     auto replace = [&](double& rz, double& rr64) {
         double v[2] = {0.0, 0.0};
-        for (int64_t nd = i0; nd < g.nnode; nd += stride) {
+        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock) {
             int iy, ix, iz;
             g.coords(nd, iy, ix, iz, DIM);
             double ax[DIM];
-            mf64.apply(nd, iy, ix, iz, Src1<double>{u}, ax);
+            mf64.apply(nd, iy, ix, iz, Src1<DIM, double>{u, o}, ax);
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
                 const int64_t i = DIM * nd + c;
-                st_dev(cand + i, ld_dev(u + i));
+                cand[i] = u[i];                 // own range only
                 const double ri = fm[i] ? A.f[i] - ax[c] : 0.0;
                 r64[i] = ri;
                 const float rf = (float)ri, zf = dinv[i] * rf;
                 r[i] = rf;
-                st_dev(z + i, zf);
+                o.st(z, nd, i, zf);
                 v[0] += (double)rf * (double)zf;
                 v[1] += ri * ri;
             }
@@ -432,8 +455,8 @@ __device__ bool mixed_cg(Ctx& C, const Geo& g, const SolveArgs& A, const Op32& o
     const double drop = A.inner_rtol;
     while (C.alive && iters < budget) {
         double v1[1] = {0.0};
-        const SrcZP<float> src{z, pold, (float)beta};
-        for (int64_t nd = i0; nd < g.nnode; nd += stride) {
+        const SrcZP<DIM, float> src{z, pold, (float)beta, o};
+        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock) {
             int iy, ix, iz;
             g.coords(nd, iy, ix, iz, DIM);
             float ap[DIM];
@@ -441,9 +464,9 @@ __device__ bool mixed_cg(Ctx& C, const Geo& g, const SolveArgs& A, const Op32& o
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
                 const int64_t i = DIM * nd + c;
-                const float pi = src(i);
+                const float pi = src(nd, c);
                 const float qi = fm[i] ? ap[c] : 0.0f;
-                st_dev(pnew + i, pi);
+                o.st(pnew, nd, i, pi);
                 q[i] = qi;
                 v1[0] += (double)pi * (double)qi;
             }
@@ -454,15 +477,15 @@ __device__ bool mixed_cg(Ctx& C, const Geo& g, const SolveArgs& A, const Op32& o
         const double alpha = rz / pq;
         const float af = (float)alpha;
         double v2[2] = {0.0, 0.0};
-        for (int64_t nd = i0; nd < g.nnode; nd += stride) {
+        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock) {
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
                 const int64_t i = DIM * nd + c;
-                st_dev(u + i, ld_dev(u + i) + alpha * (double)ld_dev(pnew + i));
+                o.st(u, nd, i, u[i] + alpha * (double)pnew[i]);
                 const float ri = r[i] - af * q[i];
                 const float zi = dinv[i] * ri;
                 r[i] = ri;
-                st_dev(z + i, zi);
+                o.st(z, nd, i, zi);
                 v2[0] += (double)ri * (double)zi;
                 v2[1] += (double)ri * (double)ri;
             }
@@ -507,23 +530,35 @@ template <int DIM, int MODE>
 __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs A) {
     __shared__ double sh[kWaves];
     __shared__ double res[4];
-    Ctx C{A.partial, GridBar{}, sh, res, 0, true};
+    Ctx C{A.partial, GridBar{}, sh, res, 0, true, Own{}};
     C.gb.init(A.bar);
+    {
+        // contiguous node range of this block; band = largest node-index
+        // distance between two nodes of one element
+        const int64_t nn = A.geo.nnode;
+        const int64_t chunk = (nn + gridDim.x - 1) / gridDim.x;
+        C.o.lo = min(nn, (int64_t)blockIdx.x * chunk);
+        C.o.hi = min(nn, C.o.lo + chunk);
+        C.o.band = DIM == 2 ? (int64_t)A.geo.ny + 2
+                            : (int64_t)(A.geo.ny + 1) * (A.geo.nz + 1) + A.geo.ny + 2;
+    }
+    const Own& o = C.o;
     const Geo& g = A.geo;
     const int64_t n = g.nnode * DIM;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double* u = A.u;
 
     // |f_free|, and u = 0 on fixed DOFs (or everywhere when asked)
     {
         double v[1] = {0.0};
-        for (int64_t i = i0; i < n; i += stride) {
-            const bool fr = A.freem[i] != 0;
-            if (!fr || A.zero_x0) st_dev(u + i, 0.0);
-            const double fi = fr ? A.f[i] : 0.0;
-            v[0] += fi * fi;
-        }
+        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const int64_t i = DIM * nd + c;
+                const bool fr = A.freem[i] != 0;
+                if (!fr || A.zero_x0) o.st(u, nd, i, 0.0);
+                const double fi = fr ? A.f[i] : 0.0;
+                v[0] += fi * fi;
+            }
         C.reduce<1>(v);
     }
     const double bnorm = sqrt(res[0]);
@@ -536,13 +571,12 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs A) {
         double *r = A.v64[0], *z = A.v64[1], *pa = A.v64[2], *pb = A.v64[3], *q = A.v64[4], *dinv = A.v64[5];
         if (MODE == 0) {
             CsrS<DIM, double> op{A.rp, (const double*)A.kval, g.nx, g.ny, g.nz};
-            jacobi<DIM, double>(op, g, A.freem, dinv);
+            jacobi<DIM, double>(op, g, C.o, A.freem, dinv);
             Pcg<DIM, double, CsrS<DIM, double>> cg{op, g, A.freem, C};
             iters = cg.run(A.f, u, false, dinv, r, z, pa, pb, q, tol, A.maxit, restarts);
         } else {
             if (A.kdiag32) {   // FP32 fields: Jacobi from the FP32 assembled diagonal
-                const int64_t stride = (int64_t)gridDim.x * kBlock;
-                for (int64_t nd = (int64_t)blockIdx.x * kBlock + threadIdx.x; nd < g.nnode; nd += stride)
+                for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock)
 #pragma unroll
                     for (int c = 0; c < DIM; ++c) {
                         const int64_t i = DIM * nd + c;
@@ -550,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs A) {
                         dinv[i] = A.freem[i] && dg != 0.0 ? 1.0 / dg : 0.0;
                     }
             } else {
-                jacobi<DIM, double>(mf64, g, A.freem, dinv);
+                jacobi<DIM, double>(mf64, g, C.o, A.freem, dinv);
             }
             Pcg<DIM, double, MatFree<DIM, double>> cg{mf64, g, A.freem, C};
             iters = cg.run(A.f, u, false, dinv, r, z, pa, pb, q, tol, A.maxit, restarts);
@@ -561,20 +595,22 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs A) {
         double* dinv64 = A.v64[5];
         CsrS<DIM, float> csr32{A.rp, (const float*)A.kval, g.nx, g.ny, g.nz};
         MatFree<DIM, float> mf32{A.E32, A.kf32, g.nx, g.ny, g.nz};
-        jacobi<DIM, double>(mf64, g, A.freem, dinv64);   // for the fallback
+        jacobi<DIM, double>(mf64, g, C.o, A.freem, dinv64);   // for the fallback
         bool converged = false;
         double* ubest = A.v64[6];
         if (MODE == 2) {
-            jacobi<DIM, float>(csr32, g, A.freem, A.v32[7]);
+            jacobi<DIM, float>(csr32, g, C.o, A.freem, A.v32[7]);
             converged = mixed_cg<DIM>(C, g, A, csr32, mf64, tol, iters, outer, resid, ubest);
         } else {
-            jacobi<DIM, float>(mf32, g, A.freem, A.v32[7]);
+            jacobi<DIM, float>(mf32, g, C.o, A.freem, A.v32[7]);
             converged = mixed_cg<DIM>(C, g, A, mf32, mf64, tol, iters, outer, resid, ubest);
         }
         if (!converged && C.alive) {
             fallback = 1;
             // restart from the iterate with the smallest FP64 residual
-            for (int64_t i = i0; i < n; i += stride) st_dev(u + i, ld_dev(ubest + i));
+            for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock)
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) o.st(u, nd, DIM * nd + c, ubest[DIM * nd + c]);
             C.alive = C.gb.sync() && C.alive;
             const int left = A.maxit - iters;
             Pcg<DIM, double, MatFree<DIM, double>> cg64{mf64, g, A.freem, C};
@@ -604,6 +640,7 @@ static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream
     int64_t want = (A.geo.nnode + kBlock - 1) / kBlock;
     int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, p->num_cu), want));
     if (req_blocks > 0) blocks = std::min(req_blocks, maxb);
+    blocks = std::min(blocks, 4 * kBlock);   // the grid reduction gathers at most 4 partials per thread
     void* args[] = {&A};
     TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(kBlock), args, 0, s));
     return TO_OK;
