@@ -41,30 +41,54 @@ def workloads_by_name():
     return out
 
 
-def stage_bytes(cfg, info, dt_bytes, cg_iters, op, precision):
-    """Algorithmic bytes per launch of each stage (each array the kernel must
-    touch counted once; caches not credited)."""
-    m, n, nnz, npairs, d = info.m, info.n, info.nnz_lower, info.n_pairs, info.d
+def solve_path(cfg, op, solve):
+    """Which solve kernel to_solve runs: (operator, vector precision)."""
+    f32 = cfg.precision == "f32"
+    mixed = f32 and solve == "mixed"
+    assembled = op == "assembled" and (not f32 or mixed)
+    return ("assembled" if assembled else "matfree"), ("f32" if mixed else "f64")
+
+
+def stage_bytes(cfg, info, dt_bytes, op, solve):
+    """Algorithmic bytes per launch of each stage: every array the kernel must
+    read or write counted once (no credit for caches, no charge for re-reads)."""
+    m, n, nnz, npairs = info.m, info.n, info.nnz_lower, info.n_pairs
     F = dt_bytes
-    nodes_per_elem = n / info.dim / m
     b = {}
-    b["filter"] = 2 * F * m + F * m                          # x in, xtilde out, Hs
-    b["project"] = (F * m) * 3 + F * m * 3 + m               # newton sweeps read xtilde; write xphys, dprj; codes
-    b["assemble"] = 4 * npairs + 4 * (nnz + 1) + F * nnz + 2 * F * m   # perm, seg_ptr, kval, moduli
-    b["sensitivity"] = 8 * n + F * m * 2 + m + 16 * n        # u gather, xphys, dc, codes, f.u
-    b["backfilter"] = 3 * F * m + F * m + 2 * F * m          # dc, dv, dprj, Hs in; 2 out
-    b["oc"] = F * m * 3 + 8 * m * 2 + F * m                  # x, dc, dv; ocP write/read; x out
-    # one CG iteration
-    if op == "matfree":
-        vec = (4 if precision == "f32" else 8)
-        spmv = F * m + 2 * vec * n + 2 * vec * n
-    else:
-        vec = (4 if precision == "f32" else 8)
-        spmv = F * (2 * nnz - n) + 4 * nnz + 8 * (nnz - n) + 8 * n + 2 * vec * n + 2 * vec * n
-    upd = 8 * n * 2 + vec * n * 6 + n
-    b["solve_per_iter"] = spmv + upd
-    b["solve"] = b["solve_per_iter"] * max(cg_iters, 1)
+    b["filter"] = F * m + F * m + F * m                       # x in, Hs in, xtilde out
+    b["project"] = F * m + 2 * F * m + m                      # xtilde in; xphys, dprj out; passive codes
+    b["assemble"] = 4 * npairs + 4 * (nnz + 1) + F * nnz + F * m   # perm, seg_ptr, kval out, xphys in
+    b["sensitivity"] = 8 * n + F * m * 2 + m + 8 * n          # u gather, xphys in, dc out, codes, f for f.u
+    b["backfilter"] = 3 * F * m + F * m + 2 * F * m           # dc, dv, dprj, Hs in; dc~, dv~ out
+    b["oc"] = F * m * 3 + m + F * m                           # x, dc~, dv~, codes in; x out
+    # one CG iteration of the kernel to_solve runs (vectors in node-major DOF order)
+    opk, vp = solve_path(cfg, op, solve)
+    V = 4 if vp == "f32" else 8
+    mat = (F * nnz + 4 * (n + 1)) if opk == "assembled" else V * m   # K^(s) values + row_ptr | moduli
+    phase_a = mat + 2 * V * n + 2 * V * n + n                 # z, p_old in; p_new, q out; free mask
+    phase_b = 5 * V * n + 3 * V * n                           # x, p, r, q, dinv in; x, r, z out
+    if vp == "f32":
+        phase_b += 2 * 4 * n                                  # the iterate u stays FP64
+    b["solve_per_iter"] = phase_a + phase_b
+    b["solve_kernel"] = {"operator": opk, "vectors": vp}
     return b
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per CG iteration from the committed counter summary, or None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    fn = os.path.join(ROOT, "profiles", "solve_kernel_traffic.json")
+    try:
+        rec = json.load(open(fn))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel") != kernel_key:
+        return None
+    src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in rec["sources"])
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_cg_iteration"]
 
 
 def cpu_baseline(cfg, budget_taps=1500):
@@ -137,6 +161,8 @@ def main():
     ap.add_argument("--op", default="assembled", choices=["assembled", "matfree"])
     ap.add_argument("--solve", default="auto", choices=["auto", "f64", "mixed"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this size once (a counter calibration kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (how it would shard is "
@@ -160,7 +186,9 @@ def main():
     print(f"[bench] {cfg.name} m={I.m} n={I.n} nnz_lower={I.nnz_lower} precision={cfg.precision} op={args.op}",
           file=sys.stderr, flush=True)
 
-    def timed_step(ev):
+    sst_hist = torch.zeros((max(args.steps, 1), g.sst.numel()), dtype=torch.uint8, device=g.sst.device)
+
+    def timed_step(ev, k=None):
         """One redesign iteration through the single-stage entry points (the
         same sequence to_step runs), with an event after each stage."""
         h, dt, st = g.plan.handle, g.dtype, g.state
@@ -170,7 +198,7 @@ def main():
         L.to_project(h, dt, cfg.ft, g.xtilde, g.x, g.xphys, g.dprj, st.beta, g.eta, cfg.volfrac,
                      g.xphys_old, g.pst)
         ev[2].record(stream)
-        if op == L.TO_OP_ASSEMBLED and (dt == L.TO_F64 or sp != L.TO_SOLVE_F64):
+        if op == L.TO_OP_ASSEMBLED:
             L.to_assemble(h, dt, g.xphys, st.penal, g.kval)
         ev[3].record(stream)
         L.to_solve(h, dt, g.kval, g.xphys, st.penal, g.f, g.u, g.params.solve, g.sst)
@@ -181,6 +209,8 @@ def main():
         ev[6].record(stream)
         L.to_oc_update(h, dt, g.x, g.dcf, g.dv0, cfg.volfrac, cfg.move, g.ost)
         ev[7].record(stream)
+        if k is not None:
+            sst_hist[k].copy_(g.sst, non_blocking=True)     # device-to-device, after the timed stages
         g.xphys_old.copy_(g.xphys)
         st.loop += 1
         st.penal = L.to_continuation(st.penal, g.params.penal_sched, st.loop)
@@ -192,65 +222,72 @@ def main():
     print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
 
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(8)] for _ in range(args.steps)]
-    cg_iters = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        timed_step(evs[k])
+        timed_step(evs[k], k)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    K = args.steps
     stage_ms = {s: 0.0 for s in STAGES}
-    for k in range(args.steps):
+    solve_launch_ms = []
+    for k in range(K):
         for j, s in enumerate(STAGES):
             stage_ms[s] += evs[k][j].elapsed_time(evs[k][j + 1])
+        solve_launch_ms.append(evs[k][3].elapsed_time(evs[k][4]))
+    hist = sst_hist.cpu().numpy()
+    solve_stats = [L.SolveStats.from_buffer_copy(hist[k].tobytes()) for k in range(K)]
+    iters = [s.iterations for s in solve_stats]
     last = g.stats()
-    print(f"[bench] timed {args.steps} steps in {wall:.3f} s; last: {json.dumps(last)}", file=sys.stderr,
-          flush=True)
+    print(f"[bench] timed {K} steps in {wall:.3f} s; cg iterations per step {iters}; last: {json.dumps(last)}",
+          file=sys.stderr, flush=True)
 
-    # solve iterations of the timed steps: re-run the same steps' count from the stats of each
-    # step would need a sync per step; take the average from one extra synchronised pass below
-    K = args.steps
     non_solve_s = sum(stage_ms[s] for s in NON_SOLVE) / 1e3
     value = I.m * K / non_solve_s
     ms_per_step = wall * 1e3 / K
-
-    # per-launch solve statistics from a few extra synchronised steps
-    iters = []
-    solve_ms = []
-    for _ in range(3):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
-        timed_step(ev)
-        torch.cuda.synchronize()
-        s = read_struct(g.sst, L.SolveStats)
-        iters.append(s.iterations)
-        solve_ms.append(ev[3].elapsed_time(ev[4]))
     dt_bytes = 8 if cfg.precision == "f64" else 4
-    sb = stage_bytes(cfg, I, dt_bytes, 1, args.op, cfg.precision)
+    sb = stage_bytes(cfg, I, dt_bytes, args.op, args.solve)
     avg_ms = {s: stage_ms[s] / K for s in STAGES}
     gbps = {s: sb[s] / (avg_ms[s] * 1e-3) / 1e9 for s in NON_SOLVE}
-    per_iter_us = 1e3 * sum(solve_ms) / max(sum(iters), 1)
-    solve_gbps = sb["solve_per_iter"] / (per_iter_us * 1e-6) / 1e9
-    # dominant kernel: the solve (persistent CG kernel), bytes per launch = iterations x bytes/iter
-    avg_iters = sum(iters) / len(iters)
-    roof = {"kernel": "solve_kernel (persistent Jacobi-PCG)", "bound": "hbm",
-            "achieved": round(solve_gbps, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-            "frac": round(solve_gbps * 1e9 / HBM_PEAK, 4), "traffic": None,
-            "bytes_per_cg_iteration": int(sb["solve_per_iter"]), "cg_iterations_per_launch": avg_iters,
-            "us_per_cg_iteration": round(per_iter_us, 2)}
+    # dominant kernel: the persistent PCG kernel (one launch per step); algorithmic bytes per
+    # launch = bytes per CG iteration x the launch's iterations, over the launch's event time
+    solve_bytes = sum(sb["solve_per_iter"] * it for it in iters)
+    solve_s = sum(solve_launch_ms) / 1e3
+    solve_gbps = solve_bytes / solve_s / 1e9
+    per_iter_us = 1e6 * solve_s / max(sum(iters), 1)
+    kern = sb["solve_kernel"]
+    tpi = measured_traffic("solve_kernel<2, 1>") if (I.dim == 2 and kern["operator"] == "matfree"
+                                                     and kern["vectors"] == "f64") else None
+    traffic = None if tpi is None else round(tpi * sum(iters) / K)
+    roof = {"kernel": f"solve_kernel ({kern['operator']} operator, {kern['vectors']} vectors)",
+            "bound": "hbm", "achieved": round(solve_gbps, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": round(solve_gbps * 1e9 / HBM_PEAK, 4), "traffic": traffic,
+            "avg_launch_ms": round(1e3 * solve_s / K, 3), "bytes_per_cg_iteration": int(sb["solve_per_iter"]),
+            "cg_iterations_per_launch": round(sum(iters) / K, 1), "us_per_cg_iteration": round(per_iter_us, 2)}
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "elem/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 fields + f64 solve" if cfg.precision == "f32" else "f64",
+        "dtype": "f32" if cfg.precision == "f32" else "f64",
         "data": "synthetic", "config": {"workload": cfg.name, "elements": I.m, "dofs": I.n, "rmin": cfg.rmin,
                                         "precision": cfg.precision, "operator": args.op, "solve": args.solve,
+                                        "solve_vectors": "f64" if kern["vectors"] == "f64" else "f32+f64",
                                         "iterations_timed": f"{args.warmup + 1}-{args.warmup + K}"},
         "to_iters_per_s": round(1e3 / ms_per_step, 3),
         "stage_ms_per_step": {s: round(v, 4) for s, v in avg_ms.items()},
         "stage_gbps": {s: round(v, 1) for s, v in gbps.items()},
+        "stage_hbm_frac": {s: round(v * 1e9 / HBM_PEAK, 4) for s, v in gbps.items()},
         "roofline": roof,
     }
+    if args.copy_probe_mib > 0:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=g.sst.device)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_probe_bytes"] = nb
+        del src, dst
     if not args.no_cpu:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(cfg)
