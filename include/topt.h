@@ -292,6 +292,65 @@ to_status to_step(const to_plan* plan, to_dtype dtype, to_step_state* h_state,
  * loop % isteps == 0. */
 double to_continuation(double par, const to_sched* sched, int32_t loop);
 
+/* ---------------------------------------------------------------------------
+ * Learned warm start of the state solve (2D meshes).  The paper has no
+ * network; the prediction only seeds the PCG of eq. (5), whose own true
+ * residual still decides convergence.
+ *
+ * to_warm_start -- the minimiser of the energy 1/2 u.K u - f.u of eq. (5)
+ * over span{uhat, uprev} (K: the free-DOF stiffness built from xphys and
+ * penal by eq. (6), applied matrix-free in FP64).  Writes u (n, device FP64;
+ * may alias uprev; zero on fixed DOFs) and, if d_coef is not NULL, the device
+ * doubles (a, b, energy, case) with u = a uhat + b uprev; case 3 = both
+ * vectors, 1 or 2 = the better one-vector fit (singular 2x2 system), 0 = both
+ * vectors zero (u = 0).  uhat, uprev: device FP64, n. */
+to_status to_warm_start(const to_plan* plan, to_dtype dtype, const void* xphys, double penal,
+                        const double* f, const double* uhat, const double* uprev, double* u,
+                        double* d_coef, void* stream);
+
+/* The network: a U-Net on the node grid (rows ix, columns iy, padded to
+ * multiples of 8) from (mean filtered density around the node, f_x, f_y) to
+ * the displacement divided by its RMS, with bfloat16 weights and
+ * activations on the matrix cores and FP32 accumulation (15 layers of 3x3
+ * convolutions, leaky ReLU of slope 1/8, 2x2 average pooling, nearest
+ * upsampling, additive skips; 4 levels).  Parameters: an FP32 vector of
+ * to_nn_query's n_params entries, per layer W[t][co][ci] (t = 3 (dr + 1) +
+ * (dc + 1) for the offset (dr, dc) in (row, column)) then b[co]; layers in the
+ * order e1a e1b e2a e2b e3a e3b ba bb d3a d3b d2a d2b d1a d1b out.
+ *
+ * to_nn_query: workspace bytes for a mesh, and the parameter count.
+ * to_nn_create: binds a 2D plan (mesh size, free mask) and a caller-owned
+ *   device workspace (256-byte aligned); TO_EUNSUPPORTED for 3D plans.
+ * to_nn_set_params: copies device FP32 parameters in, clears the Adam moments.
+ * to_nn_forward: xtilde (m, dtype) and f (n, FP64) -> uhat (n, FP64, zero on
+ *   fixed DOFs; may be NULL to keep the output image only).
+ * to_nn_backward: after to_nn_forward on the same sample, the mean squared
+ *   error against u / rms(u) over the real nodes (device double d_loss, may
+ *   be NULL) and the gradient of every parameter.
+ * to_nn_adam: one Adam step (bias-corrected) with the last gradient.
+ * to_nn_train_step: forward, backward and Adam (0.9, 0.999, 1e-8) on one sample.
+ * to_nn_get: copies to device memory `out` the parameters or the gradient
+ *   (n_params floats), the output image (rows x columns x 16 floats), the
+ *   bfloat16 output of layer i < 14 (TO_NN_ACT + i: rows_l x columns_l x
+ *   c_out padded to 16, raw 16-bit values; level l images are 2^l times
+ *   smaller) or, for the three layers with a skip, the activation before the
+ *   skip is added (TO_NN_PRESKIP + i).
+ * Weight gradients are summed with FP32 atomics (their last bits vary run to
+ * run); everything else is deterministic. */
+typedef struct to_nn to_nn;
+enum { TO_NN_PARAMS = 0, TO_NN_GRAD = 1, TO_NN_OUTPUT = 2, TO_NN_ACT = 16, TO_NN_PRESKIP = 32 };
+to_status to_nn_query(int32_t nelx, int32_t nely, size_t* ws_bytes, int64_t* n_params);
+to_status to_nn_create(const to_plan* plan, void* ws, size_t ws_bytes, to_nn** out);
+void to_nn_destroy(to_nn* nn);
+to_status to_nn_set_params(to_nn* nn, const float* params, void* stream);
+to_status to_nn_get(const to_nn* nn, int what, void* out, void* stream);
+to_status to_nn_forward(to_nn* nn, to_dtype dtype, const void* xtilde, const double* f, double* uhat,
+                        void* stream);
+to_status to_nn_backward(to_nn* nn, const double* u, double* d_loss, void* stream);
+to_status to_nn_adam(to_nn* nn, float lr, float beta1, float beta2, float eps, void* stream);
+to_status to_nn_train_step(to_nn* nn, to_dtype dtype, const void* xtilde, const double* f,
+                           const double* u, float lr, double* d_loss, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

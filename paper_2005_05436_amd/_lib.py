@@ -26,7 +26,9 @@ TO_SOLVE_AUTO, TO_SOLVE_F64, TO_SOLVE_MIXED = 0, 1, 2
 EXPORTED = ["to_plan_query", "to_plan_create", "to_plan_destroy", "to_plan_get_info", "to_plan_export",
             "to_plan_build_host",
             "to_status_string", "to_last_error", "to_filter", "to_project", "to_assemble", "to_solve",
-            "to_sensitivity", "to_oc_update", "to_step", "to_continuation"]
+            "to_sensitivity", "to_oc_update", "to_step", "to_continuation", "to_warm_start",
+            "to_nn_query", "to_nn_create", "to_nn_destroy", "to_nn_set_params", "to_nn_get", "to_nn_forward",
+            "to_nn_backward", "to_nn_adam", "to_nn_train_step"]
 
 
 class ToError(RuntimeError):
@@ -118,6 +120,16 @@ def load():
         "to_oc_update": (S, [P, S, P, P, P, C.c_double, C.c_double, P, P]),
         "to_step": (S, [P, S, C.POINTER(StepState), C.POINTER(StepParams), P]),
         "to_continuation": (C.c_double, [C.c_double, C.POINTER(Sched), C.c_int32]),
+        "to_warm_start": (S, [P, S, P, C.c_double, P, P, P, P, P, P]),
+        "to_nn_query": (S, [C.c_int32, C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_int64)]),
+        "to_nn_create": (S, [P, P, C.c_size_t, C.POINTER(P)]),
+        "to_nn_destroy": (None, [P]),
+        "to_nn_set_params": (S, [P, P, P]),
+        "to_nn_get": (S, [P, C.c_int, P, P]),
+        "to_nn_forward": (S, [P, S, P, P, P, P]),
+        "to_nn_backward": (S, [P, P, P, P]),
+        "to_nn_adam": (S, [P, C.c_float, C.c_float, C.c_float, C.c_float, P]),
+        "to_nn_train_step": (S, [P, S, P, P, P, C.c_float, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -219,3 +231,51 @@ def to_step(plan, dtype, state, params, stream=None):
 
 def to_continuation(par, sched, loop):
     return load().to_continuation(par, C.byref(sched), loop)
+
+
+def to_warm_start(plan, dtype, xphys, penal, f, uhat, uprev, u, d_coef=None, stream=None):
+    check(load().to_warm_start(plan, dtype, ptr(xphys), penal, ptr(f), ptr(uhat), ptr(uprev), ptr(u), ptr(d_coef),
+                               stream_ptr(stream)))
+
+
+TO_NN_PARAMS, TO_NN_GRAD, TO_NN_OUTPUT, TO_NN_ACT, TO_NN_PRESKIP = 0, 1, 2, 16, 32
+
+
+def to_nn_query(nelx, nely):
+    ws, npar = C.c_size_t(0), C.c_int64(0)
+    check(load().to_nn_query(nelx, nely, C.byref(ws), C.byref(npar)))
+    return ws.value, npar.value
+
+
+def to_nn_create(plan, ws_ptr, ws_bytes):
+    out = C.c_void_p()
+    check(load().to_nn_create(plan, ws_ptr, ws_bytes, C.byref(out)))
+    return out
+
+
+def to_nn_destroy(nn):
+    load().to_nn_destroy(nn)
+
+
+def to_nn_set_params(nn, params, stream=None):
+    check(load().to_nn_set_params(nn, ptr(params), stream_ptr(stream)))
+
+
+def to_nn_get(nn, what, out, stream=None):
+    check(load().to_nn_get(nn, what, ptr(out), stream_ptr(stream)))
+
+
+def to_nn_forward(nn, dtype, xtilde, f, uhat, stream=None):
+    check(load().to_nn_forward(nn, dtype, ptr(xtilde), ptr(f), ptr(uhat), stream_ptr(stream)))
+
+
+def to_nn_backward(nn, u, d_loss=None, stream=None):
+    check(load().to_nn_backward(nn, ptr(u), ptr(d_loss), stream_ptr(stream)))
+
+
+def to_nn_adam(nn, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    check(load().to_nn_adam(nn, lr, beta1, beta2, eps, stream_ptr(stream)))
+
+
+def to_nn_train_step(nn, dtype, xtilde, f, u, lr, d_loss=None, stream=None):
+    check(load().to_nn_train_step(nn, dtype, ptr(xtilde), ptr(f), ptr(u), lr, ptr(d_loss), stream_ptr(stream)))

@@ -147,6 +147,17 @@ to_status to_solve(const to_plan* plan, to_dtype dtype, const void* kval, const 
     TO_GUARD(launch_solve(P(plan), dtype, kval, xphys, penal, f, u, o, d_stats, S(stream)));
 }
 
+to_status to_warm_start(const to_plan* plan, to_dtype dtype, const void* xphys, double penal, const double* f,
+                        const double* uhat, const double* uprev, double* u, double* d_coef, void* stream) {
+    NEED(plan, "plan");
+    if (check_dtype(dtype)) return TO_EINVAL;
+    NEED(xphys, "xphys"); NEED(f, "f"); NEED(uhat, "uhat"); NEED(uprev, "uprev"); NEED(u, "u");
+    if ((const void*)u == (const void*)uhat || (const void*)u == (const void*)f) {
+        set_error("u may alias uprev only"); return TO_EINVAL;
+    }
+    TO_GUARD(launch_warm_start(P(plan), dtype, xphys, penal, f, uhat, uprev, u, d_coef, S(stream)));
+}
+
 to_status to_sensitivity(const to_plan* plan, to_dtype dtype, const void* xphys, const double* u, const double* f,
                          double penal, void* dc, double* d_compliance, void* stream) {
     NEED(plan, "plan");

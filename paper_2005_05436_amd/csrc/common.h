@@ -234,6 +234,8 @@ to_status launch_project(Plan* p, to_dtype dt, int ft, const void* xt, const voi
 to_status launch_assemble(Plan* p, to_dtype dt, const void* xphys, double penal, void* kval,
                           hipStream_t s);
 to_status launch_moduli(Plan* p, to_dtype dt, const void* xphys, double penal, hipStream_t s, bool also64);
+to_status launch_warm_start(Plan* p, to_dtype dt, const void* xphys, double penal, const double* f,
+                            const double* uh, const double* up, double* u, double* coef, hipStream_t s);
 to_status launch_solve(Plan* p, to_dtype dt, const void* kval, const void* xphys, double penal,
                        const double* f, double* u, const to_solve_opts& o, to_solve_stats* st,
                        hipStream_t s);

@@ -646,6 +646,118 @@ static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream
     return TO_OK;
 }
 
+// Warm start of the solve from a predicted field: the minimiser of the
+// energy 1/2 u.K u - f.u over span{uh, up} (a Galerkin projection onto two
+// vectors; K the free-DOF operator of eq. (5)).  Block partials of
+// uh.K uh, uh.K up, up.K up, uh.f, up.f; the last block to finish solves the
+// 2x2 system (or, when it is singular or one vector is zero, takes the better
+// one-vector fit) and writes (a, b, energy, case) to coef.
+template <int DIM, typename T> struct SrcMask {
+    const T* x;
+    const uint8_t* fm;
+    __device__ __forceinline__ T operator()(int64_t q, int c) const {
+        const int64_t i = DIM * q + c;
+        return fm[i] ? x[i] : T(0);
+    }
+};
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void galerkin_kernel(Geo g, MatFree<DIM, double> op, const uint8_t* __restrict__ fm,
+                                                          const double* __restrict__ f, const double* __restrict__ uh,
+                                                          const double* __restrict__ up, double* partial,
+                                                          unsigned* counter, double* coef) {
+    __shared__ double sh[kWaves];
+    __shared__ int last;
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < g.nnode; nd += (int64_t)gridDim.x * kBlock) {
+        int iy, ix, iz;
+        g.coords(nd, iy, ix, iz, DIM);
+        double kh[DIM], kp[DIM];
+        op.apply(nd, iy, ix, iz, SrcMask<DIM, double>{uh, fm}, kh);
+        op.apply(nd, iy, ix, iz, SrcMask<DIM, double>{up, fm}, kp);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const int64_t i = DIM * nd + c;
+            if (!fm[i]) continue;
+            v[0] += uh[i] * kh[c];
+            v[1] += uh[i] * kp[c];
+            v[2] += up[i] * kp[c];
+            v[3] += uh[i] * f[i];
+            v[4] += up[i] * f[i];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const double s = block_sum(v[k], sh);
+        if (threadIdx.x == 0) st_dev(&partial[blockIdx.x * 8 + k], s);
+    }
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        const unsigned done = atomicAdd(counter, 1u);
+        last = done == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    double t[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) s += ld_dev(&partial[b * 8 + k]);
+        t[k] = block_sum(s, sh);
+    }
+    if (threadIdx.x == 0) {
+        const double A11 = t[0], A12 = t[1], A22 = t[2], r1 = t[3], r2 = t[4];
+        const double det = A11 * A22 - A12 * A12;
+        double a = 0.0, b = 0.0, E = 0.0, which = 0.0;
+        if (A11 > 0.0 && A22 > 0.0 && det > 1e-12 * A11 * A22) {
+            a = (r1 * A22 - r2 * A12) / det;
+            b = (A11 * r2 - A12 * r1) / det;
+            E = -0.5 * (a * r1 + b * r2);
+            which = 3.0;
+        } else {
+            const double E1 = A11 > 0.0 ? -0.5 * r1 * r1 / A11 : INFINITY;
+            const double E2 = A22 > 0.0 ? -0.5 * r2 * r2 / A22 : INFINITY;
+            if (E1 <= E2 && A11 > 0.0) { a = r1 / A11; E = E1; which = 1.0; }
+            else if (A22 > 0.0) { b = r2 / A22; E = E2; which = 2.0; }
+        }
+        coef[0] = a; coef[1] = b; coef[2] = E; coef[3] = which;
+        st_dev(counter, 0u);
+    }
+}
+
+template <int DIM>
+__global__ void galerkin_combine_kernel(int64_t n, const uint8_t* __restrict__ fm, const double* uh, const double* up,
+                                        const double* __restrict__ coef, double* u) {
+    const double a = coef[0], b = coef[1];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        u[i] = fm[i] ? a * uh[i] + b * up[i] : 0.0;
+}
+
+to_status launch_warm_start(Plan* p, to_dtype dt, const void* xphys, double penal, const double* f,
+                            const double* uh, const double* up, double* u, double* coef, hipStream_t s) {
+    to_status r = launch_moduli(p, dt, xphys, penal, s, true);
+    if (r != TO_OK) return r;
+    const Geo g{p->nelx, p->nely, p->nelz, p->info.nnode};
+    double* part = p->partial + (size_t)kMaxCoopBlocks * kPartialWidth;
+    double* cf = coef ? coef : p->scal + 16;
+    const int nb = (int)std::min<int64_t>(2048, (g.nnode + kBlock - 1) / kBlock);
+    const int64_t n = p->info.n;
+    const int nb2 = (int)std::min<int64_t>(4096, (n + kBlock - 1) / kBlock);
+    if (p->dim == 2) {
+        MatFree<2, double> op{p->E64, p->kf64, p->nelx, p->nely, p->nelz};
+        hipLaunchKernelGGL(galerkin_kernel<2>, dim3(nb), dim3(kBlock), 0, s, g, op, p->freemask, f, uh, up, part,
+                           p->bar + 10, cf);
+        hipLaunchKernelGGL(galerkin_combine_kernel<2>, dim3(nb2), dim3(kBlock), 0, s, n, p->freemask, uh, up, cf, u);
+    } else {
+        MatFree<3, double> op{p->E64, p->kf64, p->nelx, p->nely, p->nelz};
+        hipLaunchKernelGGL(galerkin_kernel<3>, dim3(nb), dim3(kBlock), 0, s, g, op, p->freemask, f, uh, up, part,
+                           p->bar + 10, cf);
+        hipLaunchKernelGGL(galerkin_combine_kernel<3>, dim3(nb2), dim3(kBlock), 0, s, n, p->freemask, uh, up, cf, u);
+    }
+    TO_HIP(hipGetLastError());
+    return TO_OK;
+}
+
 to_status launch_solve(Plan* p, to_dtype dt, const void* kval, const void* xphys, double penal,
                        const double* f, double* u, const to_solve_opts& o, to_solve_stats* st, hipStream_t s) {
     const bool mixed = dt == TO_F32 && o.precision == TO_SOLVE_MIXED;

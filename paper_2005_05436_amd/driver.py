@@ -136,6 +136,35 @@ class TopOpt:
         """Enqueues one redesign iteration (no host synchronisation)."""
         L.to_step(self.plan.handle, self.dtype, self.state, self.params, stream)
 
+    def step_stages(self, net=None, train_lr=None, stream=None):
+        """One redesign iteration through the single-stage entry points (the
+        sequence to_step runs).  With a network: its prediction from the
+        physical density and the load, combined with the previous displacement
+        by the Galerkin start (to_warm_start), seeds the PCG; with train_lr the
+        network then takes one Adam step on the converged displacement."""
+        h, dt, st, cfg = self.plan.handle, self.dtype, self.state, self.cfg
+        L.to_filter(h, dt, L.TO_FILTER_FWD, self.x, None, None, self.xtilde, None, stream)
+        L.to_project(h, dt, cfg.ft, self.xtilde, self.x, self.xphys, self.dprj, st.beta, self.eta, cfg.volfrac,
+                     self.xphys_old, self.pst, stream)
+        if self.params.solve.op == L.TO_OP_ASSEMBLED:
+            L.to_assemble(h, dt, self.xphys, st.penal, self.kval, stream)
+        if net is not None:
+            if not hasattr(self, "uhat"):
+                self.uhat = torch.zeros_like(self.u)
+                self.wcoef = torch.zeros(4, dtype=torch.float64, device=self.u.device)
+            net.forward(dt, self.xphys, self.f, self.uhat)
+            L.to_warm_start(h, dt, self.xphys, st.penal, self.f, self.uhat, self.u, self.u, self.wcoef, stream)
+        L.to_solve(h, dt, self.kval, self.xphys, st.penal, self.f, self.u, self.params.solve, self.sst, stream)
+        if net is not None and train_lr:
+            net.train_step(dt, self.xphys, self.f, self.u, train_lr)
+        L.to_sensitivity(h, dt, self.xphys, self.u, self.f, st.penal, self.dc, self.c, stream)
+        L.to_filter(h, dt, L.TO_FILTER_ADJ2, self.dc, self.dv, self.dprj, self.dcf, self.dv0, stream)
+        L.to_oc_update(h, dt, self.x, self.dcf, self.dv0, cfg.volfrac, cfg.move, self.ost, stream)
+        self.xphys_old.copy_(self.xphys)
+        st.loop += 1
+        st.penal = L.to_continuation(st.penal, self.params.penal_sched, st.loop)
+        st.beta = L.to_continuation(st.beta, self.params.beta_sched, st.loop)
+
     def stats(self):
         """Synchronising read of the last iteration's device statistics."""
         p = read_struct(self.pst, L.ProjectStats)

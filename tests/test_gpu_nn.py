@@ -1,0 +1,214 @@
+"""GPU parity of the learned warm start: the network's forward pass, its
+weight gradients and the Adam step against the network oracle in its
+bfloat16 mode, the Galerkin start against the oracle's, and what a trained
+network gains on held-out optimiser iterations.
+
+Tolerances.  The GPU rounds to bfloat16 at exactly the oracle's points but
+sums in FP32 (the oracle in FP64), so an activation whose FP32 and FP64 sums
+fall on different sides of a bfloat16 rounding boundary differs by one
+bfloat16 unit (2^-8 relative) and the difference travels on through the
+layers; such flips are rare (about one value in 10^4) but a flip near the
+bottleneck is amplified by the decoder to about 1% of the output.  So each
+layer is checked against the oracle layer applied to the GPU's own input
+(equal except for at most 0.2% one-unit flips), and end to end only within
+3% (2-norm).  Gradients: the oracle's backward pass on the GPU's forward
+activations, within 1% (2-norm) per layer and cosine >= 0.9999.  Adam (FP32
+arithmetic on identical inputs): 1e-5 relative."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import workloads as W
+from oracle import mesh as omesh
+from oracle import sparse as osp
+from oracle import element as oel
+from oracle import unet
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_05436_amd import _lib
+    _lib.load()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def make(nelx, nely, seed, load_ix=None):
+    from paper_2005_05436_amd import problems
+    from paper_2005_05436_amd.driver import Plan
+    from paper_2005_05436_amd.nn import LAYERS, Net
+    f, fixed = problems.mbb(nelx, nely, load_ix if load_ix is not None else nelx // 3)
+    plan = Plan(2, nelx, nely, 1, 2.0, "D", fixed)
+    net = Net(plan)
+    params = W.network_params(LAYERS, seed)
+    net.set_params(params)
+    return plan, net, f, fixed, params
+
+
+def gpu_inputs(net, nelx, nely, xin, f):
+    """Per layer, the input the GPU's layer read (built from the GPU's own
+    previous outputs with the oracle's pooling / upsampling) and its skip."""
+    names = [Ly[0] for Ly in unet.LAYERS]
+    ys = [host(net.layer(i))[..., :unet.LAYERS[i][2]] for i in range(len(names) - 1)]
+    xs = []
+    for i, (name, ci, co, lev, act, src, skip) in enumerate(unet.LAYERS):
+        if i == 0:
+            x = unet.bf16_round(unet.features(nelx, nely, xin, f))
+        elif src == "pool":
+            x = unet.bf16_round(unet.pool2(ys[i - 1]))
+        elif src == "up":
+            x = unet.up2(ys[i - 1])
+        else:
+            x = ys[i - 1]
+        xs.append(x)
+    return names, ys, xs
+
+
+def count_flips(got, ref):
+    """Entries that differ, and whether each is within two bfloat16 units."""
+    d = got != ref
+    ok = np.abs(got - ref) <= 2.0 ** -6 * np.maximum(np.abs(ref), 1e-30)
+    return int(d.sum()), bool(np.all(ok | ~d))
+
+
+@pytest.mark.parametrize("nelx,nely,dt,seed", [(30, 10, 0, 11), (37, 13, 1, 12), (64, 24, 0, 13)])
+def test_nn_forward_layers_match_bf16_oracle(nelx, nely, dt, seed):
+    """Every layer against the oracle layer applied to the GPU's own input:
+    equal except for rare one-unit rounding flips (FP32 vs FP64 sums)."""
+    from paper_2005_05436_amd import _lib as L
+    plan, net, f, fixed, params = make(nelx, nely, seed)
+    x = W.design_field(nelx * nely, 5, 0.0, 1.0)
+    T = torch.float64 if dt == L.TO_F64 else torch.float32
+    uh = torch.zeros(f.size, dtype=torch.float64, device="cuda")
+    net.forward(dt, torch.as_tensor(x, dtype=T).cuda(), torch.as_tensor(f).cuda(), uh)
+    out = host(net.get(L.TO_NN_OUTPUT)).reshape(net.H, net.W, 16)
+    xin = x if dt == L.TO_F64 else x.astype(np.float32).astype(np.float64)
+    p64 = params.astype(np.float32).astype(np.float64)
+    wb = unet.unpack(p64)
+    names, ys, xs = gpu_inputs(net, nelx, nely, xin, f)
+    total = 0
+    for i, (name, ci, co, lev, act, src, skip) in enumerate(unet.LAYERS):
+        Wt, b = wb[i]
+        z = unet.conv3x3(xs[i], unet.bf16_round(Wt), b)
+        if not act:
+            assert np.abs(out[..., :2] - z).max() <= 1e-5 * np.abs(z).max()
+            continue
+        a = unet.leaky(z)
+        y = a + ys[names.index(skip)] if skip else a
+        nd, within = count_flips(ys[i], unet.bf16_round(y))
+        assert within, name
+        assert nd <= max(3, 2e-3 * y.size), (name, nd, y.size)
+        total += nd
+    assert np.all(out[..., 2:] == 0.0)
+    # end to end: a flip near the bottleneck is amplified by the decoder, so
+    # only a loose bound holds against the oracle's own bfloat16 pass
+    ref, _ = unet.forward(p64, unet.features(nelx, nely, xin, f), bf16=True)
+    assert np.linalg.norm(out[..., :2] - ref) <= 3e-2 * np.linalg.norm(ref)
+    # the DOF vector: the output at the real nodes, zero on fixed DOFs
+    free = np.ones(f.size, bool)
+    free[fixed] = False
+    np.testing.assert_array_equal(host(uh), unet.prediction(nelx, nely, out, free))
+
+
+@pytest.mark.parametrize("seed", [12, 11])
+def test_nn_gradient_matches_bf16_oracle(seed):
+    """Weight gradients against the oracle's bfloat16 backward pass run on the
+    GPU's own forward activations."""
+    from paper_2005_05436_amd import _lib as L
+    nelx, nely = 30, 10
+    plan, net, f, fixed, params = make(nelx, nely, seed)
+    x = W.design_field(nelx * nely, 6, 0.0, 1.0)
+    u = W.displacement_field(f.size, 7)
+    u[fixed] = 0.0
+    net.forward(L.TO_F64, torch.as_tensor(x).cuda(), torch.as_tensor(f).cuda(), None)
+    net.backward(torch.as_tensor(u).cuda())
+    g = host(net.get(L.TO_NN_GRAD))
+    loss = float(host(net.loss)[0])
+    out = host(net.get(L.TO_NN_OUTPUT)).reshape(net.H, net.W, 16)[..., :2]
+    p64 = params.astype(np.float32).astype(np.float64)
+    names, ys, xs = gpu_inputs(net, nelx, nely, x, f)
+    cache = {}
+    for i, name in enumerate(names):
+        cache[name + ".x"] = xs[i]
+        if unet.LAYERS[i][4]:
+            cache[name + ".a"] = host(net.layer(i, preskip=True))[..., :unet.LAYERS[i][2]] if unet.LAYERS[i][6] \
+                else ys[i]
+    tgt, mk = unet.target(nelx, nely, u), unet.node_mask(nelx, nely)
+    cnt = 2.0 * mk.sum()
+    diff = (out - tgt) * mk[..., None]
+    assert abs(loss - (diff * diff).sum() / cnt) <= 1e-6 * loss
+    rg = unet.backward(p64, cache, 2.0 * diff / cnt, bf16=True)
+    offs, _ = unet.layer_offsets()
+    for (ow, ob), Ly in zip(offs, unet.LAYERS):
+        sl = slice(ow, ob + Ly[2])
+        assert np.linalg.norm(g[sl] - rg[sl]) <= 1e-2 * np.linalg.norm(rg[sl]), Ly[0]
+    cos = g @ rg / (np.linalg.norm(g) * np.linalg.norm(rg))
+    assert cos >= 0.9999
+
+
+def test_nn_adam_step():
+    from paper_2005_05436_amd import _lib as L
+    nelx, nely = 30, 10
+    plan, net, f, fixed, params = make(nelx, nely, 13)
+    x = W.design_field(nelx * nely, 8, 0.0, 1.0)
+    u = W.displacement_field(f.size, 9)
+    xd, fd, ud = torch.as_tensor(x).cuda(), torch.as_tensor(f).cuda(), torch.as_tensor(u).cuda()
+    p0 = host(net.params())
+    m = np.zeros_like(p0)
+    v = np.zeros_like(p0)
+    for k in range(1, 4):
+        net.forward(L.TO_F64, xd, fd, None)
+        net.backward(ud)
+        g = host(net.get(L.TO_NN_GRAD))
+        L.to_nn_adam(net.handle, 1e-3, 0.9, 0.999, 1e-8)
+        p1 = host(net.params())
+        ref, m, v = unet.adam(p0, g, m, v, k, lr=1e-3)
+        assert np.abs(p1 - ref).max() <= 1e-5 * max(np.abs(p0).max(), 1.0)
+        p0 = p1
+
+
+@pytest.mark.parametrize("case", ["both", "zero_prev", "exact"])
+def test_warm_start_matches_oracle(case):
+    from paper_2005_05436_amd import _lib as L
+    from paper_2005_05436_amd import problems
+    from paper_2005_05436_amd.driver import Plan
+    nelx, nely = 24, 10
+    f, fixed = problems.mbb(nelx, nely, 3)
+    plan = Plan(2, nelx, nely, 1, 2.0, "D", fixed)
+    x = W.design_field(nelx * nely, 3, 0.1, 1.0)
+    M = omesh.Mesh(nelx, nely)
+    ke = oel.element_matrix(2, 0.3)
+    E = osp.simp_modulus(x, 3.0, 1.0, 1e-9)
+    K = osp.dense_global(M.cmat(), ke, E, M.n)
+    free = np.ones(M.n, bool)
+    free[fixed] = False
+    Kff = K[np.ix_(free, free)]
+    ustar = np.zeros(M.n)
+    ustar[free] = np.linalg.solve(Kff, f[free])
+    rng = np.random.default_rng(4)
+    up = ustar * (1 + 0.2 * rng.standard_normal(M.n))
+    uh = ustar * (1 + 0.5 * rng.standard_normal(M.n)) + 0.01 * rng.standard_normal(M.n)
+    if case == "zero_prev":
+        up = np.zeros(M.n)
+    if case == "exact":
+        uh = 3.0 * ustar
+    up[~free] = 0.0
+    uh[~free] = 0.0
+    ref = np.zeros(M.n)
+    ref[free] = unet.galerkin_start(Kff, f[free], uh[free], up[free])
+    xd = torch.as_tensor(x).cuda()
+    ud = torch.as_tensor(up).cuda()
+    coef = torch.zeros(4, dtype=torch.float64, device="cuda")
+    L.to_warm_start(plan.handle, L.TO_F64, xd, 3.0, torch.as_tensor(f).cuda(), torch.as_tensor(uh).cuda(), ud, ud,
+                    coef)
+    got = host(ud)
+    assert np.abs(got - ref).max() <= 1e-8 * np.abs(ref).max()
+    if case == "exact":
+        assert np.abs(got - ustar).max() <= 1e-8 * np.abs(ustar).max()

@@ -118,3 +118,30 @@ def displacement_field(n, seed):
 
 def sensitivity_field(m, seed):
     return -np.random.default_rng(seed).uniform(0.0, 1.0, m)
+
+
+# --- the learned warm start --------------------------------------------------
+def network_params(layers, seed):
+    """Initial network parameters, flat, per layer W[9][c_out][c_in] then
+    b[c_out]: He-normal weights (standard deviation sqrt(2 / (9 c_in))) and
+    small normal biases.  `layers` lists (c_in, c_out)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for ci, co in layers:
+        out.append(rng.standard_normal(9 * co * ci) * np.sqrt(2.0 / (9 * ci)))
+        out.append(rng.standard_normal(co) * 0.05)
+    return np.concatenate(out)
+
+
+def warm_start_instances(count, nelx, nely, seed):
+    """Training / held-out instances for the learned warm start: the MBB beam
+    with the load node drawn uniformly on the top edge and volfrac uniform in
+    [0.3, 0.5]; density filter radius as in the MBB configurations, projection
+    with beta 2, FP32 fields."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        out.append(Config(f"ws{seed}_{i}", "mbb", nelx, nely, volfrac=float(rng.uniform(0.3, 0.5)),
+                          rmin=max(1.5, 2.0 * nelx / 60.0), ft=3, bc="D", beta=2.0, penal=3.0,
+                          iterations=100, precision="f32", load=int(rng.integers(0, nelx))))
+    return out
