@@ -151,6 +151,53 @@ def cpu_baseline(cfg, budget_taps=1500):
             "host_cpus": len(os.sched_getaffinity(0))}
 
 
+def nn_run(args, cfg, op, sp, plain_iters):
+    """The same timed steps with the learned warm start: the network is first
+    trained on the GPU (one Adam step per redesign iteration) on a run of the
+    same problem, then a fresh run warm-starts every solve from the Galerkin
+    combination of its prediction and the previous displacement."""
+    import torch
+    import workloads as W
+    from paper_2005_05436_amd import _lib as L
+    from paper_2005_05436_amd.driver import TopOpt
+    from paper_2005_05436_amd.nn import LAYERS, Net
+    t0 = time.perf_counter()
+    gt = TopOpt(cfg, op=op, solve_precision=sp)
+    net = Net(gt.plan)
+    net.set_params(W.network_params(LAYERS, 0))
+    for _ in range(args.nn_train_steps):
+        gt.step_stages(net, train_lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    train_loss = float(net.loss.item())
+    del gt
+    g = TopOpt(cfg, op=op, solve_precision=sp)
+    for _ in range(args.warmup):
+        g.step_stages(net)
+    K = args.steps
+    hist = torch.zeros((K, g.sst.numel()), dtype=torch.uint8, device=g.sst.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        g.step_stages(net)
+        hist[k].copy_(g.sst, non_blocking=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    h = hist.cpu().numpy()
+    st = [L.SolveStats.from_buffer_copy(h[k].tobytes()) for k in range(K)]
+    its = [s.iterations for s in st]
+    print(f"[bench] warm-started run: cg iterations per step {its}", file=sys.stderr, flush=True)
+    return {"to_iters_per_s": round(K / wall, 3), "ms_per_step": round(1e3 * wall / K, 3),
+            "cg_iterations_per_step": round(sum(its) / K, 1),
+            "plain_cg_iterations_per_step": round(sum(plain_iters) / K, 1),
+            "all_converged": bool(all(s.converged for s in st)),
+            "max_true_residual": max(s.residual for s in st),
+            "train_steps": args.nn_train_steps, "train_seconds": round(train_s, 2),
+            "last_train_loss": round(train_loss, 5),
+            "note": "network trained on the first iterations of the same problem (in-sample); "
+                    "held-out gains are measured by the test suite"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +208,9 @@ def main():
     ap.add_argument("--op", default="assembled", choices=["assembled", "matfree"])
     ap.add_argument("--solve", default="auto", choices=["auto", "f64", "mixed"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--nn-train-steps", type=int, default=13,
+                    help="redesign iterations used to train the warm-start network before its timed run "
+                         "(0: skip the network-warm-started run)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size once (a counter calibration kernel)")
     args = ap.parse_args()
@@ -279,6 +329,8 @@ def main():
         "stage_hbm_frac": {s: round(v * 1e9 / HBM_PEAK, 4) for s, v in gbps.items()},
         "roofline": roof,
     }
+    if args.nn_train_steps > 0 and I.dim == 2:
+        line["nn_warm_start"] = nn_run(args, cfg, op, sp, iters)
     if args.copy_probe_mib > 0:
         nb = args.copy_probe_mib << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device=g.sst.device)
