@@ -351,6 +351,60 @@ to_status to_nn_adam(to_nn* nn, float lr, float beta1, float beta2, float eps, v
 to_status to_nn_train_step(to_nn* nn, to_dtype dtype, const void* xtilde, const double* f,
                            const double* u, float lr, double* d_loss, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Launch-shape autotuning.  to_plan_autotune times, on the plan's own arrays,
+ * the candidate shapes of the 2D filter kernel (output columns per tile 4 or
+ * 8; waves per block automatic or equal to the columns) and of the assembly
+ * kernel (128, 256 or 512 threads per block; only when kval, a device buffer
+ * of nnz_lower entries of `dtype`, is given) and keeps the fastest in the
+ * plan.  It synchronises `stream` and overwrites the plan's scratch arrays
+ * (moduli, filter staging) and kval.  Every shape computes the same
+ * quantities (the filter sums taps in a shape-dependent order).
+ * to_plan_set_tuning / to_plan_get_tuning force or read the shapes. */
+typedef struct {
+    int32_t filt_v;              /* 4 or 8 */
+    int32_t filt_parts;          /* 0 (automatic) .. 16 */
+    int32_t asm_block;           /* 128, 256 or 512 */
+    int32_t tuned;               /* 1 once autotuned */
+} to_tuning;
+to_status to_plan_autotune(to_plan* plan, to_dtype dtype, void* kval, to_tuning* h_out, void* stream);
+to_status to_plan_set_tuning(to_plan* plan, const to_tuning* h_tuning);
+to_status to_plan_get_tuning(const to_plan* plan, to_tuning* h_out);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent designs of different sizes advanced together
+ * by one redesign iteration each (the iteration of to_step for every design).
+ * The projection (with its threshold Newton), the PCG state solve and the OC
+ * bisection each run as ONE cooperative launch for the whole batch, its
+ * blocks split into per-design groups in proportion to the design sizes; the
+ * filter, assembly and sensitivity stages are launched per design.  With
+ * use_graph the iteration is captured into a HIP graph on first use and
+ * replayed while every design's (penal, beta, volfrac, move, target, ft)
+ * stay the same; any change recaptures it.
+ *
+ * to_batch_query: device workspace bytes for `count` designs.
+ * to_batch_create: plans[count], one to_step_state and one to_step_params per
+ *   design (the state buffers are bound to the batch: to_step_batched must get
+ *   the same device pointers; ft and the solve options are fixed and must be
+ *   equal for all designs, and all designs 2D or all 3D).  autotune != 0 runs
+ *   to_plan_autotune on every plan not yet tuned (synchronising).  The
+ *   workspace is caller-owned device memory (256-byte aligned).  Returns
+ *   TO_EUNSUPPORTED when there are more designs than blocks that can be
+ *   co-resident for a stage.
+ * to_step_batched: one iteration of every design on `stream`; updates each
+ *   state's host fields (loop, penal, beta) as to_step does.
+ * to_batch_get_info: int32[6] = designs, blocks of the projection, solve and
+ *   OC launches, graph captures, graph launches. */
+typedef struct to_batch to_batch;
+to_status to_batch_query(int32_t count, size_t* ws_bytes);
+to_status to_batch_create(to_plan* const* plans, int32_t count, to_dtype dtype, const to_step_state* states,
+                          const to_step_params* params, int32_t autotune, void* ws, size_t ws_bytes,
+                          void* stream, to_batch** out);
+to_status to_step_batched(to_batch* batch, to_step_state* states, const to_step_params* params,
+                          int32_t use_graph, void* stream);
+to_status to_batch_get_info(const to_batch* batch, int32_t* h_out);
+void to_batch_destroy(to_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

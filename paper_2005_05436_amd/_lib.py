@@ -28,7 +28,9 @@ EXPORTED = ["to_plan_query", "to_plan_create", "to_plan_destroy", "to_plan_get_i
             "to_status_string", "to_last_error", "to_filter", "to_project", "to_assemble", "to_solve",
             "to_sensitivity", "to_oc_update", "to_step", "to_continuation", "to_warm_start",
             "to_nn_query", "to_nn_create", "to_nn_destroy", "to_nn_set_params", "to_nn_get", "to_nn_forward",
-            "to_nn_backward", "to_nn_adam", "to_nn_train_step"]
+            "to_nn_backward", "to_nn_adam", "to_nn_train_step", "to_plan_autotune", "to_plan_set_tuning",
+            "to_plan_get_tuning", "to_batch_query", "to_batch_create", "to_step_batched", "to_batch_get_info",
+            "to_batch_destroy"]
 
 
 class ToError(RuntimeError):
@@ -93,6 +95,10 @@ class StepState(C.Structure):
 _lib = None
 
 
+class Tuning(C.Structure):
+    _fields_ = [("filt_v", C.c_int32), ("filt_parts", C.c_int32), ("asm_block", C.c_int32), ("tuned", C.c_int32)]
+
+
 def load():
     """Loads libtopt.so (built in-tree); raises if it is missing."""
     global _lib
@@ -121,6 +127,14 @@ def load():
         "to_step": (S, [P, S, C.POINTER(StepState), C.POINTER(StepParams), P]),
         "to_continuation": (C.c_double, [C.c_double, C.POINTER(Sched), C.c_int32]),
         "to_warm_start": (S, [P, S, P, C.c_double, P, P, P, P, P, P]),
+        "to_plan_autotune": (S, [P, S, P, C.POINTER(Tuning), P]),
+        "to_plan_set_tuning": (S, [P, C.POINTER(Tuning)]),
+        "to_plan_get_tuning": (S, [P, C.POINTER(Tuning)]),
+        "to_batch_query": (S, [C.c_int32, C.POINTER(C.c_size_t)]),
+        "to_batch_create": (S, [P, C.c_int32, S, P, P, C.c_int32, P, C.c_size_t, P, C.POINTER(P)]),
+        "to_step_batched": (S, [P, P, P, C.c_int32, P]),
+        "to_batch_get_info": (S, [P, C.POINTER(C.c_int32)]),
+        "to_batch_destroy": (None, [P]),
         "to_nn_query": (S, [C.c_int32, C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_int64)]),
         "to_nn_create": (S, [P, P, C.c_size_t, C.POINTER(P)]),
         "to_nn_destroy": (None, [P]),
@@ -279,3 +293,50 @@ def to_nn_adam(nn, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
 
 def to_nn_train_step(nn, dtype, xtilde, f, u, lr, d_loss=None, stream=None):
     check(load().to_nn_train_step(nn, dtype, ptr(xtilde), ptr(f), ptr(u), lr, ptr(d_loss), stream_ptr(stream)))
+
+
+def to_plan_autotune(plan, dtype, kval=None, stream=None):
+    t = Tuning()
+    check(load().to_plan_autotune(plan, dtype, ptr(kval), C.byref(t), stream_ptr(stream)))
+    return t
+
+
+def to_plan_set_tuning(plan, filt_v=8, filt_parts=0, asm_block=256, tuned=0):
+    check(load().to_plan_set_tuning(plan, C.byref(Tuning(filt_v, filt_parts, asm_block, tuned))))
+
+
+def to_plan_get_tuning(plan):
+    t = Tuning()
+    check(load().to_plan_get_tuning(plan, C.byref(t)))
+    return t
+
+
+def to_batch_query(count):
+    n = C.c_size_t(0)
+    check(load().to_batch_query(count, C.byref(n)))
+    return n.value
+
+
+def to_batch_create(plans, dtype, states, params, autotune, ws_ptr, ws_bytes, stream=None):
+    """plans: list of plan handles; states / params: ctypes arrays of StepState / StepParams."""
+    arr = (C.c_void_p * len(plans))(*[p.value if isinstance(p, C.c_void_p) else p for p in plans])
+    out = C.c_void_p()
+    check(load().to_batch_create(arr, len(plans), dtype, C.cast(states, C.c_void_p), C.cast(params, C.c_void_p),
+                                 1 if autotune else 0, ws_ptr, ws_bytes, stream_ptr(stream), C.byref(out)))
+    return out
+
+
+def to_step_batched(batch, states, params, use_graph=False, stream=None):
+    check(load().to_step_batched(batch, C.cast(states, C.c_void_p), C.cast(params, C.c_void_p),
+                                 1 if use_graph else 0, stream_ptr(stream)))
+
+
+def to_batch_get_info(batch):
+    out = (C.c_int32 * 6)()
+    check(load().to_batch_get_info(batch, out))
+    return dict(designs=out[0], project_blocks=out[1], solve_blocks=out[2], oc_blocks=out[3],
+                graph_captures=out[4], graph_launches=out[5])
+
+
+def to_batch_destroy(batch):
+    load().to_batch_destroy(batch)

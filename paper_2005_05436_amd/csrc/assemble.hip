@@ -19,15 +19,15 @@ __global__ __launch_bounds__(kBlock) void moduli_kernel(int64_t m, const TX* __r
         E[e] = Emin + pow((T)x[e], penal) * (E0 - Emin);
 }
 
-template <typename T, int DT>
-__global__ __launch_bounds__(kBlock) void assemble_kernel(int64_t nnz, const int32_t* __restrict__ seg,
-                                                           const int32_t* __restrict__ perm,
-                                                           const T* __restrict__ ke, const T* __restrict__ E,
-                                                           T* __restrict__ kval) {
+template <typename T, int DT, int NT>
+__global__ __launch_bounds__(NT) void assemble_kernel(int64_t nnz, const int32_t* __restrict__ seg,
+                                                       const int32_t* __restrict__ perm,
+                                                       const T* __restrict__ ke, const T* __restrict__ E,
+                                                       T* __restrict__ kval) {
     __shared__ T ke_s[DT];
-    for (int i = threadIdx.x; i < DT; i += kBlock) ke_s[i] = ke[i];
+    for (int i = threadIdx.x; i < DT; i += NT) ke_s[i] = ke[i];
     __syncthreads();
-    for (int64_t s = blockIdx.x * (int64_t)kBlock + threadIdx.x; s < nnz; s += (int64_t)gridDim.x * kBlock) {
+    for (int64_t s = blockIdx.x * (int64_t)NT + threadIdx.x; s < nnz; s += (int64_t)gridDim.x * NT) {
         const int32_t a = seg[s], b = seg[s + 1];
         T acc = T(0);
         for (int32_t t = a; t < b; ++t) {
@@ -36,6 +36,21 @@ __global__ __launch_bounds__(kBlock) void assemble_kernel(int64_t nnz, const int
             acc += ke_s[pk - e * DT] * E[e];
         }
         kval[s] = acc;
+    }
+}
+
+template <typename T, int DT, int NT>
+static void assemble_nt(Plan* p, int64_t nnz, const T* ke, const T* E, T* kval, hipStream_t s) {
+    const int blocks = (int)std::min<int64_t>(1 << 16, (nnz + NT - 1) / NT);
+    hipLaunchKernelGGL((assemble_kernel<T, DT, NT>), dim3(blocks), dim3(NT), 0, s, nnz, p->seg_ptr, p->perm, ke, E, kval);
+}
+
+template <typename T, int DT>
+static void assemble_t(Plan* p, int64_t nnz, const T* ke, const T* E, T* kval, hipStream_t s) {
+    switch (p->tune.asm_block) {
+    case 128: assemble_nt<T, DT, 128>(p, nnz, ke, E, kval, s); break;
+    case 512: assemble_nt<T, DT, 512>(p, nnz, ke, E, kval, s); break;
+    default: assemble_nt<T, DT, 256>(p, nnz, ke, E, kval, s); break;
     }
 }
 
@@ -63,21 +78,12 @@ to_status launch_assemble(Plan* p, to_dtype dt, const void* xphys, double penal,
     to_status st = launch_moduli(p, dt, xphys, penal, s, false);
     if (st != TO_OK) return st;
     const int64_t nnz = p->info.nnz_lower;
-    const int blocks = (int)std::min<int64_t>(1 << 16, (nnz + kBlock - 1) / kBlock);
     if (dt == TO_F64) {
-        if (p->dim == 2)
-            hipLaunchKernelGGL((assemble_kernel<double, 36>), dim3(blocks), dim3(kBlock), 0, s, nnz, p->seg_ptr,
-                               p->perm, p->ke64, p->E64, (double*)kval);
-        else
-            hipLaunchKernelGGL((assemble_kernel<double, 300>), dim3(blocks), dim3(kBlock), 0, s, nnz, p->seg_ptr,
-                               p->perm, p->ke64, p->E64, (double*)kval);
+        if (p->dim == 2) assemble_t<double, 36>(p, nnz, p->ke64, p->E64, (double*)kval, s);
+        else assemble_t<double, 300>(p, nnz, p->ke64, p->E64, (double*)kval, s);
     } else {
-        if (p->dim == 2)
-            hipLaunchKernelGGL((assemble_kernel<float, 36>), dim3(blocks), dim3(kBlock), 0, s, nnz, p->seg_ptr,
-                               p->perm, p->ke32, p->E32, (float*)kval);
-        else
-            hipLaunchKernelGGL((assemble_kernel<float, 300>), dim3(blocks), dim3(kBlock), 0, s, nnz, p->seg_ptr,
-                               p->perm, p->ke32, p->E32, (float*)kval);
+        if (p->dim == 2) assemble_t<float, 36>(p, nnz, p->ke32, p->E32, (float*)kval, s);
+        else assemble_t<float, 300>(p, nnz, p->ke32, p->E32, (float*)kval, s);
     }
     TO_HIP(hipGetLastError());
     return TO_OK;

@@ -55,6 +55,14 @@ struct Plan {
     float* v32[8] = {};                                  // n each
     double* fx64 = nullptr;  float* fx32 = nullptr;      // m (filter staging)
 
+    // launch shapes chosen by the autotuner (or defaults)
+    struct Tune {
+        int filt_v = 8;        // 2D filter: output columns per tile (4 or 8)
+        int filt_parts = 0;    // 2D filter: waves per block (0: automatic)
+        int asm_block = 256;   // assembly: threads per block (128, 256 or 512)
+        int tuned = 0;
+    } tune;
+
     // host copies
     std::vector<double> ke_lower, ke_full, h;
     std::vector<int32_t> hlim_host;
@@ -155,8 +163,12 @@ constexpr int kBarGroups = 16;
 struct GridBar {
     unsigned* bar;
     unsigned gen;        // thread 0 only
-    __device__ __forceinline__ void init(unsigned* b) {
+    unsigned nblk, bid;  // blocks taking part and this block's index among them
+    __device__ __forceinline__ void init(unsigned* b) { init(b, blockIdx.x, gridDim.x); }
+    __device__ __forceinline__ void init(unsigned* b, unsigned block, unsigned nblocks) {
         bar = b;
+        bid = block;
+        nblk = nblocks;
         if (threadIdx.x == 0) gen = (ld_dev(&b[0]) >> 20) & 0xFFFu;
     }
     // Returns false in every thread once a block has timed out (then
@@ -167,9 +179,9 @@ struct GridBar {
         __syncthreads();
         if (threadIdx.x == 0) {
             int ok = 1;
-            const unsigned nb = gridDim.x;
+            const unsigned nb = nblk;
             const unsigned G = nb < (unsigned)kBarGroups ? nb : (unsigned)kBarGroups;
-            const unsigned g = blockIdx.x % G;
+            const unsigned g = bid % G;
             const unsigned ng = nb / G + (g < nb % G ? 1u : 0u);
             unsigned* grp = &bar[64 + 32 * g];
             const unsigned old = atomicAdd(grp, 1u);
@@ -205,14 +217,14 @@ struct GridBar {
 // All loads are issued before the additions (one memory latency per
 // reduction, not one per block); gridDim.x <= 4 * NB.
 template <int K, int NB = kBlock>
-__device__ __forceinline__ void grid_reduce(const double* partial, double* out_sh, double* sh) {
+__device__ __forceinline__ void grid_reduce(const double* partial, double* out_sh, double* sh, int nblocks) {
     double v[K][4];
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int b = threadIdx.x + q * NB;
-            v[k][q] = b < (int)gridDim.x ? ld_acq(&partial[b * kPartialWidth + k]) : 0.0;
+            v[k][q] = b < nblocks ? ld_acq(&partial[b * kPartialWidth + k]) : 0.0;
         }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -234,6 +246,33 @@ to_status launch_project(Plan* p, to_dtype dt, int ft, const void* xt, const voi
 to_status launch_assemble(Plan* p, to_dtype dt, const void* xphys, double penal, void* kval,
                           hipStream_t s);
 to_status launch_moduli(Plan* p, to_dtype dt, const void* xphys, double penal, hipStream_t s, bool also64);
+// Batched persistent kernels: block b of a launch works on instance inst[b],
+// as block b - first[inst] of a group of count[inst] blocks.
+struct BatchMap {
+    const int32_t* inst;
+    const int32_t* first;
+    const int32_t* count;
+    int blocks;
+};
+size_t project_args_bytes(to_dtype dt);
+void project_args_fill(Plan* p, to_dtype dt, int ft, const void* xt, const void* x, void* xphys, void* dprj,
+                       double* d_eta, const void* xold, to_project_stats* st, const double* dyn, void* dst);
+int project_batch_capacity(to_dtype dt, int num_cu);
+to_status launch_project_batch(to_dtype dt, const void* tab, const BatchMap& mp, hipStream_t s);
+size_t oc_args_bytes(to_dtype dt);
+void oc_args_fill(Plan* p, to_dtype dt, void* x, const void* dc, const void* dv, to_oc_stats* st, const double* dyn,
+                  void* dst);
+int oc_batch_capacity(to_dtype dt, int num_cu);
+to_status launch_oc_batch(to_dtype dt, const void* tab, const BatchMap& mp, hipStream_t s);
+int solve_mode(to_dtype dt, const to_solve_opts& o);
+to_status solve_prepare(Plan* p, to_dtype dt, const void* xphys, double penal, const to_solve_opts& o, hipStream_t s);
+size_t solve_args_bytes();
+void solve_args_fill(Plan* p, to_dtype dt, const void* kval, const double* f, double* u, const to_solve_opts& o,
+                     to_solve_stats* st, void* dst);
+int solve_batch_capacity(int dim, int mode, int num_cu);
+to_status launch_solve_batch(int dim, int mode, const void* tab, const BatchMap& mp, hipStream_t s);
+
+to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuning* out);
 to_status launch_warm_start(Plan* p, to_dtype dt, const void* xphys, double penal, const double* f,
                             const double* uh, const double* up, double* u, double* coef, hipStream_t s);
 to_status launch_solve(Plan* p, to_dtype dt, const void* kval, const void* xphys, double penal,

@@ -250,6 +250,34 @@ __global__ __launch_bounds__(kBlock) void filter3d_kernel(
 }
 
 // ---------------------------------------------------------------------------
+template <typename T, int MODE, int V>
+static to_status run_filter2d(Plan* p, const T* hp, const T* Hs, const T* in, const T* in2, const T* sc, T* out,
+                              T* out2, hipStream_t s) {
+    constexpr int NF = MODE == M_ADJ2 ? 2 : 1;
+    const int R = p->R;
+    const size_t lds_max = 160 * 1024;
+    const int W = 2 * R + 1;
+    // waves per block: at least V (wave q finishes output column q); by
+    // default 16 when there are enough tap rows to split, else V
+    int parts = W >= 16 ? kFiltMaxParts : V;
+    if (p->tune.filt_parts > 0) parts = std::max(V, std::min(kFiltMaxParts, p->tune.filt_parts));
+    size_t lds = (size_t)NF * (64 + 2 * R) * (V + 2 * R + V) * sizeof(T);
+    lds = std::max(lds, (size_t)parts * NF * V * 64 * sizeof(T));   // partial-sum reuse
+    if (lds > lds_max) { set_error("filter radius too large for the LDS tile"); return TO_EUNSUPPORTED; }
+    auto k = filter2d_kernel<T, MODE, V>;
+    TO_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, 64 * parts, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const int ntiles = ((p->nely + 63) / 64) * ((p->nelx + V - 1) / V);
+    const int blocks = std::max(1, std::min(ntiles, per_cu * p->num_cu));
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * parts), lds, s, p->nely, p->nelx, R, p->bc, hp, p->hp_stride,
+                       p->hlim, Hs, in, in2, sc, out, out2, p->bar + 16);
+    TO_HIP(hipGetLastError());
+    return TO_OK;
+}
+
 template <typename T, int MODE>
 static to_status run_filter(Plan* p, const T* h, const T* hp, const T* Hs, const T* in, const T* in2, const T* sc,
                             T* out, T* out2, hipStream_t s) {
@@ -257,24 +285,8 @@ static to_status run_filter(Plan* p, const T* h, const T* hp, const T* Hs, const
     const int R = p->R;
     const size_t lds_max = 160 * 1024;
     if (p->dim == 2) {
-        constexpr int V = kFiltV;
-        const int W = 2 * R + 1;
-        // waves per block: at least V (wave q finishes output column q), 16
-        // when there are enough tap rows to split
-        const int parts = W >= 16 ? kFiltMaxParts : V;
-        size_t lds = (size_t)NF * (64 + 2 * R) * (V + 2 * R + V) * sizeof(T);
-        lds = std::max(lds, (size_t)parts * NF * V * 64 * sizeof(T));   // partial-sum reuse
-        if (lds > lds_max) { set_error("filter radius too large for the LDS tile"); return TO_EUNSUPPORTED; }
-        auto k = filter2d_kernel<T, MODE, V>;
-        TO_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, 64 * parts, lds) != hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-        const int ntiles = ((p->nely + 63) / 64) * ((p->nelx + V - 1) / V);
-        const int blocks = std::max(1, std::min(ntiles, per_cu * p->num_cu));
-        hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * parts), lds, s, p->nely, p->nelx, R, p->bc, hp,
-                           p->hp_stride, p->hlim, Hs, in, in2, sc, out, out2, p->bar + 16);
+        if (p->tune.filt_v == 4) return run_filter2d<T, MODE, 4>(p, hp, Hs, in, in2, sc, out, out2, s);
+        return run_filter2d<T, MODE, kFiltV>(p, hp, Hs, in, in2, sc, out, out2, s);
     } else {
         size_t lds = (size_t)NF * (64 + 2 * R) * (4 + 2 * R) * (4 + 2 * R) * sizeof(T);
         if (lds > lds_max) { set_error("3D filter radius too large for the LDS tile"); return TO_EUNSUPPORTED; }

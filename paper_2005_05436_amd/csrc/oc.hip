@@ -12,6 +12,7 @@
 // four times fewer grid barriers.  Volume sums are double-double, so every
 // decision agrees with an exactly rounded sum except in exact ties.
 #include <cmath>
+#include <cstring>
 #include <type_traits>
 
 #include "common.h"
@@ -34,21 +35,42 @@ __device__ __forceinline__ double oc_clamp(double ocp, double lm, double x, doub
 constexpr int kOcBlock = 512;   // 15 double-double accumulators per lane need the register room
 
 template <typename T>
-__global__ __launch_bounds__(kOcBlock) void oc_kernel(int64_t m, const uint8_t* __restrict__ pas, T* __restrict__ x,
-                                                     const T* __restrict__ dc, const T* __restrict__ dv,
-                                                     double volfrac, double move, double* __restrict__ ocp_buf,
-                                                     to_oc_stats* st, double* partial, unsigned* bar) {
+struct OcArgs {
+    int64_t m;
+    const uint8_t* pas;
+    T* x;
+    const T* dc;
+    const T* dv;
+    double volfrac, move;
+    double* ocp_buf;
+    to_oc_stats* st;
+    double* partial;
+    unsigned* bar;
+    const double* dyn;      // batch: device (volfrac, move) at dyn[2], dyn[3] (nullable)
+};
+
+// The update of one design, run by `nb` blocks of which this is `bid`.
+template <typename T>
+__device__ void oc_body(const OcArgs<T>& A, int bid, int nb) {
     constexpr int NB = kOcBlock, NW = NB / 64;
     __shared__ double wsum[NW * kCand * 2];
     __shared__ double gsum[NB * 2];
     __shared__ double tot[2 * kCand];
-    const int64_t stride = (int64_t)gridDim.x * NB;
-    const int64_t i0 = (int64_t)blockIdx.x * NB + threadIdx.x;
+    const int64_t m = A.m;
+    const uint8_t* __restrict__ pas = A.pas;
+    T* __restrict__ x = A.x;
+    const T* __restrict__ dc = A.dc;
+    const T* __restrict__ dv = A.dv;
+    const double volfrac = A.dyn ? A.dyn[2] : A.volfrac, move = A.dyn ? A.dyn[3] : A.move;
+    double* __restrict__ ocp_buf = A.ocp_buf;
+    double* partial = A.partial;
+    const int64_t stride = (int64_t)nb * NB;
+    const int64_t i0 = (int64_t)bid * NB + threadIdx.x;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     bool alive = true;
     int region = 0;
     GridBar gb;
-    gb.init(bar);
+    gb.init(A.bar, bid, nb);
 
     // Block-level double-double sums of K values (K compile-time, unrolled so
     // v stays in registers): every wave reduces all K with shuffles, one
@@ -66,8 +88,8 @@ __global__ __launch_bounds__(kOcBlock) void oc_kernel(int64_t m, const uint8_t* 
             const int k = threadIdx.x;
             dd b{wsum[k * 2], wsum[k * 2 + 1]};
             for (int i = 1; i < NW; ++i) b = dd_add(b, dd{wsum[(i * K + k) * 2], wsum[(i * K + k) * 2 + 1]});
-            st_dev(&reg[blockIdx.x * kPartialWidth + 2 * k], b.hi);
-            st_dev(&reg[blockIdx.x * kPartialWidth + 2 * k + 1], b.lo);
+            st_dev(&reg[bid * kPartialWidth + 2 * k], b.hi);
+            st_dev(&reg[bid * kPartialWidth + 2 * k + 1], b.lo);
         }
         __syncthreads();
     };
@@ -86,7 +108,7 @@ __global__ __launch_bounds__(kOcBlock) void oc_kernel(int64_t m, const uint8_t* 
 #pragma unroll
             for (int q = 0; q < kMaxPer; ++q) {
                 const int b = j + q * S;
-                const bool ok = b < (int)gridDim.x;
+                const bool ok = b < nb;
                 hv[q] = ok ? ld_dev(&reg[b * kPartialWidth + 2 * k]) : 0.0;
                 lv[q] = ok ? ld_dev(&reg[b * kPartialWidth + 2 * k + 1]) : 0.0;
             }
@@ -178,14 +200,38 @@ __global__ __launch_bounds__(kOcBlock) void oc_kernel(int64_t m, const uint8_t* 
     if (n_bs > 0 && alive)
         for (int64_t e = i0; e < m; e += stride)
             if (pas[e] == TO_ACTIVE) x[e] = (T)oc_clamp(ocp_buf[e], lmid, (double)x[e], move);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         to_oc_stats s;
         s.lmid = lmid; s.l1 = l1; s.l2 = l2;
         s.vol = n_bs > 0 ? vol_last : NAN;
         s.n_bs = n_bs; s.capped = n_bs >= cap ? 1 : 0;
         s.passes = passes; s.pad = alive ? 0 : 1;
-        *st = s;
+        *A.st = s;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kOcBlock) void oc_kernel(OcArgs<T> a) {
+    oc_body(a, blockIdx.x, gridDim.x);
+}
+
+// A batch of designs in one launch (block b: design inst[b], block b - first[inst] of count[inst]).
+template <typename T>
+__global__ __launch_bounds__(kOcBlock) void oc_batch_kernel(const OcArgs<T>* __restrict__ tab,
+                                                            const int32_t* __restrict__ inst,
+                                                            const int32_t* __restrict__ first,
+                                                            const int32_t* __restrict__ count) {
+    const int i = inst[blockIdx.x];
+    oc_body(tab[i], (int)blockIdx.x - first[i], count[i]);
+}
+
+template <typename T>
+static OcArgs<T> oc_args(Plan* p, T* x, const T* dc, const T* dv, double volfrac, double move, to_oc_stats* st) {
+    OcArgs<T> a{};
+    a.m = p->info.m; a.pas = p->passive; a.x = x; a.dc = dc; a.dv = dv;
+    a.volfrac = volfrac; a.move = move; a.ocp_buf = p->fx64; a.st = st;
+    a.partial = p->partial; a.bar = p->bar;
+    return a;
 }
 
 template <typename T>
@@ -198,12 +244,36 @@ static to_status run_oc(Plan* p, T* x, const T* dc, const T* dv, double volfrac,
     // unrolled gather of the grid reduction
     int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, 2 * p->num_cu), (m + kOcBlock - 1) / kOcBlock));
     blocks = std::min(blocks, 1024);
-    const uint8_t* pas = p->passive;
-    double* ocp = p->fx64;
-    double* partial = p->partial;
-    unsigned* bar = p->bar;
-    void* args[] = {&m, &pas, &x, &dc, &dv, &volfrac, &move, &ocp, &st, &partial, &bar};
+    OcArgs<T> a = oc_args<T>(p, x, dc, dv, volfrac, move, st);
+    void* args[] = {&a};
     TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(kOcBlock), args, 0, s));
+    return TO_OK;
+}
+
+size_t oc_args_bytes(to_dtype dt) { return dt == TO_F64 ? sizeof(OcArgs<double>) : sizeof(OcArgs<float>); }
+
+void oc_args_fill(Plan* p, to_dtype dt, void* x, const void* dc, const void* dv, to_oc_stats* st, const double* dyn,
+                  void* dst) {
+    if (dt == TO_F64) {
+        OcArgs<double> a = oc_args<double>(p, (double*)x, (const double*)dc, (const double*)dv, 0.0, 0.0, st);
+        a.dyn = dyn;
+        std::memcpy(dst, &a, sizeof a);
+    } else {
+        OcArgs<float> a = oc_args<float>(p, (float*)x, (const float*)dc, (const float*)dv, 0.0, 0.0, st);
+        a.dyn = dyn;
+        std::memcpy(dst, &a, sizeof a);
+    }
+}
+
+int oc_batch_capacity(to_dtype dt, int num_cu) {
+    const void* k = dt == TO_F64 ? (const void*)oc_batch_kernel<double> : (const void*)oc_batch_kernel<float>;
+    return std::min(coop_blocks_for(k, kOcBlock, 0, num_cu), 2 * num_cu);
+}
+
+to_status launch_oc_batch(to_dtype dt, const void* tab, const BatchMap& mp, hipStream_t s) {
+    const void* k = dt == TO_F64 ? (const void*)oc_batch_kernel<double> : (const void*)oc_batch_kernel<float>;
+    void* args[] = {(void*)&tab, (void*)&mp.inst, (void*)&mp.first, (void*)&mp.count};
+    TO_HIP(hipLaunchCooperativeKernel(k, dim3(mp.blocks), dim3(kOcBlock), args, 0, s));
     return TO_OK;
 }
 

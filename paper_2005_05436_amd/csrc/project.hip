@@ -8,6 +8,7 @@
 // (so every block takes the same Newton decision).  A final sweep writes
 // xphys and dprj and accumulates the change and the volume.
 #include <cmath>
+#include <cstring>
 
 #include "common.h"
 
@@ -41,27 +42,51 @@ __device__ __forceinline__ double pre_value(const T* xt, const T* x, const uint8
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBigBlock) void project_kernel(
-    int64_t m, int ft, const T* __restrict__ xt, const T* __restrict__ x, const uint8_t* __restrict__ pas,
-    T* __restrict__ xphys, T* __restrict__ dprj, double beta, double* d_eta, double target,
-    int mean_target, const T* __restrict__ xold, to_project_stats* st, double* partial, unsigned* bar) {
+struct ProjArgs {
+    int64_t m;
+    int ft;
+    const T* xt; const T* x; const uint8_t* pas;
+    T* xphys; T* dprj;
+    double beta;
+    double* d_eta;
+    double target;
+    int mean_target;
+    const T* xold;
+    to_project_stats* st;
+    double* partial;
+    unsigned* bar;
+    const double* dyn;      // batch: device (beta, target) replacing the fields above (nullable)
+};
+
+// The whole block for one design, run by `nb` blocks of which this is `bid`.
+template <typename T>
+__device__ void project_body(const ProjArgs<T>& a, int bid, int nb) {
     constexpr int NB = kBigBlock;
     __shared__ double sh[NB / 64];
     __shared__ double red[4];
-    const int64_t stride = (int64_t)gridDim.x * NB;
-    const int64_t i0 = (int64_t)blockIdx.x * NB + threadIdx.x;
-    double eta = *d_eta;
+    const int64_t m = a.m;
+    const T* __restrict__ xt = a.xt;
+    const T* __restrict__ x = a.x;
+    const uint8_t* __restrict__ pas = a.pas;
+    double* partial = a.partial;
+    const int64_t stride = (int64_t)nb * NB;
+    const int64_t i0 = (int64_t)bid * NB + threadIdx.x;
+    double eta = *a.d_eta;
+    double target = a.dyn ? a.dyn[1] : a.target;
+    const double beta = a.dyn ? a.dyn[0] : a.beta;
+    const int mean_target = a.dyn ? (isnan(target) ? 1 : 0) : a.mean_target;
+    const int ft = a.ft;
     bool alive = true;
     GridBar gb;
-    gb.init(bar);
+    gb.init(a.bar, bid, nb);
 
-    if (ft == 3 && mean_target) {                     // eq. (17): target = volume of the pre-projection field
+    if (ft == 3 && mean_target) {                   // eq. (17): target = volume of the pre-projection field
         double s = 0.0;
         for (int64_t e = i0; e < m; e += stride) s += pre_value(xt, x, pas, e);
         s = block_sum<NB>(s, sh);
-        if (threadIdx.x == 0) st_dev(&partial[blockIdx.x * kPartialWidth], s);
+        if (threadIdx.x == 0) st_dev(&partial[bid * kPartialWidth], s);
         alive = gb.sync();
-        grid_reduce<1, NB>(partial, red, sh);
+        grid_reduce<1, NB>(partial, red, sh, nb);
         target = red[0] / (double)m;
         alive = alive && gb.sync();              // partial buffer is reused below
     }
@@ -82,11 +107,11 @@ __global__ __launch_bounds__(kBigBlock) void project_kernel(
             sp = block_sum<NB>(sp, sh);
             sd = block_sum<NB>(sd, sh);
             if (threadIdx.x == 0) {
-                st_dev(&partial[blockIdx.x * kPartialWidth + 0], sp);
-                st_dev(&partial[blockIdx.x * kPartialWidth + 1], sd);
+                st_dev(&partial[bid * kPartialWidth + 0], sp);
+                st_dev(&partial[bid * kPartialWidth + 1], sd);
             }
             alive = gb.sync() && alive;
-            grid_reduce<2, NB>(partial, red, sh);
+            grid_reduce<2, NB>(partial, red, sh, nb);
             g = red[0] / (double)m - target;
             if (!(fabs(g) > 1e-6) || steps >= 50 || !alive) break;
             eta = eta - g / (red[1] / (double)m);
@@ -103,10 +128,10 @@ __global__ __launch_bounds__(kBigBlock) void project_kernel(
             double xp = ft >= 2 ? P.prj(v) : v;
             double dp = ft >= 2 ? P.dprj((double)xt[e]) : 1.0;
             T xpT = (T)xp;
-            xphys[e] = xpT;
-            dprj[e] = (T)dp;
-            if (xold) {
-                double dlt = (double)xpT - (double)xold[e];
+            a.xphys[e] = xpT;
+            a.dprj[e] = (T)dp;
+            if (a.xold) {
+                double dlt = (double)xpT - (double)a.xold[e];
                 sc += dlt * dlt;
             }
             sv += (double)xpT;
@@ -114,25 +139,41 @@ __global__ __launch_bounds__(kBigBlock) void project_kernel(
     sc = block_sum<NB>(sc, sh);
     sv = block_sum<NB>(sv, sh);
     if (threadIdx.x == 0) {
-        st_dev(&partial[blockIdx.x * kPartialWidth + 0], sc);
-        st_dev(&partial[blockIdx.x * kPartialWidth + 1], sv);
+        st_dev(&partial[bid * kPartialWidth + 0], sc);
+        st_dev(&partial[bid * kPartialWidth + 1], sv);
     }
     alive = gb.sync() && alive;
-    if (blockIdx.x == 0) {
-        grid_reduce<2, NB>(partial, red, sh);
+    if (bid == 0) {
+        grid_reduce<2, NB>(partial, red, sh, nb);
         if (threadIdx.x == 0) {
             to_project_stats s;
             s.eta = eta;
             s.g = g;
-            s.ch = xold ? sqrt(red[0]) / sqrt((double)m) : NAN;
+            s.ch = a.xold ? sqrt(red[0]) / sqrt((double)m) : NAN;
             s.vol = red[1] / (double)m;
             s.n_newton = steps;
             s.converged = (ft != 3 || fabs(g) <= 1e-6) && alive ? 1 : 0;
             s.pad[0] = s.pad[1] = 0;
-            *st = s;
-            *d_eta = eta;
+            *a.st = s;
+            *a.d_eta = eta;
         }
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBigBlock) void project_kernel(ProjArgs<T> a) {
+    project_body(a, blockIdx.x, gridDim.x);
+}
+
+// A batch of designs in one launch: block b works on design inst[b], as block
+// b - first[inst] of its group of count[inst] blocks.
+template <typename T>
+__global__ __launch_bounds__(kBigBlock) void project_batch_kernel(const ProjArgs<T>* __restrict__ tab,
+                                                                  const int32_t* __restrict__ inst,
+                                                                  const int32_t* __restrict__ first,
+                                                                  const int32_t* __restrict__ count) {
+    const int i = inst[blockIdx.x];
+    project_body(tab[i], (int)blockIdx.x - first[i], count[i]);
 }
 
 int coop_blocks_for(const void* kernel, int block, size_t smem, int num_cu) {
@@ -143,6 +184,19 @@ int coop_blocks_for(const void* kernel, int block, size_t smem, int num_cu) {
 }
 
 template <typename T>
+static ProjArgs<T> proj_args(Plan* p, int ft, const void* xt, const void* x, void* xphys, void* dprj, double beta,
+                             double* d_eta, double target, const void* xold, to_project_stats* st) {
+    ProjArgs<T> a{};
+    a.m = p->info.m; a.ft = ft;
+    a.xt = (const T*)xt; a.x = (const T*)x; a.pas = p->passive;
+    a.xphys = (T*)xphys; a.dprj = (T*)dprj;
+    a.beta = beta; a.d_eta = d_eta; a.target = target; a.mean_target = std::isnan(target) ? 1 : 0;
+    a.xold = (const T*)xold; a.st = st;
+    a.partial = p->partial; a.bar = p->bar;
+    return a;
+}
+
+template <typename T>
 static to_status run_project(Plan* p, int ft, const void* xt, const void* x, void* xphys, void* dprj,
                              double beta, double* d_eta, double target, const void* xold,
                              to_project_stats* st, hipStream_t s) {
@@ -150,12 +204,36 @@ static to_status run_project(Plan* p, int ft, const void* xt, const void* x, voi
     int64_t m = p->info.m;
     int maxb = coop_blocks_for((const void*)k, kBigBlock, 0, p->num_cu);
     int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, p->num_cu), (m + kBigBlock - 1) / kBigBlock));
-    int mean_target = std::isnan(target) ? 1 : 0;
-    const T* a = (const T*)xt; const T* b = (const T*)x; const uint8_t* pas = p->passive;
-    T* c = (T*)xphys; T* dp = (T*)dprj; const T* xo = (const T*)xold;
-    double* partial = p->partial; unsigned* bar = p->bar;
-    void* args[] = {&m, &ft, &a, &b, &pas, &c, &dp, &beta, &d_eta, &target, &mean_target, &xo, &st, &partial, &bar};
+    ProjArgs<T> a = proj_args<T>(p, ft, xt, x, xphys, dprj, beta, d_eta, target, xold, st);
+    void* args[] = {&a};
     TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(kBigBlock), args, 0, s));
+    return TO_OK;
+}
+
+size_t project_args_bytes(to_dtype dt) { return dt == TO_F64 ? sizeof(ProjArgs<double>) : sizeof(ProjArgs<float>); }
+
+void project_args_fill(Plan* p, to_dtype dt, int ft, const void* xt, const void* x, void* xphys, void* dprj,
+                       double* d_eta, const void* xold, to_project_stats* st, const double* dyn, void* dst) {
+    if (dt == TO_F64) {
+        ProjArgs<double> a = proj_args<double>(p, ft, xt, x, xphys, dprj, 0.0, d_eta, NAN, xold, st);
+        a.dyn = dyn;
+        std::memcpy(dst, &a, sizeof a);
+    } else {
+        ProjArgs<float> a = proj_args<float>(p, ft, xt, x, xphys, dprj, 0.0, d_eta, NAN, xold, st);
+        a.dyn = dyn;
+        std::memcpy(dst, &a, sizeof a);
+    }
+}
+
+int project_batch_capacity(to_dtype dt, int num_cu) {
+    const void* k = dt == TO_F64 ? (const void*)project_batch_kernel<double> : (const void*)project_batch_kernel<float>;
+    return coop_blocks_for(k, kBigBlock, 0, num_cu);
+}
+
+to_status launch_project_batch(to_dtype dt, const void* tab, const BatchMap& mp, hipStream_t s) {
+    const void* k = dt == TO_F64 ? (const void*)project_batch_kernel<double> : (const void*)project_batch_kernel<float>;
+    void* args[] = {(void*)&tab, (void*)&mp.inst, (void*)&mp.first, (void*)&mp.count};
+    TO_HIP(hipLaunchCooperativeKernel(k, dim3(mp.blocks), dim3(kBigBlock), args, 0, s));
     return TO_OK;
 }
 

@@ -24,6 +24,7 @@
 // Mixed precision (FP32 fields): FP32 CG with FP64 residual replacement from
 // the FP64 matrix-free operator; FP64 PCG fallback when it stalls.
 #include <cmath>
+#include <cstring>
 
 #include "common.h"
 
@@ -254,10 +255,10 @@ struct Ctx {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             double s = block_sum(v[k], sh);
-                if (threadIdx.x == 0) st_dev(&region[blockIdx.x * kPartialWidth + k], s);
+            if (threadIdx.x == 0) st_dev(&region[gb.bid * kPartialWidth + k], s);
         }
         alive = gb.sync() && alive;
-        grid_reduce<K>(region, res, sh);
+        grid_reduce<K>(region, res, sh, (int)gb.nblk);
         ++red;
     }
 };
@@ -527,17 +528,17 @@ __device__ bool mixed_cg(Ctx& C, const Geo& g, const SolveArgs& A, const Op32& o
 // MODE 0: FP64, assembled operator; 1: FP64, matrix-free;
 //      2: mixed, FP32 assembled inner; 3: mixed, FP32 matrix-free inner.
 template <int DIM, int MODE>
-__global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs A) {
+__device__ void solve_body(const SolveArgs& A, int bid, int nb) {
     __shared__ double sh[kWaves];
     __shared__ double res[4];
     Ctx C{A.partial, GridBar{}, sh, res, 0, true, Own{}};
-    C.gb.init(A.bar);
+    C.gb.init(A.bar, bid, nb);
     {
         // contiguous node range of this block; band = largest node-index
         // distance between two nodes of one element
         const int64_t nn = A.geo.nnode;
-        const int64_t chunk = (nn + gridDim.x - 1) / gridDim.x;
-        C.o.lo = min(nn, (int64_t)blockIdx.x * chunk);
+        const int64_t chunk = (nn + nb - 1) / nb;
+        C.o.lo = min(nn, (int64_t)bid * chunk);
         C.o.hi = min(nn, C.o.lo + chunk);
         C.o.band = DIM == 2 ? (int64_t)A.geo.ny + 2
                             : (int64_t)(A.geo.ny + 1) * (A.geo.nz + 1) + A.geo.ny + 2;
@@ -619,7 +620,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs A) {
         }
         resid /= (bnorm > 0 ? bnorm : 1.0);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         to_solve_stats s;
         s.residual = resid;
         s.bnorm = bnorm;
@@ -631,6 +632,21 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs A) {
         s.pad = C.alive ? 0 : 1;
         *A.st = s;
     }
+}
+
+template <int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs A) {
+    solve_body<DIM, MODE>(A, blockIdx.x, gridDim.x);
+}
+
+// A batch of systems in one launch (block b: system inst[b], block b - first[inst] of count[inst]).
+template <int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void solve_batch_kernel(const SolveArgs* __restrict__ tab,
+                                                             const int32_t* __restrict__ inst,
+                                                             const int32_t* __restrict__ first,
+                                                             const int32_t* __restrict__ count) {
+    const int i = inst[blockIdx.x];
+    solve_body<DIM, MODE>(tab[i], (int)blockIdx.x - first[i], count[i]);
 }
 
 template <int DIM, int MODE>
@@ -758,29 +774,46 @@ to_status launch_warm_start(Plan* p, to_dtype dt, const void* xphys, double pena
     return TO_OK;
 }
 
-to_status launch_solve(Plan* p, to_dtype dt, const void* kval, const void* xphys, double penal,
-                       const double* f, double* u, const to_solve_opts& o, to_solve_stats* st, hipStream_t s) {
+int solve_mode(to_dtype dt, const to_solve_opts& o) {
     const bool mixed = dt == TO_F32 && o.precision == TO_SOLVE_MIXED;
     const bool assembled = o.op == TO_OP_ASSEMBLED && (dt == TO_F64 || mixed);
-    if (o.op == TO_OP_ASSEMBLED && !kval) { set_error("kval is NULL"); return TO_EINVAL; }
-    // moduli for the matrix-free operators (FP64 always; FP32 too in mixed mode)
-    if (!(dt == TO_F64 && assembled)) {
-        to_status r = launch_moduli(p, dt, xphys, penal, s, true);
-        if (r != TO_OK) return r;
-    }
+    return !mixed ? (assembled ? 0 : 1) : (assembled ? 2 : 3);
+}
+
+// moduli for the matrix-free operators (FP64 always; FP32 too in mixed mode)
+to_status solve_prepare(Plan* p, to_dtype dt, const void* xphys, double penal, const to_solve_opts& o, hipStream_t s) {
+    if (solve_mode(dt, o) != 0) return launch_moduli(p, dt, xphys, penal, s, true);
+    return TO_OK;
+}
+
+size_t solve_args_bytes() { return sizeof(SolveArgs); }
+
+void solve_args_fill(Plan* p, to_dtype dt, const void* kval, const double* f, double* u, const to_solve_opts& o,
+                     to_solve_stats* st, void* dst) {
+    const int mode = solve_mode(dt, o);
     SolveArgs A{};
     A.geo = Geo{p->nelx, p->nely, p->nelz, p->info.nnode};
     A.freem = p->freemask;
     A.rp = p->row_ptr;
     A.kval = kval;
-    A.kdiag32 = (dt == TO_F32 && !mixed && o.op == TO_OP_ASSEMBLED) ? (const float*)kval : nullptr;
+    A.kdiag32 = (dt == TO_F32 && mode == 1 && o.op == TO_OP_ASSEMBLED) ? (const float*)kval : nullptr;
     A.E64 = p->E64; A.E32 = p->E32; A.kf64 = p->kf64; A.kf32 = p->kf32;
     A.f = f; A.u = u;
     for (int i = 0; i < 8; ++i) { A.v64[i] = p->v64[i]; A.v32[i] = p->v32[i]; }
     A.rtol = o.rtol; A.inner_rtol = o.inner_rtol; A.maxit = o.maxit;
     A.zero_x0 = o.zero_x0;
     A.partial = p->partial; A.bar = p->bar; A.st = st;
-    const int mode = !mixed ? (assembled ? 0 : 1) : (assembled ? 2 : 3);
+    std::memcpy(dst, &A, sizeof A);
+}
+
+to_status launch_solve(Plan* p, to_dtype dt, const void* kval, const void* xphys, double penal,
+                       const double* f, double* u, const to_solve_opts& o, to_solve_stats* st, hipStream_t s) {
+    if (o.op == TO_OP_ASSEMBLED && !kval) { set_error("kval is NULL"); return TO_EINVAL; }
+    to_status r = solve_prepare(p, dt, xphys, penal, o, s);
+    if (r != TO_OK) return r;
+    SolveArgs A;
+    solve_args_fill(p, dt, kval, f, u, o, st, &A);
+    const int mode = solve_mode(dt, o);
     if (p->dim == 2) {
         switch (mode) {
         case 0: return launch_solve_t<2, 0>(p, A, o.grid_blocks, s);
@@ -795,6 +828,33 @@ to_status launch_solve(Plan* p, to_dtype dt, const void* kval, const void* xphys
     case 2: return launch_solve_t<3, 2>(p, A, o.grid_blocks, s);
     default: return launch_solve_t<3, 3>(p, A, o.grid_blocks, s);
     }
+}
+
+static const void* solve_batch_fn(int dim, int mode) {
+    if (dim == 2) {
+        switch (mode) {
+        case 0: return (const void*)solve_batch_kernel<2, 0>;
+        case 1: return (const void*)solve_batch_kernel<2, 1>;
+        case 2: return (const void*)solve_batch_kernel<2, 2>;
+        default: return (const void*)solve_batch_kernel<2, 3>;
+        }
+    }
+    switch (mode) {
+    case 0: return (const void*)solve_batch_kernel<3, 0>;
+    case 1: return (const void*)solve_batch_kernel<3, 1>;
+    case 2: return (const void*)solve_batch_kernel<3, 2>;
+    default: return (const void*)solve_batch_kernel<3, 3>;
+    }
+}
+
+int solve_batch_capacity(int dim, int mode, int num_cu) {
+    return coop_blocks_for(solve_batch_fn(dim, mode), kBlock, 0, num_cu);
+}
+
+to_status launch_solve_batch(int dim, int mode, const void* tab, const BatchMap& mp, hipStream_t s) {
+    void* args[] = {(void*)&tab, (void*)&mp.inst, (void*)&mp.first, (void*)&mp.count};
+    TO_HIP(hipLaunchCooperativeKernel(solve_batch_fn(dim, mode), dim3(mp.blocks), dim3(kBlock), args, 0, s));
+    return TO_OK;
 }
 
 }  // namespace topt

@@ -182,3 +182,47 @@ class TopOpt:
             if log:
                 out.append(self.stats())
         return out
+
+
+class Batch:
+    """Many independent designs advanced together (to_step_batched): one
+    persistent launch per projection / solve / OC stage for the whole batch,
+    optionally replayed from a HIP graph."""
+
+    def __init__(self, cfgs, op=L.TO_OP_ASSEMBLED, rtol=1e-8, precision=None, solve_precision=L.TO_SOLVE_AUTO,
+                 autotune=True, maxit=200000):
+        self.runs = [TopOpt(c, op=op, rtol=rtol, precision=precision, solve_precision=solve_precision, maxit=maxit)
+                     for c in cfgs]
+        dts = {g.dtype for g in self.runs}
+        if len(dts) != 1:
+            raise ValueError("all designs of a batch need the same precision")
+        self.dtype = dts.pop()
+        n = len(self.runs)
+        self.states = (L.StepState * n)(*[g.state for g in self.runs])
+        self.params = (L.StepParams * n)(*[g.params for g in self.runs])
+        for i, g in enumerate(self.runs):          # the array is the live host state from now on
+            g.state = self.states[i]
+            g.params = self.params[i]
+        self.ws_bytes = L.to_batch_query(n)
+        dev = self.runs[0].plan.device
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        self.ws_ptr = (self.ws.data_ptr() + 255) & ~255
+        self.handle = L.to_batch_create([g.plan.handle for g in self.runs], self.dtype, self.states, self.params,
+                                        autotune, self.ws_ptr, self.ws_bytes)
+
+    def step(self, use_graph=False, stream=None):
+        L.to_step_batched(self.handle, self.states, self.params, use_graph, stream)
+
+    def info(self):
+        return L.to_batch_get_info(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.to_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
