@@ -151,6 +151,46 @@ def cpu_baseline(cfg, budget_taps=1500):
             "host_cpus": len(os.sched_getaffinity(0))}
 
 
+def batch_run(args):
+    """The 64-design ragged batch (nelx 100..400, nely = nelx / 2, MBB and
+    cantilever loads, FP32 fields): graph-replayed batched iterations against
+    the same designs advanced one by one with to_step."""
+    import torch
+    import workloads as W
+    from paper_2005_05436_amd.driver import Batch, TopOpt
+    cfgs = W.batch_configs(64, 0)
+    m_total = sum(c.m for c in cfgs)
+    b = Batch(cfgs, autotune=True)
+    b.step(use_graph=True)                       # warm-up: capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        b.step(use_graph=True)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / args.batch_steps
+    info = b.info()
+    cg = sum(g.stats()["cg_it"] for g in b.runs)
+    del b
+    singles = [TopOpt(c) for c in cfgs]
+    for g in singles:
+        g.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        for g in singles:
+            g.step()
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / args.batch_steps
+    print(f"[bench] batch64: {1e3 * tb:.1f} ms per batched iteration, {1e3 * ts:.1f} ms one by one",
+          file=sys.stderr, flush=True)
+    return {"designs": len(cfgs), "elements": m_total, "steps": args.batch_steps,
+            "ms_per_batched_step": round(1e3 * tb, 2), "ms_per_step_one_by_one": round(1e3 * ts, 2),
+            "speedup": round(ts / tb, 2), "elem_iters_per_s": round(m_total / tb, 1),
+            "cg_iterations_last_step": cg, "launch_blocks": {k: info[k] for k in ("project_blocks", "solve_blocks",
+                                                                                  "oc_blocks")},
+            "graph_captures": info["graph_captures"]}
+
+
 def nn_run(args, cfg, op, sp, plain_iters):
     """The same timed steps with the learned warm start: the network is first
     trained on the GPU (one Adam step per redesign iteration) on a run of the
@@ -211,6 +251,9 @@ def main():
     ap.add_argument("--nn-train-steps", type=int, default=13,
                     help="redesign iterations used to train the warm-start network before its timed run "
                          "(0: skip the network-warm-started run)")
+    ap.add_argument("--batch-steps", type=int, default=3,
+                    help="redesign iterations of the 64-design ragged batch, batched (graph) and one by one "
+                         "(0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size once (a counter calibration kernel)")
     args = ap.parse_args()
@@ -331,6 +374,8 @@ def main():
     }
     if args.nn_train_steps > 0 and I.dim == 2:
         line["nn_warm_start"] = nn_run(args, cfg, op, sp, iters)
+    if args.batch_steps > 0:
+        line["batch64"] = batch_run(args)
     if args.copy_probe_mib > 0:
         nb = args.copy_probe_mib << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device=g.sst.device)

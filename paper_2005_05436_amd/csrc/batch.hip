@@ -349,10 +349,13 @@ to_status to_batch_create(to_plan* const* plans, int32_t count, to_dtype dtype, 
         for (int i = 0; i < count; ++i) {
             const Plan* p = b.plans[i];
             wm[i] = (double)p->info.m;
-            wn[i] = (double)p->info.nnode;
+            // CG iterations grow with the mesh's linear size, so a design's
+            // solve work goes as (nodes)^1.5
+            wn[i] = std::pow((double)p->info.nnode, 1.5);
             cap_p[i] = (int)std::min<int64_t>(num_cu, (p->info.m + kBigBlock - 1) / kBigBlock);
             cap_o[i] = (int)std::min<int64_t>(1024, (p->info.m + 511) / 512);
-            cap_s[i] = (int)std::min<int64_t>(4 * kBlock, (p->info.nnode + kBlock - 1) / kBlock);
+            const int sb = solve_block_size(b.dim, b.mode);
+            cap_s[i] = (int)std::min<int64_t>(kMaxCoopBlocks, (p->info.nnode + sb - 1) / sb);
         }
         const int gp = std::min(project_batch_capacity(dtype, num_cu), kMaxCoopBlocks);
         const int go = std::min(oc_batch_capacity(dtype, num_cu), kMaxCoopBlocks);

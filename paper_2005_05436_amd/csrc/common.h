@@ -18,6 +18,10 @@ constexpr int kBigBlock = 1024;         // persistent design-field kernels (16 w
 constexpr int kMaxCoopBlocks = 4096;    // partial-sum slots reserved per reduction
 constexpr int kPartialWidth = 32;       // doubles per block in the partial buffer
 constexpr unsigned kSpinLimit = 1u << 27;   // grid-barrier spin cap (~several seconds)
+// Flagged partial sums (see FlagReduce): per region, block and value, two
+// 64-bit words (32-bit half of the double, 32-bit tag).
+constexpr int kLLVals = 4;
+constexpr size_t kLLBytes = 2 * (size_t)kMaxCoopBlocks * kLLVals * 2 * 8;
 
 // Device error bits written to plan->flags (never host-visible errors).
 enum : unsigned { FLAG_BARRIER_TIMEOUT = 1u, FLAG_NONFINITE = 2u };
@@ -49,6 +53,7 @@ struct Plan {
     // scratch (device)
     double* E64 = nullptr;   float* E32 = nullptr;       // m
     double* partial = nullptr;                           // kMaxCoopBlocks * kPartialWidth
+    unsigned long long* ll = nullptr;                    // flagged partial sums (kLLBytes)
     double* scal = nullptr;                              // 256 scalars
     unsigned* bar = nullptr;                             // barrier words (1024)
     double* v64[8] = {};                                 // n each
@@ -87,10 +92,28 @@ to_status hip_fail(hipError_t e, const char* what);
 
 template <typename T> struct Acc { using type = T; };
 
+// Wave-wide sum through DPP lane moves (no LDS traffic): inclusive prefix
+// sums inside each 16-lane row (shift right by 1, 2, 4, 8), then the row
+// totals are carried across rows with the row broadcasts of lanes 15 and 31;
+// lane 63 ends with the total, read back as a wave-uniform value.  The
+// order of the additions is fixed.
+template <int CTRL, int ROWS, bool BOUND>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWS, 0xf, BOUND);
+    const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWS, 0xf, BOUND);
+    return __hiloint2double(h2, l2);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
+    v += dpp_move<0x111, 0xf, true>(v);     // row_shr:1
+    v += dpp_move<0x112, 0xf, true>(v);     // row_shr:2
+    v += dpp_move<0x114, 0xf, true>(v);     // row_shr:4
+    v += dpp_move<0x118, 0xf, true>(v);     // row_shr:8
+    v += dpp_move<0x142, 0xa, false>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc, false>(v);    // row_bcast:31 into rows 2 and 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 // Deterministic block sum; result valid in every thread.  `sh` holds NB/64 doubles.
@@ -233,6 +256,110 @@ __device__ __forceinline__ void grid_reduce(const double* partial, double* out_s
     }
 }
 
+// Grid-wide sums without a separate barrier: every block publishes its K
+// block sums as flagged words (the 32-bit halves of each double, each paired
+// with a 32-bit tag in one 64-bit word, so a word is read whole or not at all)
+// and every block polls all blocks' words until they carry the current tag,
+// then sums them in block order (identical in every block).  Arrival and data
+// travel together: one device round trip for the publication and one for the
+// poll, instead of the counter atomics, the spin on the barrier word and the
+// separate read of the partials.  Tags: a per-plan epoch word (bar[4]) read
+// at kernel start, plus the reduction's running number; the kernel's block 0
+// advances the epoch at the end.  Two regions alternate, so a block can
+// publish reduction k+1 while a slower one still reads reduction k (it cannot
+// get two ahead: reduction k+1 needs every block's k+1 words, written after
+// that block finished reading k).
+struct FlagReduce {
+    unsigned long long* ll;
+    unsigned* bar;
+    unsigned epoch;
+    int red;
+    unsigned bid, nblk;
+    __device__ __forceinline__ void init(unsigned long long* l, unsigned* b, unsigned block, unsigned nblocks) {
+        ll = l; bar = b; bid = block; nblk = nblocks; red = 0;
+        epoch = ld_dev(&b[4]);
+    }
+    // K <= kLLVals; results in out_sh[0..K) (valid in every thread); false if
+    // the wait timed out or another block aborted.  Two block barriers: one
+    // after the waves' partial sums, one after the waves' shares of the poll.
+    template <int K>
+    __device__ bool reduce(const double (&v)[K], double* out_sh, double* /*unused*/) {
+        constexpr int NWMAX = 16;                      // up to 1024 threads
+        __shared__ double shA[NWMAX][K];
+        __shared__ double shB[NWMAX][K + 1];
+        const int NW = (int)(blockDim.x >> 6), NB = (int)blockDim.x;
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        unsigned long long* region = ll + (size_t)(red & 1) * kMaxCoopBlocks * kLLVals * 2;
+        const unsigned tag = epoch + (unsigned)red + 1u;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double s = wave_sum(v[k]);
+            if (lane == 0) shA[w][k] = s;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                double s = shA[0][k];
+                for (int i = 1; i < NW; ++i) s += shA[i][k];
+                const unsigned long long bits = (unsigned long long)__double_as_longlong(s);
+                unsigned long long* wd = region + ((size_t)bid * kLLVals + k) * 2;
+                st_dev(wd, ((unsigned long long)tag << 32) | (bits & 0xFFFFFFFFull));
+                st_dev(wd + 1, ((unsigned long long)tag << 32) | (bits >> 32));
+            }
+        }
+        bool ok = true;
+        double acc[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] = 0.0;
+        for (int b = threadIdx.x; b < (int)nblk; b += NB) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const unsigned long long* wd = region + ((size_t)b * kLLVals + k) * 2;
+                unsigned long long lo = ld_dev(wd), hi = ld_dev(wd + 1);
+                unsigned spins = 0;
+                while (ok && ((unsigned)(lo >> 32) != tag || (unsigned)(hi >> 32) != tag)) {
+                    if ((++spins & 255u) == 0u) {
+                        if (ld_dev(&bar[2]) != 0u) ok = false;
+                        else if (spins > kSpinLimit) {
+                            atomicOr(&bar[3], FLAG_BARRIER_TIMEOUT);
+                            atomicExch(&bar[2], 1u);
+                            ok = false;
+                        }
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    lo = ld_dev(wd);
+                    hi = ld_dev(wd + 1);
+                }
+                acc[k] += __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double s = wave_sum(acc[k]);
+            if (lane == 0) shB[w][k] = s;
+        }
+        const bool wave_ok = __all(ok);
+        if (lane == 0) shB[w][K] = wave_ok ? 1.0 : 0.0;
+        __syncthreads();
+        bool all_ok = true;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = shB[0][k];
+            for (int i = 1; i < NW; ++i) s += shB[i][k];
+            out_sh[k] = s;
+        }
+        for (int i = 0; i < NW; ++i) all_ok = all_ok && shB[i][K] != 0.0;
+        ++red;
+        return all_ok;
+    }
+    // block 0 advances the epoch once every block has published its last sums
+    __device__ __forceinline__ void finish() {
+        if (bid == 0 && threadIdx.x == 0) st_dev(&bar[4], epoch + (unsigned)red);
+    }
+};
+
 #endif  // __HIPCC__
 
 // ---------------------------------------------------------------------------
@@ -270,6 +397,7 @@ size_t solve_args_bytes();
 void solve_args_fill(Plan* p, to_dtype dt, const void* kval, const double* f, double* u, const to_solve_opts& o,
                      to_solve_stats* st, void* dst);
 int solve_batch_capacity(int dim, int mode, int num_cu);
+int solve_block_size(int dim, int mode);
 to_status launch_solve_batch(int dim, int mode, const void* tab, const BatchMap& mp, hipStream_t s);
 
 to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuning* out);

@@ -239,7 +239,7 @@ static void filter_table(const Sizes& S, double rmin, std::vector<double>& h, st
 
 struct Offsets {
     size_t perm, seg, rowp, col, pas, freem, ke64, ke32, kf64, kf32, h64, h32,
-        hlim, hp64, hp32, Hs64, Hs32, E64, E32, partial, scal, bar, v64[8], v32[8], fx64, fx32, total;
+        hlim, hp64, hp32, Hs64, Hs32, E64, E32, partial, ll, scal, bar, v64[8], v32[8], fx64, fx32, total;
 };
 
 static Offsets layout(const Sizes& S) {
@@ -265,6 +265,7 @@ static Offsets layout(const Sizes& S) {
     o.E64 = L.take(8 * S.m);
     o.E32 = L.take(4 * S.m);
     o.partial = L.take(8 * 2 * (size_t)kMaxCoopBlocks * kPartialWidth);   // two regions
+    o.ll = L.take(kLLBytes);
     o.scal = L.take(8 * 256);
     o.bar = L.take(4 * 1024);
     for (int i = 0; i < 8; ++i) o.v64[i] = L.take(8 * S.n);
@@ -411,6 +412,7 @@ to_status plan_create(const to_mesh_desc* D, void* ws, size_t ws_bytes, hipStrea
     p->Hs64 = (double*)(base + o.Hs64); p->Hs32 = (float*)(base + o.Hs32);
     p->E64 = (double*)(base + o.E64); p->E32 = (float*)(base + o.E32);
     p->partial = (double*)(base + o.partial); p->scal = (double*)(base + o.scal);
+    p->ll = (unsigned long long*)(base + o.ll);
     p->bar = (unsigned*)(base + o.bar);
     for (int i = 0; i < 8; ++i) { p->v64[i] = (double*)(base + o.v64[i]); p->v32[i] = (float*)(base + o.v32[i]); }
     p->fx64 = (double*)(base + o.fx64); p->fx32 = (float*)(base + o.fx32);
@@ -467,6 +469,7 @@ to_status plan_create(const to_mesh_desc* D, void* ws, size_t ws_bytes, hipStrea
     UP(p->hp64, hp); UP(p->hp32, hp32v);
 #undef UP
     if (e == hipSuccess) e = hipMemsetAsync(p->bar, 0, 4 * 1024, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(p->ll, 0, kLLBytes, stream);
     if (e == hipSuccess) e = hipMemsetAsync(p->scal, 0, 8 * 256, stream);
     if (e != hipSuccess) { delete p; return hip_fail(e, "plan upload"); }
     st = launch_fill_hs(p, stream);

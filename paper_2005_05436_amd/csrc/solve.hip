@@ -137,6 +137,69 @@ struct MatFree {
     }
 };
 
+// 2D: the node's 3x3 neighbourhood is gathered once (18 values of the source,
+// one load per neighbour node and component) and the four adjacent element
+// rows are applied from registers; element a of the node sees local corner b
+// at neighbourhood offset (CY[b] - CY[a], CX[b] - CX[a]).  Fully unrolled, so
+// the Ke entries are compile-time offsets into the (wave-uniform) matrix.
+template <typename T>
+struct MatFree<2, T> {
+    const T* __restrict__ E;
+    const T* __restrict__ ke;
+    int nx, ny, nz;
+    static constexpr int D = 8;
+
+    template <class S>
+    __device__ __forceinline__ void apply(int64_t nd, int iy, int ix, int, const S& src, T (&out)[2]) const {
+        constexpr int CY[4] = {1, 1, 0, 0};
+        constexpr int CX[4] = {0, 1, 1, 0};
+        const int64_t col = ny + 1;
+        T pv[3][3][2];                       // [dx + 1][dy + 1][component]
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx)
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+                const bool ok = iy + dy >= 0 && iy + dy <= ny && ix + dx >= 0 && ix + dx <= nx;
+                const int64_t q = nd + dy + col * dx;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) pv[dx + 1][dy + 1][c] = ok ? src(q, c) : T(0);
+            }
+        out[0] = T(0);
+        out[1] = T(0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int ey = iy - CY[a], ex = ix - CX[a];
+            if (ey < 0 || ey >= ny || ex < 0 || ex >= nx) continue;
+            const T Ee = E[ey + (int64_t)ny * ex];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const T* kr = ke + (a * 2 + c) * D;
+                T acc = T(0);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int dy = CY[b] - CY[a], dx = CX[b] - CX[a];
+                    acc += kr[2 * b] * pv[dx + 1][dy + 1][0] + kr[2 * b + 1] * pv[dx + 1][dy + 1][1];
+                }
+                out[c] += Ee * acc;
+            }
+        }
+    }
+    __device__ __forceinline__ void diag(int64_t, int iy, int ix, int, T (&out)[2]) const {
+        constexpr int CY[4] = {1, 1, 0, 0};
+        constexpr int CX[4] = {0, 1, 1, 0};
+        out[0] = T(0);
+        out[1] = T(0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int ey = iy - CY[a], ex = ix - CX[a];
+            if (ey < 0 || ey >= ny || ex < 0 || ex >= nx) continue;
+            const T Ee = E[ey + (int64_t)ny * ex];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) out[c] += Ee * ke[(a * 2 + c) * D + a * 2 + c];
+        }
+    }
+};
+
 // The assembled K^(s) in the plan's CSR order, read with the structure of the
 // grid instead of column indices.  The lower row of DOF (n, c) holds, for each
 // existing neighbour q < n in ascending node order, the DIM entries of q, then
@@ -236,6 +299,7 @@ struct SolveArgs {
     double rtol, inner_rtol;
     int maxit, zero_x0;
     double* partial; unsigned* bar;
+    unsigned long long* ll;
     to_solve_stats* st;
 };
 
@@ -249,16 +313,10 @@ struct Ctx {
     int red;
     bool alive;
     Own o;
+    FlagReduce fr;
     template <int K>
     __device__ __forceinline__ void reduce(const double (&v)[K]) {
-        double* region = partial + (size_t)(red & 1) * kMaxCoopBlocks * kPartialWidth;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double s = block_sum(v[k], sh);
-            if (threadIdx.x == 0) st_dev(&region[gb.bid * kPartialWidth + k], s);
-        }
-        alive = gb.sync() && alive;
-        grid_reduce<K>(region, res, sh, (int)gb.nblk);
+        alive = fr.reduce<K>(v, res, sh) && alive;
         ++red;
     }
 };
@@ -274,7 +332,7 @@ struct Pcg {
     __device__ void residual(const T* b, const T* x, bool x_zero, const T* dinv, T* r, T* z) {
         double v[2] = {0.0, 0.0};
         const Own& o = C.o;
-        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock) {
+        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
             int iy, ix, iz;
             g.coords(nd, iy, ix, iz, DIM);
             T ax[DIM];
@@ -303,7 +361,7 @@ struct Pcg {
                        double tol, int maxit, int& restarts, bool confirm = true) {
         const Own& o = C.o;
         if (x_zero)
-            for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock)
+            for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x)
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) o.st(x, nd, DIM * nd + c, T(0));
         residual(b, x, x_zero, dinv, r, z);
@@ -327,7 +385,7 @@ struct Pcg {
             // phase A: pnew = z + beta pold; q = A pnew
             double v1[1] = {0.0};
             const SrcZP<DIM, T> src{z, pold, (T)beta, o};
-            for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock) {
+            for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
                 int iy, ix, iz;
                 g.coords(nd, iy, ix, iz, DIM);
                 T ap[DIM];
@@ -349,7 +407,7 @@ struct Pcg {
             // phase B: x += alpha p; r -= alpha q; z = dinv r
             double v2[2] = {0.0, 0.0};
             const T a = (T)alpha;
-            for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock) {
+            for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) {
                     const int64_t i = DIM * nd + c;
@@ -378,7 +436,7 @@ struct Pcg {
 
 template <int DIM, typename T, class Op>
 __device__ void jacobi(const Op& op, const Geo& g, const Own& o, const uint8_t* fm, T* dinv) {
-    for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock) {
+    for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
         int iy, ix, iz;
         g.coords(nd, iy, ix, iz, DIM);
         T dg[DIM];
@@ -419,7 +477,7 @@ __device__ bool mixed_cg(Ctx& C, const Geo& g, const SolveArgs& A, const Op32& o
     // u is copied to the candidate buffer in the same sweep
     auto replace = [&](double& rz, double& rr64) {
         double v[2] = {0.0, 0.0};
-        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock) {
+        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
             int iy, ix, iz;
             g.coords(nd, iy, ix, iz, DIM);
             double ax[DIM];
@@ -457,7 +515,7 @@ __device__ bool mixed_cg(Ctx& C, const Geo& g, const SolveArgs& A, const Op32& o
     while (C.alive && iters < budget) {
         double v1[1] = {0.0};
         const SrcZP<DIM, float> src{z, pold, (float)beta, o};
-        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock) {
+        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
             int iy, ix, iz;
             g.coords(nd, iy, ix, iz, DIM);
             float ap[DIM];
@@ -478,7 +536,7 @@ __device__ bool mixed_cg(Ctx& C, const Geo& g, const SolveArgs& A, const Op32& o
         const double alpha = rz / pq;
         const float af = (float)alpha;
         double v2[2] = {0.0, 0.0};
-        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock) {
+        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
                 const int64_t i = DIM * nd + c;
@@ -529,10 +587,11 @@ __device__ bool mixed_cg(Ctx& C, const Geo& g, const SolveArgs& A, const Op32& o
 //      2: mixed, FP32 assembled inner; 3: mixed, FP32 matrix-free inner.
 template <int DIM, int MODE>
 __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
-    __shared__ double sh[kWaves];
+    __shared__ double sh[16];
     __shared__ double res[4];
-    Ctx C{A.partial, GridBar{}, sh, res, 0, true, Own{}};
+    Ctx C{A.partial, GridBar{}, sh, res, 0, true, Own{}, FlagReduce{}};
     C.gb.init(A.bar, bid, nb);
+    C.fr.init(A.ll, A.bar, bid, nb);
     {
         // contiguous node range of this block; band = largest node-index
         // distance between two nodes of one element
@@ -551,7 +610,7 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
     // |f_free|, and u = 0 on fixed DOFs (or everywhere when asked)
     {
         double v[1] = {0.0};
-        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock)
+        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x)
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
                 const int64_t i = DIM * nd + c;
@@ -577,7 +636,7 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
             iters = cg.run(A.f, u, false, dinv, r, z, pa, pb, q, tol, A.maxit, restarts);
         } else {
             if (A.kdiag32) {   // FP32 fields: Jacobi from the FP32 assembled diagonal
-                for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock)
+                for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x)
 #pragma unroll
                     for (int c = 0; c < DIM; ++c) {
                         const int64_t i = DIM * nd + c;
@@ -609,7 +668,7 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
         if (!converged && C.alive) {
             fallback = 1;
             // restart from the iterate with the smallest FP64 residual
-            for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += kBlock)
+            for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x)
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) o.st(u, nd, DIM * nd + c, ubest[DIM * nd + c]);
             C.alive = C.gb.sync() && C.alive;
@@ -620,6 +679,7 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
         }
         resid /= (bnorm > 0 ? bnorm : 1.0);
     }
+    C.fr.finish();
     if (bid == 0 && threadIdx.x == 0) {
         to_solve_stats s;
         s.residual = resid;
@@ -634,14 +694,19 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
     }
 }
 
+// Threads per block of the persistent solve: 2D FP64 kernels fit in 128
+// registers, so a block of 16 waves (one block per CU) hides the gather
+// latency without adding blocks to every grid reduction; the others use 4.
+constexpr int solve_block(int dim, int mode) { return dim == 2 && mode <= 1 ? 1024 : 256; }
+
 template <int DIM, int MODE>
-__global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs A) {
+__global__ __launch_bounds__(solve_block(DIM, MODE)) void solve_kernel(SolveArgs A) {
     solve_body<DIM, MODE>(A, blockIdx.x, gridDim.x);
 }
 
 // A batch of systems in one launch (block b: system inst[b], block b - first[inst] of count[inst]).
 template <int DIM, int MODE>
-__global__ __launch_bounds__(kBlock) void solve_batch_kernel(const SolveArgs* __restrict__ tab,
+__global__ __launch_bounds__(solve_block(DIM, MODE)) void solve_batch_kernel(const SolveArgs* __restrict__ tab,
                                                              const int32_t* __restrict__ inst,
                                                              const int32_t* __restrict__ first,
                                                              const int32_t* __restrict__ count) {
@@ -652,13 +717,14 @@ __global__ __launch_bounds__(kBlock) void solve_batch_kernel(const SolveArgs* __
 template <int DIM, int MODE>
 static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream_t s) {
     auto k = solve_kernel<DIM, MODE>;
-    int maxb = coop_blocks_for((const void*)k, kBlock, 0, p->num_cu);
-    int64_t want = (A.geo.nnode + kBlock - 1) / kBlock;
+    constexpr int SB = solve_block(DIM, MODE);
+    int maxb = coop_blocks_for((const void*)k, SB, 0, p->num_cu);
+    int64_t want = (A.geo.nnode + SB - 1) / SB;
     int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, p->num_cu), want));
     if (req_blocks > 0) blocks = std::min(req_blocks, maxb);
-    blocks = std::min(blocks, 4 * kBlock);   // the grid reduction gathers at most 4 partials per thread
+    blocks = std::min(blocks, kMaxCoopBlocks);
     void* args[] = {&A};
-    TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(kBlock), args, 0, s));
+    TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(SB), args, 0, s));
     return TO_OK;
 }
 
@@ -802,7 +868,7 @@ void solve_args_fill(Plan* p, to_dtype dt, const void* kval, const double* f, do
     for (int i = 0; i < 8; ++i) { A.v64[i] = p->v64[i]; A.v32[i] = p->v32[i]; }
     A.rtol = o.rtol; A.inner_rtol = o.inner_rtol; A.maxit = o.maxit;
     A.zero_x0 = o.zero_x0;
-    A.partial = p->partial; A.bar = p->bar; A.st = st;
+    A.partial = p->partial; A.bar = p->bar; A.ll = p->ll; A.st = st;
     std::memcpy(dst, &A, sizeof A);
 }
 
@@ -847,13 +913,16 @@ static const void* solve_batch_fn(int dim, int mode) {
     }
 }
 
+int solve_block_size(int dim, int mode) { return solve_block(dim, mode); }
+
 int solve_batch_capacity(int dim, int mode, int num_cu) {
-    return coop_blocks_for(solve_batch_fn(dim, mode), kBlock, 0, num_cu);
+    return coop_blocks_for(solve_batch_fn(dim, mode), solve_block(dim, mode), 0, num_cu);
 }
 
 to_status launch_solve_batch(int dim, int mode, const void* tab, const BatchMap& mp, hipStream_t s) {
     void* args[] = {(void*)&tab, (void*)&mp.inst, (void*)&mp.first, (void*)&mp.count};
-    TO_HIP(hipLaunchCooperativeKernel(solve_batch_fn(dim, mode), dim3(mp.blocks), dim3(kBlock), args, 0, s));
+    TO_HIP(hipLaunchCooperativeKernel(solve_batch_fn(dim, mode), dim3(mp.blocks), dim3(solve_block(dim, mode)), args,
+                                      0, s));
     return TO_OK;
 }
 
