@@ -357,15 +357,18 @@ to_status to_nn_train_step(to_nn* nn, to_dtype dtype, const void* xtilde, const 
  * 8; waves per block automatic or equal to the columns) and of the assembly
  * kernel (128, 256 or 512 threads per block; only when kval, a device buffer
  * of nnz_lower entries of `dtype`, is given) and keeps the fastest in the
- * plan.  It synchronises `stream` and overwrites the plan's scratch arrays
+ * plan (the waves per block separately for the one-field and the fused
+ * two-field filter).  It synchronises `stream` and overwrites the plan's scratch arrays
  * (moduli, filter staging) and kval.  Every shape computes the same
  * quantities (the filter sums taps in a shape-dependent order).
  * to_plan_set_tuning / to_plan_get_tuning force or read the shapes. */
 typedef struct {
     int32_t filt_v;              /* 4 or 8 */
-    int32_t filt_parts;          /* 0 (automatic) .. 16 */
+    int32_t filt_parts;          /* waves per block, one field: 0 (automatic) .. 16 */
     int32_t asm_block;           /* 128, 256 or 512 */
     int32_t tuned;               /* 1 once autotuned */
+    int32_t filt_parts2;         /* waves per block, fused double adjoint: 0 .. 16 */
+    int32_t pad;
 } to_tuning;
 to_status to_plan_autotune(to_plan* plan, to_dtype dtype, void* kval, to_tuning* h_out, void* stream);
 to_status to_plan_set_tuning(to_plan* plan, const to_tuning* h_tuning);

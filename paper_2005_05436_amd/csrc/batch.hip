@@ -179,6 +179,7 @@ to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuni
     void* scratch = dt == TO_F64 ? (void*)p->fx64 : (void*)p->fx32;
     Plan::Tune best = p->tune;
     if (p->dim == 2) {
+        // one-field filter: columns per tile and waves per block
         struct Cand { int v, parts; };
         const Cand cands[] = {{8, 0}, {8, 8}, {4, 0}, {4, 4}};
         float tbest = 1e30f;
@@ -194,6 +195,19 @@ to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuni
         }
         p->tune.filt_v = best.filt_v;
         p->tune.filt_parts = best.filt_parts;
+        // fused double adjoint: waves per block with the chosen columns
+        void* scratch2 = dt == TO_F64 ? (void*)p->v64[7] : (void*)p->v32[7];   // n >= m entries
+        tbest = 1e30f;
+        for (int parts : {0, 8, 16}) {
+            p->tune.filt_parts2 = parts;
+            to_status st = TO_OK;
+            const float t = time_ms(s, [&] {
+                if (st == TO_OK) st = launch_filter(p, dt, TO_FILTER_ADJ2, Hs, Hs, nullptr, scratch, scratch2, s);
+            }, 3);
+            if (st != TO_OK) continue;
+            if (t < tbest) { tbest = t; best.filt_parts2 = parts; }
+        }
+        p->tune.filt_parts2 = best.filt_parts2;
     }
     if (kval) {
         float tbest = 1e30f;
@@ -215,6 +229,8 @@ to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuni
         out->filt_parts = p->tune.filt_parts;
         out->asm_block = p->tune.asm_block;
         out->tuned = p->tune.tuned;
+        out->filt_parts2 = p->tune.filt_parts2;
+        out->pad = 0;
     }
     return TO_OK;
 }
@@ -244,7 +260,8 @@ to_status to_plan_autotune(to_plan* plan, to_dtype dtype, void* kval, to_tuning*
 
 to_status to_plan_set_tuning(to_plan* plan, const to_tuning* t) {
     if (!plan || !t) { set_error("to_plan_set_tuning: NULL argument"); return TO_EINVAL; }
-    if ((t->filt_v != 4 && t->filt_v != 8) || t->filt_parts < 0 || t->filt_parts > 16 ||
+    if ((t->filt_v != 4 && t->filt_v != 8) || t->filt_parts < 0 || t->filt_parts > 16 || t->filt_parts2 < 0 ||
+        t->filt_parts2 > 16 ||
         (t->asm_block != 128 && t->asm_block != 256 && t->asm_block != 512)) {
         set_error("to_plan_set_tuning: filt_v must be 4 or 8, filt_parts 0..16, asm_block 128, 256 or 512");
         return TO_EINVAL;
@@ -252,6 +269,7 @@ to_status to_plan_set_tuning(to_plan* plan, const to_tuning* t) {
     Plan* p = topt::P(plan);
     p->tune.filt_v = t->filt_v;
     p->tune.filt_parts = t->filt_parts;
+    p->tune.filt_parts2 = t->filt_parts2;
     p->tune.asm_block = t->asm_block;
     p->tune.tuned = t->tuned;
     return TO_OK;
@@ -262,8 +280,10 @@ to_status to_plan_get_tuning(const to_plan* plan, to_tuning* out) {
     const Plan* p = topt::P(plan);
     out->filt_v = p->tune.filt_v;
     out->filt_parts = p->tune.filt_parts;
+    out->filt_parts2 = p->tune.filt_parts2;
     out->asm_block = p->tune.asm_block;
     out->tuned = p->tune.tuned;
+    out->pad = 0;
     return TO_OK;
 }
 

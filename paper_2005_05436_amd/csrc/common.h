@@ -63,7 +63,8 @@ struct Plan {
     // launch shapes chosen by the autotuner (or defaults)
     struct Tune {
         int filt_v = 8;        // 2D filter: output columns per tile (4 or 8)
-        int filt_parts = 0;    // 2D filter: waves per block (0: automatic)
+        int filt_parts = 0;    // 2D filter: waves per block (0: automatic), one field
+        int filt_parts2 = 0;   // 2D filter: waves per block for the fused double adjoint
         int asm_block = 256;   // assembly: threads per block (128, 256 or 512)
         int tuned = 0;
     } tune;

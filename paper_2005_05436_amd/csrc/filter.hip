@@ -54,7 +54,46 @@ __device__ __forceinline__ T staged_value(int mode, const T* in, const T* sc, co
 // V spare window columns.  Partial sums of the parts are added through LDS.
 constexpr int kFiltV = 8, kFiltMaxParts = 16;
 
-template <typename T, int MODE, int V>
+// One chunk of V taps of a tap row: the window is cur[0..V) followed by
+// nxt[0..V) (columns kV .. kV+2V-1 after the row's first column); while the
+// FMAs run, the columns of the chunk after next are fetched into fut and the
+// next chunk's weights into wnext.  The weights come through vector memory
+// loads with a uniform address (a zero the compiler cannot see through keeps
+// them off the scalar path): scalar loads share the LDS wait counter and may
+// complete out of order, so waiting for a scalar weight would also wait for
+// the column prefetch just issued.
+template <typename T, int NF, int V, int LS>
+__device__ __forceinline__ void filt_chunk(const T* __restrict__ hrow, int k, const T* col0, const T* col0b,
+                                           int ls, int nch, T (&cur)[V], T (&nxt)[V], T (&fut)[V],
+                                           T (&cur2)[V], T (&nxt2)[V], T (&fut2)[V], const T (&wk)[V],
+                                           T (&wnext)[V], T (&acc)[V], T (&acc2)[V]) {
+    const int stride = LS ? LS : ls;
+    if (k + 1 < nch) {
+        const T* p = col0 + (size_t)(k + 2) * V * stride;
+#pragma unroll
+        for (int u = 0; u < V; ++u) fut[u] = p[(size_t)u * stride];
+        if (NF == 2) {
+            const T* p2 = col0b + (size_t)(k + 2) * V * stride;
+#pragma unroll
+            for (int u = 0; u < V; ++u) fut2[u] = p2[(size_t)u * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < V; ++u) wnext[u] = hrow[(k + 1) * V + u];
+    }
+#pragma unroll
+    for (int u = 0; u < V; ++u)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int j = u + v;
+            acc[v] += wk[u] * (j < V ? cur[j] : nxt[j - V]);
+            if (NF == 2) acc2[v] += wk[u] * (j < V ? cur2[j] : nxt2[j - V]);
+        }
+}
+
+// LS: the LDS column stride when known at compile time (0: 64 + 2R at run
+// time); a compile-time stride turns the V column reads of a chunk into one
+// base address with immediate offsets.
+template <typename T, int MODE, int V, int LS>
 __global__ __launch_bounds__(64 * kFiltMaxParts) void filter2d_kernel(
     int nely, int nelx, int R, char bc, const T* __restrict__ hp, int hps, const int32_t* __restrict__ hlim,
     const T* __restrict__ Hs, const T* __restrict__ in, const T* __restrict__ in2,
@@ -64,7 +103,8 @@ __global__ __launch_bounds__(64 * kFiltMaxParts) void filter2d_kernel(
     T* tile = reinterpret_cast<T*>(smem_raw);
     constexpr int NF = MODE == M_ADJ2 ? 2 : 1;
     const int W = 2 * R + 1;
-    const int LY = 64 + 2 * R;           // LDS column height (y, contiguous)
+    const int LY = 64 + 2 * R;           // staged rows (y, contiguous)
+    const int ls = LS ? LS : LY;         // column stride
     const int LX = V + 2 * R + V;        // LDS columns (x), V spare
     const int nty = (nely + 63) / 64, ntiles = nty * ((nelx + V - 1) / V);
     const int lane = threadIdx.x & 63;
@@ -72,7 +112,7 @@ __global__ __launch_bounds__(64 * kFiltMaxParts) void filter2d_kernel(
     // weights are scalar loads (SGPRs) rather than per-lane loads
     const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int parts = blockDim.x >> 6;
-    T* tile2 = tile + (size_t)LY * LX;
+    T* tile2 = tile + (size_t)ls * LX;
 
     for (;;) {
         if (threadIdx.x == 0) tile_sh = (int)atomicAdd(&ctr[0], 1u);
@@ -97,8 +137,8 @@ __global__ __launch_bounds__(64 * kFiltMaxParts) void filter2d_kernel(
                 else v = staged_value<T>(MODE, in, sc, Hs, e);
                 if (NF == 2) v2 = staged_value<T>(MODE, in2, sc, Hs, e);
             }
-            tile[i] = v;
-            if (NF == 2) tile2[i] = v2;
+            tile[(size_t)lx * ls + ly] = v;
+            if (NF == 2) tile2[(size_t)lx * ls + ly] = v2;
         }
         __syncthreads();
 
@@ -108,37 +148,34 @@ __global__ __launch_bounds__(64 * kFiltMaxParts) void filter2d_kernel(
         for (int dyi = part; dyi < W; dyi += parts) {
             const int lim = hlim[dyi];
             if (lim < 0) continue;
-            const T* hrow = hp + (size_t)dyi * hps;         // hrow[t] = h(dy, t - lim), zero past 2 lim
-            const T* base = tile + lane + dyi;              // LDS row of this lane at this dy
-            const T* base2 = tile2 + lane + dyi;
-            const int c0 = R - lim;                         // LDS column of output 0 at dx = -lim
-            const int ntap = 2 * lim + 1;
-            T ring[V], ring2[V];
+            // hrow[t] = h(dy, t - lim), zero past 2 lim; read per lane (see filt_chunk)
+            int zero;
+            asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+            const T* hrow = hp + (size_t)dyi * hps + zero;
+            // column R - lim of this lane's LDS row at this dy: output 0 at dx = -lim
+            const T* col0 = tile + lane + dyi + (size_t)(R - lim) * ls;
+            const T* col0b = tile2 + lane + dyi + (size_t)(R - lim) * ls;
+            const int nch = (2 * lim + 1 + V - 1) / V;
+            T A[V], B[V], C[V], A2[V], B2[V], C2[V], WA[V], WB[V], WC[V];
 #pragma unroll
-            for (int k = 0; k < V - 1; ++k) {
-                ring[k] = base[(size_t)(c0 + k) * LY];
-                if (NF == 2) ring2[k] = base2[(size_t)(c0 + k) * LY];
+            for (int u = 0; u < V; ++u) {
+                A[u] = col0[(size_t)u * ls];
+                B[u] = col0[(size_t)(V + u) * ls];
+                if (NF == 2) {
+                    A2[u] = col0b[(size_t)u * ls];
+                    B2[u] = col0b[(size_t)(V + u) * ls];
+                }
+                WA[u] = hrow[u];
             }
-            for (int t0 = 0; t0 < ntap; t0 += V) {
-                // weights and the V new columns of this chunk are fetched up front
-                T wk[V], nx[V], nx2[V];
-#pragma unroll
-                for (int u = 0; u < V; ++u) {
-                    wk[u] = hrow[t0 + u];
-                    const size_t col = (size_t)(c0 + t0 + u + V - 1) * LY;
-                    nx[u] = base[col];
-                    if (NF == 2) nx2[u] = base2[col];
-                }
-#pragma unroll
-                for (int u = 0; u < V; ++u) {
-                    ring[(u + V - 1) % V] = nx[u];
-                    if (NF == 2) ring2[(u + V - 1) % V] = nx2[u];
-#pragma unroll
-                    for (int v = 0; v < V; ++v) {
-                        acc[v] += wk[u] * ring[(u + v) % V];
-                        if (NF == 2) acc2[v] += wk[u] * ring2[(u + v) % V];
-                    }
-                }
+            // three buffers of columns and of weights rotate, so no register moves are needed
+            for (int k = 0; k < nch; k += 3) {
+                filt_chunk<T, NF, V, LS>(hrow, k, col0, col0b, ls, nch, A, B, C, A2, B2, C2, WA, WB, acc, acc2);
+                if (k + 1 < nch)
+                    filt_chunk<T, NF, V, LS>(hrow, k + 1, col0, col0b, ls, nch, B, C, A, B2, C2, A2, WB, WC, acc,
+                                             acc2);
+                if (k + 2 < nch)
+                    filt_chunk<T, NF, V, LS>(hrow, k + 2, col0, col0b, ls, nch, C, A, B, C2, A2, B2, WC, WA, acc,
+                                             acc2);
             }
         }
         // combine the parts' partial sums (the window is no longer needed)
@@ -250,9 +287,9 @@ __global__ __launch_bounds__(kBlock) void filter3d_kernel(
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, int V>
-static to_status run_filter2d(Plan* p, const T* hp, const T* Hs, const T* in, const T* in2, const T* sc, T* out,
-                              T* out2, hipStream_t s) {
+template <typename T, int MODE, int V, int LS>
+static to_status run_filter2d_ls(Plan* p, const T* hp, const T* Hs, const T* in, const T* in2, const T* sc, T* out,
+                                 T* out2, hipStream_t s) {
     constexpr int NF = MODE == M_ADJ2 ? 2 : 1;
     const int R = p->R;
     const size_t lds_max = 160 * 1024;
@@ -260,11 +297,13 @@ static to_status run_filter2d(Plan* p, const T* hp, const T* Hs, const T* in, co
     // waves per block: at least V (wave q finishes output column q); by
     // default 16 when there are enough tap rows to split, else V
     int parts = W >= 16 ? kFiltMaxParts : V;
-    if (p->tune.filt_parts > 0) parts = std::max(V, std::min(kFiltMaxParts, p->tune.filt_parts));
-    size_t lds = (size_t)NF * (64 + 2 * R) * (V + 2 * R + V) * sizeof(T);
+    const int ptune = NF == 2 ? p->tune.filt_parts2 : p->tune.filt_parts;
+    if (ptune > 0) parts = std::max(V, std::min(kFiltMaxParts, ptune));
+    const int ls = LS ? LS : 64 + 2 * R;
+    size_t lds = (size_t)NF * ls * (V + 2 * R + V) * sizeof(T);
     lds = std::max(lds, (size_t)parts * NF * V * 64 * sizeof(T));   // partial-sum reuse
     if (lds > lds_max) { set_error("filter radius too large for the LDS tile"); return TO_EUNSUPPORTED; }
-    auto k = filter2d_kernel<T, MODE, V>;
+    auto k = filter2d_kernel<T, MODE, V, LS>;
     TO_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, 64 * parts, lds) != hipSuccess ||
@@ -276,6 +315,19 @@ static to_status run_filter2d(Plan* p, const T* hp, const T* Hs, const T* in, co
                        p->hlim, Hs, in, in2, sc, out, out2, p->bar + 16);
     TO_HIP(hipGetLastError());
     return TO_OK;
+}
+
+// the LDS column stride as a compile-time constant where the radius allows
+template <typename T, int MODE, int V>
+static to_status run_filter2d(Plan* p, const T* hp, const T* Hs, const T* in, const T* in2, const T* sc, T* out,
+                              T* out2, hipStream_t s) {
+    const int ly = 64 + 2 * p->R;
+    if constexpr (V == kFiltV) {
+        if (ly <= 96) return run_filter2d_ls<T, MODE, V, 96>(p, hp, Hs, in, in2, sc, out, out2, s);
+        if (ly <= 160) return run_filter2d_ls<T, MODE, V, 160>(p, hp, Hs, in, in2, sc, out, out2, s);
+        if (ly <= 224) return run_filter2d_ls<T, MODE, V, 224>(p, hp, Hs, in, in2, sc, out, out2, s);
+    }
+    return run_filter2d_ls<T, MODE, V, 0>(p, hp, Hs, in, in2, sc, out, out2, s);
 }
 
 template <typename T, int MODE>
