@@ -202,7 +202,7 @@ def nn_run(args, cfg, op, sp, plain_iters):
     from paper_2005_05436_amd.driver import TopOpt
     from paper_2005_05436_amd.nn import LAYERS, Net
     t0 = time.perf_counter()
-    gt = TopOpt(cfg, op=op, solve_precision=sp)
+    gt = TopOpt(cfg, op=op, solve_precision=sp, autotune=True)
     net = Net(gt.plan)
     net.set_params(W.network_params(LAYERS, 0))
     for _ in range(args.nn_train_steps):
@@ -211,7 +211,7 @@ def nn_run(args, cfg, op, sp, plain_iters):
     train_s = time.perf_counter() - t0
     train_loss = float(net.loss.item())
     del gt
-    g = TopOpt(cfg, op=op, solve_precision=sp)
+    g = TopOpt(cfg, op=op, solve_precision=sp, autotune=True)
     for _ in range(args.warmup):
         g.step_stages(net)
     K = args.steps
@@ -273,10 +273,12 @@ def main():
     op = L.TO_OP_MATFREE if args.op == "matfree" else L.TO_OP_ASSEMBLED
     torch.cuda.set_device(0)
     sp = {"auto": L.TO_SOLVE_AUTO, "f64": L.TO_SOLVE_F64, "mixed": L.TO_SOLVE_MIXED}[args.solve]
-    g = TopOpt(cfg, op=op, solve_precision=sp)
+    g = TopOpt(cfg, op=op, solve_precision=sp, autotune=True)
     I = g.plan.info
     stream = torch.cuda.current_stream()
-    print(f"[bench] {cfg.name} m={I.m} n={I.n} nnz_lower={I.nnz_lower} precision={cfg.precision} op={args.op}",
+    t = g.tuning
+    print(f"[bench] {cfg.name} m={I.m} n={I.n} nnz_lower={I.nnz_lower} precision={cfg.precision} op={args.op} "
+          f"tuning: filter columns {t.filt_v}, waves {t.filt_parts} / {t.filt_parts2}, assembly block {t.asm_block}",
           file=sys.stderr, flush=True)
 
     sst_hist = torch.zeros((max(args.steps, 1), g.sst.numel()), dtype=torch.uint8, device=g.sst.device)

@@ -206,8 +206,11 @@ typedef struct {
     int32_t zero_x0;             /* 1: ignore u on entry, start from 0 */
     int32_t grid_blocks;         /* 0: automatic; else blocks of the persistent solve kernel
                                     (clamped to what can be co-resident) */
-    int32_t pad;
+    int32_t precond;             /* TO_PREC_JACOBI (default) or TO_PREC_GMG: geometric multigrid
+                                    V-cycle (2D meshes; FP64 vectors and operators for either
+                                    field precision; op and precision are then ignored) */
 } to_solve_opts;
+enum { TO_PREC_JACOBI = 0, TO_PREC_GMG = 1 };
 typedef struct {
     double residual;             /* final true relative residual (FP64) */
     double bnorm;                /* |f_free|_2 */

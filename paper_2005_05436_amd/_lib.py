@@ -58,10 +58,13 @@ class ProjectStats(C.Structure):
                 ("n_newton", C.c_int32), ("converged", C.c_int32), ("pad", C.c_int32 * 2)]
 
 
+TO_PREC_JACOBI, TO_PREC_GMG = 0, 1
+
+
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("inner_rtol", C.c_double), ("maxit", C.c_int32),
                 ("op", C.c_int32), ("precision", C.c_int32), ("zero_x0", C.c_int32),
-                ("grid_blocks", C.c_int32), ("pad", C.c_int32)]
+                ("grid_blocks", C.c_int32), ("precond", C.c_int32)]
 
 
 class SolveStats(C.Structure):

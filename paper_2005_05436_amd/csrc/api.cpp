@@ -126,7 +126,7 @@ to_status to_assemble(const to_plan* plan, to_dtype dtype, const void* xphys, do
 static to_solve_opts default_opts() {
     to_solve_opts o;
     o.rtol = 1e-8; o.inner_rtol = 0.1; o.maxit = 200000; o.op = TO_OP_ASSEMBLED;
-    o.precision = TO_SOLVE_AUTO; o.zero_x0 = 0; o.grid_blocks = 0; o.pad = 0;
+    o.precision = TO_SOLVE_AUTO; o.zero_x0 = 0; o.grid_blocks = 0; o.precond = TO_PREC_JACOBI;
     return o;
 }
 
@@ -139,7 +139,7 @@ to_status to_solve(const to_plan* plan, to_dtype dtype, const void* kval, const 
     if (!(o.rtol > 0) || !(o.inner_rtol > 0 && o.inner_rtol < 1) || o.maxit < 0 || o.grid_blocks < 0 ||
         (o.op != TO_OP_ASSEMBLED && o.op != TO_OP_MATFREE) ||
         (o.precision != TO_SOLVE_AUTO && o.precision != TO_SOLVE_F64 && o.precision != TO_SOLVE_MIXED) ||
-        (o.precision == TO_SOLVE_MIXED && dtype == TO_F64)) {
+        (o.precision == TO_SOLVE_MIXED && dtype == TO_F64) || (o.precond != TO_PREC_JACOBI && o.precond != TO_PREC_GMG)) {
         set_error("bad solve options"); return TO_EINVAL;
     }
     if ((o.op == TO_OP_MATFREE || dtype == TO_F32) && !xphys) { set_error("xphys is NULL"); return TO_EINVAL; }

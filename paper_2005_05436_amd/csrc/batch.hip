@@ -342,6 +342,9 @@ to_status to_batch_create(to_plan* const* plans, int32_t count, to_dtype dtype, 
         b.dim = b.plans[0]->dim;
         for (Plan* p : b.plans)
             if (p->dim != b.dim) { delete h; set_error("to_batch_create: designs must all be 2D or all 3D"); return TO_EINVAL; }
+        if (b.solve.precond != TO_PREC_JACOBI) {
+            delete h; set_error("to_batch_create: batches use the Jacobi-preconditioned solve"); return TO_EUNSUPPORTED;
+        }
         if (b.solve.precision == TO_SOLVE_MIXED && dtype == TO_F64) {
             delete h; set_error("to_batch_create: the mixed solve needs TO_F32 fields"); return TO_EINVAL;
         }

@@ -23,6 +23,48 @@ constexpr unsigned kSpinLimit = 1u << 27;   // grid-barrier spin cap (~several s
 constexpr int kLLVals = 4;
 constexpr size_t kLLBytes = 2 * (size_t)kMaxCoopBlocks * kLLVals * 2 * 8;
 
+// Geometric multigrid hierarchy (2D): level l+1 has ceil(n_l / 2) elements
+// per direction; coarsening stops once the level has at most kGmgCoarseMax
+// DOFs (that level is inverted densely).
+constexpr int kGmgMaxLevels = 16;
+constexpr int kGmgCoarseMax = 640;
+struct GmgShape {
+    int L = 0;
+    int nx[kGmgMaxLevels] = {}, ny[kGmgMaxLevels] = {};
+};
+inline GmgShape gmg_shape(int nelx, int nely) {
+    GmgShape g;
+    g.L = 1;
+    g.nx[0] = nelx;
+    g.ny[0] = nely;
+    while (g.L < kGmgMaxLevels) {
+        const int nx = g.nx[g.L - 1], ny = g.ny[g.L - 1];
+        const int64_t dofs = 2LL * (nx + 1) * (ny + 1);
+        if ((dofs <= kGmgCoarseMax && g.L >= 2) || (nx < 2 && ny < 2)) break;
+        g.nx[g.L] = (nx + 1) / 2;
+        g.ny[g.L] = (ny + 1) / 2;
+        ++g.L;
+    }
+    if (2LL * (g.nx[g.L - 1] + 1) * (g.ny[g.L - 1] + 1) > kGmgCoarseMax) g.L = 0;   // cannot coarsen far enough
+    return g;
+}
+struct GmgLevel {
+    int nx = 0, ny = 0;
+    int64_t nnode = 0, n = 0, m = 0;
+    double* K = nullptr;           // element matrices, 64 each (levels >= 1)
+    double *x = nullptr, *xt = nullptr, *b = nullptr, *r = nullptr, *dinv = nullptr;
+};
+struct GmgScal {
+    double rz, pq, alpha, beta, rr, bnorm, tol, roz, rz_old;
+    int32_t it, done, maxit, confirm, restarts, pad;
+};
+struct Gmg {
+    int L = 0;
+    GmgLevel lv[kGmgMaxLevels];
+    double* Ainv = nullptr;        // dense inverse of the coarsest level
+    GmgScal* scal = nullptr;
+};
+
 // Device error bits written to plan->flags (never host-visible errors).
 enum : unsigned { FLAG_BARRIER_TIMEOUT = 1u, FLAG_NONFINITE = 2u };
 
@@ -59,6 +101,8 @@ struct Plan {
     double* v64[8] = {};                                 // n each
     float* v32[8] = {};                                  // n each
     double* fx64 = nullptr;  float* fx32 = nullptr;      // m (filter staging)
+
+    Gmg gmg;                                             // multigrid hierarchy (2D)
 
     // launch shapes chosen by the autotuner (or defaults)
     struct Tune {
@@ -402,6 +446,8 @@ int solve_block_size(int dim, int mode);
 to_status launch_solve_batch(int dim, int mode, const void* tab, const BatchMap& mp, hipStream_t s);
 
 to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuning* out);
+to_status launch_solve_gmg(Plan* p, to_dtype dt, const void* xphys, double penal, const double* f, double* u,
+                           const to_solve_opts& o, to_solve_stats* st, hipStream_t s);
 to_status launch_warm_start(Plan* p, to_dtype dt, const void* xphys, double penal, const double* f,
                             const double* uh, const double* up, double* u, double* coef, hipStream_t s);
 to_status launch_solve(Plan* p, to_dtype dt, const void* kval, const void* xphys, double penal,

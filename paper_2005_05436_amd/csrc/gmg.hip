@@ -1,0 +1,654 @@
+// Geometric-multigrid preconditioned CG for the 2D state solve (eq. (5)),
+// the iterative solver family the paper uses for its large 3D runs.
+//
+// Hierarchy: level l+1 has ceil(nelx_l / 2) x ceil(nely_l / 2) elements;
+// bilinear prolongation P (a fine node at an odd index takes the mean of its
+// two coarse neighbours, so any element count coarsens; fine elements missing
+// from a coarse element simply contribute nothing).  Coarse operators are
+// Galerkin, A_{l+1} = P^T A_l P, formed element by element: inside a coarse
+// element the prolongated field is the bilinear interpolation of its four
+// corners, so a coarse element matrix is the sum over its (up to four) child
+// element matrices of P_c^T A_child P_c, with P_c the 8 x 8 local
+// interpolation of child position c.  On the finest level the child matrices
+// are E_e Ke with the rows and columns of fixed DOFs removed (the masked
+// operator of eq. (5)), so the coarse spaces respect the supports.  Coarse
+// element matrices are stored (64 doubles each); the coarsest level (at most
+// kGmgCoarseMax DOFs) is inverted densely by Gauss-Jordan elimination in one
+// block and applied as a dense matrix-vector product.
+//
+// V-cycle: damped Jacobi (weight kGmgOmega, kGmgNu sweeps before and after,
+// the same number, so the preconditioner is symmetric), residual, restriction
+// P^T, coarse correction, prolongation.  Outer iteration: flexible
+// (Polak-Ribiere) PCG, FP64, convergence on the recursive residual confirmed
+// by the true residual, like the Jacobi PCG.  All scalars live on the device;
+// every kernel returns at once when the device `done` flag is set, so the host
+// enqueues iterations in batches and reads the flag between batches.
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+#include "operators.h"
+
+namespace topt {
+
+constexpr double kGmgOmega = 0.6;
+constexpr int kGmgNu = 2;
+constexpr int kGmgBatch = 8;           // iterations enqueued between host checks
+
+
+// --- deterministic block partials + last-block finish --------------------------
+template <int K>
+__device__ __forceinline__ bool last_block_sums(const double (&v)[K], double* partial, unsigned* counter,
+                                                double (&tot)[K]) {
+    __shared__ double sh[kWaves];
+    __shared__ int last;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double s = block_sum(v[k], sh);
+        if (threadIdx.x == 0) st_dev(&partial[blockIdx.x * 8 + k], s);
+    }
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        const unsigned done = atomicAdd(counter, 1u);
+        last = done == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) s += ld_dev(&partial[b * 8 + k]);
+        tot[k] = block_sum(s, sh);
+    }
+    if (threadIdx.x == 0) st_dev(counter, 0u);
+    return true;
+}
+
+__device__ __forceinline__ void node_coords(int64_t nd, int ny, int& iy, int& ix) {
+    iy = (int)(nd % (ny + 1));
+    ix = (int)(nd / (ny + 1));
+}
+
+// --- level operators ----------------------------------------------------------
+// y = A x at node nd for a level with stored element matrices (row-major 8x8)
+__device__ __forceinline__ void elem_apply(const double* __restrict__ K, const double* __restrict__ x, int nx, int ny,
+                                           int64_t nd, int iy, int ix, double (&out)[2]) {
+    constexpr int CY[4] = {1, 1, 0, 0};
+    constexpr int CX[4] = {0, 1, 1, 0};
+    const int64_t col = ny + 1;
+    double pv[3][3][2];
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            const bool ok = iy + dy >= 0 && iy + dy <= ny && ix + dx >= 0 && ix + dx <= nx;
+            const int64_t q = nd + dy + col * dx;
+            pv[dx + 1][dy + 1][0] = ok ? x[2 * q] : 0.0;
+            pv[dx + 1][dy + 1][1] = ok ? x[2 * q + 1] : 0.0;
+        }
+    out[0] = out[1] = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int ey = iy - CY[a], ex = ix - CX[a];
+        if (ey < 0 || ey >= ny || ex < 0 || ex >= nx) continue;
+        const double* Ke = K + (size_t)(ey + (int64_t)ny * ex) * 64;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const double* kr = Ke + (2 * a + c) * 8;
+            double acc = 0.0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int dy = CY[b] - CY[a], dx = CX[b] - CX[a];
+                acc += kr[2 * b] * pv[dx + 1][dy + 1][0] + kr[2 * b + 1] * pv[dx + 1][dy + 1][1];
+            }
+            out[c] += acc;
+        }
+    }
+}
+
+struct LevelArgs {
+    int nx, ny;
+    int64_t nnode;
+    const double* K;          // stored element matrices (levels >= 1), else null
+    const double* E;          // level 0: moduli
+    const double* ke;         // level 0: element matrix
+    const uint8_t* fm;        // level 0: free mask (null above)
+};
+
+__device__ __forceinline__ void level_apply(const LevelArgs& L, const double* x, int64_t nd, int iy, int ix,
+                                            double (&out)[2]) {
+    if (L.K) {
+        elem_apply(L.K, x, L.nx, L.ny, nd, iy, ix, out);
+    } else {
+        MatFree<2, double> op{L.E, L.ke, L.nx, L.ny, 0};
+        op.apply(nd, iy, ix, 0, SrcMask<2, double>{x, L.fm}, out);
+    }
+}
+
+// mode 0: r = b - A x;  mode 1: y = x + w dinv (b - A x);  mode 2: y = w dinv b (x = 0)
+__global__ __launch_bounds__(kBlock) void gmg_sweep_kernel(LevelArgs L, int mode, const double* __restrict__ x,
+                                                           const double* __restrict__ b, const double* __restrict__ dinv,
+                                                           double* __restrict__ y, const int32_t* done) {
+    if (*done) return;
+    for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < L.nnode; nd += (int64_t)gridDim.x * kBlock) {
+        int iy, ix;
+        node_coords(nd, L.ny, iy, ix);
+        double ax[2] = {0.0, 0.0};
+        if (mode != 2) level_apply(L, x, nd, iy, ix, ax);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int64_t i = 2 * nd + c;
+            const bool fr = !L.fm || L.fm[i];
+            double v;
+            if (mode == 0) v = b[i] - ax[c];
+            else if (mode == 1) v = x[i] + kGmgOmega * dinv[i] * (b[i] - ax[c]);
+            else v = kGmgOmega * dinv[i] * b[i];
+            y[i] = fr ? v : 0.0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void gmg_diag_kernel(LevelArgs L, double* __restrict__ dinv) {
+    constexpr int CY[4] = {1, 1, 0, 0};
+    constexpr int CX[4] = {0, 1, 1, 0};
+    for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < L.nnode; nd += (int64_t)gridDim.x * kBlock) {
+        int iy, ix;
+        node_coords(nd, L.ny, iy, ix);
+        double d[2] = {0.0, 0.0};
+        for (int a = 0; a < 4; ++a) {
+            const int ey = iy - CY[a], ex = ix - CX[a];
+            if (ey < 0 || ey >= L.ny || ex < 0 || ex >= L.nx) continue;
+            const int64_t e = ey + (int64_t)L.ny * ex;
+            for (int c = 0; c < 2; ++c) {
+                const int r = 2 * a + c;
+                d[c] += L.K ? L.K[e * 64 + r * 8 + r] : L.E[e] * L.ke[r * 8 + r];
+            }
+        }
+        for (int c = 0; c < 2; ++c) {
+            const int64_t i = 2 * nd + c;
+            const bool fr = !L.fm || L.fm[i];
+            dinv[i] = fr && d[c] > 0.0 ? 1.0 / d[c] : 0.0;
+        }
+    }
+}
+
+// coarse element matrices from the children (Galerkin, element by element)
+__global__ __launch_bounds__(kBlock) void gmg_galerkin_kernel(int fnx, int fny, int cnx, int cny,
+                                                              const double* __restrict__ E,
+                                                              const double* __restrict__ ke,
+                                                              const uint8_t* __restrict__ fm,
+                                                              const double* __restrict__ Kf, double* __restrict__ Kc) {
+    constexpr int CY[4] = {1, 1, 0, 0};
+    constexpr int CX[4] = {0, 1, 1, 0};
+    const int64_t mc = (int64_t)cnx * cny;
+    for (int64_t E_c = blockIdx.x * (int64_t)kBlock + threadIdx.x; E_c < mc; E_c += (int64_t)gridDim.x * kBlock) {
+        const int ey = (int)(E_c % cny), ex = (int)(E_c / cny);
+        double acc[64];
+#pragma unroll
+        for (int i = 0; i < 64; ++i) acc[i] = 0.0;
+        for (int cx = 0; cx < 2; ++cx)
+            for (int cy = 0; cy < 2; ++cy) {
+                const int fy = 2 * ey + cy, fx = 2 * ex + cx;
+                if (fy >= fny || fx >= fnx) continue;
+                const int64_t fe = fy + (int64_t)fny * fx;
+                // interpolation weights w[b][a]: child corner b from coarse corner a
+                double w[4][4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const double yb = 0.5 * (cy + CY[b]), xb = 0.5 * (cx + CX[b]);
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) w[b][a] = (CY[a] ? yb : 1.0 - yb) * (CX[a] ? xb : 1.0 - xb);
+                }
+                // child DOF mask (finest level only)
+                bool live[8];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int64_t node = (fy + CY[b]) + (int64_t)(fny + 1) * (fx + CX[b]);
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) live[2 * b + c] = !fm || fm[2 * node + c];
+                }
+                const double Ee = E ? E[fe] : 1.0;
+                const double* A = Kf ? Kf + fe * 64 : ke;
+                // T = A_child P_c (8 x 8), then acc += P_c^T T
+#pragma unroll
+                for (int col = 0; col < 8; ++col) {            // coarse DOF 2a' + k'
+                    const int a2 = col >> 1, k2 = col & 1;
+                    double t[8];
+#pragma unroll
+                    for (int row = 0; row < 8; ++row) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int b2 = 0; b2 < 4; ++b2) {
+                            const int cc = 2 * b2 + k2;
+                            const double aij = (live[row] && live[cc]) ? Ee * A[row * 8 + cc] : 0.0;
+                            s += aij * w[b2][a2];
+                        }
+                        t[row] = s;
+                    }
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int k = 0; k < 2; ++k) {
+                            double s = 0.0;
+#pragma unroll
+                            for (int b = 0; b < 4; ++b) s += w[b][a] * t[2 * b + k];
+                            acc[(2 * a + k) * 8 + col] += s;
+                        }
+                }
+            }
+#pragma unroll
+        for (int i = 0; i < 64; ++i) Kc[E_c * 64 + i] = acc[i];
+    }
+}
+
+// b_c = P^T r_f
+__global__ __launch_bounds__(kBlock) void gmg_restrict_kernel(int fnx, int fny, int cnx, int cny,
+                                                              const double* __restrict__ rf, double* __restrict__ bc,
+                                                              const int32_t* done) {
+    if (*done) return;
+    const int64_t nc = (int64_t)(cnx + 1) * (cny + 1);
+    for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < nc; nd += (int64_t)gridDim.x * kBlock) {
+        const int I = (int)(nd % (cny + 1)), J = (int)(nd / (cny + 1));
+        double s0 = 0.0, s1 = 0.0;
+        for (int dx = -1; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int fy = 2 * I + dy, fx = 2 * J + dx;
+                if (fy < 0 || fy > fny || fx < 0 || fx > fnx) continue;
+                const double w = (dy ? 0.5 : 1.0) * (dx ? 0.5 : 1.0);
+                const int64_t q = fy + (int64_t)(fny + 1) * fx;
+                s0 += w * rf[2 * q];
+                s1 += w * rf[2 * q + 1];
+            }
+        bc[2 * nd] = s0;
+        bc[2 * nd + 1] = s1;
+    }
+}
+
+// x_f += P x_c (fixed DOFs of the finest level untouched)
+__global__ __launch_bounds__(kBlock) void gmg_prolong_kernel(int fnx, int fny, int cny, const double* __restrict__ xc,
+                                                             const uint8_t* __restrict__ fm, double* __restrict__ xf,
+                                                             const int32_t* done) {
+    if (*done) return;
+    const int64_t nf = (int64_t)(fnx + 1) * (fny + 1);
+    for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < nf; nd += (int64_t)gridDim.x * kBlock) {
+        const int fy = (int)(nd % (fny + 1)), fx = (int)(nd / (fny + 1));
+        const int y0 = fy >> 1, y1 = (fy + 1) >> 1, x0 = fx >> 1, x1 = (fx + 1) >> 1;
+        const double wy = (y0 == y1) ? 1.0 : 0.5, wx = (x0 == x1) ? 1.0 : 0.5;
+        double s[2] = {0.0, 0.0};
+        const int ys[2] = {y0, y1}, xs[2] = {x0, x1};
+        for (int i = 0; i < (x0 == x1 ? 1 : 2); ++i)
+            for (int j = 0; j < (y0 == y1 ? 1 : 2); ++j) {
+                const int64_t q = ys[j] + (int64_t)(cny + 1) * xs[i];
+                s[0] += wy * wx * xc[2 * q];
+                s[1] += wy * wx * xc[2 * q + 1];
+            }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int64_t i = 2 * nd + c;
+            if (!fm || fm[i]) xf[i] += s[c];
+        }
+    }
+}
+
+// dense coarsest matrix (rows of DOFs no element reaches get 1 on the diagonal)
+__global__ __launch_bounds__(kBlock) void gmg_dense_kernel(int nx, int ny, const double* __restrict__ K, int nc,
+                                                           double* __restrict__ A) {
+    constexpr int CY[4] = {1, 1, 0, 0};
+    constexpr int CX[4] = {0, 1, 1, 0};
+    for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < (int64_t)nc * nc;
+         idx += (int64_t)gridDim.x * kBlock) {
+        const int i = (int)(idx / nc), j = (int)(idx % nc);
+        const int ni = i >> 1, ci = i & 1, nj = j >> 1, cj = j & 1;
+        int iy, ix, jy, jx;
+        node_coords(ni, ny, iy, ix);
+        node_coords(nj, ny, jy, jx);
+        double s = 0.0;
+        if (abs(iy - jy) <= 1 && abs(ix - jx) <= 1) {
+            for (int a = 0; a < 4; ++a) {
+                const int ey = iy - CY[a], ex = ix - CX[a];
+                if (ey < 0 || ey >= ny || ex < 0 || ex >= nx) continue;
+                for (int b = 0; b < 4; ++b) {
+                    if (ey + CY[b] != jy || ex + CX[b] != jx) continue;
+                    s += K[(ey + (int64_t)ny * ex) * 64 + (2 * a + ci) * 8 + 2 * b + cj];
+                }
+            }
+        }
+        A[idx] = s;
+    }
+}
+
+// In-place inverse of the SPD coarsest matrix by Gauss-Jordan elimination
+// (one block; no pivoting is needed for SPD matrices).  A zero pivot marks a
+// DOF no coarse basis function reaches: its row and column become identity.
+__global__ __launch_bounds__(1024) void gmg_invert_kernel(double* A, int n) {
+    __shared__ double piv_row[kGmgCoarseMax];
+    __shared__ double piv_col[kGmgCoarseMax];
+    __shared__ double inv_p;
+    for (int k = 0; k < n; ++k) {
+        if (threadIdx.x == 0) {
+            const double p = A[(size_t)k * n + k];
+            inv_p = p > 0.0 ? 1.0 / p : 0.0;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            piv_row[j] = A[(size_t)k * n + j];
+            piv_col[j] = A[(size_t)j * n + k];
+        }
+        __syncthreads();
+        const double ip = inv_p;
+        for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += blockDim.x) {
+            const int i = (int)(idx / n), j = (int)(idx % n);
+            double v;
+            if (ip == 0.0) {
+                v = (i == k || j == k) ? 0.0 : A[idx];
+            } else if (i == k && j == k) {
+                v = ip;
+            } else if (i == k) {
+                v = piv_row[j] * ip;
+            } else if (j == k) {
+                v = -piv_col[i] * ip;
+            } else {
+                v = A[idx] - piv_col[i] * piv_row[j] * ip;
+            }
+            A[idx] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// x_c = A^{-1} b_c (the inverse is symmetric: thread i reads column i)
+__global__ __launch_bounds__(kBlock) void gmg_coarse_solve_kernel(const double* __restrict__ Ainv, int n,
+                                                                  const double* __restrict__ b, double* __restrict__ x,
+                                                                  const int32_t* done) {
+    if (*done) return;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += Ainv[(size_t)j * n + i] * b[j];
+        x[i] = s;
+    }
+}
+
+// --- outer flexible PCG ---------------------------------------------------------
+// r = f - A u on free DOFs, u = 0 on fixed ones; |f|, |r|
+__global__ __launch_bounds__(kBlock) void fcg_residual_kernel(LevelArgs L, const double* __restrict__ f, double* u,
+                                                              double* __restrict__ r, double* partial,
+                                                              unsigned* counter, GmgScal* S, int first) {
+    double v[2] = {0.0, 0.0};
+    for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < L.nnode; nd += (int64_t)gridDim.x * kBlock) {
+        int iy, ix;
+        node_coords(nd, L.ny, iy, ix);
+        double ax[2];
+        level_apply(L, u, nd, iy, ix, ax);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int64_t i = 2 * nd + c;
+            const bool fr = L.fm[i];
+            const double ri = fr ? f[i] - ax[c] : 0.0;
+            r[i] = ri;
+            v[0] += fr ? f[i] * f[i] : 0.0;
+            v[1] += ri * ri;
+        }
+    }
+    double tot[2];
+    if (last_block_sums<2>(v, partial, counter, tot) && threadIdx.x == 0) {
+        if (first) {
+            S->bnorm = sqrt(tot[0]);
+            S->it = 0;
+            S->restarts = 0;
+        }
+        S->rr = tot[1];
+        S->done = (tot[1] <= S->tol * S->tol) ? 1 : 0;
+    }
+}
+
+// z = M r finished: rz = r.z, roz = r_old.z; beta = (rz - roz) / rz_old (0 on restart)
+__global__ __launch_bounds__(kBlock) void fcg_dots_kernel(int64_t n, const double* __restrict__ r,
+                                                          const double* __restrict__ rold, const double* __restrict__ z,
+                                                          double* partial, unsigned* counter, GmgScal* S, int restart) {
+    if (S->done) return;
+    double v[2] = {0.0, 0.0};
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        v[0] += r[i] * z[i];
+        if (!restart) v[1] += rold[i] * z[i];
+    }
+    double tot[2];
+    if (last_block_sums<2>(v, partial, counter, tot) && threadIdx.x == 0) {
+        S->beta = restart ? 0.0 : (tot[0] - tot[1]) / S->rz_old;
+        S->rz = tot[0];
+        S->rz_old = tot[0];
+    }
+}
+
+// p = z + beta p (in place), q = A p; pq -> alpha
+__global__ __launch_bounds__(kBlock) void fcg_dir_kernel(LevelArgs L, const double* __restrict__ z,
+                                                         const double* __restrict__ pold, double* __restrict__ pnew,
+                                                         double* __restrict__ q, double* partial, unsigned* counter,
+                                                         GmgScal* S) {
+    if (S->done) return;
+    const double beta = S->beta;
+    double v[1] = {0.0};
+    for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < L.nnode; nd += (int64_t)gridDim.x * kBlock) {
+        int iy, ix;
+        node_coords(nd, L.ny, iy, ix);
+        double ap[2];
+        MatFree<2, double> op{L.E, L.ke, L.nx, L.ny, 0};
+        op.apply(nd, iy, ix, 0, SrcZP<2, double>{z, pold, beta, Own{0, L.nnode, 0}}, ap);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int64_t i = 2 * nd + c;
+            const bool fr = L.fm[i];
+            const double pi = fr ? z[i] + beta * pold[i] : 0.0;
+            const double qi = fr ? ap[c] : 0.0;
+            pnew[i] = pi;
+            q[i] = qi;
+            v[0] += pi * qi;
+        }
+    }
+    double tot[1];
+    if (last_block_sums<1>(v, partial, counter, tot) && threadIdx.x == 0) {
+        S->pq = tot[0];
+        S->alpha = tot[0] > 0.0 ? S->rz / tot[0] : 0.0;
+        if (!(tot[0] > 0.0)) S->done = 2;            // breakdown: stop
+    }
+}
+
+// u += alpha p; r_old = r; r -= alpha q; |r|
+__global__ __launch_bounds__(kBlock) void fcg_update_kernel(int64_t n, const double* __restrict__ p,
+                                                            const double* __restrict__ q, double* __restrict__ u,
+                                                            double* __restrict__ r, double* __restrict__ rold,
+                                                            double* partial, unsigned* counter, GmgScal* S) {
+    if (S->done) return;
+    const double a = S->alpha;
+    double v[1] = {0.0};
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        u[i] += a * p[i];
+        const double ri = r[i];
+        rold[i] = ri;
+        const double rn = ri - a * q[i];
+        r[i] = rn;
+        v[0] += rn * rn;
+    }
+    double tot[1];
+    if (last_block_sums<1>(v, partial, counter, tot) && threadIdx.x == 0) {
+        S->rr = tot[0];
+        S->it += 1;
+        if (tot[0] <= S->tol * S->tol || S->it >= S->maxit) S->done = 1;
+    }
+}
+
+__global__ void fcg_stats_kernel(const GmgScal* S, to_solve_stats* st, double rtol) {
+    to_solve_stats s;
+    const double bn = S->bnorm > 0.0 ? S->bnorm : 1.0;
+    s.residual = sqrt(S->rr) / bn;
+    s.bnorm = S->bnorm;
+    s.iterations = S->it;
+    s.outer = 0;
+    s.converged = s.residual <= rtol ? 1 : 0;
+    s.fallback = 0;
+    s.restarts = S->restarts;
+    s.pad = 0;
+    *st = s;
+}
+
+__global__ void fill_zero_f64_kernel(double* p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+__global__ void fcg_init_kernel(GmgScal* S, int maxit) {
+    S->it = 0;
+    S->done = 0;
+    S->maxit = maxit;
+    S->restarts = 0;
+    S->rz_old = 1.0;
+}
+
+__global__ void fcg_tol_kernel(GmgScal* S, double rtol) {
+    S->tol = rtol * S->bnorm;
+    S->done = (S->rr <= S->tol * S->tol) ? 1 : 0;
+}
+
+__global__ void fcg_reopen_kernel(GmgScal* S) {
+    if (S->rr > S->tol * S->tol && S->it < S->maxit) { S->done = 0; S->restarts += 1; }
+}
+
+// --- host ------------------------------------------------------------------------
+static int grid_of(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + kBlock - 1) / kBlock)); }
+
+static LevelArgs level_args(const Plan* p, int l) {
+    const GmgLevel& v = p->gmg.lv[l];
+    LevelArgs L{};
+    L.nx = v.nx; L.ny = v.ny; L.nnode = v.nnode;
+    if (l == 0) { L.K = nullptr; L.E = p->E64; L.ke = p->kf64; L.fm = p->freemask; }
+    else { L.K = v.K; L.E = nullptr; L.ke = nullptr; L.fm = nullptr; }
+    return L;
+}
+
+// z = M r: one V-cycle from level l (x0 = 0); level-0 vectors b = r, x = z
+static void vcycle(Plan* p, int l, const double* b, double* x, const int32_t* done, hipStream_t s) {
+    Gmg& G = p->gmg;
+    GmgLevel& v = G.lv[l];
+    if (l == G.L - 1) {
+        hipLaunchKernelGGL(gmg_coarse_solve_kernel, dim3(grid_of(v.n)), dim3(kBlock), 0, s, G.Ainv, (int)v.n, b, x,
+                           done);
+        return;
+    }
+    const LevelArgs L = level_args(p, l);
+    double* t = v.xt;     // ping-pong partner of x
+    double* r = v.r;
+    const int g = grid_of(v.nnode);
+    // pre-smoothing: first sweep from x = 0, then kGmgNu - 1 sweeps (ending in x)
+    double* cur = (kGmgNu % 2 == 1) ? x : t;
+    double* nxt = (kGmgNu % 2 == 1) ? t : x;
+    hipLaunchKernelGGL(gmg_sweep_kernel, dim3(g), dim3(kBlock), 0, s, L, 2, (const double*)nullptr, b, v.dinv, cur,
+                       done);
+    for (int k = 1; k < kGmgNu; ++k) {
+        hipLaunchKernelGGL(gmg_sweep_kernel, dim3(g), dim3(kBlock), 0, s, L, 1, cur, b, v.dinv, nxt, done);
+        std::swap(cur, nxt);
+    }
+    // residual, restriction, coarse correction, prolongation
+    hipLaunchKernelGGL(gmg_sweep_kernel, dim3(g), dim3(kBlock), 0, s, L, 0, x, b, v.dinv, r, done);
+    GmgLevel& c = G.lv[l + 1];
+    hipLaunchKernelGGL(gmg_restrict_kernel, dim3(grid_of(c.nnode)), dim3(kBlock), 0, s, v.nx, v.ny, c.nx, c.ny, r,
+                       c.b, done);
+    vcycle(p, l + 1, c.b, c.x, done, s);
+    hipLaunchKernelGGL(gmg_prolong_kernel, dim3(g), dim3(kBlock), 0, s, v.nx, v.ny, c.ny, c.x,
+                       l == 0 ? p->freemask : nullptr, x, done);
+    // post-smoothing (same count: the cycle is symmetric)
+    cur = x;
+    nxt = t;
+    for (int k = 0; k < kGmgNu; ++k) {
+        hipLaunchKernelGGL(gmg_sweep_kernel, dim3(g), dim3(kBlock), 0, s, L, 1, cur, b, v.dinv, nxt, done);
+        std::swap(cur, nxt);
+    }
+    if (cur != x) (void)hipMemcpyAsync(x, cur, 8 * v.n, hipMemcpyDeviceToDevice, s);
+}
+
+to_status gmg_setup(Plan* p, hipStream_t s) {
+    Gmg& G = p->gmg;
+    for (int l = 0; l + 1 < G.L; ++l) {
+        const GmgLevel& f = G.lv[l];
+        GmgLevel& c = G.lv[l + 1];
+        hipLaunchKernelGGL(gmg_galerkin_kernel, dim3(grid_of(c.m)), dim3(kBlock), 0, s, f.nx, f.ny, c.nx, c.ny,
+                           l == 0 ? p->E64 : nullptr, l == 0 ? p->kf64 : nullptr, l == 0 ? p->freemask : nullptr,
+                           l == 0 ? nullptr : f.K, c.K);
+    }
+    for (int l = 0; l + 1 < G.L; ++l) {
+        const LevelArgs L = level_args(p, l);
+        hipLaunchKernelGGL(gmg_diag_kernel, dim3(grid_of(G.lv[l].nnode)), dim3(kBlock), 0, s, L, G.lv[l].dinv);
+    }
+    const GmgLevel& cl = G.lv[G.L - 1];
+    const int nc = (int)cl.n;
+    hipLaunchKernelGGL(gmg_dense_kernel, dim3(grid_of((int64_t)nc * nc)), dim3(kBlock), 0, s, cl.nx, cl.ny, cl.K, nc,
+                       G.Ainv);
+    hipLaunchKernelGGL(gmg_invert_kernel, dim3(1), dim3(1024), 0, s, G.Ainv, nc);
+    TO_HIP(hipGetLastError());
+    return TO_OK;
+}
+
+to_status launch_solve_gmg(Plan* p, to_dtype dt, const void* xphys, double penal, const double* f, double* u,
+                           const to_solve_opts& o, to_solve_stats* st, hipStream_t s) {
+    Gmg& G = p->gmg;
+    if (p->dim != 2 || G.L < 2) {
+        set_error("the multigrid preconditioner is built for 2D meshes");
+        return TO_EUNSUPPORTED;
+    }
+    // FP64 moduli of the design (the FP32 design promoted for TO_F32)
+    to_status r0 = launch_moduli(p, dt, xphys, penal, s, true);
+    if (r0 != TO_OK) return r0;
+    r0 = gmg_setup(p, s);
+    if (r0 != TO_OK) return r0;
+    GmgScal* S = G.scal;
+    int32_t* done = &S->done;
+    const int64_t n = p->info.n;
+    double *r = p->v64[0], *z = p->v64[1], *pa = p->v64[2], *pb = p->v64[3], *q = p->v64[4], *rold = p->v64[5];
+    double* part = p->partial + (size_t)kMaxCoopBlocks * kPartialWidth;
+    unsigned* ctr = p->bar + 12;
+    const LevelArgs L0 = level_args(p, 0);
+    const int g0 = grid_of(p->info.nnode), gn = grid_of(n);
+    if (o.zero_x0)
+        hipLaunchKernelGGL(fill_zero_f64_kernel, dim3(gn), dim3(kBlock), 0, s, u, n);
+    hipLaunchKernelGGL(fcg_init_kernel, dim3(1), dim3(1), 0, s, S, o.maxit);
+    hipLaunchKernelGGL(fcg_residual_kernel, dim3(g0), dim3(kBlock), 0, s, L0, f, u, r, part, ctr, S, 1);
+    hipLaunchKernelGGL(fcg_tol_kernel, dim3(1), dim3(1), 0, s, S, o.rtol);
+    double* pold = z;          // beta = 0 on the first direction: p = z
+    double* pnew = pa;
+    bool restart = true;
+    const int max_rounds = 64;  // true-residual confirmations
+    for (int round = 0; round < max_rounds; ++round) {
+        int32_t h_done = 0, h_it = 0;
+        for (;;) {
+            for (int k = 0; k < kGmgBatch; ++k) {
+                vcycle(p, 0, r, z, done, s);
+                hipLaunchKernelGGL(fcg_dots_kernel, dim3(gn), dim3(kBlock), 0, s, n, r, rold, z, part, ctr, S,
+                                   restart ? 1 : 0);
+                hipLaunchKernelGGL(fcg_dir_kernel, dim3(g0), dim3(kBlock), 0, s, L0, z, pold, pnew, q, part, ctr, S);
+                hipLaunchKernelGGL(fcg_update_kernel, dim3(gn), dim3(kBlock), 0, s, n, pnew, q, u, r, rold, part, ctr,
+                                   S);
+                restart = false;
+                std::swap(pa, pb);
+                pold = pnew;
+                pnew = pa;
+            }
+            TO_HIP(hipGetLastError());
+            TO_HIP(hipMemcpyAsync(&h_done, &S->done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            TO_HIP(hipMemcpyAsync(&h_it, &S->it, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            TO_HIP(hipStreamSynchronize(s));
+            if (h_done) break;
+        }
+        if (h_done == 2 || h_it >= o.maxit) break;
+        // confirm on the true residual; reopen (restart the directions) if it misses
+        hipLaunchKernelGGL(fcg_residual_kernel, dim3(g0), dim3(kBlock), 0, s, L0, f, u, r, part, ctr, S, 0);
+        hipLaunchKernelGGL(fcg_reopen_kernel, dim3(1), dim3(1), 0, s, S);
+        TO_HIP(hipMemcpyAsync(&h_done, &S->done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        TO_HIP(hipStreamSynchronize(s));
+        if (h_done) break;
+        restart = true;
+        pold = z;
+    }
+    hipLaunchKernelGGL(fcg_stats_kernel, dim3(1), dim3(1), 0, s, S, st, o.rtol);
+    TO_HIP(hipGetLastError());
+    return TO_OK;
+}
+
+}  // namespace topt

@@ -240,6 +240,10 @@ static void filter_table(const Sizes& S, double rmin, std::vector<double>& h, st
 struct Offsets {
     size_t perm, seg, rowp, col, pas, freem, ke64, ke32, kf64, kf32, h64, h32,
         hlim, hp64, hp32, Hs64, Hs32, E64, E32, partial, ll, scal, bar, v64[8], v32[8], fx64, fx32, total;
+    // multigrid hierarchy (2D)
+    GmgShape gs;
+    size_t gK[kGmgMaxLevels], gx[kGmgMaxLevels], gxt[kGmgMaxLevels], gb[kGmgMaxLevels], gr[kGmgMaxLevels],
+        gd[kGmgMaxLevels], gAinv, gscal;
 };
 
 static Offsets layout(const Sizes& S) {
@@ -272,6 +276,23 @@ static Offsets layout(const Sizes& S) {
     for (int i = 0; i < 8; ++i) o.v32[i] = L.take(4 * S.n);
     o.fx64 = L.take(8 * S.m);
     o.fx32 = L.take(4 * S.m);
+    if (S.G.dim == 2) {
+        o.gs = gmg_shape(S.G.nx, S.G.ny);
+        for (int l = 0; l < o.gs.L; ++l) {
+            const int64_t nx = o.gs.nx[l], ny = o.gs.ny[l];
+            const int64_t n = 2 * (nx + 1) * (ny + 1);
+            o.gK[l] = l ? L.take(8 * 64 * (size_t)(nx * ny)) : 0;
+            o.gx[l] = l ? L.take(8 * n) : 0;
+            o.gb[l] = l ? L.take(8 * n) : 0;
+            o.gxt[l] = L.take(8 * n);
+            o.gr[l] = L.take(8 * n);
+            o.gd[l] = L.take(8 * n);
+        }
+        if (o.gs.L) {
+            o.gAinv = L.take(8 * (size_t)kGmgCoarseMax * kGmgCoarseMax);
+            o.gscal = L.take(sizeof(GmgScal));
+        }
+    }
     o.total = L.off;
     return o;
 }
@@ -416,6 +437,24 @@ to_status plan_create(const to_mesh_desc* D, void* ws, size_t ws_bytes, hipStrea
     p->bar = (unsigned*)(base + o.bar);
     for (int i = 0; i < 8; ++i) { p->v64[i] = (double*)(base + o.v64[i]); p->v32[i] = (float*)(base + o.v32[i]); }
     p->fx64 = (double*)(base + o.fx64); p->fx32 = (float*)(base + o.fx32);
+    p->gmg.L = o.gs.L;
+    for (int l = 0; l < o.gs.L; ++l) {
+        GmgLevel& v = p->gmg.lv[l];
+        v.nx = o.gs.nx[l]; v.ny = o.gs.ny[l];
+        v.nnode = (int64_t)(v.nx + 1) * (v.ny + 1);
+        v.n = 2 * v.nnode;
+        v.m = (int64_t)v.nx * v.ny;
+        v.K = l ? (double*)(base + o.gK[l]) : nullptr;
+        v.x = l ? (double*)(base + o.gx[l]) : nullptr;
+        v.b = l ? (double*)(base + o.gb[l]) : nullptr;
+        v.xt = (double*)(base + o.gxt[l]);
+        v.r = (double*)(base + o.gr[l]);
+        v.dinv = (double*)(base + o.gd[l]);
+    }
+    if (o.gs.L) {
+        p->gmg.Ainv = (double*)(base + o.gAinv);
+        p->gmg.scal = (GmgScal*)(base + o.gscal);
+    }
 
     int dev = 0;
     hipDeviceProp_t prop;
