@@ -14,8 +14,12 @@ and resident in HBM before the timed region.
 Printed: one JSON line.  value = elements per second through the non-solve
 path (filter + projection + assembly + sensitivity + back-filter + OC),
 m * K / (sum of those stage times); to_iters_per_s = whole iterations per
-second including the solve.  Stage times come from HIP events recorded on the
-stream the kernels run on.
+second including the Jacobi-preconditioned CG solve (the plain CG of the
+metric); roofline = the persistent PCG kernel.  Also in the line: the same
+steps with the multigrid-preconditioned CG (gmg, to_iters_per_s_gmg), with
+the learned warm start for both solvers (nn_warm_start), the 64-design
+ragged batch (batch64) and the FP64 oracle on the host (cpu_baseline).
+Stage times come from HIP events recorded on the stream the kernels run on.
 """
 import argparse
 import json
@@ -191,27 +195,14 @@ def batch_run(args):
             "graph_captures": info["graph_captures"]}
 
 
-def nn_run(args, cfg, op, sp, plain_iters):
-    """The same timed steps with the learned warm start: the network is first
-    trained on the GPU (one Adam step per redesign iteration) on a run of the
-    same problem, then a fresh run warm-starts every solve from the Galerkin
-    combination of its prediction and the previous displacement."""
+def solver_run(args, cfg, op, sp, precond, net=None):
+    """The same redesign iterations (steps warmup+1 .. warmup+K of the run)
+    with another solve set-up: the multigrid preconditioner and/or the
+    network warm start.  Returns the rate and per-step CG statistics."""
     import torch
-    import workloads as W
     from paper_2005_05436_amd import _lib as L
     from paper_2005_05436_amd.driver import TopOpt
-    from paper_2005_05436_amd.nn import LAYERS, Net
-    t0 = time.perf_counter()
-    gt = TopOpt(cfg, op=op, solve_precision=sp, autotune=True)
-    net = Net(gt.plan)
-    net.set_params(W.network_params(LAYERS, 0))
-    for _ in range(args.nn_train_steps):
-        gt.step_stages(net, train_lr=1e-3)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    train_loss = float(net.loss.item())
-    del gt
-    g = TopOpt(cfg, op=op, solve_precision=sp, autotune=True)
+    g = TopOpt(cfg, op=op, solve_precision=sp, autotune=True, precond=precond)
     for _ in range(args.warmup):
         g.step_stages(net)
     K = args.steps
@@ -226,16 +217,29 @@ def nn_run(args, cfg, op, sp, plain_iters):
     h = hist.cpu().numpy()
     st = [L.SolveStats.from_buffer_copy(h[k].tobytes()) for k in range(K)]
     its = [s.iterations for s in st]
-    print(f"[bench] warm-started run: cg iterations per step {its}", file=sys.stderr, flush=True)
     return {"to_iters_per_s": round(K / wall, 3), "ms_per_step": round(1e3 * wall / K, 3),
-            "cg_iterations_per_step": round(sum(its) / K, 1),
-            "plain_cg_iterations_per_step": round(sum(plain_iters) / K, 1),
+            "cg_iterations_per_step": round(sum(its) / K, 1), "cg_iterations": its,
             "all_converged": bool(all(s.converged for s in st)),
-            "max_true_residual": max(s.residual for s in st),
-            "train_steps": args.nn_train_steps, "train_seconds": round(train_s, 2),
-            "last_train_loss": round(train_loss, 5),
-            "note": "network trained on the first iterations of the same problem (in-sample); "
-                    "held-out gains are measured by the test suite"}
+            "max_true_residual": max(s.residual for s in st)}
+
+
+def train_net(args, cfg, op, sp, precond):
+    """The warm-start network trained on the GPU (one Adam step per redesign
+    iteration) on a run of the same problem (in-sample; held-out gains are
+    measured by the test suite)."""
+    import torch
+    import workloads as W
+    from paper_2005_05436_amd.driver import TopOpt
+    from paper_2005_05436_amd.nn import LAYERS, Net
+    t0 = time.perf_counter()
+    gt = TopOpt(cfg, op=op, solve_precision=sp, autotune=True, precond=precond)
+    net = Net(gt.plan)
+    net.set_params(W.network_params(LAYERS, 0))
+    for _ in range(args.nn_train_steps):
+        gt.step_stages(net, train_lr=1e-3)
+    torch.cuda.synchronize()
+    return net, {"train_steps": args.nn_train_steps, "train_seconds": round(time.perf_counter() - t0, 2),
+                 "last_train_loss": round(float(net.loss.item()), 5)}
 
 
 def main():
@@ -251,6 +255,8 @@ def main():
     ap.add_argument("--nn-train-steps", type=int, default=13,
                     help="redesign iterations used to train the warm-start network before its timed run "
                          "(0: skip the network-warm-started run)")
+    ap.add_argument("--no-gmg", dest="gmg", action="store_false",
+                    help="skip the run with the multigrid-preconditioned solve")
     ap.add_argument("--batch-steps", type=int, default=3,
                     help="redesign iterations of the 64-design ragged batch, batched (graph) and one by one "
                          "(0: skip)")
@@ -374,8 +380,28 @@ def main():
         "stage_hbm_frac": {s: round(v * 1e9 / HBM_PEAK, 4) for s, v in gbps.items()},
         "roofline": roof,
     }
+    if I.dim == 2 and args.gmg:
+        from paper_2005_05436_amd import _lib as L2
+        r = solver_run(args, cfg, op, sp, L2.TO_PREC_GMG)
+        print(f"[bench] multigrid run: cg iterations per step {r['cg_iterations']}", file=sys.stderr, flush=True)
+        line["gmg"] = r
+        line["to_iters_per_s_gmg"] = r["to_iters_per_s"]
     if args.nn_train_steps > 0 and I.dim == 2:
-        line["nn_warm_start"] = nn_run(args, cfg, op, sp, iters)
+        from paper_2005_05436_amd import _lib as L2
+        out = {"note": "network trained on the first iterations of the same problem (in-sample); "
+                       "held-out gains are measured by the test suite",
+               "plain_cg_iterations_per_step": round(sum(iters) / K, 1)}
+        net, info = train_net(args, cfg, op, sp, L2.TO_PREC_JACOBI)
+        out.update(info)
+        r = solver_run(args, cfg, op, sp, L2.TO_PREC_JACOBI, net)
+        print(f"[bench] warm-started run: cg iterations per step {r['cg_iterations']}", file=sys.stderr, flush=True)
+        out["jacobi"] = r
+        if args.gmg:
+            r = solver_run(args, cfg, op, sp, L2.TO_PREC_GMG, net)
+            print(f"[bench] warm-started multigrid run: cg iterations per step {r['cg_iterations']}",
+                  file=sys.stderr, flush=True)
+            out["gmg"] = r
+        line["nn_warm_start"] = out
     if args.batch_steps > 0:
         line["batch64"] = batch_run(args)
     if args.copy_probe_mib > 0:

@@ -90,7 +90,8 @@ class TopOpt:
     """The redesign loop on the GPU: state buffers + to_step."""
 
     def __init__(self, cfg, op=L.TO_OP_ASSEMBLED, rtol=1e-8, inner_rtol=0.1, maxit=200000,
-                 precision=None, passive=None, solve_precision=L.TO_SOLVE_AUTO, grid_blocks=0, autotune=False):
+                 precision=None, passive=None, solve_precision=L.TO_SOLVE_AUTO, grid_blocks=0, autotune=False,
+                 precond=L.TO_PREC_JACOBI):
         self.cfg = cfg
         self.plan, f = plan_for_config(cfg, passive)
         dev = self.plan.device
@@ -126,7 +127,8 @@ class TopOpt:
                                  cfg.penal, cfg.beta, 0, 0)
         self.params = L.StepParams(cfg.volfrac, cfg.move, cfg.ft, 0, math.nan, _sched(cfg.penal_sched),
                                    _sched(cfg.beta_sched),
-                                   L.SolveOpts(rtol, inner_rtol, maxit, op, solve_precision, 0, grid_blocks, 0))
+                                   L.SolveOpts(rtol, inner_rtol, maxit, op, solve_precision, 0, grid_blocks,
+                                               precond))
         if autotune:
             self.tuning = L.to_plan_autotune(self.plan.handle, self.dtype, self.kval if op == L.TO_OP_ASSEMBLED else None)
 
