@@ -27,7 +27,7 @@ constexpr size_t kLLBytes = 2 * (size_t)kMaxCoopBlocks * kLLVals * 2 * 8;
 // per direction; coarsening stops once the level has at most kGmgCoarseMax
 // DOFs (that level is inverted densely).
 constexpr int kGmgMaxLevels = 16;
-constexpr int kGmgCoarseMax = 640;
+constexpr int kGmgCoarseMax = 128;
 struct GmgShape {
     int L = 0;
     int nx[kGmgMaxLevels] = {}, ny[kGmgMaxLevels] = {};

@@ -172,7 +172,8 @@ __global__ __launch_bounds__(kBlock) void gmg_diag_kernel(LevelArgs L, double* _
     }
 }
 
-// coarse element matrices from the children (Galerkin, element by element)
+// coarse element matrices from the children (Galerkin, element by element):
+// one thread per (coarse element, row of its 8 x 8 matrix)
 __global__ __launch_bounds__(kBlock) void gmg_galerkin_kernel(int fnx, int fny, int cnx, int cny,
                                                               const double* __restrict__ E,
                                                               const double* __restrict__ ke,
@@ -181,25 +182,27 @@ __global__ __launch_bounds__(kBlock) void gmg_galerkin_kernel(int fnx, int fny, 
     constexpr int CY[4] = {1, 1, 0, 0};
     constexpr int CX[4] = {0, 1, 1, 0};
     const int64_t mc = (int64_t)cnx * cny;
-    for (int64_t E_c = blockIdx.x * (int64_t)kBlock + threadIdx.x; E_c < mc; E_c += (int64_t)gridDim.x * kBlock) {
+    for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < 8 * mc; t += (int64_t)gridDim.x * kBlock) {
+        const int64_t E_c = t >> 3;
+        const int row = (int)(t & 7);                  // coarse DOF 2a + k
+        const int a = row >> 1, k = row & 1;
         const int ey = (int)(E_c % cny), ex = (int)(E_c / cny);
-        double acc[64];
+        double acc[8];
 #pragma unroll
-        for (int i = 0; i < 64; ++i) acc[i] = 0.0;
+        for (int i = 0; i < 8; ++i) acc[i] = 0.0;
         for (int cx = 0; cx < 2; ++cx)
             for (int cy = 0; cy < 2; ++cy) {
                 const int fy = 2 * ey + cy, fx = 2 * ex + cx;
                 if (fy >= fny || fx >= fnx) continue;
                 const int64_t fe = fy + (int64_t)fny * fx;
-                // interpolation weights w[b][a]: child corner b from coarse corner a
+                // interpolation weights w[b][a']: child corner b from coarse corner a'
                 double w[4][4];
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const double yb = 0.5 * (cy + CY[b]), xb = 0.5 * (cx + CX[b]);
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) w[b][a] = (CY[a] ? yb : 1.0 - yb) * (CX[a] ? xb : 1.0 - xb);
+                    for (int a2 = 0; a2 < 4; ++a2) w[b][a2] = (CY[a2] ? yb : 1.0 - yb) * (CX[a2] ? xb : 1.0 - xb);
                 }
-                // child DOF mask (finest level only)
                 bool live[8];
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
@@ -209,35 +212,26 @@ __global__ __launch_bounds__(kBlock) void gmg_galerkin_kernel(int fnx, int fny, 
                 }
                 const double Ee = E ? E[fe] : 1.0;
                 const double* A = Kf ? Kf + fe * 64 : ke;
-                // T = A_child P_c (8 x 8), then acc += P_c^T T
+                // Kc[row][2a' + k'] += sum_{b, b'} w[b][a] A[2b + k][2b' + k'] w[b'][a']
 #pragma unroll
-                for (int col = 0; col < 8; ++col) {            // coarse DOF 2a' + k'
-                    const int a2 = col >> 1, k2 = col & 1;
-                    double t[8];
+                for (int b = 0; b < 4; ++b) {
+                    const int fr = 2 * b + k;
+                    if (!live[fr] || w[b][a] == 0.0) continue;
+                    const double wr = w[b][a] * Ee;
 #pragma unroll
-                    for (int row = 0; row < 8; ++row) {
-                        double s = 0.0;
+                    for (int b2 = 0; b2 < 4; ++b2)
 #pragma unroll
-                        for (int b2 = 0; b2 < 4; ++b2) {
-                            const int cc = 2 * b2 + k2;
-                            const double aij = (live[row] && live[cc]) ? Ee * A[row * 8 + cc] : 0.0;
-                            s += aij * w[b2][a2];
-                        }
-                        t[row] = s;
-                    }
+                        for (int k2 = 0; k2 < 2; ++k2) {
+                            const int fc = 2 * b2 + k2;
+                            if (!live[fc]) continue;
+                            const double v = wr * A[fr * 8 + fc];
 #pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int k = 0; k < 2; ++k) {
-                            double s = 0.0;
-#pragma unroll
-                            for (int b = 0; b < 4; ++b) s += w[b][a] * t[2 * b + k];
-                            acc[(2 * a + k) * 8 + col] += s;
+                            for (int a2 = 0; a2 < 4; ++a2) acc[2 * a2 + k2] += v * w[b2][a2];
                         }
                 }
             }
 #pragma unroll
-        for (int i = 0; i < 64; ++i) Kc[E_c * 64 + i] = acc[i];
+        for (int i = 0; i < 8; ++i) Kc[E_c * 64 + row * 8 + i] = acc[i];
     }
 }
 
@@ -317,43 +311,37 @@ __global__ __launch_bounds__(kBlock) void gmg_dense_kernel(int nx, int ny, const
     }
 }
 
-// In-place inverse of the SPD coarsest matrix by Gauss-Jordan elimination
-// (one block; no pivoting is needed for SPD matrices).  A zero pivot marks a
-// DOF no coarse basis function reaches: its row and column become identity.
+// In-place inverse of the SPD coarsest matrix by Gauss-Jordan elimination in
+// LDS (one block; no pivoting is needed for SPD matrices).  A zero pivot marks
+// a DOF no coarse basis function reaches: its row and column become zero.
 __global__ __launch_bounds__(1024) void gmg_invert_kernel(double* A, int n) {
+    __shared__ double M[kGmgCoarseMax * kGmgCoarseMax];
     __shared__ double piv_row[kGmgCoarseMax];
     __shared__ double piv_col[kGmgCoarseMax];
-    __shared__ double inv_p;
+    const int nn = n * n;
+    for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) M[idx] = A[idx];
+    __syncthreads();
     for (int k = 0; k < n; ++k) {
-        if (threadIdx.x == 0) {
-            const double p = A[(size_t)k * n + k];
-            inv_p = p > 0.0 ? 1.0 / p : 0.0;
-        }
-        __syncthreads();
         for (int j = threadIdx.x; j < n; j += blockDim.x) {
-            piv_row[j] = A[(size_t)k * n + j];
-            piv_col[j] = A[(size_t)j * n + k];
+            piv_row[j] = M[k * n + j];
+            piv_col[j] = M[j * n + k];
         }
         __syncthreads();
-        const double ip = inv_p;
-        for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += blockDim.x) {
-            const int i = (int)(idx / n), j = (int)(idx % n);
+        const double p = piv_row[k];
+        const double ip = p > 0.0 ? 1.0 / p : 0.0;
+        for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) {
+            const int i = idx / n, j = idx - i * n;
             double v;
-            if (ip == 0.0) {
-                v = (i == k || j == k) ? 0.0 : A[idx];
-            } else if (i == k && j == k) {
-                v = ip;
-            } else if (i == k) {
-                v = piv_row[j] * ip;
-            } else if (j == k) {
-                v = -piv_col[i] * ip;
-            } else {
-                v = A[idx] - piv_col[i] * piv_row[j] * ip;
-            }
-            A[idx] = v;
+            if (ip == 0.0) v = (i == k || j == k) ? 0.0 : M[idx];
+            else if (i == k && j == k) v = ip;
+            else if (i == k) v = piv_row[j] * ip;
+            else if (j == k) v = -piv_col[i] * ip;
+            else v = M[idx] - piv_col[i] * piv_row[j] * ip;
+            M[idx] = v;
         }
         __syncthreads();
     }
+    for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) A[idx] = M[idx];
 }
 
 // x_c = A^{-1} b_c (the inverse is symmetric: thread i reads column i)
@@ -569,7 +557,7 @@ to_status gmg_setup(Plan* p, hipStream_t s) {
     for (int l = 0; l + 1 < G.L; ++l) {
         const GmgLevel& f = G.lv[l];
         GmgLevel& c = G.lv[l + 1];
-        hipLaunchKernelGGL(gmg_galerkin_kernel, dim3(grid_of(c.m)), dim3(kBlock), 0, s, f.nx, f.ny, c.nx, c.ny,
+        hipLaunchKernelGGL(gmg_galerkin_kernel, dim3(grid_of(8 * c.m)), dim3(kBlock), 0, s, f.nx, f.ny, c.nx, c.ny,
                            l == 0 ? p->E64 : nullptr, l == 0 ? p->kf64 : nullptr, l == 0 ? p->freemask : nullptr,
                            l == 0 ? nullptr : f.K, c.K);
     }
