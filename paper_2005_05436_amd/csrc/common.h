@@ -63,6 +63,17 @@ struct Gmg {
     GmgLevel lv[kGmgMaxLevels];
     double* Ainv = nullptr;        // dense inverse of the coarsest level
     GmgScal* scal = nullptr;
+    // captured batches of outer iterations (first batch after a restart, and
+    // the steady batch), valid for the (u, f) they were captured with
+    hipStream_t cap = nullptr;
+    hipGraphExec_t g_first = nullptr, g_steady = nullptr;
+    const double* key_u = nullptr;
+    const double* key_f = nullptr;
+    ~Gmg() {
+        if (g_first) (void)hipGraphExecDestroy(g_first);
+        if (g_steady) (void)hipGraphExecDestroy(g_steady);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
 };
 
 // Device error bits written to plan->flags (never host-visible errors).

@@ -599,26 +599,48 @@ to_status launch_solve_gmg(Plan* p, to_dtype dt, const void* xphys, double penal
     hipLaunchKernelGGL(fcg_init_kernel, dim3(1), dim3(1), 0, s, S, o.maxit);
     hipLaunchKernelGGL(fcg_residual_kernel, dim3(g0), dim3(kBlock), 0, s, L0, f, u, r, part, ctr, S, 1);
     hipLaunchKernelGGL(fcg_tol_kernel, dim3(1), dim3(1), 0, s, S, o.rtol);
-    double* pold = z;          // beta = 0 on the first direction: p = z
-    double* pnew = pa;
+    // A batch of kGmgBatch outer iterations; the direction buffers alternate
+    // with period 2, so every batch after the first has the same launches.
+    auto enqueue_batch = [&](bool restart_first, hipStream_t cs) {
+        double* pold = restart_first ? z : pb;
+        double* pnew = pa;
+        double* other = pb;
+        for (int k = 0; k < kGmgBatch; ++k) {
+            vcycle(p, 0, r, z, done, cs);
+            hipLaunchKernelGGL(fcg_dots_kernel, dim3(gn), dim3(kBlock), 0, cs, n, r, rold, z, part, ctr, S,
+                               (restart_first && k == 0) ? 1 : 0);
+            hipLaunchKernelGGL(fcg_dir_kernel, dim3(g0), dim3(kBlock), 0, cs, L0, z, pold, pnew, q, part, ctr, S);
+            hipLaunchKernelGGL(fcg_update_kernel, dim3(gn), dim3(kBlock), 0, cs, n, pnew, q, u, r, rold, part, ctr, S);
+            pold = pnew;
+            std::swap(pnew, other);
+        }
+    };
+    // capture both batch kinds once per (u, f) and replay them
+    if (!G.cap) TO_HIP(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+    if (G.key_u != u || G.key_f != f || !G.g_first || !G.g_steady) {
+        for (hipGraphExec_t* ex : {&G.g_first, &G.g_steady}) {
+            if (*ex) { TO_HIP(hipGraphExecDestroy(*ex)); *ex = nullptr; }
+        }
+        for (int kind = 0; kind < 2; ++kind) {
+            TO_HIP(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+            enqueue_batch(kind == 0, G.cap);
+            hipGraph_t gr = nullptr;
+            hipError_t e = hipStreamEndCapture(G.cap, &gr);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(kind == 0 ? &G.g_first : &G.g_steady, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        }
+        G.key_u = u;
+        G.key_f = f;
+    }
     bool restart = true;
     const int max_rounds = 64;  // true-residual confirmations
     for (int round = 0; round < max_rounds; ++round) {
         int32_t h_done = 0, h_it = 0;
         for (;;) {
-            for (int k = 0; k < kGmgBatch; ++k) {
-                vcycle(p, 0, r, z, done, s);
-                hipLaunchKernelGGL(fcg_dots_kernel, dim3(gn), dim3(kBlock), 0, s, n, r, rold, z, part, ctr, S,
-                                   restart ? 1 : 0);
-                hipLaunchKernelGGL(fcg_dir_kernel, dim3(g0), dim3(kBlock), 0, s, L0, z, pold, pnew, q, part, ctr, S);
-                hipLaunchKernelGGL(fcg_update_kernel, dim3(gn), dim3(kBlock), 0, s, n, pnew, q, u, r, rold, part, ctr,
-                                   S);
-                restart = false;
-                std::swap(pa, pb);
-                pold = pnew;
-                pnew = pa;
-            }
-            TO_HIP(hipGetLastError());
+            TO_HIP(hipGraphLaunch(restart ? G.g_first : G.g_steady, s));
+            restart = false;
             TO_HIP(hipMemcpyAsync(&h_done, &S->done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
             TO_HIP(hipMemcpyAsync(&h_it, &S->it, sizeof(int32_t), hipMemcpyDeviceToHost, s));
             TO_HIP(hipStreamSynchronize(s));
@@ -632,7 +654,6 @@ to_status launch_solve_gmg(Plan* p, to_dtype dt, const void* xphys, double penal
         TO_HIP(hipStreamSynchronize(s));
         if (h_done) break;
         restart = true;
-        pold = z;
     }
     hipLaunchKernelGGL(fcg_stats_kernel, dim3(1), dim3(1), 0, s, S, st, o.rtol);
     TO_HIP(hipGetLastError());
