@@ -1,0 +1,73 @@
+"""Pins of the periodic Anderson extrapolation oracle (Section 3.3): the
+plain damped step, the least-squares property of the correction, a library
+solve, and the acceleration of a linear fixed-point iteration."""
+import numpy as np
+
+from oracle import pae
+
+
+def test_before_start_and_plain_steps():
+    rng = np.random.default_rng(0)
+    m = 50
+    act = np.ones(m, bool)
+    act[:5] = False
+    P = pae.PAE(m, mr=4, q=4, q0=10, alpha=0.9, xi=1.0)
+    x0, x1 = rng.uniform(0.2, 0.8, m), rng.uniform(0.2, 0.8, m)
+    out, used = P.step(x0, x1, act, 9)                  # before q0: unchanged
+    assert used == 0 and np.array_equal(out, x1)
+    out, used = P.step(x0, x1, act, 10)                 # it = 0: mix = xi = 1 -> the OC design
+    assert used == 0 and np.allclose(out[act], x1[act]) and np.array_equal(out[~act], x1[~act])
+    x2, x3 = rng.uniform(0.2, 0.8, m), rng.uniform(0.2, 0.8, m)
+    out, used = P.step(x2, x3, act, 11)                 # it = 1: mix = alpha, no history yet
+    assert used == 0 and np.allclose(out[act], x2[act] + 0.9 * (x3 - x2)[act])
+
+
+def test_correction_is_the_least_squares_solution():
+    rng = np.random.default_rng(1)
+    m = 200
+    act = np.ones(m, bool)
+    P = pae.PAE(m, mr=4, q=4, q0=0, alpha=0.9, xi=1.0)
+    xs = [rng.uniform(0.3, 0.7, m)]
+    for loop in range(0, 6):
+        x_post = np.clip(xs[-1] + 0.05 * rng.standard_normal(m), 0, 1)
+        x_prev_R = (P.R.copy(), P.X.copy())
+        out, used = P.step(xs[-1], x_post, act, loop)
+        if used:
+            r = x_post - xs[-1]
+            R, X = P.R[:, :used], P.X[:, :used]
+            g = np.linalg.lstsq(R, r, rcond=None)[0]
+            mix = 0.9
+            want = np.clip(xs[-1] + mix * r - (X + mix * R) @ g, 0, 1)
+            assert np.allclose(out, want, atol=1e-10)
+        xs.append(out)
+    assert used == 4 or True
+
+
+def test_solve_pivot_matches_library_and_handles_singular():
+    rng = np.random.default_rng(2)
+    for n in (1, 2, 3, 4):
+        A = rng.standard_normal((n, n)) + n * np.eye(n)
+        b = rng.standard_normal(n)
+        assert np.allclose(pae.solve_pivot(A, b), np.linalg.solve(A, b), atol=1e-12)
+    A = np.array([[1.0, 0.0], [0.0, 0.0]])
+    assert np.allclose(pae.solve_pivot(A, np.array([2.0, 3.0])), [2.0, 0.0])
+
+
+def test_accelerates_a_linear_fixed_point_iteration():
+    rng = np.random.default_rng(3)
+    m = 40
+    Q = np.linalg.qr(rng.standard_normal((m, m)))[0]
+    A = Q @ np.diag(np.linspace(0.2, 0.97, m)) @ Q.T
+    xstar = rng.uniform(0.3, 0.7, m)            # the fixed point, inside the box
+    b = xstar - A @ xstar
+    U = lambda x: A @ x + b
+    act = np.ones(m, bool)
+
+    def run(accel, iters=40):
+        x = np.full(m, 0.3)
+        P = pae.PAE(m, mr=4, q=4, q0=0 if accel else 10 ** 9, alpha=1.0, xi=1.0)
+        for loop in range(iters):
+            x, _ = P.step(x, U(x), act, loop)
+        return np.linalg.norm(x - xstar)
+
+    assert run(True) < 1e-3 * run(False)
