@@ -15,9 +15,12 @@ result is clipped to [0, 1].  Only active elements take part.
 Readings (the paper's formula for the second case of eq. (23) is garbled;
 the code given with it is followed): the step counter it = loop - q0; the
 history gains a column from it = 2 on (column (it - 1) mod m_r); the Anderson
-correction is applied when it > 1 and (it - 1) mod q == 0; the normal
-equations are solved by Gaussian elimination with partial pivoting (a
-singular system gives gamma = 0).
+correction is applied when it > 1 and (it - 1) mod q == 0; the history
+arrays of the code grow to the largest column index written, so the
+correction uses min(it, m_r) columns, the first of which is still zero
+before it = m_r + 1; the normal equations are solved by Gaussian elimination
+with partial pivoting, a zero pivot giving that coefficient 0 (so a zero
+column drops out).
 """
 import numpy as np
 
@@ -51,7 +54,7 @@ class PAE:
             self.X[:, k] = x - self.xold
             self.R[:, k] = r - self.rold
             if (it - 1) % self.q == 0:
-                nc = min(it - 1, self.mr)
+                nc = min(it, self.mr)
                 Xc, Rc = self.X[:, :nc], self.R[:, :nc]
                 gamma = solve_pivot(Rc.T @ Rc, Rc.T @ r)
                 dp = (Xc + mix * Rc) @ gamma

@@ -71,3 +71,32 @@ def test_accelerates_a_linear_fixed_point_iteration():
         return np.linalg.norm(x - xstar)
 
     assert run(True) < 1e-3 * run(False)
+
+
+def test_early_correction_uses_every_written_column():
+    """q < m_r: the first correction (it = 3) uses the two differences formed
+    at it = 2 and it = 3 (the code's history has grown to three columns, the
+    first still zero and dropping out), i.e. the least-squares fit over those
+    two columns only."""
+    rng = np.random.default_rng(4)
+    m = 120
+    act = np.ones(m, bool)
+    P = pae.PAE(m, mr=4, q=2, q0=0, alpha=0.8, xi=0.7)
+    x = rng.uniform(0.3, 0.7, m)
+    pres, rs = [], []
+    for loop in range(4):
+        x_post = np.clip(x + 0.05 * rng.standard_normal(m), 0, 1)
+        pres.append(x.copy())
+        rs.append(x_post - x)
+        out, used = P.step(x, x_post, act, loop)
+        if loop == 3:
+            assert used == 3
+            Xc = np.stack([pres[2] - pres[1], pres[3] - pres[2]], 1)
+            Rc = np.stack([rs[2] - rs[1], rs[3] - rs[2]], 1)
+            g = np.linalg.lstsq(Rc, rs[3], rcond=None)[0]
+            mix = 0.8                               # it = 3 is not a multiple of q
+            want = np.clip(pres[3] + mix * rs[3] - (Xc + mix * Rc) @ g, 0, 1)
+            assert np.allclose(out, want, atol=1e-10)
+        else:
+            assert used == 0
+        x = out
