@@ -411,6 +411,29 @@ to_status to_step_batched(to_batch* batch, to_step_state* states, const to_step_
 to_status to_batch_get_info(const to_batch* batch, int32_t* h_out);
 void to_batch_destroy(to_batch* batch);
 
+/* ---------------------------------------------------------------------------
+ * to_pae_step -- periodic Anderson extrapolation of the OC iteration (Section
+ * 3.3, eq. (20)-(23), following the code given there).  Call after the OC
+ * update of iteration `loop` with x = the design after it (device, m, in/out)
+ * and x_pre = the design before it (device, m).  For it = loop - q0 >= 0:
+ * r = x - x_pre on active elements; mix = xi if it % q == 0 else alpha; from
+ * it = 2 on the history column (it - 1) % mr receives x_pre - x_pre_old and
+ * r - r_old; when it > 1 and (it - 1) % q == 0, gamma solves
+ * R^T R gamma = R^T r (Gaussian elimination with partial pivoting; a zero
+ * pivot sets that coefficient to 0) over the min(it, mr) columns and
+ * dp = (X + mix R) gamma, else dp = 0; x = clip(x_pre + mix r - dp, 0, 1) on
+ * active elements.  Before q0 nothing is done.  ws: caller-owned device
+ * memory of to_pae_query bytes holding the FP64 history; it must be zeroed
+ * before the first call of a run and kept between calls.  d_gamma (nullable):
+ * device doubles receiving the coefficients.  mr <= 8, q >= 1. */
+typedef struct {
+    int32_t mr, q, q0, pad;
+    double alpha, xi;
+} to_pae_params;
+to_status to_pae_query(const to_plan* plan, const to_pae_params* h_params, size_t* ws_bytes);
+to_status to_pae_step(const to_plan* plan, to_dtype dtype, void* x, const void* x_pre, int32_t loop,
+                      const to_pae_params* h_params, void* ws, double* d_gamma, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

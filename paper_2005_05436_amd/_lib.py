@@ -30,7 +30,7 @@ EXPORTED = ["to_plan_query", "to_plan_create", "to_plan_destroy", "to_plan_get_i
             "to_nn_query", "to_nn_create", "to_nn_destroy", "to_nn_set_params", "to_nn_get", "to_nn_forward",
             "to_nn_backward", "to_nn_adam", "to_nn_train_step", "to_plan_autotune", "to_plan_set_tuning",
             "to_plan_get_tuning", "to_batch_query", "to_batch_create", "to_step_batched", "to_batch_get_info",
-            "to_batch_destroy"]
+            "to_batch_destroy", "to_pae_query", "to_pae_step"]
 
 
 class ToError(RuntimeError):
@@ -98,6 +98,11 @@ class StepState(C.Structure):
 _lib = None
 
 
+class PaeParams(C.Structure):
+    _fields_ = [("mr", C.c_int32), ("q", C.c_int32), ("q0", C.c_int32), ("pad", C.c_int32),
+                ("alpha", C.c_double), ("xi", C.c_double)]
+
+
 class Tuning(C.Structure):
     _fields_ = [("filt_v", C.c_int32), ("filt_parts", C.c_int32), ("asm_block", C.c_int32), ("tuned", C.c_int32),
                 ("filt_parts2", C.c_int32), ("pad", C.c_int32)]
@@ -139,6 +144,8 @@ def load():
         "to_step_batched": (S, [P, P, P, C.c_int32, P]),
         "to_batch_get_info": (S, [P, C.POINTER(C.c_int32)]),
         "to_batch_destroy": (None, [P]),
+        "to_pae_query": (S, [P, C.POINTER(PaeParams), C.POINTER(C.c_size_t)]),
+        "to_pae_step": (S, [P, S, P, P, C.c_int32, C.POINTER(PaeParams), P, P, P]),
         "to_nn_query": (S, [C.c_int32, C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_int64)]),
         "to_nn_create": (S, [P, P, C.c_size_t, C.POINTER(P)]),
         "to_nn_destroy": (None, [P]),
@@ -254,6 +261,17 @@ def to_continuation(par, sched, loop):
 def to_warm_start(plan, dtype, xphys, penal, f, uhat, uprev, u, d_coef=None, stream=None):
     check(load().to_warm_start(plan, dtype, ptr(xphys), penal, ptr(f), ptr(uhat), ptr(uprev), ptr(u), ptr(d_coef),
                                stream_ptr(stream)))
+
+
+def to_pae_query(plan, params):
+    ws = C.c_size_t(0)
+    check(load().to_pae_query(plan, C.byref(params), C.byref(ws)))
+    return ws.value
+
+
+def to_pae_step(plan, dtype, x, x_pre, loop, params, ws, d_gamma=None, stream=None):
+    check(load().to_pae_step(plan, dtype, ptr(x), ptr(x_pre), loop, C.byref(params), ptr(ws), ptr(d_gamma),
+                             stream_ptr(stream)))
 
 
 TO_NN_PARAMS, TO_NN_GRAD, TO_NN_OUTPUT, TO_NN_ACT, TO_NN_PRESKIP = 0, 1, 2, 16, 32

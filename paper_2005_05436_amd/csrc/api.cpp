@@ -176,6 +176,28 @@ to_status to_oc_update(const to_plan* plan, to_dtype dtype, void* x, const void*
     TO_GUARD(launch_oc(P(plan), dtype, x, dc, dv, volfrac, move, d_stats, S(stream)));
 }
 
+static bool pae_params_ok(const to_pae_params* q) {
+    return q && q->mr >= 1 && q->mr <= 8 && q->q >= 1 && q->q0 >= 0 && std::isfinite(q->alpha) &&
+           std::isfinite(q->xi);
+}
+
+to_status to_pae_query(const to_plan* plan, const to_pae_params* prm, size_t* ws_bytes) {
+    NEED(plan, "plan"); NEED(ws_bytes, "ws_bytes");
+    if (!pae_params_ok(prm)) { set_error("pae: mr must be 1..8, q >= 1, q0 >= 0, alpha and xi finite"); return TO_EINVAL; }
+    *ws_bytes = pae_workspace_bytes(P(plan)->info.m, prm->mr);
+    return TO_OK;
+}
+
+to_status to_pae_step(const to_plan* plan, to_dtype dtype, void* x, const void* x_pre, int32_t loop,
+                      const to_pae_params* prm, void* ws, double* d_gamma, void* stream) {
+    NEED(plan, "plan");
+    if (check_dtype(dtype)) return TO_EINVAL;
+    NEED(x, "x"); NEED(x_pre, "x_pre"); NEED(ws, "ws");
+    if (!pae_params_ok(prm)) { set_error("pae: mr must be 1..8, q >= 1, q0 >= 0, alpha and xi finite"); return TO_EINVAL; }
+    if (x == x_pre) { set_error("pae: x and x_pre may not alias"); return TO_EINVAL; }
+    TO_GUARD(launch_pae(P(plan), dtype, x, x_pre, loop, *prm, ws, d_gamma, S(stream)));
+}
+
 double to_continuation(double par, const to_sched* s, int32_t loop) {
     if (!s || !s->enabled || s->isteps <= 0) return par;
     if (loop >= s->istart && par < s->maxpar && loop % s->isteps == 0) return s->mul ? par * s->delta : par + s->delta;

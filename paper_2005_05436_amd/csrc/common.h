@@ -456,6 +456,9 @@ int solve_batch_capacity(int dim, int mode, int num_cu);
 int solve_block_size(int dim, int mode);
 to_status launch_solve_batch(int dim, int mode, const void* tab, const BatchMap& mp, hipStream_t s);
 
+size_t pae_workspace_bytes(int64_t m, int mr);
+to_status launch_pae(Plan* p, to_dtype dt, void* x, const void* xpre, int32_t loop, const to_pae_params& prm,
+                     void* ws, double* d_gamma, hipStream_t s);
 to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuning* out);
 to_status launch_solve_gmg(Plan* p, to_dtype dt, const void* xphys, double penal, const double* f, double* u,
                            const to_solve_opts& o, to_solve_stats* st, hipStream_t s);

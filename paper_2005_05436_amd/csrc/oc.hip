@@ -284,3 +284,186 @@ to_status launch_oc(Plan* p, to_dtype dt, void* x, const void* dc, const void* d
 }
 
 }  // namespace topt
+
+// ---------------------------------------------------------------------------
+// Periodic Anderson extrapolation of the OC fixed-point iteration (Section
+// 3.3, eq. (20)-(23) with the code given there): r = x_post - x_pre on the
+// active elements; the history holds the last m_r differences of the
+// pre-OC designs (X) and of the residuals (R) in FP64; every q-th step the
+// correction dp = (X + mix R) gamma, gamma solving the normal equations
+// R^T R gamma = R^T r; the design becomes clip(x_pre + mix r - dp, 0, 1).
+// Kernel 1 updates the history column and, on correction steps, reduces the
+// Gram matrix and right-hand side (block partials, the last block solves the
+// small system by Gaussian elimination with partial pivoting); kernel 2
+// applies the update.  The history has min(it, m_r) columns by the
+// correction steps; before it = m_r + 1 the first is still zero (it was never
+// written) and drops out through the zero-pivot rule.
+namespace topt {
+
+constexpr int kPaeMaxM = 8;
+
+struct PaeArgs {
+    int64_t m;
+    const uint8_t* pas;
+    int mr, col, nc, gram;      // history length, column to write (-1: none), columns used, correction?
+    double mix;
+    double* X; double* R; double* xold; double* rold;   // mr x m, mr x m, m, m
+    double* gamma;                                      // kPaeMaxM
+    double* partial;
+    unsigned* counter;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void pae_history_kernel(PaeArgs a, const T* __restrict__ xpost,
+                                                             const T* __restrict__ xpre) {
+    constexpr int NV = kPaeMaxM * (kPaeMaxM + 1) / 2 + kPaeMaxM;
+    __shared__ double sh[kWaves];
+    __shared__ int last;
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.m; i += (int64_t)gridDim.x * kBlock) {
+        const bool act = a.pas[i] == TO_ACTIVE;
+        const double x = act ? (double)xpre[i] : 0.0;
+        const double r = act ? (double)xpost[i] - (double)xpre[i] : 0.0;
+        if (a.col >= 0) {
+            a.X[(size_t)a.col * a.m + i] = x - a.xold[i];
+            a.R[(size_t)a.col * a.m + i] = r - a.rold[i];
+        }
+        if (a.gram) {
+            double Rc[kPaeMaxM];
+#pragma unroll
+            for (int c = 0; c < kPaeMaxM; ++c) Rc[c] = c < a.nc ? a.R[(size_t)c * a.m + i] : 0.0;
+            int t = 0;
+#pragma unroll
+            for (int c = 0; c < kPaeMaxM; ++c)
+#pragma unroll
+                for (int d = 0; d <= c; ++d) v[t++] += Rc[c] * Rc[d];
+#pragma unroll
+            for (int c = 0; c < kPaeMaxM; ++c) v[t++] += Rc[c] * r;
+        }
+    }
+    if (!a.gram) return;
+    // block partials, then the last block sums them in block order and solves
+    double tot[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double s = block_sum(v[k], sh);
+        if (threadIdx.x == 0) st_dev(&a.partial[(size_t)blockIdx.x * 64 + k], s);
+    }
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        last = atomicAdd(a.counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) s += ld_dev(&a.partial[(size_t)b * 64 + k]);
+        tot[k] = block_sum(s, sh);
+    }
+    if (threadIdx.x == 0) {
+        const int n = a.nc;
+        double A[kPaeMaxM][kPaeMaxM], b[kPaeMaxM], g[kPaeMaxM];
+        int t = 0;
+        for (int c = 0; c < kPaeMaxM; ++c)
+            for (int d = 0; d <= c; ++d, ++t) { A[c][d] = tot[t]; A[d][c] = tot[t]; }
+        for (int c = 0; c < kPaeMaxM; ++c) b[c] = tot[t++];
+        double scale = 0.0;
+        for (int c = 0; c < n; ++c)
+            for (int d = 0; d < n; ++d) scale = fmax(scale, fabs(A[c][d]));
+        scale = fmax(scale, 1e-300);
+        for (int k = 0; k < n; ++k) {
+            int p = k;
+            for (int i = k + 1; i < n; ++i) if (fabs(A[i][k]) > fabs(A[p][k])) p = i;
+            if (p != k) {
+                for (int j = 0; j < n; ++j) { const double tmp = A[k][j]; A[k][j] = A[p][j]; A[p][j] = tmp; }
+                const double tb = b[k]; b[k] = b[p]; b[p] = tb;
+            }
+            if (fabs(A[k][k]) <= 1e-14 * scale) {          // singular: this unknown is 0
+                for (int j = 0; j < n; ++j) { A[k][j] = 0.0; A[j][k] = 0.0; }
+                A[k][k] = 1.0;
+                b[k] = 0.0;
+                continue;
+            }
+            for (int i = k + 1; i < n; ++i) {
+                const double f = A[i][k] / A[k][k];
+                for (int j = k; j < n; ++j) A[i][j] -= f * A[k][j];
+                b[i] -= f * b[k];
+            }
+        }
+        for (int k = n - 1; k >= 0; --k) {
+            double s = b[k];
+            for (int j = k + 1; j < n; ++j) s -= A[k][j] * g[j];
+            g[k] = s / A[k][k];
+        }
+        for (int k = 0; k < kPaeMaxM; ++k) a.gamma[k] = k < n ? g[k] : 0.0;
+        st_dev(a.counter, 0u);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void pae_update_kernel(PaeArgs a, T* __restrict__ x, const T* __restrict__ xpre) {
+    double g[kPaeMaxM];
+#pragma unroll
+    for (int c = 0; c < kPaeMaxM; ++c) g[c] = a.gram && c < a.nc ? a.gamma[c] : 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.m; i += (int64_t)gridDim.x * kBlock) {
+        const bool act = a.pas[i] == TO_ACTIVE;
+        const double xp = act ? (double)xpre[i] : 0.0;
+        const double r = act ? (double)x[i] - (double)xpre[i] : 0.0;
+        double dp = 0.0;
+        if (a.gram) {
+#pragma unroll
+            for (int c = 0; c < kPaeMaxM; ++c)
+                if (c < a.nc) dp += g[c] * (a.X[(size_t)c * a.m + i] + a.mix * a.R[(size_t)c * a.m + i]);
+        }
+        a.xold[i] = xp;
+        a.rold[i] = r;
+        if (act) x[i] = (T)fmin(fmax(xp + a.mix * r - dp, 0.0), 1.0);
+    }
+}
+
+size_t pae_workspace_bytes(int64_t m, int mr) { return sizeof(double) * ((size_t)(2 * mr + 2) * m + kPaeMaxM); }
+
+to_status launch_pae(Plan* p, to_dtype dt, void* x, const void* xpre, int32_t loop, const to_pae_params& prm,
+                     void* ws, double* d_gamma, hipStream_t s) {
+    const int64_t m = p->info.m;
+    const int it = loop - prm.q0;
+    if (it < 0) return TO_OK;
+    PaeArgs a{};
+    a.m = m;
+    a.pas = p->passive;
+    a.mr = prm.mr;
+    double* w = (double*)ws;
+    a.X = w;
+    a.R = w + (size_t)prm.mr * m;
+    a.xold = w + (size_t)2 * prm.mr * m;
+    a.rold = w + (size_t)(2 * prm.mr + 1) * m;
+    a.gamma = d_gamma ? d_gamma : w + (size_t)(2 * prm.mr + 2) * m;
+    a.partial = p->partial + (size_t)kMaxCoopBlocks * kPartialWidth;
+    a.counter = p->bar + 14;
+    a.mix = (it % prm.q == 0) ? prm.xi : prm.alpha;
+    a.col = it > 1 ? (it - 1) % prm.mr : -1;
+    a.gram = (it > 1 && (it - 1) % prm.q == 0) ? 1 : 0;
+    a.nc = a.gram ? std::min(it, prm.mr) : 0;     // the history has grown to min(it, mr) columns
+    const int blocks = (int)std::min<int64_t>(2048, (m + kBlock - 1) / kBlock);
+    const bool hist = a.col >= 0 || a.gram;
+    if (dt == TO_F64) {
+        if (hist)
+            hipLaunchKernelGGL(pae_history_kernel<double>, dim3(blocks), dim3(kBlock), 0, s, a, (const double*)x,
+                               (const double*)xpre);
+        hipLaunchKernelGGL(pae_update_kernel<double>, dim3(blocks), dim3(kBlock), 0, s, a, (double*)x,
+                           (const double*)xpre);
+    } else {
+        if (hist)
+            hipLaunchKernelGGL(pae_history_kernel<float>, dim3(blocks), dim3(kBlock), 0, s, a, (const float*)x,
+                               (const float*)xpre);
+        hipLaunchKernelGGL(pae_update_kernel<float>, dim3(blocks), dim3(kBlock), 0, s, a, (float*)x,
+                           (const float*)xpre);
+    }
+    TO_HIP(hipGetLastError());
+    return TO_OK;
+}
+
+}  // namespace topt

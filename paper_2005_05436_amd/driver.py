@@ -91,7 +91,7 @@ class TopOpt:
 
     def __init__(self, cfg, op=L.TO_OP_ASSEMBLED, rtol=1e-8, inner_rtol=0.1, maxit=200000,
                  precision=None, passive=None, solve_precision=L.TO_SOLVE_AUTO, grid_blocks=0, autotune=False,
-                 precond=L.TO_PREC_JACOBI):
+                 precond=L.TO_PREC_JACOBI, pae=None):
         self.cfg = cfg
         self.plan, f = plan_for_config(cfg, passive)
         dev = self.plan.device
@@ -131,14 +131,41 @@ class TopOpt:
                                                precond))
         if autotune:
             self.tuning = L.to_plan_autotune(self.plan.handle, self.dtype, self.kval if op == L.TO_OP_ASSEMBLED else None)
+        self.pae = None
+        if pae is not None:
+            self.enable_pae(**pae)
+
+    def enable_pae(self, mr=4, q=4, q0=20, alpha=0.9, xi=1.0):
+        """Periodic Anderson extrapolation of the OC iteration from loop q0 on
+        (Section 3.3; the defaults are the paper's m_r, q, alpha and a full
+        step on the extrapolated iterations)."""
+        self.pae = L.PaeParams(mr, q, q0, 0, alpha, xi)
+        nbytes = L.to_pae_query(self.plan.handle, self.pae)
+        dev = self.x.device
+        self.pae_ws = torch.zeros((nbytes + 7) // 8, dtype=torch.float64, device=dev)
+        self.pae_gamma = torch.zeros(8, dtype=torch.float64, device=dev)
+        self.x_pre = torch.empty_like(self.x)
+
+    def _pae_pre(self, stream):
+        if self.pae is not None:
+            with torch.cuda.stream(stream or torch.cuda.current_stream()):
+                self.x_pre.copy_(self.x)
+
+    def _pae_post(self, stream):
+        if self.pae is not None:
+            L.to_pae_step(self.plan.handle, self.dtype, self.x, self.x_pre, self.state.loop, self.pae, self.pae_ws,
+                          self.pae_gamma, stream)
 
     @property
     def loop(self):
         return self.state.loop
 
     def step(self, stream=None):
-        """Enqueues one redesign iteration (no host synchronisation)."""
+        """Enqueues one redesign iteration (no host synchronisation); with
+        PAE on, the extrapolation follows the OC update."""
+        self._pae_pre(stream)
         L.to_step(self.plan.handle, self.dtype, self.state, self.params, stream)
+        self._pae_post(stream)
 
     def step_stages(self, net=None, train_lr=None, stream=None):
         """One redesign iteration through the single-stage entry points (the
@@ -147,6 +174,7 @@ class TopOpt:
         by the Galerkin start (to_warm_start), seeds the PCG; with train_lr the
         network then takes one Adam step on the converged displacement."""
         h, dt, st, cfg = self.plan.handle, self.dtype, self.state, self.cfg
+        self._pae_pre(stream)
         L.to_filter(h, dt, L.TO_FILTER_FWD, self.x, None, None, self.xtilde, None, stream)
         L.to_project(h, dt, cfg.ft, self.xtilde, self.x, self.xphys, self.dprj, st.beta, self.eta, cfg.volfrac,
                      self.xphys_old, self.pst, stream)
@@ -166,6 +194,7 @@ class TopOpt:
         L.to_oc_update(h, dt, self.x, self.dcf, self.dv0, cfg.volfrac, cfg.move, self.ost, stream)
         self.xphys_old.copy_(self.xphys)
         st.loop += 1
+        self._pae_post(stream)
         st.penal = L.to_continuation(st.penal, self.params.penal_sched, st.loop)
         st.beta = L.to_continuation(st.beta, self.params.beta_sched, st.loop)
 
