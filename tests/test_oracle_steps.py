@@ -246,15 +246,15 @@ def test_oc_volume_monotone_in_lambda():
 
 
 def test_oc_bisection_agrees_with_primal_dual_appendix_a():
-    """App. A: for the density filter alone the multiplier has the explicit
-    primal-dual fixed point of eq. (26)-(27); the bisection's sqrt(lambda)
-    agrees to the bisection tolerance."""
+    """Appendix A: for the density filter alone the multiplier has the
+    explicit primal-dual fixed point; the bisection's sqrt(lambda) agrees to
+    the bisection tolerance."""
     m = 4000
     x, dc, dv = _oc_inputs(m, 11)
     act = np.ones(m, bool)
     _, st = oc.oc_update(x, dc, dv, act, 0.5, 0.2)
-    lm = oc.primal_dual_lambda(x, dc, dv, 0.5, 0.2, m)
-    assert abs(st["lmid"] - lm) / lm < 2e-4
+    _, pd = oc.oc_update_pd(x, dc, dv, act, 0.5, 0.2)
+    assert abs(st["lmid"] - pd["lm"]) / pd["lm"] < 2e-4
 
 
 def test_oc_empty_bracket_keeps_design():
