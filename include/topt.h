@@ -256,6 +256,43 @@ to_status to_oc_update(const to_plan* plan, to_dtype dtype, void* x, const void*
                        void* stream);
 
 /* ---------------------------------------------------------------------------
+ * to_oc_update_pd -- the OC update with the explicit primal-dual iteration
+ * for lm = sqrt(lambda) (Appendix A, the primal and dual maps and the code
+ * given with them) instead of bisection.  On the active set, with
+ * xU' = min(x + move, 1), xL' = max(x - move, 0), ocP = x sqrt(max(0, -dc/dv)):
+ *   lm = mean(ocP) / volfrac; repeat while |lm - lm_old| > 1e-10 (cap 200):
+ *     tmp = ocP / lm; U = {tmp > xU'}, L = {tmp < xL'}, M = {xL' < tmp < xU'}
+ *     (tmp exactly on a bound with xL' < xU' is in no set; xL' = xU' = tmp is
+ *     in M); lm = sum_M ocP / (volfrac m - sum_passive x - sum_U xU' - sum_L xL');
+ *   x = clip(ocP / lm, xL', xU').
+ * The constraint is the mean of the design over all m elements (the volume of
+ * x: volume-preserving for the density filter alone).  A non-positive
+ * denominator stops the iteration, and a multiplier that is not positive and
+ * finite leaves x unchanged; both set capped.  Stats: lmid = l2 = lm, l1 = the
+ * previous lm, vol = the design volume of the last pass, n_bs = passes =
+ * iterations.  Arguments as to_oc_update. */
+to_status to_oc_update_pd(const to_plan* plan, to_dtype dtype, void* x, const void* dc,
+                          const void* dv, double volfrac, double move, to_oc_stats* d_stats,
+                          void* stream);
+
+/* ---------------------------------------------------------------------------
+ * to_oc_update_filtered -- the bisection of to_oc_update with the volume test
+ * taken on the physical field of each candidate (Sec. 3.2, the code given for
+ * a fixed threshold): xf = forward filter of the candidate (eq. (2), the
+ * plan's boundary rule); xf = 1 / 0 on passive solid / void elements; for
+ * ft > 1, xf = prj(xf, eta, beta) (eq. (1)); l1 = lmid if mean(xf) > volfrac
+ * else l2 = lmid.  Same bracket and stop test as to_oc_update; at most 48
+ * steps (capped is set when the cap ends the loop).  d_eta: device double
+ * (read for ft > 1, may be NULL for ft = 1).  Every step costs one filter
+ * application; the steps are enqueued without host synchronisation and the
+ * ones after the stop return at once.  Uses the plan's scratch vectors (as
+ * to_solve does).  Stats as to_oc_update (passes = n_bs). */
+to_status to_oc_update_filtered(const to_plan* plan, to_dtype dtype, int ft, void* x,
+                                const void* dc, const void* dv, double volfrac, double move,
+                                double beta, const double* d_eta, to_oc_stats* d_stats,
+                                void* stream);
+
+/* ---------------------------------------------------------------------------
  * to_step -- one redesign iteration (blocks RL.1-RL.4): filter, projection,
  * change, assembly, solve, sensitivities + compliance, back-filter of dc and
  * dV, OC, then parameter continuation.  All buffers are device memory of
@@ -266,10 +303,12 @@ typedef struct {
     double maxpar, delta;        /* up to maxpar, by +delta (mul = 0) or *delta (mul = 1) */
     int32_t mul, enabled;
 } to_sched;
+enum { TO_OC_BISECT = 0, TO_OC_PD = 1, TO_OC_FILTERED = 2 };
 typedef struct {
     double volfrac, move;
     int32_t ft;                  /* 1, 2 or 3 */
-    int32_t pad;
+    int32_t oc;                  /* TO_OC_BISECT (to_oc_update), TO_OC_PD (to_oc_update_pd) or
+                                    TO_OC_FILTERED (to_oc_update_filtered with the state's beta and eta) */
     double target;               /* Newton target; NaN -> volfrac (the codes' choice) */
     to_sched penal_sched, beta_sched;
     to_solve_opts solve;

@@ -57,7 +57,9 @@ def oc_update_pd(x, dc, dv0, act, volfrac, move, tol=1e-10, cap=200):
     values, so their sum is moved to the right-hand side with the bounds (the
     code, written without passive elements, has volfrac m - sum_U - sum_L).
     A non-positive denominator stops the iteration (reported as capped); the
-    cap on iterations is 200 (the paper sets none).
+    cap on iterations is 200 (the paper sets none).  A multiplier that is not
+    positive and finite (every ocP zero) leaves the design unchanged and is
+    reported as capped (the paper does not treat the case).
     Returns (x_new, stats) with stats = dict(lm, lm_old, n_it, vol, capped)."""
     x = np.array(x, dtype=np.float64)
     act = np.asarray(act, bool)
@@ -82,6 +84,8 @@ def oc_update_pd(x, dc, dv0, act, volfrac, move, tol=1e-10, cap=200):
             bad = True
             break
         lm_old, lm = lm, summ / den
+    if not (lm > 0.0 and math.isfinite(lm)):
+        return x, dict(lm=lm, lm_old=lm_old, n_it=it, vol=vol, capped=True)
     x[act] = np.maximum(np.maximum(np.minimum(np.minimum(ocp / lm, xt + move), 1.0), xt - move), 0.0)
     return x, dict(lm=lm, lm_old=lm_old, n_it=it, vol=vol, capped=bad or it >= cap)
 

@@ -31,6 +31,7 @@ class Problem:
         self.row_ptr, self.col_idx, self.perm, self.seg_ptr = sparse.csr_pattern(self.ir, mesh.n)
         self.filter = filt.Filter(mesh, rmin, bc)
         self.x0, self.dv, self.act = _mesh.initial_design(mesh, volfrac, passive)
+        self.code = np.zeros(mesh.m, np.int64) if passive is None else np.asarray(passive)
 
 
 class State:
@@ -43,8 +44,11 @@ class State:
         self.loop = 0
 
 
-def step(prob, st, solver="auto", rtol=1e-8):
-    """One redesign iteration; mutates st and returns a stats dict."""
+def step(prob, st, solver="auto", rtol=1e-8, oc_method="bisect"):
+    """One redesign iteration; mutates st and returns a stats dict.
+    oc_method: 'bisect' (block RL.4), 'pd' (the primal-dual update of
+    Appendix A) or 'filtered' (the bisection that filters and projects each
+    candidate, Sec. 3.2, with this iteration's eta and beta)."""
     st.loop += 1
     m = prob.mesh.m
     xt = prob.filter.forward(st.x)
@@ -69,7 +73,14 @@ def step(prob, st, solver="auto", rtol=1e-8):
                                     st.penal, prob.E0, prob.Emin)
     dcf = prob.filter.adjoint(dc, dp)
     dv0 = prob.filter.adjoint(prob.dv, dp)
-    st.x, ocs = oc.oc_update(st.x, dcf, dv0, prob.act, prob.volfrac, prob.move)
+    if oc_method == "pd":
+        st.x, pd = oc.oc_update_pd(st.x, dcf, dv0, prob.act, prob.volfrac, prob.move)
+        ocs = dict(n_bs=pd["n_it"], lmid=pd["lm"])
+    elif oc_method == "filtered":
+        st.x, ocs = oc.oc_update_filtered(st.x, dcf, dv0, prob.code, prob.volfrac, prob.move, prob.filter,
+                                          prob.ft, st.eta, st.beta)
+    else:
+        st.x, ocs = oc.oc_update(st.x, dcf, dv0, prob.act, prob.volfrac, prob.move)
     st.penal = continuation.cnt(st.penal, prob.penal_sched, st.loop)
     st.beta = continuation.cnt(st.beta, prob.beta_sched, st.loop)
     return dict(loop=st.loop, c=c, vol=float(np.mean(xphys)), ch=ch, eta=st.eta,

@@ -22,11 +22,12 @@ TO_ACTIVE, TO_SOLID, TO_VOID = 0, 1, 2
 TO_FILTER_FWD, TO_FILTER_ADJ, TO_FILTER_ADJ2 = 0, 1, 2
 TO_OP_ASSEMBLED, TO_OP_MATFREE = 0, 1
 TO_SOLVE_AUTO, TO_SOLVE_F64, TO_SOLVE_MIXED = 0, 1, 2
+TO_OC_BISECT, TO_OC_PD, TO_OC_FILTERED = 0, 1, 2
 
 EXPORTED = ["to_plan_query", "to_plan_create", "to_plan_destroy", "to_plan_get_info", "to_plan_export",
             "to_plan_build_host",
             "to_status_string", "to_last_error", "to_filter", "to_project", "to_assemble", "to_solve",
-            "to_sensitivity", "to_oc_update", "to_step", "to_continuation", "to_warm_start",
+            "to_sensitivity", "to_oc_update", "to_oc_update_pd", "to_oc_update_filtered", "to_step", "to_continuation", "to_warm_start",
             "to_nn_query", "to_nn_create", "to_nn_destroy", "to_nn_set_params", "to_nn_get", "to_nn_forward",
             "to_nn_backward", "to_nn_adam", "to_nn_train_step", "to_plan_autotune", "to_plan_set_tuning",
             "to_plan_get_tuning", "to_batch_query", "to_batch_create", "to_step_batched", "to_batch_get_info",
@@ -84,7 +85,7 @@ class Sched(C.Structure):
 
 
 class StepParams(C.Structure):
-    _fields_ = [("volfrac", C.c_double), ("move", C.c_double), ("ft", C.c_int32), ("pad", C.c_int32),
+    _fields_ = [("volfrac", C.c_double), ("move", C.c_double), ("ft", C.c_int32), ("oc", C.c_int32),
                 ("target", C.c_double), ("penal_sched", Sched), ("beta_sched", Sched), ("solve", SolveOpts)]
 
 
@@ -133,6 +134,8 @@ def load():
         "to_solve": (S, [P, S, P, P, C.c_double, P, P, C.POINTER(SolveOpts), P, P]),
         "to_sensitivity": (S, [P, S, P, P, P, C.c_double, P, P, P]),
         "to_oc_update": (S, [P, S, P, P, P, C.c_double, C.c_double, P, P]),
+        "to_oc_update_pd": (S, [P, S, P, P, P, C.c_double, C.c_double, P, P]),
+        "to_oc_update_filtered": (S, [P, S, C.c_int, P, P, P, C.c_double, C.c_double, C.c_double, P, P, P]),
         "to_step": (S, [P, S, C.POINTER(StepState), C.POINTER(StepParams), P]),
         "to_continuation": (C.c_double, [C.c_double, C.POINTER(Sched), C.c_int32]),
         "to_warm_start": (S, [P, S, P, C.c_double, P, P, P, P, P, P]),
@@ -248,6 +251,16 @@ def to_sensitivity(plan, dtype, xphys, u, f, penal, dc, d_compliance, stream=Non
 def to_oc_update(plan, dtype, x, dc, dv, volfrac, move, d_stats, stream=None):
     check(load().to_oc_update(plan, dtype, ptr(x), ptr(dc), ptr(dv), volfrac, move, ptr(d_stats),
                               stream_ptr(stream)))
+
+
+def to_oc_update_pd(plan, dtype, x, dc, dv, volfrac, move, d_stats, stream=None):
+    check(load().to_oc_update_pd(plan, dtype, ptr(x), ptr(dc), ptr(dv), volfrac, move, ptr(d_stats),
+                                 stream_ptr(stream)))
+
+
+def to_oc_update_filtered(plan, dtype, ft, x, dc, dv, volfrac, move, beta, d_eta, d_stats, stream=None):
+    check(load().to_oc_update_filtered(plan, dtype, ft, ptr(x), ptr(dc), ptr(dv), volfrac, move, beta, ptr(d_eta),
+                                       ptr(d_stats), stream_ptr(stream)))
 
 
 def to_step(plan, dtype, state, params, stream=None):

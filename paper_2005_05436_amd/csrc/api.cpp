@@ -176,6 +176,30 @@ to_status to_oc_update(const to_plan* plan, to_dtype dtype, void* x, const void*
     TO_GUARD(launch_oc(P(plan), dtype, x, dc, dv, volfrac, move, d_stats, S(stream)));
 }
 
+to_status to_oc_update_pd(const to_plan* plan, to_dtype dtype, void* x, const void* dc, const void* dv,
+                          double volfrac, double move, to_oc_stats* d_stats, void* stream) {
+    NEED(plan, "plan");
+    if (check_dtype(dtype)) return TO_EINVAL;
+    NEED(x, "x"); NEED(dc, "dc"); NEED(dv, "dv"); NEED(d_stats, "d_stats");
+    if (!(volfrac > 0 && volfrac < 1)) { set_error("volfrac must be in (0, 1)"); return TO_EINVAL; }
+    if (!(move > 0 && move <= 1)) { set_error("move must be in (0, 1]"); return TO_EINVAL; }
+    TO_GUARD(launch_oc(P(plan), dtype, x, dc, dv, volfrac, move, d_stats, S(stream), TO_OC_PD));
+}
+
+to_status to_oc_update_filtered(const to_plan* plan, to_dtype dtype, int ft, void* x, const void* dc, const void* dv,
+                                double volfrac, double move, double beta, const double* d_eta, to_oc_stats* d_stats,
+                                void* stream) {
+    NEED(plan, "plan");
+    if (check_dtype(dtype)) return TO_EINVAL;
+    NEED(x, "x"); NEED(dc, "dc"); NEED(dv, "dv"); NEED(d_stats, "d_stats");
+    if (ft < 1 || ft > 3) { set_error("ft must be 1, 2 or 3"); return TO_EINVAL; }
+    if (ft > 1) NEED(d_eta, "d_eta");
+    if (ft > 1 && !(beta > 0 && std::isfinite(beta))) { set_error("beta must be positive and finite"); return TO_EINVAL; }
+    if (!(volfrac > 0 && volfrac < 1)) { set_error("volfrac must be in (0, 1)"); return TO_EINVAL; }
+    if (!(move > 0 && move <= 1)) { set_error("move must be in (0, 1]"); return TO_EINVAL; }
+    TO_GUARD(launch_oc_filtered(P(plan), dtype, ft, x, dc, dv, volfrac, move, beta, d_eta, d_stats, S(stream)));
+}
+
 static bool pae_params_ok(const to_pae_params* q) {
     return q && q->mr >= 1 && q->mr <= 8 && q->q >= 1 && q->q0 >= 0 && std::isfinite(q->alpha) &&
            std::isfinite(q->xi);
@@ -213,6 +237,7 @@ to_status to_step(const to_plan* plan, to_dtype dtype, to_step_state* st, const 
     NEED(st->u, "u"); NEED(st->f, "f"); NEED(st->eta, "eta"); NEED(st->compliance, "compliance");
     NEED(st->pstats, "pstats"); NEED(st->sstats, "sstats"); NEED(st->ostats, "ostats");
     if (prm->ft < 1 || prm->ft > 3) { set_error("ft must be 1, 2 or 3"); return TO_EINVAL; }
+    if (prm->oc < TO_OC_BISECT || prm->oc > TO_OC_FILTERED) { set_error("oc must be TO_OC_BISECT, TO_OC_PD or TO_OC_FILTERED"); return TO_EINVAL; }
     // op TO_OP_ASSEMBLED: K^(s) is assembled every iteration; it is the CG
     // operator (FP64 fields, or the mixed scheme) or, for the FP64 solve of
     // FP32 fields, the source of the FP32 Jacobi preconditioner
@@ -237,7 +262,12 @@ to_status to_step(const to_plan* plan, to_dtype dtype, to_step_state* st, const 
         if ((r = launch_sensitivity(p, dtype, st->xphys, st->u, st->f, st->penal, st->dc, st->compliance, s))) return r;
         if ((r = launch_filter(p, dtype, TO_FILTER_ADJ2, st->dc, st->dv, st->dprj, st->dcf, st->dv0, s))) return r;
         // RL.4: OC, then continuation
-        if ((r = launch_oc(p, dtype, st->x, st->dcf, st->dv0, prm->volfrac, prm->move, st->ostats, s))) return r;
+        if (prm->oc == TO_OC_FILTERED)
+            r = launch_oc_filtered(p, dtype, prm->ft, st->x, st->dcf, st->dv0, prm->volfrac, prm->move, st->beta,
+                                   st->eta, st->ostats, s);
+        else
+            r = launch_oc(p, dtype, st->x, st->dcf, st->dv0, prm->volfrac, prm->move, st->ostats, s, prm->oc);
+        if (r) return r;
         TO_HIP(hipMemcpyAsync(st->xphys_old, st->xphys, bytes, hipMemcpyDeviceToDevice, s));
         st->loop += 1;
         st->penal = to_continuation(st->penal, &prm->penal_sched, st->loop);

@@ -71,7 +71,7 @@ static int split_blocks(const std::vector<double>& work, const std::vector<int>&
 struct Batch {
     std::vector<Plan*> plans;
     std::vector<to_step_state> st0;     // device pointers fixed at creation
-    std::vector<int> ft;
+    std::vector<int> ft, oc;
     to_dtype dt = TO_F32;
     int n = 0, dim = 2, mode = 0;
     to_solve_opts solve{};
@@ -301,6 +301,10 @@ static to_status check_state(const to_step_state& st, const to_step_params& prm)
     }
     if (prm.solve.op == TO_OP_ASSEMBLED && !st.kval) { set_error("batch: kval is NULL"); return TO_EINVAL; }
     if (prm.ft < 1 || prm.ft > 3) { set_error("batch: ft must be 1, 2 or 3"); return TO_EINVAL; }
+    if (prm.oc != TO_OC_BISECT && prm.oc != TO_OC_PD) {
+        set_error("batch: oc must be TO_OC_BISECT or TO_OC_PD (the filtered bisection runs one design at a time)");
+        return TO_EINVAL;
+    }
     if (!(prm.volfrac > 0 && prm.volfrac < 1) || !(prm.move > 0 && prm.move <= 1)) {
         set_error("batch: volfrac must be in (0, 1) and move in (0, 1]");
         return TO_EINVAL;
@@ -338,6 +342,7 @@ to_status to_batch_create(to_plan* const* plans, int32_t count, to_dtype dtype, 
             b.plans.push_back(topt::P(plans[i]));
             b.st0.push_back(states[i]);
             b.ft.push_back(params[i].ft);
+            b.oc.push_back(params[i].oc);
         }
         b.dim = b.plans[0]->dim;
         for (Plan* p : b.plans)
@@ -364,7 +369,7 @@ to_status to_batch_create(to_plan* const* plans, int32_t count, to_dtype dtype, 
             double* dyn = b.dyn + 4 * (size_t)i;
             project_args_fill(p, dtype, params[i].ft, st.xtilde, st.x, st.xphys, st.dprj, st.eta, st.xphys_old,
                               st.pstats, dyn, hp.data() + pa * i);
-            oc_args_fill(p, dtype, st.x, st.dcf, st.dv0, st.ostats, dyn, ho.data() + oa * i);
+            oc_args_fill(p, dtype, st.x, st.dcf, st.dv0, st.ostats, dyn, params[i].oc, ho.data() + oa * i);
             solve_args_fill(p, dtype, st.kval, st.f, st.u, b.solve, st.sstats, hs.data() + sa * i);
         }
         std::vector<double> wm(count), wn(count);
@@ -448,9 +453,10 @@ to_status to_step_batched(to_batch* h, to_step_state* states, const to_step_para
             set_error("to_step_batched: state buffers differ from the ones the batch was created with");
             return TO_EINVAL;
         }
-        if (params[i].ft != b.ft[i] || params[i].solve.op != b.solve.op ||
+        if (params[i].ft != b.ft[i] || params[i].oc != b.oc[i] || params[i].solve.op != b.solve.op ||
             params[i].solve.precision != b.solve.precision) {
-            set_error("to_step_batched: ft and the solve operator / precision are fixed at batch creation");
+            set_error("to_step_batched: ft, the OC method and the solve operator / precision are fixed at batch "
+                      "creation");
             return TO_EINVAL;
         }
     }

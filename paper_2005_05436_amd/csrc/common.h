@@ -114,6 +114,7 @@ struct Plan {
     double* fx64 = nullptr;  float* fx32 = nullptr;      // m (filter staging)
 
     Gmg gmg;                                             // multigrid hierarchy (2D)
+    const unsigned* filt_skip = nullptr;                 // device flag: filter launches return at once when set
 
     // launch shapes chosen by the autotuner (or defaults)
     struct Tune {
@@ -444,7 +445,7 @@ int project_batch_capacity(to_dtype dt, int num_cu);
 to_status launch_project_batch(to_dtype dt, const void* tab, const BatchMap& mp, hipStream_t s);
 size_t oc_args_bytes(to_dtype dt);
 void oc_args_fill(Plan* p, to_dtype dt, void* x, const void* dc, const void* dv, to_oc_stats* st, const double* dyn,
-                  void* dst);
+                  int method, void* dst);
 int oc_batch_capacity(to_dtype dt, int num_cu);
 to_status launch_oc_batch(to_dtype dt, const void* tab, const BatchMap& mp, hipStream_t s);
 int solve_mode(to_dtype dt, const to_solve_opts& o);
@@ -470,7 +471,9 @@ to_status launch_solve(Plan* p, to_dtype dt, const void* kval, const void* xphys
 to_status launch_sensitivity(Plan* p, to_dtype dt, const void* xphys, const double* u,
                              const double* f, double penal, void* dc, double* c, hipStream_t s);
 to_status launch_oc(Plan* p, to_dtype dt, void* x, const void* dc, const void* dv, double volfrac,
-                    double move, to_oc_stats* st, hipStream_t s);
+                    double move, to_oc_stats* st, hipStream_t s, int method = TO_OC_BISECT);
+to_status launch_oc_filtered(Plan* p, to_dtype dt, int ft, void* x, const void* dc, const void* dv, double volfrac,
+                             double move, double beta, const double* d_eta, to_oc_stats* st, hipStream_t s);
 int coop_blocks_for(const void* kernel, int block, size_t smem, int num_cu);
 
 }  // namespace topt

@@ -97,9 +97,10 @@ template <typename T, int MODE, int V, int LS>
 __global__ __launch_bounds__(64 * kFiltMaxParts) void filter2d_kernel(
     int nely, int nelx, int R, char bc, const T* __restrict__ hp, int hps, const int32_t* __restrict__ hlim,
     const T* __restrict__ Hs, const T* __restrict__ in, const T* __restrict__ in2,
-    const T* __restrict__ sc, T* __restrict__ out, T* __restrict__ out2, unsigned* ctr) {
+    const T* __restrict__ sc, T* __restrict__ out, T* __restrict__ out2, unsigned* ctr, const unsigned* skip) {
     extern __shared__ unsigned char smem_raw[];
     __shared__ int tile_sh;
+    if (skip && *skip) return;          // the whole launch is cancelled (the tile counter is untouched)
     T* tile = reinterpret_cast<T*>(smem_raw);
     constexpr int NF = MODE == M_ADJ2 ? 2 : 1;
     const int W = 2 * R + 1;
@@ -221,8 +222,10 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void filter3d_kernel(
     int nely, int nelz, int nelx, int R, char bc, const T* __restrict__ h,
     const int32_t* __restrict__ hlim, const T* __restrict__ Hs, const T* __restrict__ in,
-    const T* __restrict__ in2, const T* __restrict__ sc, T* __restrict__ out, T* __restrict__ out2) {
+    const T* __restrict__ in2, const T* __restrict__ sc, T* __restrict__ out, T* __restrict__ out2,
+    const unsigned* skip) {
     extern __shared__ unsigned char smem_raw[];
+    if (skip && *skip) return;          // the whole launch is cancelled
     T* tile = reinterpret_cast<T*>(smem_raw);
     constexpr int NF = MODE == M_ADJ2 ? 2 : 1;
     constexpr int TZ = 4, TXo = 4;
@@ -312,7 +315,7 @@ static to_status run_filter2d_ls(Plan* p, const T* hp, const T* Hs, const T* in,
     const int ntiles = ((p->nely + 63) / 64) * ((p->nelx + V - 1) / V);
     const int blocks = std::max(1, std::min(ntiles, per_cu * p->num_cu));
     hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * parts), lds, s, p->nely, p->nelx, R, p->bc, hp, p->hp_stride,
-                       p->hlim, Hs, in, in2, sc, out, out2, p->bar + 16);
+                       p->hlim, Hs, in, in2, sc, out, out2, p->bar + 16, p->filt_skip);
     TO_HIP(hipGetLastError());
     return TO_OK;
 }
@@ -347,7 +350,7 @@ static to_status run_filter(Plan* p, const T* h, const T* hp, const T* Hs, const
         int nzt = (p->nelz + 3) / 4, nxt = (p->nelx + 3) / 4;
         dim3 grid((p->nely + 63) / 64, nzt * nxt);
         hipLaunchKernelGGL(k, grid, dim3(kBlock), lds, s, p->nely, p->nelz, p->nelx, R, p->bc, h, p->hlim,
-                           Hs, in, in2, sc, out, out2);
+                           Hs, in, in2, sc, out, out2, p->filt_skip);
     }
     TO_HIP(hipGetLastError());
     return TO_OK;

@@ -47,6 +47,7 @@ struct OcArgs {
     double* partial;
     unsigned* bar;
     const double* dyn;      // batch: device (volfrac, move) at dyn[2], dyn[3] (nullable)
+    int method;             // TO_OC_BISECT or TO_OC_PD
 };
 
 // The update of one design, run by `nb` blocks of which this is `bid`.
@@ -151,6 +152,57 @@ __device__ void oc_body(const OcArgs<T>& A, int bid, int nb) {
     }
     const double n_act = tot[2] + tot[3];
     const dd pas_sum{tot[4], tot[5]};
+    if (A.method == TO_OC_PD) {
+        // explicit primal-dual iteration (Appendix A): each pass sums ocP over
+        // the free set M and the active bounds over U and L, then solves the
+        // volume equation for lm; an element exactly on a bound (with
+        // xL' < xU') is in none of the sets
+        const double psum = pas_sum.hi + pas_sum.lo, md = (double)m;
+        double lm = ((tot[0] + tot[1]) / n_act) / volfrac, lm_old = 0.0, vol = NAN;
+        int it = 0, passes_pd = 0;
+        bool bad = false;
+        const int cap = 200;
+        while (alive && fabs(lm - lm_old) > 1e-10 && it < cap) {
+            dd v[2] = {{0, 0}, {0, 0}};
+            for (int64_t e = i0; e < m; e += stride) {
+                if (pas[e] != TO_ACTIVE) continue;
+                const double q = ocp_buf[e], xe = (double)x[e];
+                const double up = fmin(xe + move, 1.0), lo = fmax(xe - move, 0.0), tmp = q / lm;
+                if (tmp > up) v[1] = dd_add1(v[1], up);
+                else if (tmp < lo) v[1] = dd_add1(v[1], lo);
+                else if (!((tmp == lo || tmp == up) && lo < up)) v[0] = dd_add1(v[0], q);
+            }
+            double* reg = partial + (size_t)region * kMaxCoopBlocks * kPartialWidth;
+            block_dd(v, std::integral_constant<int, 2>{}, reg);
+            alive = gb.sync() && alive;
+            grid_dd(std::integral_constant<int, 2>{}, reg);
+            region ^= 1;
+            ++passes_pd;
+            const double summ = tot[0] + tot[1], bnd = tot[2] + tot[3];
+            ++it;
+            vol = (summ / lm + bnd + psum) / md;
+            const double den = volfrac * md - psum - bnd;
+            if (!(den > 0.0)) { bad = true; break; }
+            lm_old = lm;
+            lm = summ / den;
+        }
+        // a multiplier that is not positive and finite (e.g. every ocP is 0)
+        // leaves the design unchanged and is reported
+        const bool ok = lm > 0.0 && lm < INFINITY;
+        if (alive && ok)
+            for (int64_t e = i0; e < m; e += stride)
+                if (pas[e] == TO_ACTIVE) x[e] = (T)oc_clamp(ocp_buf[e], lm, (double)x[e], move);
+        bad = bad || !ok;
+        if (bid == 0 && threadIdx.x == 0) {
+            to_oc_stats s;
+            s.lmid = lm; s.l1 = lm_old; s.l2 = lm;
+            s.vol = vol;
+            s.n_bs = it; s.capped = (bad || it >= cap) ? 1 : 0;
+            s.passes = passes_pd; s.pad = alive ? 0 : 1;
+            *A.st = s;
+        }
+        return;
+    }
     double l1 = 0.0, l2 = ((tot[0] + tot[1]) / n_act) / volfrac;
     double lmid = NAN, vol_last = NAN;
     int n_bs = 0, passes = 0;
@@ -236,7 +288,7 @@ static OcArgs<T> oc_args(Plan* p, T* x, const T* dc, const T* dv, double volfrac
 
 template <typename T>
 static to_status run_oc(Plan* p, T* x, const T* dc, const T* dv, double volfrac, double move, to_oc_stats* st,
-                        hipStream_t s) {
+                        hipStream_t s, int method) {
     auto k = oc_kernel<T>;
     int64_t m = p->info.m;
     int maxb = coop_blocks_for((const void*)k, kOcBlock, 0, p->num_cu);
@@ -245,6 +297,7 @@ static to_status run_oc(Plan* p, T* x, const T* dc, const T* dv, double volfrac,
     int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, 2 * p->num_cu), (m + kOcBlock - 1) / kOcBlock));
     blocks = std::min(blocks, 1024);
     OcArgs<T> a = oc_args<T>(p, x, dc, dv, volfrac, move, st);
+    a.method = method;
     void* args[] = {&a};
     TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(kOcBlock), args, 0, s));
     return TO_OK;
@@ -253,14 +306,16 @@ static to_status run_oc(Plan* p, T* x, const T* dc, const T* dv, double volfrac,
 size_t oc_args_bytes(to_dtype dt) { return dt == TO_F64 ? sizeof(OcArgs<double>) : sizeof(OcArgs<float>); }
 
 void oc_args_fill(Plan* p, to_dtype dt, void* x, const void* dc, const void* dv, to_oc_stats* st, const double* dyn,
-                  void* dst) {
+                  int method, void* dst) {
     if (dt == TO_F64) {
         OcArgs<double> a = oc_args<double>(p, (double*)x, (const double*)dc, (const double*)dv, 0.0, 0.0, st);
         a.dyn = dyn;
+        a.method = method;
         std::memcpy(dst, &a, sizeof a);
     } else {
         OcArgs<float> a = oc_args<float>(p, (float*)x, (const float*)dc, (const float*)dv, 0.0, 0.0, st);
         a.dyn = dyn;
+        a.method = method;
         std::memcpy(dst, &a, sizeof a);
     }
 }
@@ -278,9 +333,210 @@ to_status launch_oc_batch(to_dtype dt, const void* tab, const BatchMap& mp, hipS
 }
 
 to_status launch_oc(Plan* p, to_dtype dt, void* x, const void* dc, const void* dv, double volfrac, double move,
-                    to_oc_stats* st, hipStream_t s) {
-    if (dt == TO_F64) return run_oc<double>(p, (double*)x, (const double*)dc, (const double*)dv, volfrac, move, st, s);
-    return run_oc<float>(p, (float*)x, (const float*)dc, (const float*)dv, volfrac, move, st, s);
+                    to_oc_stats* st, hipStream_t s, int method) {
+    if (dt == TO_F64)
+        return run_oc<double>(p, (double*)x, (const double*)dc, (const double*)dv, volfrac, move, st, s, method);
+    return run_oc<float>(p, (float*)x, (const float*)dc, (const float*)dv, volfrac, move, st, s, method);
+}
+
+// ---------------------------------------------------------------------------
+// Bisection whose volume test filters and (ft > 1) projects every candidate
+// (Sec. 3.2, the code offered for a fixed projection threshold).  A candidate
+// depends on the whole design through the filter, so each bisection step is
+// three launches: the candidate design, the plan's LDS-tiled forward filter,
+// and a volume kernel whose last block takes the step's decision on device.
+// The host enqueues a fixed number of steps; once the stop test holds a
+// device flag makes the remaining launches (the filter's included) return at
+// once, so no host synchronisation is needed.
+constexpr int kOcfCap = 48;
+
+struct OcfState {
+    double l1, l2, lmid, vol;
+    unsigned done, n_bs, cap, pad;
+};
+
+__device__ __forceinline__ dd block_dd_sum(dd v, double* sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v = wave_dd_sum(v);
+    if (lane == 0) { sh[2 * w] = v.hi; sh[2 * w + 1] = v.lo; }
+    __syncthreads();
+    dd s{sh[0], sh[1]};
+    for (int i = 1; i < kBlock / 64; ++i) s = dd_add(s, dd{sh[2 * i], sh[2 * i + 1]});
+    __syncthreads();
+    return s;
+}
+
+// Block partials of two double-double sums, then the last block to arrive
+// combines them in block order (deterministic) into out[0..1] (hi + lo).
+__device__ __forceinline__ bool last_block_dd2(dd a, dd b, double* partial, unsigned* counter, double* sh,
+                                               dd* out) {
+    __shared__ int last;
+    a = block_dd_sum(a, sh);
+    b = block_dd_sum(b, sh);
+    if (threadIdx.x == 0) {
+        double* q = partial + (size_t)blockIdx.x * 4;
+        st_dev(q, a.hi); st_dev(q + 1, a.lo); st_dev(q + 2, b.hi); st_dev(q + 3, b.lo);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return false;
+    // thread t combines blocks t, t + kBlock, ... in order, then the fixed
+    // shuffle tree of block_dd_sum: the same order on every run
+    dd sa{0.0, 0.0}, sb{0.0, 0.0};
+    for (int k = threadIdx.x; k < (int)gridDim.x; k += kBlock) {
+        const double* q = partial + (size_t)k * 4;
+        sa = dd_add(sa, dd{ld_dev(q), ld_dev(q + 1)});
+        sb = dd_add(sb, dd{ld_dev(q + 2), ld_dev(q + 3)});
+    }
+    sa = block_dd_sum(sa, sh);
+    sb = block_dd_sum(sb, sh);
+    if (threadIdx.x == 0) {
+        out[0] = sa; out[1] = sb;
+        st_dev(counter, 0u);
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool ocf_more(double l1, double l2, unsigned n_bs, unsigned cap) {
+    return (l1 + l2) > 0.0 && (l2 - l1) / (l2 + l1) > 1e-4 && n_bs < cap;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void ocf_init_kernel(int64_t m, const uint8_t* __restrict__ pas,
+                                                          const T* __restrict__ x, const T* __restrict__ dc,
+                                                          const T* __restrict__ dv, double volfrac,
+                                                          double* __restrict__ ocp, double* partial,
+                                                          unsigned* counter, OcfState* st) {
+    __shared__ double sh[2 * kWaves];
+    dd s{0.0, 0.0}, c{0.0, 0.0};
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < m; e += (int64_t)gridDim.x * kBlock) {
+        if (pas[e] != TO_ACTIVE) continue;
+        const double q = (double)x[e] * sqrt(fmax(0.0, -(double)dc[e] / (double)dv[e]));
+        ocp[e] = q;
+        s = dd_add1(s, q);
+        c.hi += 1.0;
+    }
+    dd tot[2];
+    if (!last_block_dd2(s, c, partial, counter, sh, tot)) return;
+    if (threadIdx.x == 0) {
+        const double l2 = ((tot[0].hi + tot[0].lo) / (tot[1].hi + tot[1].lo)) / volfrac;
+        st->l1 = 0.0;
+        st->l2 = l2;
+        st->lmid = NAN;
+        st->vol = NAN;
+        st->n_bs = 0;
+        st->cap = kOcfCap;
+        st->done = ocf_more(0.0, l2, 0, kOcfCap) ? 0u : 1u;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void ocf_cand_kernel(int64_t m, const uint8_t* __restrict__ pas,
+                                                          const T* __restrict__ x, const double* __restrict__ ocp,
+                                                          double move, const OcfState* __restrict__ st,
+                                                          T* __restrict__ xc) {
+    if (st->done) return;
+    const double lmid = 0.5 * (st->l1 + st->l2);
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < m; e += (int64_t)gridDim.x * kBlock)
+        xc[e] = pas[e] == TO_ACTIVE ? (T)oc_clamp(ocp[e], lmid, (double)x[e], move) : x[e];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void ocf_vol_kernel(int64_t m, const uint8_t* __restrict__ pas,
+                                                         const T* __restrict__ xf, int ft, double beta,
+                                                         const double* __restrict__ d_eta, double volfrac,
+                                                         double* partial, unsigned* counter, OcfState* st) {
+    __shared__ double sh[2 * kWaves];
+    if (st->done) return;
+    double tbe = 0.0, den = 1.0, eta = 0.0;
+    if (ft > 1) {
+        eta = *d_eta;
+        tbe = tanh(beta * eta);
+        den = tbe + tanh(beta * (1.0 - eta));
+    }
+    dd s{0.0, 0.0}, z{0.0, 0.0};
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < m; e += (int64_t)gridDim.x * kBlock) {
+        const uint8_t c = pas[e];
+        double v = c == TO_SOLID ? 1.0 : c == TO_VOID ? 0.0 : (double)xf[e];
+        if (ft > 1) v = (tbe + tanh(beta * (v - eta))) / den;
+        s = dd_add1(s, v);
+    }
+    dd tot[2];
+    if (!last_block_dd2(s, z, partial, counter, sh, tot)) return;
+    if (threadIdx.x == 0) {
+        double l1 = st->l1, l2 = st->l2;
+        const double lmid = 0.5 * (l1 + l2);
+        const double vol = (tot[0].hi + tot[0].lo) / (double)m;
+        if (vol > volfrac) l1 = lmid;
+        else l2 = lmid;
+        const unsigned n = st->n_bs + 1;
+        st->l1 = l1;
+        st->l2 = l2;
+        st->lmid = lmid;
+        st->vol = vol;
+        st->n_bs = n;
+        st->done = ocf_more(l1, l2, n, st->cap) ? 0u : 1u;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void ocf_final_kernel(int64_t m, const uint8_t* __restrict__ pas,
+                                                           T* __restrict__ x, const double* __restrict__ ocp,
+                                                           double move, const OcfState* __restrict__ st,
+                                                           to_oc_stats* stats) {
+    const unsigned n = st->n_bs;
+    const double lmid = st->lmid;
+    if (n > 0)
+        for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < m; e += (int64_t)gridDim.x * kBlock)
+            if (pas[e] == TO_ACTIVE) x[e] = (T)oc_clamp(ocp[e], lmid, (double)x[e], move);
+    if (stats && blockIdx.x == 0 && threadIdx.x == 0) {
+        to_oc_stats s;
+        s.lmid = n > 0 ? lmid : NAN; s.l1 = st->l1; s.l2 = st->l2;
+        s.vol = n > 0 ? st->vol : NAN;
+        s.n_bs = (int32_t)n; s.capped = n >= st->cap ? 1 : 0;
+        s.passes = (int32_t)n; s.pad = 0;
+        *stats = s;
+    }
+}
+
+template <typename T>
+static to_status run_oc_filtered(Plan* p, to_dtype dt, int ft, T* x, const T* dc, const T* dv, double volfrac,
+                                 double move, double beta, const double* d_eta, to_oc_stats* stats, T* xc, T* xf,
+                                 hipStream_t s) {
+    const int64_t m = p->info.m;
+    OcfState* fs = reinterpret_cast<OcfState*>(p->scal + 32);
+    double* part = p->partial + (size_t)kMaxCoopBlocks * kPartialWidth;
+    unsigned* ctr = p->bar + 20;
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (m + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(ocf_init_kernel<T>, dim3(blocks), dim3(kBlock), 0, s, m, p->passive, x, dc, dv, volfrac,
+                       p->fx64, part, ctr, fs);
+    TO_HIP(hipGetLastError());
+    p->filt_skip = &fs->done;
+    to_status r = TO_OK;
+    for (int k = 0; k < kOcfCap && r == TO_OK; ++k) {
+        hipLaunchKernelGGL(ocf_cand_kernel<T>, dim3(blocks), dim3(kBlock), 0, s, m, p->passive, x, p->fx64, move,
+                           fs, xc);
+        r = launch_filter(p, dt, TO_FILTER_FWD, xc, nullptr, nullptr, xf, nullptr, s);
+        if (r != TO_OK) break;
+        hipLaunchKernelGGL(ocf_vol_kernel<T>, dim3(blocks), dim3(kBlock), 0, s, m, p->passive, xf, ft, beta, d_eta,
+                           volfrac, part, ctr, fs);
+    }
+    p->filt_skip = nullptr;
+    if (r != TO_OK) return r;
+    hipLaunchKernelGGL(ocf_final_kernel<T>, dim3(blocks), dim3(kBlock), 0, s, m, p->passive, x, p->fx64, move, fs,
+                       stats);
+    TO_HIP(hipGetLastError());
+    return TO_OK;
+}
+
+to_status launch_oc_filtered(Plan* p, to_dtype dt, int ft, void* x, const void* dc, const void* dv, double volfrac,
+                             double move, double beta, const double* d_eta, to_oc_stats* st, hipStream_t s) {
+    if (dt == TO_F64)
+        return run_oc_filtered<double>(p, dt, ft, (double*)x, (const double*)dc, (const double*)dv, volfrac, move,
+                                       beta, d_eta, st, p->v64[6], p->v64[7], s);
+    return run_oc_filtered<float>(p, dt, ft, (float*)x, (const float*)dc, (const float*)dv, volfrac, move, beta,
+                                  d_eta, st, p->v32[6], p->v32[7], s);
 }
 
 }  // namespace topt
@@ -292,10 +548,10 @@ to_status launch_oc(Plan* p, to_dtype dt, void* x, const void* dc, const void* d
 // pre-OC designs (X) and of the residuals (R) in FP64; every q-th step the
 // correction dp = (X + mix R) gamma, gamma solving the normal equations
 // R^T R gamma = R^T r; the design becomes clip(x_pre + mix r - dp, 0, 1).
-// Kernel 1 updates the history column and, on correction steps, reduces the
-// Gram matrix and right-hand side (block partials, the last block solves the
-// small system by Gaussian elimination with partial pivoting); kernel 2
-// applies the update.  The history has min(it, m_r) columns by the
+// The first kernel updates the history column and, on correction steps, forms
+// block partials of the Gram matrix and right-hand side; a one-block kernel
+// sums them in block order and solves the small system by Gaussian
+// elimination with partial pivoting; the last kernel applies the update.  The history has min(it, m_r) columns by the
 // correction steps; before it = m_r + 1 the first is still zero (it was never
 // written) and drops out through the zero-pivot rule.
 namespace topt {
@@ -309,16 +565,20 @@ struct PaeArgs {
     double mix;
     double* X; double* R; double* xold; double* rold;   // mr x m, mr x m, m, m
     double* gamma;                                      // kPaeMaxM
-    double* partial;
-    unsigned* counter;
+    double* partial;                                    // per block: kPaeMaxNV values
 };
 
-template <typename T>
+constexpr int kPaeMaxNV = kPaeMaxM * (kPaeMaxM + 1) / 2 + kPaeMaxM;   // Gram (lower) + right-hand side
+constexpr int kPaeBlocks = 512;
+
+// History column update and, on correction steps, block partials of the
+// lower Gram matrix R^T R and of R^T r.  MR: compile-time bound on the
+// columns (4 or 8), so the accumulators stay in registers.
+template <typename T, int MR>
 __global__ __launch_bounds__(kBlock) void pae_history_kernel(PaeArgs a, const T* __restrict__ xpost,
                                                              const T* __restrict__ xpre) {
-    constexpr int NV = kPaeMaxM * (kPaeMaxM + 1) / 2 + kPaeMaxM;
+    constexpr int NV = MR * (MR + 1) / 2 + MR;
     __shared__ double sh[kWaves];
-    __shared__ int last;
     double v[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
@@ -331,83 +591,90 @@ __global__ __launch_bounds__(kBlock) void pae_history_kernel(PaeArgs a, const T*
             a.R[(size_t)a.col * a.m + i] = r - a.rold[i];
         }
         if (a.gram) {
-            double Rc[kPaeMaxM];
+            double Rc[MR];
 #pragma unroll
-            for (int c = 0; c < kPaeMaxM; ++c) Rc[c] = c < a.nc ? a.R[(size_t)c * a.m + i] : 0.0;
+            for (int c = 0; c < MR; ++c) Rc[c] = c < a.nc ? a.R[(size_t)c * a.m + i] : 0.0;
             int t = 0;
 #pragma unroll
-            for (int c = 0; c < kPaeMaxM; ++c)
+            for (int c = 0; c < MR; ++c)
 #pragma unroll
                 for (int d = 0; d <= c; ++d) v[t++] += Rc[c] * Rc[d];
 #pragma unroll
-            for (int c = 0; c < kPaeMaxM; ++c) v[t++] += Rc[c] * r;
+            for (int c = 0; c < MR; ++c) v[t++] += Rc[c] * r;
         }
     }
     if (!a.gram) return;
-    // block partials, then the last block sums them in block order and solves
-    double tot[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         const double s = block_sum(v[k], sh);
-        if (threadIdx.x == 0) st_dev(&a.partial[(size_t)blockIdx.x * 64 + k], s);
-    }
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        last = atomicAdd(a.counter, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) s += ld_dev(&a.partial[(size_t)b * 64 + k]);
-        tot[k] = block_sum(s, sh);
-    }
-    if (threadIdx.x == 0) {
-        const int n = a.nc;
-        double A[kPaeMaxM][kPaeMaxM], b[kPaeMaxM], g[kPaeMaxM];
-        int t = 0;
-        for (int c = 0; c < kPaeMaxM; ++c)
-            for (int d = 0; d <= c; ++d, ++t) { A[c][d] = tot[t]; A[d][c] = tot[t]; }
-        for (int c = 0; c < kPaeMaxM; ++c) b[c] = tot[t++];
-        double scale = 0.0;
-        for (int c = 0; c < n; ++c)
-            for (int d = 0; d < n; ++d) scale = fmax(scale, fabs(A[c][d]));
-        scale = fmax(scale, 1e-300);
-        for (int k = 0; k < n; ++k) {
-            int p = k;
-            for (int i = k + 1; i < n; ++i) if (fabs(A[i][k]) > fabs(A[p][k])) p = i;
-            if (p != k) {
-                for (int j = 0; j < n; ++j) { const double tmp = A[k][j]; A[k][j] = A[p][j]; A[p][j] = tmp; }
-                const double tb = b[k]; b[k] = b[p]; b[p] = tb;
-            }
-            if (fabs(A[k][k]) <= 1e-14 * scale) {          // singular: this unknown is 0
-                for (int j = 0; j < n; ++j) { A[k][j] = 0.0; A[j][k] = 0.0; }
-                A[k][k] = 1.0;
-                b[k] = 0.0;
-                continue;
-            }
-            for (int i = k + 1; i < n; ++i) {
-                const double f = A[i][k] / A[k][k];
-                for (int j = k; j < n; ++j) A[i][j] -= f * A[k][j];
-                b[i] -= f * b[k];
-            }
-        }
-        for (int k = n - 1; k >= 0; --k) {
-            double s = b[k];
-            for (int j = k + 1; j < n; ++j) s -= A[k][j] * g[j];
-            g[k] = s / A[k][k];
-        }
-        for (int k = 0; k < kPaeMaxM; ++k) a.gamma[k] = k < n ? g[k] : 0.0;
-        st_dev(a.counter, 0u);
+        if (threadIdx.x == 0) a.partial[(size_t)blockIdx.x * kPaeMaxNV + k] = s;
     }
 }
 
-template <typename T>
+// One block: sums the partials in block order, then thread 0 solves the
+// normal equations by Gaussian elimination with partial pivoting (a pivot
+// below 1e-14 of the largest entry sets that coefficient to 0).
+template <int MR>
+__global__ __launch_bounds__(kBlock) void pae_solve_kernel(PaeArgs a, int nblocks) {
+    constexpr int NV = MR * (MR + 1) / 2 + MR;
+    constexpr int G = kBlock / 64;                      // block groups per value
+    __shared__ double part[G][64];
+    __shared__ double tot[64];
+    const int k = threadIdx.x & 63, g = threadIdx.x >> 6;
+    double s = 0.0;
+    if (k < NV)
+        for (int b = g; b < nblocks; b += G) s += a.partial[(size_t)b * kPaeMaxNV + k];
+    part[g][k] = s;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double t = 0.0;
+        for (int q = 0; q < G; ++q) t += part[q][threadIdx.x];
+        tot[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int n = a.nc;
+    double A[MR][MR], bv[MR], gv[MR];
+    int t = 0;
+    for (int c = 0; c < MR; ++c)
+        for (int d = 0; d <= c; ++d, ++t) { A[c][d] = tot[t]; A[d][c] = tot[t]; }
+    for (int c = 0; c < MR; ++c) bv[c] = tot[t++];
+    double scale = 0.0;
+    for (int c = 0; c < n; ++c)
+        for (int d = 0; d < n; ++d) scale = fmax(scale, fabs(A[c][d]));
+    scale = fmax(scale, 1e-300);
+    for (int kk = 0; kk < n; ++kk) {
+        int p = kk;
+        for (int i = kk + 1; i < n; ++i) if (fabs(A[i][kk]) > fabs(A[p][kk])) p = i;
+        if (p != kk) {
+            for (int j = 0; j < n; ++j) { const double tmp = A[kk][j]; A[kk][j] = A[p][j]; A[p][j] = tmp; }
+            const double tb = bv[kk]; bv[kk] = bv[p]; bv[p] = tb;
+        }
+        if (fabs(A[kk][kk]) <= 1e-14 * scale) {          // singular: this unknown is 0
+            for (int j = 0; j < n; ++j) { A[kk][j] = 0.0; A[j][kk] = 0.0; }
+            A[kk][kk] = 1.0;
+            bv[kk] = 0.0;
+            continue;
+        }
+        for (int i = kk + 1; i < n; ++i) {
+            const double f = A[i][kk] / A[kk][kk];
+            for (int j = kk; j < n; ++j) A[i][j] -= f * A[kk][j];
+            bv[i] -= f * bv[kk];
+        }
+    }
+    for (int kk = n - 1; kk >= 0; --kk) {
+        double acc = bv[kk];
+        for (int j = kk + 1; j < n; ++j) acc -= A[kk][j] * gv[j];
+        gv[kk] = acc / A[kk][kk];
+    }
+    for (int c = 0; c < kPaeMaxM; ++c) a.gamma[c] = c < n ? gv[c] : 0.0;
+}
+
+template <typename T, int MR>
 __global__ __launch_bounds__(kBlock) void pae_update_kernel(PaeArgs a, T* __restrict__ x, const T* __restrict__ xpre) {
-    double g[kPaeMaxM];
+    double g[MR];
 #pragma unroll
-    for (int c = 0; c < kPaeMaxM; ++c) g[c] = a.gram && c < a.nc ? a.gamma[c] : 0.0;
+    for (int c = 0; c < MR; ++c) g[c] = a.gram && c < a.nc ? a.gamma[c] : 0.0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.m; i += (int64_t)gridDim.x * kBlock) {
         const bool act = a.pas[i] == TO_ACTIVE;
         const double xp = act ? (double)xpre[i] : 0.0;
@@ -415,13 +682,21 @@ __global__ __launch_bounds__(kBlock) void pae_update_kernel(PaeArgs a, T* __rest
         double dp = 0.0;
         if (a.gram) {
 #pragma unroll
-            for (int c = 0; c < kPaeMaxM; ++c)
+            for (int c = 0; c < MR; ++c)
                 if (c < a.nc) dp += g[c] * (a.X[(size_t)c * a.m + i] + a.mix * a.R[(size_t)c * a.m + i]);
         }
         a.xold[i] = xp;
         a.rold[i] = r;
         if (act) x[i] = (T)fmin(fmax(xp + a.mix * r - dp, 0.0), 1.0);
     }
+}
+
+template <typename T, int MR>
+static void pae_launch(const PaeArgs& a, T* x, const T* xpre, int blocks, bool hist, hipStream_t s) {
+    if (hist)
+        hipLaunchKernelGGL((pae_history_kernel<T, MR>), dim3(blocks), dim3(kBlock), 0, s, a, (const T*)x, xpre);
+    if (a.gram) hipLaunchKernelGGL(pae_solve_kernel<MR>, dim3(1), dim3(kBlock), 0, s, a, blocks);
+    hipLaunchKernelGGL((pae_update_kernel<T, MR>), dim3(blocks), dim3(kBlock), 0, s, a, x, xpre);
 }
 
 size_t pae_workspace_bytes(int64_t m, int mr) { return sizeof(double) * ((size_t)(2 * mr + 2) * m + kPaeMaxM); }
@@ -442,25 +717,18 @@ to_status launch_pae(Plan* p, to_dtype dt, void* x, const void* xpre, int32_t lo
     a.rold = w + (size_t)(2 * prm.mr + 1) * m;
     a.gamma = d_gamma ? d_gamma : w + (size_t)(2 * prm.mr + 2) * m;
     a.partial = p->partial + (size_t)kMaxCoopBlocks * kPartialWidth;
-    a.counter = p->bar + 14;
     a.mix = (it % prm.q == 0) ? prm.xi : prm.alpha;
     a.col = it > 1 ? (it - 1) % prm.mr : -1;
     a.gram = (it > 1 && (it - 1) % prm.q == 0) ? 1 : 0;
     a.nc = a.gram ? std::min(it, prm.mr) : 0;     // the history has grown to min(it, mr) columns
-    const int blocks = (int)std::min<int64_t>(2048, (m + kBlock - 1) / kBlock);
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kPaeBlocks, (m + kBlock - 1) / kBlock));
     const bool hist = a.col >= 0 || a.gram;
     if (dt == TO_F64) {
-        if (hist)
-            hipLaunchKernelGGL(pae_history_kernel<double>, dim3(blocks), dim3(kBlock), 0, s, a, (const double*)x,
-                               (const double*)xpre);
-        hipLaunchKernelGGL(pae_update_kernel<double>, dim3(blocks), dim3(kBlock), 0, s, a, (double*)x,
-                           (const double*)xpre);
+        if (prm.mr <= 4) pae_launch<double, 4>(a, (double*)x, (const double*)xpre, blocks, hist, s);
+        else pae_launch<double, kPaeMaxM>(a, (double*)x, (const double*)xpre, blocks, hist, s);
     } else {
-        if (hist)
-            hipLaunchKernelGGL(pae_history_kernel<float>, dim3(blocks), dim3(kBlock), 0, s, a, (const float*)x,
-                               (const float*)xpre);
-        hipLaunchKernelGGL(pae_update_kernel<float>, dim3(blocks), dim3(kBlock), 0, s, a, (float*)x,
-                           (const float*)xpre);
+        if (prm.mr <= 4) pae_launch<float, 4>(a, (float*)x, (const float*)xpre, blocks, hist, s);
+        else pae_launch<float, kPaeMaxM>(a, (float*)x, (const float*)xpre, blocks, hist, s);
     }
     TO_HIP(hipGetLastError());
     return TO_OK;

@@ -91,7 +91,7 @@ class TopOpt:
 
     def __init__(self, cfg, op=L.TO_OP_ASSEMBLED, rtol=1e-8, inner_rtol=0.1, maxit=200000,
                  precision=None, passive=None, solve_precision=L.TO_SOLVE_AUTO, grid_blocks=0, autotune=False,
-                 precond=L.TO_PREC_JACOBI, pae=None):
+                 precond=L.TO_PREC_JACOBI, pae=None, oc=L.TO_OC_BISECT):
         self.cfg = cfg
         self.plan, f = plan_for_config(cfg, passive)
         dev = self.plan.device
@@ -125,7 +125,7 @@ class TopOpt:
                                                       self.kval, self.u, self.f, self.eta, self.c,
                                                       self.pst, self.sst, self.ost)],
                                  cfg.penal, cfg.beta, 0, 0)
-        self.params = L.StepParams(cfg.volfrac, cfg.move, cfg.ft, 0, math.nan, _sched(cfg.penal_sched),
+        self.params = L.StepParams(cfg.volfrac, cfg.move, cfg.ft, oc, math.nan, _sched(cfg.penal_sched),
                                    _sched(cfg.beta_sched),
                                    L.SolveOpts(rtol, inner_rtol, maxit, op, solve_precision, 0, grid_blocks,
                                                precond))
@@ -191,7 +191,14 @@ class TopOpt:
             net.train_step(dt, self.xphys, self.f, self.u, train_lr)
         L.to_sensitivity(h, dt, self.xphys, self.u, self.f, st.penal, self.dc, self.c, stream)
         L.to_filter(h, dt, L.TO_FILTER_ADJ2, self.dc, self.dv, self.dprj, self.dcf, self.dv0, stream)
-        L.to_oc_update(h, dt, self.x, self.dcf, self.dv0, cfg.volfrac, cfg.move, self.ost, stream)
+        oc = self.params.oc
+        if oc == L.TO_OC_FILTERED:
+            L.to_oc_update_filtered(h, dt, cfg.ft, self.x, self.dcf, self.dv0, cfg.volfrac, cfg.move, st.beta,
+                                    self.eta, self.ost, stream)
+        elif oc == L.TO_OC_PD:
+            L.to_oc_update_pd(h, dt, self.x, self.dcf, self.dv0, cfg.volfrac, cfg.move, self.ost, stream)
+        else:
+            L.to_oc_update(h, dt, self.x, self.dcf, self.dv0, cfg.volfrac, cfg.move, self.ost, stream)
         self.xphys_old.copy_(self.xphys)
         st.loop += 1
         self._pae_post(stream)
@@ -223,9 +230,9 @@ class Batch:
     optionally replayed from a HIP graph."""
 
     def __init__(self, cfgs, op=L.TO_OP_ASSEMBLED, rtol=1e-8, precision=None, solve_precision=L.TO_SOLVE_AUTO,
-                 autotune=True, maxit=200000):
-        self.runs = [TopOpt(c, op=op, rtol=rtol, precision=precision, solve_precision=solve_precision, maxit=maxit)
-                     for c in cfgs]
+                 autotune=True, maxit=200000, oc=L.TO_OC_BISECT):
+        self.runs = [TopOpt(c, op=op, rtol=rtol, precision=precision, solve_precision=solve_precision, maxit=maxit,
+                            oc=oc) for c in cfgs]
         dts = {g.dtype for g in self.runs}
         if len(dts) != 1:
             raise ValueError("all designs of a batch need the same precision")

@@ -125,3 +125,11 @@ def test_filtered_bisection_brackets_the_filtered_volume(ft, bc, eta):
     assert v1 > 0.5 >= v2
     np.testing.assert_allclose(xn, cand(st["lmid"]), rtol=0, atol=0)
     assert st["lmid"] in (st["l1"], st["l2"])
+
+
+def test_pd_zero_sensitivities_keep_the_design():
+    m = 50
+    x = np.full(m, 0.5)
+    xn, st = oc.oc_update_pd(x, np.zeros(m), np.full(m, 0.04), np.ones(m, bool), 0.5, 0.2)
+    assert st["capped"] and st["n_it"] == 0
+    np.testing.assert_array_equal(xn, x)
