@@ -109,6 +109,38 @@ def cantilever3d(mesh):
     return f, np.array(sorted(fixed), dtype=np.int64)
 
 
+def frame(mesh, sign=-1.0):
+    """Frame reinforcement problem (Sec. 3.5): a solid frame of thickness
+    L/50 (the top nely/50 element rows and the nelx/50 element columns at
+    either side) is passive solid; the elements with row index >= 2 nely/5 - 1
+    and column index in [2 nelx/5 - 1, nelx - nelx/5 - 1] (0-based, the
+    code's 1-based ranges) are passive void.  Loads: -2/(nelx + 1) on the
+    y-DOF of every top node (a distributed load of density -2) and
+    sign * iy / nely^2 on the x-DOF of the node (iy, nelx) of the right edge
+    (a height-proportional load; the code gives sign = -1, the figures show
+    both signs).  Fixed: both DOFs of node 0 and the last DOF of the mesh
+    (the y-DOF of the bottom-right node).  nelx and nely must be multiples of
+    50 (the code's ranges are integral only then).
+    Returns (f, fixed, passive codes: 0 active, 1 solid, 2 void)."""
+    assert mesh.dim == 2
+    nelx, nely = mesh.nelx, mesh.nely
+    if nelx % 50 or nely % 50:
+        raise ValueError("the frame problem needs nelx and nely multiples of 50")
+    f = np.zeros(mesh.n)
+    for ix in range(nelx + 1):
+        f[2 * mesh.node(0, ix) + 1] += -2.0 / (nelx + 1)
+    for iy in range(nely + 1):
+        f[2 * mesh.node(iy, nelx)] += sign * iy / nely ** 2
+    fixed = np.array([0, 1, mesh.n - 1], dtype=np.int64)
+    code = np.zeros((nely, nelx), dtype=np.uint8)       # [iy, ix]
+    t_y, t_x = nely // 50, nelx // 50
+    code[:t_y, :] = 1
+    code[:, :t_x] = 1
+    code[:, nelx - t_x:] = 1
+    code[2 * nely // 5 - 1:, 2 * nelx // 5 - 1:nelx - nelx // 5] = 2
+    return f, fixed, code.reshape(-1, order="F")
+
+
 def free_dofs(mesh, fixed):
     mask = np.ones(mesh.n, dtype=bool)
     mask[np.asarray(fixed, dtype=np.int64)] = False

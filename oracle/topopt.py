@@ -97,6 +97,7 @@ def run(prob, iterations, solver="auto", rtol=1e-8):
 
 def problem_from_config(cfg):
     """Build the oracle's Problem from a workloads.Config (parameters only)."""
+    passive = None
     if cfg.nelz:
         M = _mesh.Mesh(cfg.nelx, cfg.nely, cfg.nelz)
         f, fixed = _mesh.cantilever3d(M)
@@ -104,8 +105,10 @@ def problem_from_config(cfg):
         M = _mesh.Mesh(cfg.nelx, cfg.nely)
         if cfg.kind == "mbb":
             f, fixed = _mesh.mbb(M, cfg.load)
+        elif cfg.kind == "frame":
+            f, fixed, passive = _mesh.frame(M, -1.0 if cfg.load == 0 else 1.0)
         else:
             f, fixed = _mesh.cantilever2d(M, cfg.load)
     return Problem(M, f, fixed, cfg.volfrac, cfg.penal, cfg.rmin, ft=cfg.ft, bc=cfg.bc,
                    eta=cfg.eta, beta=cfg.beta, move=cfg.move, E0=cfg.E0, Emin=cfg.Emin,
-                   nu=cfg.nu, penal_sched=cfg.penal_sched, beta_sched=cfg.beta_sched)
+                   nu=cfg.nu, passive=passive, penal_sched=cfg.penal_sched, beta_sched=cfg.beta_sched)

@@ -73,10 +73,14 @@ class Plan:
 
 
 def plan_for_config(cfg, passive=None):
-    f, fixed = problems.from_config(cfg)
+    """(plan, load vector, passive codes); the problem's own passive set
+    (the frame) unless one is given."""
+    f, fixed, own = problems.from_config(cfg)
+    if passive is None:
+        passive = own
     p = Plan(cfg.dim, cfg.nelx, cfg.nely, cfg.nelz or 1, cfg.rmin, cfg.bc, fixed, passive,
              cfg.E0, cfg.Emin, cfg.nu)
-    return p, f
+    return p, f, passive
 
 
 def _sched(s):
@@ -93,7 +97,7 @@ class TopOpt:
                  precision=None, passive=None, solve_precision=L.TO_SOLVE_AUTO, grid_blocks=0, autotune=False,
                  precond=L.TO_PREC_JACOBI, pae=None, oc=L.TO_OC_BISECT):
         self.cfg = cfg
-        self.plan, f = plan_for_config(cfg, passive)
+        self.plan, f, passive = plan_for_config(cfg, passive)
         dev = self.plan.device
         I = self.plan.info
         prec = precision or cfg.precision

@@ -47,10 +47,34 @@ def cantilever3d(nelx, nely, nelz):
     return f, fixed
 
 
+def frame(nelx, nely, sign=-1.0):
+    """Frame reinforcement (Sec. 3.5): solid frame of thickness L/50 on top
+    and at both sides, a void opening at the lower right of the middle, a
+    uniform downward load of total 2 on the top nodes and a horizontal load
+    sign * iy / nely^2 on the right-edge nodes; node 0 pinned, the last DOF
+    (y of the bottom-right node) fixed.  Returns (f, fixed, element codes)."""
+    if nelx % 50 or nely % 50:
+        raise ValueError("frame: nelx and nely must be multiples of 50")
+    n = 2 * (nelx + 1) * (nely + 1)
+    f = np.zeros(n)
+    ix = np.arange(nelx + 1)
+    f[2 * _node2(nely, 0, ix) + 1] = -2.0 / (nelx + 1)
+    iy = np.arange(nely + 1)
+    f[2 * _node2(nely, iy, nelx)] = sign * iy / float(nely * nely)
+    fixed = np.array([0, 1, n - 1], dtype=np.int32)
+    ey, ex = np.meshgrid(np.arange(nely), np.arange(nelx), indexing="ij")
+    solid = (ey < nely // 50) | (ex < nelx // 50) | (ex >= nelx - nelx // 50)
+    void = (ey >= 2 * nely // 5 - 1) & (ex >= 2 * nelx // 5 - 1) & (ex < nelx - nelx // 5)
+    code = np.where(solid, 1, np.where(void, 2, 0)).astype(np.uint8)
+    return f, fixed, code.T.reshape(-1)          # element e = iy + nely * ix
+
+
 def from_config(cfg):
-    """(f, fixed) for a workloads.Config."""
+    """(f, fixed, passive codes or None) for a workloads.Config."""
     if cfg.nelz:
-        return cantilever3d(cfg.nelx, cfg.nely, cfg.nelz)
+        return cantilever3d(cfg.nelx, cfg.nely, cfg.nelz) + (None,)
     if cfg.kind == "mbb":
-        return mbb(cfg.nelx, cfg.nely, cfg.load)
-    return cantilever2d(cfg.nelx, cfg.nely, cfg.load)
+        return mbb(cfg.nelx, cfg.nely, cfg.load) + (None,)
+    if cfg.kind == "frame":
+        return frame(cfg.nelx, cfg.nely, -1.0 if cfg.load == 0 else 1.0)
+    return cantilever2d(cfg.nelx, cfg.nely, cfg.load) + (None,)

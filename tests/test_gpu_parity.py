@@ -319,7 +319,7 @@ def test_solve(case):
         from dataclasses import replace
         cfg = replace(cfg, penal=3.0)
     prob, x, K = _solve_case(cfg, 31)
-    P, f = plan_for_config(cfg)
+    P, f, _ = plan_for_config(cfg)
     dt = L.TO_F64 if fields == "f64" else L.TO_F32
     T = tdt(dt)
     xd = dev(x, T)

@@ -173,3 +173,13 @@ def test_problem_definitions_match_oracle():
     f2, x2 = omesh.cantilever3d(M)
     np.testing.assert_array_equal(f1, f2)
     np.testing.assert_array_equal(x1, x2)
+
+
+@pytest.mark.parametrize("nelx,nely,sign", [(100, 100, -1.0), (150, 100, 1.0), (900, 900, -1.0)])
+def test_frame_problem_matches_oracle(nelx, nely, sign):
+    from paper_2005_05436_amd import problems
+    f1, x1, c1 = problems.frame(nelx, nely, sign)
+    f2, x2, c2 = omesh.frame(omesh.Mesh(nelx, nely), sign)
+    np.testing.assert_array_equal(f1, f2)
+    np.testing.assert_array_equal(x1, x2)
+    np.testing.assert_array_equal(c1, c2)

@@ -1,5 +1,6 @@
 """Pins of the oracle's numbering, element matrices and index sets against what
 the paper prints or what the mathematics fixes (CPU only)."""
+import math
 import os
 
 import numpy as np
@@ -163,3 +164,28 @@ def test_nnz_closed_form_60x20():
     nx, ny = M.nelx, M.nely
     pairs = nx * (ny + 1) + (nx + 1) * ny + 2 * nx * ny
     assert len(col_idx) == 3 * M.nnode + 4 * pairs == 23_363
+
+
+def test_frame_problem_matches_section_3_5():
+    """Sec. 3.5: loads sum to the resultants of the two distributed loads,
+    the passive sets have the sizes of the code's index ranges, the fixed
+    DOFs are the corner ones, and the frame rows / columns are solid."""
+    M = mesh.Mesh(150, 100)
+    f, fixed, code = mesh.frame(M, -1.0)
+    fy, fx = f[1::2], f[0::2]
+    assert math.isclose(fy.sum(), -2.0, rel_tol=1e-13)
+    assert math.isclose(fx.sum(), -(100 + 1) / (2 * 100), rel_tol=1e-13)
+    assert np.count_nonzero(fy) == 151 and np.count_nonzero(fx) == 100       # iy = 0 carries 0
+    assert fx[M.node(100, 150)] == pytest.approx(-1.0 / 100)
+    assert list(fixed) == [0, 1, M.n - 1]
+    img = code.reshape(100, 150, order="F")
+    n_solid = 2 * 150 + 2 * 3 * (100 - 2)            # top 2 rows, 3 columns either side
+    assert np.count_nonzero(img == 1) == n_solid
+    assert np.count_nonzero(img == 2) == (100 - 40 + 1) * (150 - 30 - 60 + 1)   # rows 40..100, columns 60..120 (1-based)
+    assert np.all(img[:2, :] == 1) and np.all(img[:, :3] == 1) and np.all(img[:, -3:] == 1)
+    assert img[39, 59] == 2 and img[38, 59] == 0 and img[39, 58] == 0 and img[99, 119] == 2 and img[99, 120] == 0
+    f2, _, code2 = mesh.frame(M, 1.0)
+    np.testing.assert_array_equal(code2, code)
+    np.testing.assert_array_equal(f2[0::2], -fx)
+    with pytest.raises(ValueError):
+        mesh.frame(mesh.Mesh(120, 100))

@@ -71,6 +71,18 @@ C2 = Config("cantilever96x48x48", "cantilever3d", 96, 48, 48, volfrac=0.12, pena
 C2_SMALL = replace(C2, name="cantilever12x6x6", nelx=12, nely=6, nelz=6, iterations=10)
 
 
+# Frame reinforcement (Sec. 3.5): 900 x 900, volfrac 0.2, p = 3, rmin = 8,
+# volume-preserving projection with beta = 2, no continuation, 100 steps;
+# passive frame and opening, distributed loads (load = 0: the code's sign of
+# the horizontal load, 1: the opposite one).  The filter boundary rule is not
+# stated for this example; zero-Neumann is taken.
+C4 = Config("frame900", "frame", 900, 900, volfrac=0.2, penal=3.0, rmin=8.0, ft=3, bc="N", eta=0.5, beta=2.0,
+            iterations=100, precision="f64")
+
+# The same problem small enough for the oracle.
+C4_SMALL = replace(C4, name="frame100", nelx=100, nely=100, rmin=2.0, iterations=8)
+
+
 def batch_configs(count=64, seed=0):
     """Ragged batch: per instance (drawn in this order) the problem type
     (cantilever or MBB, 1/2 each), nelx uniform over even integers in
