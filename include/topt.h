@@ -207,8 +207,8 @@ typedef struct {
     int32_t grid_blocks;         /* 0: automatic; else blocks of the persistent solve kernel
                                     (clamped to what can be co-resident) */
     int32_t precond;             /* TO_PREC_JACOBI (default) or TO_PREC_GMG: geometric multigrid
-                                    V-cycle (2D meshes; FP64 vectors and operators for either
-                                    field precision; op and precision are then ignored) */
+                                    V-cycle (2D and 3D meshes; FP64 vectors and operators for
+                                    either field precision; op and precision are then ignored) */
 } to_solve_opts;
 enum { TO_PREC_JACOBI = 0, TO_PREC_GMG = 1 };
 typedef struct {

@@ -23,35 +23,41 @@ constexpr unsigned kSpinLimit = 1u << 27;   // grid-barrier spin cap (~several s
 constexpr int kLLVals = 4;
 constexpr size_t kLLBytes = 2 * (size_t)kMaxCoopBlocks * kLLVals * 2 * 8;
 
-// Geometric multigrid hierarchy (2D): level l+1 has ceil(n_l / 2) elements
-// per direction; coarsening stops once the level has at most kGmgCoarseMax
-// DOFs (that level is inverted densely).
+// Geometric multigrid hierarchy: level l+1 has ceil(n_l / 2) elements per
+// direction; coarsening stops once the level has at most kGmgCoarseMax DOFs
+// (that level is inverted densely).
 constexpr int kGmgMaxLevels = 16;
 constexpr int kGmgCoarseMax = 128;
 struct GmgShape {
     int L = 0;
-    int nx[kGmgMaxLevels] = {}, ny[kGmgMaxLevels] = {};
+    int nx[kGmgMaxLevels] = {}, ny[kGmgMaxLevels] = {}, nz[kGmgMaxLevels] = {};
 };
-inline GmgShape gmg_shape(int nelx, int nely) {
+inline int64_t gmg_dofs(int dim, int nx, int ny, int nz) {
+    return (int64_t)dim * (nx + 1) * (ny + 1) * (dim == 3 ? nz + 1 : 1);
+}
+inline GmgShape gmg_shape(int dim, int nelx, int nely, int nelz) {
     GmgShape g;
     g.L = 1;
     g.nx[0] = nelx;
     g.ny[0] = nely;
+    g.nz[0] = dim == 3 ? nelz : 1;
     while (g.L < kGmgMaxLevels) {
-        const int nx = g.nx[g.L - 1], ny = g.ny[g.L - 1];
-        const int64_t dofs = 2LL * (nx + 1) * (ny + 1);
-        if ((dofs <= kGmgCoarseMax && g.L >= 2) || (nx < 2 && ny < 2)) break;
+        const int nx = g.nx[g.L - 1], ny = g.ny[g.L - 1], nz = g.nz[g.L - 1];
+        if ((gmg_dofs(dim, nx, ny, nz) <= kGmgCoarseMax && g.L >= 2) || (nx < 2 && ny < 2 && (dim == 2 || nz < 2)))
+            break;
         g.nx[g.L] = (nx + 1) / 2;
         g.ny[g.L] = (ny + 1) / 2;
+        g.nz[g.L] = dim == 3 ? (nz + 1) / 2 : 1;
         ++g.L;
     }
-    if (2LL * (g.nx[g.L - 1] + 1) * (g.ny[g.L - 1] + 1) > kGmgCoarseMax) g.L = 0;   // cannot coarsen far enough
+    const int t = g.L - 1;
+    if (gmg_dofs(dim, g.nx[t], g.ny[t], g.nz[t]) > kGmgCoarseMax) g.L = 0;   // cannot coarsen far enough
     return g;
 }
 struct GmgLevel {
-    int nx = 0, ny = 0;
+    int nx = 0, ny = 0, nz = 1;
     int64_t nnode = 0, n = 0, m = 0;
-    double* K = nullptr;           // element matrices, 64 each (levels >= 1)
+    double* K = nullptr;           // element matrices, (dim * 2^dim)^2 each (levels >= 1)
     double *x = nullptr, *xt = nullptr, *b = nullptr, *r = nullptr, *dinv = nullptr;
 };
 struct GmgScal {
@@ -113,7 +119,7 @@ struct Plan {
     float* v32[8] = {};                                  // n each
     double* fx64 = nullptr;  float* fx32 = nullptr;      // m (filter staging)
 
-    Gmg gmg;                                             // multigrid hierarchy (2D)
+    Gmg gmg;                                             // multigrid hierarchy
     const unsigned* filt_skip = nullptr;                 // device flag: filter launches return at once when set
 
     // launch shapes chosen by the autotuner (or defaults)

@@ -1,24 +1,31 @@
-// Geometric-multigrid preconditioned CG for the 2D state solve (eq. (5)),
-// the iterative solver family the paper uses for its large 3D runs.
+// Geometric-multigrid preconditioned CG for the state solve (eq. (5)) in 2D
+// and 3D, the solver the paper uses for its large 3D runs (Sec. 4).
 //
-// Hierarchy: level l+1 has ceil(nelx_l / 2) x ceil(nely_l / 2) elements;
-// bilinear prolongation P (a fine node at an odd index takes the mean of its
-// two coarse neighbours, so any element count coarsens; fine elements missing
-// from a coarse element simply contribute nothing).  Coarse operators are
-// Galerkin, A_{l+1} = P^T A_l P, formed element by element: inside a coarse
-// element the prolongated field is the bilinear interpolation of its four
-// corners, so a coarse element matrix is the sum over its (up to four) child
-// element matrices of P_c^T A_child P_c, with P_c the 8 x 8 local
-// interpolation of child position c.  On the finest level the child matrices
-// are E_e Ke with the rows and columns of fixed DOFs removed (the masked
-// operator of eq. (5)), so the coarse spaces respect the supports.  Coarse
-// element matrices are stored (64 doubles each); the coarsest level (at most
-// kGmgCoarseMax DOFs) is inverted densely by Gauss-Jordan elimination in one
-// block and applied as a dense matrix-vector product.
+// Hierarchy: level l+1 has ceil(n_l / 2) elements per direction; bi- or
+// trilinear prolongation P (a fine node at an odd index takes the mean of its
+// two coarse neighbours along that axis, so any element count coarsens; fine
+// elements missing from a coarse element simply contribute nothing).  Coarse
+// operators are Galerkin, A_{l+1} = P^T A_l P, formed element by element:
+// inside a coarse element the prolongated field is the multilinear
+// interpolation of its corners, so a coarse element matrix is the sum over
+// its (up to 2^dim) child element matrices of P_c^T A_child P_c, with P_c the
+// D x D local interpolation of child position c (D = 8 in 2D, 24 in 3D).  On
+// the finest level the child matrices are E_e Ke with the rows and columns of
+// fixed DOFs removed (the masked operator of eq. (5)), so the coarse spaces
+// respect the supports.  Coarse element matrices are stored (D^2 doubles
+// each); the coarsest level (at most kGmgCoarseMax DOFs) is inverted densely
+// by Gauss-Jordan elimination in one block and applied as a dense
+// matrix-vector product.
 //
-// V-cycle: damped Jacobi (weight kGmgOmega, kGmgNu sweeps before and after,
-// the same number, so the preconditioner is symmetric), residual, restriction
-// P^T, coarse correction, prolongation.  Outer iteration: flexible
+// V-cycle: Chebyshev smoothing of degree kGmgNu before and after (the same
+// polynomial, so the preconditioner is symmetric), residual, restriction P^T,
+// coarse correction, prolongation.  The smoother is the Chebyshev iteration
+// for D1^-1 A on the interval [1 / kGmgChebRatio, 1], with D1 the element-wise
+// l1 diagonal D1_ii = sum_e sum_j |A^e_ij|: D1 - A is diagonally dominant, so
+// the spectrum of D1^-1 A lies in (0, 1] on every level, in 2D and 3D and for
+// any design, and no damping weight has to be tuned (a Jacobi weight that
+// suits Q4 elements, whose D^-1 A reaches about 2.9, diverges for Hex8
+// elements, where it reaches about 4.8).  Outer iteration: flexible
 // (Polak-Ribiere) PCG, FP64, convergence on the recursive residual confirmed
 // by the true residual, like the Jacobi PCG.  All scalars live on the device;
 // every kernel returns at once when the device `done` flag is set, so the host
@@ -31,8 +38,22 @@
 
 namespace topt {
 
-constexpr double kGmgOmega = 0.6;
-constexpr int kGmgNu = 2;
+constexpr int kGmgNu = 2;                    // Chebyshev degree of each smoothing
+constexpr double kGmgChebRatio = 8.0;        // interval [1 / ratio, 1] of D1^-1 A
+
+// Coefficients of the Chebyshev iteration for D1^-1 A on [lo, hi]
+// (theta = (hi + lo) / 2, delta = (hi - lo) / 2, sigma = theta / delta):
+// d_0 = D1^-1 r_0 / theta; d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k / delta) D1^-1 r_k,
+// rho_0 = 1 / sigma, rho_k = 1 / (2 sigma - rho_{k-1}); x_{k+1} = x_k + d_k.
+struct ChebStep { double cd, cr; };
+static ChebStep cheb_step(int k) {
+    const double hi = 1.0, lo = 1.0 / kGmgChebRatio;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    if (k == 0) return {0.0, 1.0 / theta};
+    double rho = 1.0 / sigma, rho_prev = rho;
+    for (int i = 1; i <= k; ++i) { rho_prev = rho; rho = 1.0 / (2.0 * sigma - rho); }
+    return {rho * rho_prev, 2.0 * rho / delta};
+}
 constexpr int kGmgBatch = 8;           // iterations enqueued between host checks
 
 
@@ -64,50 +85,19 @@ __device__ __forceinline__ bool last_block_sums(const double (&v)[K], double* pa
     return true;
 }
 
-__device__ __forceinline__ void node_coords(int64_t nd, int ny, int& iy, int& ix) {
-    iy = (int)(nd % (ny + 1));
-    ix = (int)(nd / (ny + 1));
-}
+// Local corners of an element (2D: the first four): y, x and z offsets; the
+// corner order is the one of the element matrices.
+__device__ constexpr int kCY[8] = {1, 1, 0, 0, 1, 1, 0, 0};
+__device__ constexpr int kCX[8] = {0, 1, 1, 0, 0, 1, 1, 0};
+__device__ constexpr int kCZ[8] = {0, 0, 0, 0, 1, 1, 1, 1};
 
-// --- level operators ----------------------------------------------------------
-// y = A x at node nd for a level with stored element matrices (row-major 8x8)
-__device__ __forceinline__ void elem_apply(const double* __restrict__ K, const double* __restrict__ x, int nx, int ny,
-                                           int64_t nd, int iy, int ix, double (&out)[2]) {
-    constexpr int CY[4] = {1, 1, 0, 0};
-    constexpr int CX[4] = {0, 1, 1, 0};
-    const int64_t col = ny + 1;
-    double pv[3][3][2];
-#pragma unroll
-    for (int dx = -1; dx <= 1; ++dx)
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy) {
-            const bool ok = iy + dy >= 0 && iy + dy <= ny && ix + dx >= 0 && ix + dx <= nx;
-            const int64_t q = nd + dy + col * dx;
-            pv[dx + 1][dy + 1][0] = ok ? x[2 * q] : 0.0;
-            pv[dx + 1][dy + 1][1] = ok ? x[2 * q + 1] : 0.0;
-        }
-    out[0] = out[1] = 0.0;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int ey = iy - CY[a], ex = ix - CX[a];
-        if (ey < 0 || ey >= ny || ex < 0 || ex >= nx) continue;
-        const double* Ke = K + (size_t)(ey + (int64_t)ny * ex) * 64;
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const double* kr = Ke + (2 * a + c) * 8;
-            double acc = 0.0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int dy = CY[b] - CY[a], dx = CX[b] - CX[a];
-                acc += kr[2 * b] * pv[dx + 1][dy + 1][0] + kr[2 * b + 1] * pv[dx + 1][dy + 1][1];
-            }
-            out[c] += acc;
-        }
-    }
-}
+template <int DIM> struct Cell {
+    static constexpr int NC = DIM == 2 ? 4 : 8;     // corners
+    static constexpr int D = DIM * NC;              // element DOFs
+};
 
 struct LevelArgs {
-    int nx, ny;
+    int nx, ny, nz;
     int64_t nnode;
     const double* K;          // stored element matrices (levels >= 1), else null
     const double* E;          // level 0: moduli
@@ -115,57 +105,170 @@ struct LevelArgs {
     const uint8_t* fm;        // level 0: free mask (null above)
 };
 
-__device__ __forceinline__ void level_apply(const LevelArgs& L, const double* x, int64_t nd, int iy, int ix,
-                                            double (&out)[2]) {
-    if (L.K) {
-        elem_apply(L.K, x, L.nx, L.ny, nd, iy, ix, out);
-    } else {
-        MatFree<2, double> op{L.E, L.ke, L.nx, L.ny, 0};
-        op.apply(nd, iy, ix, 0, SrcMask<2, double>{x, L.fm}, out);
-    }
+template <int DIM>
+__device__ __forceinline__ void node_coords(int64_t nd, int ny, int nz, int& iy, int& ix, int& iz) {
+    iy = (int)(nd % (ny + 1));
+    const int64_t rest = nd / (ny + 1);
+    if (DIM == 2) { ix = (int)rest; iz = 0; }
+    else { iz = (int)(rest % (nz + 1)); ix = (int)(rest / (nz + 1)); }
+}
+template <int DIM>
+__device__ __forceinline__ int64_t node_at(int ny, int nz, int y, int x, int z) {
+    return DIM == 2 ? y + (int64_t)(ny + 1) * x : y + (int64_t)(ny + 1) * (z + (int64_t)(nz + 1) * x);
+}
+template <int DIM>
+__device__ __forceinline__ int64_t elem_at(int ny, int nz, int y, int x, int z) {
+    return DIM == 2 ? y + (int64_t)ny * x : y + (int64_t)ny * (z + (int64_t)nz * x);
+}
+template <int DIM>
+__device__ __forceinline__ bool elem_in(int nx, int ny, int nz, int y, int x, int z) {
+    return y >= 0 && y < ny && x >= 0 && x < nx && (DIM == 2 || (z >= 0 && z < nz));
 }
 
-// mode 0: r = b - A x;  mode 1: y = x + w dinv (b - A x);  mode 2: y = w dinv b (x = 0)
-__global__ __launch_bounds__(kBlock) void gmg_sweep_kernel(LevelArgs L, int mode, const double* __restrict__ x,
-                                                           const double* __restrict__ b, const double* __restrict__ dinv,
-                                                           double* __restrict__ y, const int32_t* done) {
-    if (*done) return;
-    for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < L.nnode; nd += (int64_t)gridDim.x * kBlock) {
-        int iy, ix;
-        node_coords(nd, L.ny, iy, ix);
-        double ax[2] = {0.0, 0.0};
-        if (mode != 2) level_apply(L, x, nd, iy, ix, ax);
+// --- level operators ----------------------------------------------------------
+// y = A x at node nd for a level with stored element matrices (row-major D x D).
+// 2D: the 3x3 neighbourhood is gathered once and the four element rows are
+// applied from registers; 3D: element by element (gathering the 27-node
+// neighbourhood would keep 81 values live).
+template <int DIM>
+__device__ __forceinline__ void elem_apply(const double* __restrict__ K, const double* __restrict__ x, int nx, int ny,
+                                           int nz, int64_t nd, int iy, int ix, int iz, double (&out)[DIM]) {
+    if constexpr (DIM == 2) {
+        const int64_t col = ny + 1;
+        double pv[3][3][2];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int64_t i = 2 * nd + c;
-            const bool fr = !L.fm || L.fm[i];
-            double v;
-            if (mode == 0) v = b[i] - ax[c];
-            else if (mode == 1) v = x[i] + kGmgOmega * dinv[i] * (b[i] - ax[c]);
-            else v = kGmgOmega * dinv[i] * b[i];
-            y[i] = fr ? v : 0.0;
-        }
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void gmg_diag_kernel(LevelArgs L, double* __restrict__ dinv) {
-    constexpr int CY[4] = {1, 1, 0, 0};
-    constexpr int CX[4] = {0, 1, 1, 0};
-    for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < L.nnode; nd += (int64_t)gridDim.x * kBlock) {
-        int iy, ix;
-        node_coords(nd, L.ny, iy, ix);
-        double d[2] = {0.0, 0.0};
+        for (int dx = -1; dx <= 1; ++dx)
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+                const bool ok = iy + dy >= 0 && iy + dy <= ny && ix + dx >= 0 && ix + dx <= nx;
+                const int64_t q = nd + dy + col * dx;
+                pv[dx + 1][dy + 1][0] = ok ? x[2 * q] : 0.0;
+                pv[dx + 1][dy + 1][1] = ok ? x[2 * q + 1] : 0.0;
+            }
+        out[0] = out[1] = 0.0;
+#pragma unroll
         for (int a = 0; a < 4; ++a) {
-            const int ey = iy - CY[a], ex = ix - CX[a];
-            if (ey < 0 || ey >= L.ny || ex < 0 || ex >= L.nx) continue;
-            const int64_t e = ey + (int64_t)L.ny * ex;
+            const int ey = iy - kCY[a], ex = ix - kCX[a];
+            if (ey < 0 || ey >= ny || ex < 0 || ex >= nx) continue;
+            const double* Ke = K + (size_t)(ey + (int64_t)ny * ex) * 64;
+#pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const int r = 2 * a + c;
-                d[c] += L.K ? L.K[e * 64 + r * 8 + r] : L.E[e] * L.ke[r * 8 + r];
+                const double* kr = Ke + (2 * a + c) * 8;
+                double acc = 0.0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int dy = kCY[b] - kCY[a], dx = kCX[b] - kCX[a];
+                    acc += kr[2 * b] * pv[dx + 1][dy + 1][0] + kr[2 * b + 1] * pv[dx + 1][dy + 1][1];
+                }
+                out[c] += acc;
             }
         }
-        for (int c = 0; c < 2; ++c) {
-            const int64_t i = 2 * nd + c;
+    } else {
+        constexpr int NC = Cell<3>::NC, D = Cell<3>::D;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[c] = 0.0;
+#pragma unroll 1
+        for (int a = 0; a < NC; ++a) {
+            const int ey = iy - kCY[a], ex = ix - kCX[a], ez = iz - kCZ[a];
+            if (!elem_in<3>(nx, ny, nz, ey, ex, ez)) continue;
+            const double* Ke = K + (size_t)elem_at<3>(ny, nz, ey, ex, ez) * D * D;
+            double sv[D];
+#pragma unroll
+            for (int b = 0; b < NC; ++b) {
+                const int64_t q = node_at<3>(ny, nz, ey + kCY[b], ex + kCX[b], ez + kCZ[b]);
+#pragma unroll
+                for (int c2 = 0; c2 < 3; ++c2) sv[3 * b + c2] = x[3 * q + c2];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double* kr = Ke + (3 * a + c) * D;
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) acc += kr[j] * sv[j];
+                out[c] += acc;
+            }
+        }
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ void level_apply(const LevelArgs& L, const double* x, int64_t nd, int iy, int ix, int iz,
+                                            double (&out)[DIM]) {
+    if (L.K) {
+        elem_apply<DIM>(L.K, x, L.nx, L.ny, L.nz, nd, iy, ix, iz, out);
+    } else {
+        MatFree<DIM, double> op{L.E, L.ke, L.nx, L.ny, L.nz};
+        op.apply(nd, iy, ix, iz, SrcMask<DIM, double>{x, L.fm}, out);
+    }
+}
+
+// mode 0: y = b - A x (residual);
+// mode 1: Chebyshev step  d = cd d + cr dinv (b - A x),  y = x + d;
+// mode 2: the first step from x = 0:  d = cr dinv b,  y = d.
+// d is updated in place (each entry by its own thread); y and x differ.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void gmg_sweep_kernel(LevelArgs L, int mode, const double* __restrict__ x,
+                                                           const double* __restrict__ b, const double* __restrict__ dinv,
+                                                           double* __restrict__ y, double* d, double cd, double cr,
+                                                           const int32_t* done) {
+    if (*done) return;
+    for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < L.nnode; nd += (int64_t)gridDim.x * kBlock) {
+        int iy, ix, iz;
+        node_coords<DIM>(nd, L.ny, L.nz, iy, ix, iz);
+        double ax[DIM] = {};
+        if (mode != 2) level_apply<DIM>(L, x, nd, iy, ix, iz, ax);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const int64_t i = DIM * nd + c;
+            const bool fr = !L.fm || L.fm[i];
+            if (mode == 0) {
+                y[i] = fr ? b[i] - ax[c] : 0.0;
+            } else if (mode == 1) {
+                const double dn = fr ? (cd == 0.0 ? 0.0 : cd * d[i]) + cr * dinv[i] * (b[i] - ax[c]) : 0.0;
+                d[i] = dn;
+                y[i] = fr ? x[i] + dn : 0.0;
+            } else {
+                const double dn = fr ? cr * dinv[i] * b[i] : 0.0;
+                d[i] = dn;
+                y[i] = dn;
+            }
+        }
+    }
+}
+
+// dinv = 1 / D1, D1_ii = sum over the elements of node i of sum_j |A^e_ij|
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void gmg_diag_kernel(LevelArgs L, double* __restrict__ dinv) {
+    constexpr int NC = Cell<DIM>::NC, D = Cell<DIM>::D;
+    for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < L.nnode; nd += (int64_t)gridDim.x * kBlock) {
+        int iy, ix, iz;
+        node_coords<DIM>(nd, L.ny, L.nz, iy, ix, iz);
+        double d[DIM] = {};
+        for (int a = 0; a < NC; ++a) {
+            const int ey = iy - kCY[a], ex = ix - kCX[a], ez = iz - kCZ[a];
+            if (!elem_in<DIM>(L.nx, L.ny, L.nz, ey, ex, ez)) continue;
+            const int64_t e = elem_at<DIM>(L.ny, L.nz, ey, ex, ez);
+            // columns of the element: level 0 leaves out fixed DOFs (the masked operator)
+            unsigned live = ~0u;
+            if (L.fm) {
+                live = 0u;
+                for (int b = 0; b < NC; ++b) {
+                    const int64_t q = node_at<DIM>(L.ny, L.nz, ey + kCY[b], ex + kCX[b], ez + kCZ[b]);
+                    for (int c2 = 0; c2 < DIM; ++c2)
+                        if (L.fm[DIM * q + c2]) live |= 1u << (DIM * b + c2);
+                }
+            }
+            for (int c = 0; c < DIM; ++c) {
+                const int r = DIM * a + c;
+                const double* row = L.K ? L.K + e * D * D + r * D : L.ke + r * D;
+                double s = 0.0;
+                for (int j = 0; j < D; ++j)
+                    if ((live >> j) & 1u) s += fabs(row[j]);
+                d[c] += L.K ? s : L.E[e] * s;
+            }
+        }
+        for (int c = 0; c < DIM; ++c) {
+            const int64_t i = DIM * nd + c;
             const bool fr = !L.fm || L.fm[i];
             dinv[i] = fr && d[c] > 0.0 ? 1.0 / d[c] : 0.0;
         }
@@ -173,137 +276,160 @@ __global__ __launch_bounds__(kBlock) void gmg_diag_kernel(LevelArgs L, double* _
 }
 
 // coarse element matrices from the children (Galerkin, element by element):
-// one thread per (coarse element, row of its 8 x 8 matrix)
-__global__ __launch_bounds__(kBlock) void gmg_galerkin_kernel(int fnx, int fny, int cnx, int cny,
+// one thread per (coarse element, row of its D x D matrix)
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void gmg_galerkin_kernel(int fnx, int fny, int fnz, int cnx, int cny, int cnz,
                                                               const double* __restrict__ E,
                                                               const double* __restrict__ ke,
                                                               const uint8_t* __restrict__ fm,
                                                               const double* __restrict__ Kf, double* __restrict__ Kc) {
-    constexpr int CY[4] = {1, 1, 0, 0};
-    constexpr int CX[4] = {0, 1, 1, 0};
-    const int64_t mc = (int64_t)cnx * cny;
-    for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < 8 * mc; t += (int64_t)gridDim.x * kBlock) {
-        const int64_t E_c = t >> 3;
-        const int row = (int)(t & 7);                  // coarse DOF 2a + k
-        const int a = row >> 1, k = row & 1;
-        const int ey = (int)(E_c % cny), ex = (int)(E_c / cny);
-        double acc[8];
+    constexpr int NC = Cell<DIM>::NC, D = Cell<DIM>::D;
+    const int64_t mc = (int64_t)cnx * cny * (DIM == 3 ? cnz : 1);
+    for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < D * mc; t += (int64_t)gridDim.x * kBlock) {
+        const int64_t E_c = t / D;
+        const int row = (int)(t % D);                  // coarse DOF DIM a + k
+        const int a = row / DIM, k = row % DIM;
+        int ey, ex, ez;
+        node_coords<DIM>(E_c, cny - 1, cnz - 1, ey, ex, ez);    // element grid = node grid of one less
+        double acc[D];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] = 0.0;
-        for (int cx = 0; cx < 2; ++cx)
-            for (int cy = 0; cy < 2; ++cy) {
-                const int fy = 2 * ey + cy, fx = 2 * ex + cx;
-                if (fy >= fny || fx >= fnx) continue;
-                const int64_t fe = fy + (int64_t)fny * fx;
-                // interpolation weights w[b][a']: child corner b from coarse corner a'
-                double w[4][4];
+        for (int i = 0; i < D; ++i) acc[i] = 0.0;
+#pragma unroll 1
+        for (int ch = 0; ch < NC; ++ch) {
+            const int cx = ch / (NC / 2), cy = (ch / (DIM == 3 ? 2 : 1)) & 1, cz = DIM == 3 ? (ch & 1) : 0;
+            const int fy = 2 * ey + cy, fx = 2 * ex + cx, fz = 2 * ez + cz;
+            if (fy >= fny || fx >= fnx || (DIM == 3 && fz >= fnz)) continue;
+            const int64_t fe = elem_at<DIM>(fny, fnz, fy, fx, fz);
+            // interpolation weight of child corner b from coarse corner a' is
+            // separable: W[0][CY[b]][CY[a']] W[1][CX[b]][CX[a']] W[2][CZ[b]][CZ[a']],
+            // with W[d][s][t] = t ? pos : 1 - pos, pos = (child offset + s) / 2
+            double W[3][2][2];
+            const int co[3] = {cy, cx, cz};
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const double yb = 0.5 * (cy + CY[b]), xb = 0.5 * (cx + CX[b]);
+            for (int d = 0; d < 3; ++d)
 #pragma unroll
-                    for (int a2 = 0; a2 < 4; ++a2) w[b][a2] = (CY[a2] ? yb : 1.0 - yb) * (CX[a2] ? xb : 1.0 - xb);
+                for (int sd = 0; sd < 2; ++sd) {
+                    const double pos = 0.5 * (co[d] + sd);
+                    W[d][sd][0] = 1.0 - pos;
+                    W[d][sd][1] = pos;
                 }
-                bool live[8];
+            auto w = [&](int b, int a2) {
+                double v = W[0][kCY[b]][kCY[a2]] * W[1][kCX[b]][kCX[a2]];
+                if (DIM == 3) v *= W[2][kCZ[b]][kCZ[a2]];
+                return v;
+            };
+            unsigned live = 0;                  // bit j: DOF j of the child is free
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int64_t node = (fy + CY[b]) + (int64_t)(fny + 1) * (fx + CX[b]);
+            for (int b = 0; b < NC; ++b) {
+                const int64_t node = node_at<DIM>(fny, fnz, fy + kCY[b], fx + kCX[b], fz + kCZ[b]);
 #pragma unroll
-                    for (int c = 0; c < 2; ++c) live[2 * b + c] = !fm || fm[2 * node + c];
-                }
-                const double Ee = E ? E[fe] : 1.0;
-                const double* A = Kf ? Kf + fe * 64 : ke;
-                // Kc[row][2a' + k'] += sum_{b, b'} w[b][a] A[2b + k][2b' + k'] w[b'][a']
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int fr = 2 * b + k;
-                    if (!live[fr] || w[b][a] == 0.0) continue;
-                    const double wr = w[b][a] * Ee;
-#pragma unroll
-                    for (int b2 = 0; b2 < 4; ++b2)
-#pragma unroll
-                        for (int k2 = 0; k2 < 2; ++k2) {
-                            const int fc = 2 * b2 + k2;
-                            if (!live[fc]) continue;
-                            const double v = wr * A[fr * 8 + fc];
-#pragma unroll
-                            for (int a2 = 0; a2 < 4; ++a2) acc[2 * a2 + k2] += v * w[b2][a2];
-                        }
-                }
+                for (int c = 0; c < DIM; ++c)
+                    if (!fm || fm[DIM * node + c]) live |= 1u << (DIM * b + c);
             }
+            const double Ee = E ? E[fe] : 1.0;
+            const double* A = Kf ? Kf + fe * D * D : ke;
+            // Kc[row][DIM a' + k'] += sum_{b, b'} w(b, a) A[DIM b + k][DIM b' + k'] w(b', a')
 #pragma unroll
-        for (int i = 0; i < 8; ++i) Kc[E_c * 64 + row * 8 + i] = acc[i];
+            for (int b = 0; b < NC; ++b) {
+                const int fr = DIM * b + k;
+                const double wba = w(b, a);
+                if (!((live >> fr) & 1u) || wba == 0.0) continue;
+                const double wr = wba * Ee;
+#pragma unroll
+                for (int b2 = 0; b2 < NC; ++b2)
+#pragma unroll
+                    for (int k2 = 0; k2 < DIM; ++k2) {
+                        const int fc = DIM * b2 + k2;
+                        if (!((live >> fc) & 1u)) continue;
+                        const double v = wr * A[fr * D + fc];
+#pragma unroll
+                        for (int a2 = 0; a2 < NC; ++a2) acc[DIM * a2 + k2] += v * w(b2, a2);
+                    }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) Kc[E_c * D * D + row * D + i] = acc[i];
     }
 }
 
 // b_c = P^T r_f
-__global__ __launch_bounds__(kBlock) void gmg_restrict_kernel(int fnx, int fny, int cnx, int cny,
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void gmg_restrict_kernel(int fnx, int fny, int fnz, int cnx, int cny, int cnz,
                                                               const double* __restrict__ rf, double* __restrict__ bc,
                                                               const int32_t* done) {
     if (*done) return;
-    const int64_t nc = (int64_t)(cnx + 1) * (cny + 1);
+    const int64_t nc = (int64_t)(cnx + 1) * (cny + 1) * (DIM == 3 ? cnz + 1 : 1);
     for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < nc; nd += (int64_t)gridDim.x * kBlock) {
-        const int I = (int)(nd % (cny + 1)), J = (int)(nd / (cny + 1));
-        double s0 = 0.0, s1 = 0.0;
-        for (int dx = -1; dx <= 1; ++dx)
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int fy = 2 * I + dy, fx = 2 * J + dx;
-                if (fy < 0 || fy > fny || fx < 0 || fx > fnx) continue;
-                const double w = (dy ? 0.5 : 1.0) * (dx ? 0.5 : 1.0);
-                const int64_t q = fy + (int64_t)(fny + 1) * fx;
-                s0 += w * rf[2 * q];
-                s1 += w * rf[2 * q + 1];
-            }
-        bc[2 * nd] = s0;
-        bc[2 * nd + 1] = s1;
+        int I, J, Kz;
+        node_coords<DIM>(nd, cny, cnz, I, J, Kz);
+        double s[DIM] = {};
+        for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const int fy = 2 * I + dy, fx = 2 * J + dx, fz = 2 * Kz + dz;
+                    if (fy < 0 || fy > fny || fx < 0 || fx > fnx || (DIM == 3 && (fz < 0 || fz > fnz))) continue;
+                    const double w = (dy ? 0.5 : 1.0) * (dx ? 0.5 : 1.0) * (dz ? 0.5 : 1.0);
+                    const int64_t q = node_at<DIM>(fny, fnz, fy, fx, fz);
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) s[c] += w * rf[DIM * q + c];
+                }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) bc[DIM * nd + c] = s[c];
     }
 }
 
 // x_f += P x_c (fixed DOFs of the finest level untouched)
-__global__ __launch_bounds__(kBlock) void gmg_prolong_kernel(int fnx, int fny, int cny, const double* __restrict__ xc,
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void gmg_prolong_kernel(int fnx, int fny, int fnz, int cny, int cnz,
+                                                             const double* __restrict__ xc,
                                                              const uint8_t* __restrict__ fm, double* __restrict__ xf,
                                                              const int32_t* done) {
     if (*done) return;
-    const int64_t nf = (int64_t)(fnx + 1) * (fny + 1);
+    const int64_t nf = (int64_t)(fnx + 1) * (fny + 1) * (DIM == 3 ? fnz + 1 : 1);
     for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < nf; nd += (int64_t)gridDim.x * kBlock) {
-        const int fy = (int)(nd % (fny + 1)), fx = (int)(nd / (fny + 1));
-        const int y0 = fy >> 1, y1 = (fy + 1) >> 1, x0 = fx >> 1, x1 = (fx + 1) >> 1;
-        const double wy = (y0 == y1) ? 1.0 : 0.5, wx = (x0 == x1) ? 1.0 : 0.5;
-        double s[2] = {0.0, 0.0};
-        const int ys[2] = {y0, y1}, xs[2] = {x0, x1};
-        for (int i = 0; i < (x0 == x1 ? 1 : 2); ++i)
-            for (int j = 0; j < (y0 == y1 ? 1 : 2); ++j) {
-                const int64_t q = ys[j] + (int64_t)(cny + 1) * xs[i];
-                s[0] += wy * wx * xc[2 * q];
-                s[1] += wy * wx * xc[2 * q + 1];
-            }
+        int fy, fx, fz;
+        node_coords<DIM>(nd, fny, fnz, fy, fx, fz);
+        const int ys[2] = {fy >> 1, (fy + 1) >> 1}, xs[2] = {fx >> 1, (fx + 1) >> 1};
+        const int zs[2] = {fz >> 1, (fz + 1) >> 1};
+        const int ny_ = ys[0] == ys[1] ? 1 : 2, nx_ = xs[0] == xs[1] ? 1 : 2, nz_ = zs[0] == zs[1] ? 1 : 2;
+        const double w = (ny_ == 1 ? 1.0 : 0.5) * (nx_ == 1 ? 1.0 : 0.5) * (nz_ == 1 ? 1.0 : 0.5);
+        double s[DIM] = {};
+        for (int k = 0; k < nz_; ++k)
+            for (int i = 0; i < nx_; ++i)
+                for (int j = 0; j < ny_; ++j) {
+                    const int64_t q = node_at<DIM>(cny, cnz, ys[j], xs[i], zs[k]);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int64_t i = 2 * nd + c;
+                    for (int c = 0; c < DIM; ++c) s[c] += w * xc[DIM * q + c];
+                }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const int64_t i = DIM * nd + c;
             if (!fm || fm[i]) xf[i] += s[c];
         }
     }
 }
 
-// dense coarsest matrix (rows of DOFs no element reaches get 1 on the diagonal)
-__global__ __launch_bounds__(kBlock) void gmg_dense_kernel(int nx, int ny, const double* __restrict__ K, int nc,
-                                                           double* __restrict__ A) {
-    constexpr int CY[4] = {1, 1, 0, 0};
-    constexpr int CX[4] = {0, 1, 1, 0};
+// dense coarsest matrix (rows of DOFs no element reaches stay 0: the
+// inversion zeroes them)
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void gmg_dense_kernel(int nx, int ny, int nz, const double* __restrict__ K,
+                                                           int nc, double* __restrict__ A) {
+    constexpr int NC = Cell<DIM>::NC, D = Cell<DIM>::D;
     for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < (int64_t)nc * nc;
          idx += (int64_t)gridDim.x * kBlock) {
         const int i = (int)(idx / nc), j = (int)(idx % nc);
-        const int ni = i >> 1, ci = i & 1, nj = j >> 1, cj = j & 1;
-        int iy, ix, jy, jx;
-        node_coords(ni, ny, iy, ix);
-        node_coords(nj, ny, jy, jx);
+        const int ni = i / DIM, ci = i % DIM, nj = j / DIM, cj = j % DIM;
+        int iy, ix, iz, jy, jx, jz;
+        node_coords<DIM>(ni, ny, nz, iy, ix, iz);
+        node_coords<DIM>(nj, ny, nz, jy, jx, jz);
         double s = 0.0;
-        if (abs(iy - jy) <= 1 && abs(ix - jx) <= 1) {
-            for (int a = 0; a < 4; ++a) {
-                const int ey = iy - CY[a], ex = ix - CX[a];
-                if (ey < 0 || ey >= ny || ex < 0 || ex >= nx) continue;
-                for (int b = 0; b < 4; ++b) {
-                    if (ey + CY[b] != jy || ex + CX[b] != jx) continue;
-                    s += K[(ey + (int64_t)ny * ex) * 64 + (2 * a + ci) * 8 + 2 * b + cj];
+        if (abs(iy - jy) <= 1 && abs(ix - jx) <= 1 && abs(iz - jz) <= 1) {
+            for (int a = 0; a < NC; ++a) {
+                const int ey = iy - kCY[a], ex = ix - kCX[a], ez = iz - kCZ[a];
+                if (!elem_in<DIM>(nx, ny, nz, ey, ex, ez)) continue;
+                for (int b = 0; b < NC; ++b) {
+                    if (ey + kCY[b] != jy || ex + kCX[b] != jx || ez + kCZ[b] != jz) continue;
+                    s += K[elem_at<DIM>(ny, nz, ey, ex, ez) * D * D + (DIM * a + ci) * D + DIM * b + cj];
                 }
             }
         }
@@ -358,18 +484,19 @@ __global__ __launch_bounds__(kBlock) void gmg_coarse_solve_kernel(const double* 
 
 // --- outer flexible PCG ---------------------------------------------------------
 // r = f - A u on free DOFs, u = 0 on fixed ones; |f|, |r|
+template <int DIM>
 __global__ __launch_bounds__(kBlock) void fcg_residual_kernel(LevelArgs L, const double* __restrict__ f, double* u,
                                                               double* __restrict__ r, double* partial,
                                                               unsigned* counter, GmgScal* S, int first) {
     double v[2] = {0.0, 0.0};
     for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < L.nnode; nd += (int64_t)gridDim.x * kBlock) {
-        int iy, ix;
-        node_coords(nd, L.ny, iy, ix);
-        double ax[2];
-        level_apply(L, u, nd, iy, ix, ax);
+        int iy, ix, iz;
+        node_coords<DIM>(nd, L.ny, L.nz, iy, ix, iz);
+        double ax[DIM];
+        level_apply<DIM>(L, u, nd, iy, ix, iz, ax);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int64_t i = 2 * nd + c;
+        for (int c = 0; c < DIM; ++c) {
+            const int64_t i = DIM * nd + c;
             const bool fr = L.fm[i];
             const double ri = fr ? f[i] - ax[c] : 0.0;
             r[i] = ri;
@@ -408,6 +535,7 @@ __global__ __launch_bounds__(kBlock) void fcg_dots_kernel(int64_t n, const doubl
 }
 
 // p = z + beta p (in place), q = A p; pq -> alpha
+template <int DIM>
 __global__ __launch_bounds__(kBlock) void fcg_dir_kernel(LevelArgs L, const double* __restrict__ z,
                                                          const double* __restrict__ pold, double* __restrict__ pnew,
                                                          double* __restrict__ q, double* partial, unsigned* counter,
@@ -416,14 +544,14 @@ __global__ __launch_bounds__(kBlock) void fcg_dir_kernel(LevelArgs L, const doub
     const double beta = S->beta;
     double v[1] = {0.0};
     for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < L.nnode; nd += (int64_t)gridDim.x * kBlock) {
-        int iy, ix;
-        node_coords(nd, L.ny, iy, ix);
-        double ap[2];
-        MatFree<2, double> op{L.E, L.ke, L.nx, L.ny, 0};
-        op.apply(nd, iy, ix, 0, SrcZP<2, double>{z, pold, beta, Own{0, L.nnode, 0}}, ap);
+        int iy, ix, iz;
+        node_coords<DIM>(nd, L.ny, L.nz, iy, ix, iz);
+        double ap[DIM];
+        MatFree<DIM, double> op{L.E, L.ke, L.nx, L.ny, L.nz};
+        op.apply(nd, iy, ix, iz, SrcZP<DIM, double>{z, pold, beta, Own{0, L.nnode, 0}}, ap);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int64_t i = 2 * nd + c;
+        for (int c = 0; c < DIM; ++c) {
+            const int64_t i = DIM * nd + c;
             const bool fr = L.fm[i];
             const double pi = fr ? z[i] + beta * pold[i] : 0.0;
             const double qi = fr ? ap[c] : 0.0;
@@ -506,13 +634,14 @@ static int grid_of(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_
 static LevelArgs level_args(const Plan* p, int l) {
     const GmgLevel& v = p->gmg.lv[l];
     LevelArgs L{};
-    L.nx = v.nx; L.ny = v.ny; L.nnode = v.nnode;
+    L.nx = v.nx; L.ny = v.ny; L.nz = v.nz; L.nnode = v.nnode;
     if (l == 0) { L.K = nullptr; L.E = p->E64; L.ke = p->kf64; L.fm = p->freemask; }
     else { L.K = v.K; L.E = nullptr; L.ke = nullptr; L.fm = nullptr; }
     return L;
 }
 
 // z = M r: one V-cycle from level l (x0 = 0); level-0 vectors b = r, x = z
+template <int DIM>
 static void vcycle(Plan* p, int l, const double* b, double* x, const int32_t* done, hipStream_t s) {
     Gmg& G = p->gmg;
     GmgLevel& v = G.lv[l];
@@ -525,66 +654,69 @@ static void vcycle(Plan* p, int l, const double* b, double* x, const int32_t* do
     double* t = v.xt;     // ping-pong partner of x
     double* r = v.r;
     const int g = grid_of(v.nnode);
-    // pre-smoothing: first sweep from x = 0, then kGmgNu - 1 sweeps (ending in x)
+    // pre-smoothing from x = 0: kGmgNu Chebyshev steps ending in x; the
+    // step vector d lives in r (free until the residual below)
     double* cur = (kGmgNu % 2 == 1) ? x : t;
     double* nxt = (kGmgNu % 2 == 1) ? t : x;
-    hipLaunchKernelGGL(gmg_sweep_kernel, dim3(g), dim3(kBlock), 0, s, L, 2, (const double*)nullptr, b, v.dinv, cur,
-                       done);
+    ChebStep cs = cheb_step(0);
+    hipLaunchKernelGGL(gmg_sweep_kernel<DIM>, dim3(g), dim3(kBlock), 0, s, L, 2, (const double*)nullptr, b, v.dinv,
+                       cur, r, cs.cd, cs.cr, done);
     for (int k = 1; k < kGmgNu; ++k) {
-        hipLaunchKernelGGL(gmg_sweep_kernel, dim3(g), dim3(kBlock), 0, s, L, 1, cur, b, v.dinv, nxt, done);
+        cs = cheb_step(k);
+        hipLaunchKernelGGL(gmg_sweep_kernel<DIM>, dim3(g), dim3(kBlock), 0, s, L, 1, cur, b, v.dinv, nxt, r, cs.cd,
+                           cs.cr, done);
         std::swap(cur, nxt);
     }
     // residual, restriction, coarse correction, prolongation
-    hipLaunchKernelGGL(gmg_sweep_kernel, dim3(g), dim3(kBlock), 0, s, L, 0, x, b, v.dinv, r, done);
+    hipLaunchKernelGGL(gmg_sweep_kernel<DIM>, dim3(g), dim3(kBlock), 0, s, L, 0, x, b, v.dinv, r, (double*)nullptr,
+                       0.0, 0.0, done);
     GmgLevel& c = G.lv[l + 1];
-    hipLaunchKernelGGL(gmg_restrict_kernel, dim3(grid_of(c.nnode)), dim3(kBlock), 0, s, v.nx, v.ny, c.nx, c.ny, r,
-                       c.b, done);
-    vcycle(p, l + 1, c.b, c.x, done, s);
-    hipLaunchKernelGGL(gmg_prolong_kernel, dim3(g), dim3(kBlock), 0, s, v.nx, v.ny, c.ny, c.x,
+    hipLaunchKernelGGL(gmg_restrict_kernel<DIM>, dim3(grid_of(c.nnode)), dim3(kBlock), 0, s, v.nx, v.ny, v.nz, c.nx,
+                       c.ny, c.nz, r, c.b, done);
+    vcycle<DIM>(p, l + 1, c.b, c.x, done, s);
+    hipLaunchKernelGGL(gmg_prolong_kernel<DIM>, dim3(g), dim3(kBlock), 0, s, v.nx, v.ny, v.nz, c.ny, c.nz, c.x,
                        l == 0 ? p->freemask : nullptr, x, done);
-    // post-smoothing (same count: the cycle is symmetric)
+    // post-smoothing: the same polynomial from x (r is free again)
     cur = x;
     nxt = t;
     for (int k = 0; k < kGmgNu; ++k) {
-        hipLaunchKernelGGL(gmg_sweep_kernel, dim3(g), dim3(kBlock), 0, s, L, 1, cur, b, v.dinv, nxt, done);
+        cs = cheb_step(k);
+        hipLaunchKernelGGL(gmg_sweep_kernel<DIM>, dim3(g), dim3(kBlock), 0, s, L, 1, cur, b, v.dinv, nxt, r, cs.cd,
+                           cs.cr, done);
         std::swap(cur, nxt);
     }
     if (cur != x) (void)hipMemcpyAsync(x, cur, 8 * v.n, hipMemcpyDeviceToDevice, s);
 }
 
-to_status gmg_setup(Plan* p, hipStream_t s) {
+template <int DIM>
+static to_status gmg_setup(Plan* p, hipStream_t s) {
+    constexpr int D = Cell<DIM>::D;
     Gmg& G = p->gmg;
     for (int l = 0; l + 1 < G.L; ++l) {
         const GmgLevel& f = G.lv[l];
         GmgLevel& c = G.lv[l + 1];
-        hipLaunchKernelGGL(gmg_galerkin_kernel, dim3(grid_of(8 * c.m)), dim3(kBlock), 0, s, f.nx, f.ny, c.nx, c.ny,
-                           l == 0 ? p->E64 : nullptr, l == 0 ? p->kf64 : nullptr, l == 0 ? p->freemask : nullptr,
-                           l == 0 ? nullptr : f.K, c.K);
+        hipLaunchKernelGGL(gmg_galerkin_kernel<DIM>, dim3(grid_of(D * c.m)), dim3(kBlock), 0, s, f.nx, f.ny, f.nz,
+                           c.nx, c.ny, c.nz, l == 0 ? p->E64 : nullptr, l == 0 ? p->kf64 : nullptr,
+                           l == 0 ? p->freemask : nullptr, l == 0 ? nullptr : f.K, c.K);
     }
     for (int l = 0; l + 1 < G.L; ++l) {
         const LevelArgs L = level_args(p, l);
-        hipLaunchKernelGGL(gmg_diag_kernel, dim3(grid_of(G.lv[l].nnode)), dim3(kBlock), 0, s, L, G.lv[l].dinv);
+        hipLaunchKernelGGL(gmg_diag_kernel<DIM>, dim3(grid_of(G.lv[l].nnode)), dim3(kBlock), 0, s, L, G.lv[l].dinv);
     }
     const GmgLevel& cl = G.lv[G.L - 1];
     const int nc = (int)cl.n;
-    hipLaunchKernelGGL(gmg_dense_kernel, dim3(grid_of((int64_t)nc * nc)), dim3(kBlock), 0, s, cl.nx, cl.ny, cl.K, nc,
-                       G.Ainv);
+    hipLaunchKernelGGL(gmg_dense_kernel<DIM>, dim3(grid_of((int64_t)nc * nc)), dim3(kBlock), 0, s, cl.nx, cl.ny,
+                       cl.nz, cl.K, nc, G.Ainv);
     hipLaunchKernelGGL(gmg_invert_kernel, dim3(1), dim3(1024), 0, s, G.Ainv, nc);
     TO_HIP(hipGetLastError());
     return TO_OK;
 }
 
-to_status launch_solve_gmg(Plan* p, to_dtype dt, const void* xphys, double penal, const double* f, double* u,
-                           const to_solve_opts& o, to_solve_stats* st, hipStream_t s) {
+template <int DIM>
+static to_status solve_gmg(Plan* p, const double* f, double* u, const to_solve_opts& o, to_solve_stats* st,
+                           hipStream_t s) {
     Gmg& G = p->gmg;
-    if (p->dim != 2 || G.L < 2) {
-        set_error("the multigrid preconditioner is built for 2D meshes");
-        return TO_EUNSUPPORTED;
-    }
-    // FP64 moduli of the design (the FP32 design promoted for TO_F32)
-    to_status r0 = launch_moduli(p, dt, xphys, penal, s, true);
-    if (r0 != TO_OK) return r0;
-    r0 = gmg_setup(p, s);
+    to_status r0 = gmg_setup<DIM>(p, s);
     if (r0 != TO_OK) return r0;
     GmgScal* S = G.scal;
     int32_t* done = &S->done;
@@ -597,7 +729,7 @@ to_status launch_solve_gmg(Plan* p, to_dtype dt, const void* xphys, double penal
     if (o.zero_x0)
         hipLaunchKernelGGL(fill_zero_f64_kernel, dim3(gn), dim3(kBlock), 0, s, u, n);
     hipLaunchKernelGGL(fcg_init_kernel, dim3(1), dim3(1), 0, s, S, o.maxit);
-    hipLaunchKernelGGL(fcg_residual_kernel, dim3(g0), dim3(kBlock), 0, s, L0, f, u, r, part, ctr, S, 1);
+    hipLaunchKernelGGL(fcg_residual_kernel<DIM>, dim3(g0), dim3(kBlock), 0, s, L0, f, u, r, part, ctr, S, 1);
     hipLaunchKernelGGL(fcg_tol_kernel, dim3(1), dim3(1), 0, s, S, o.rtol);
     // A batch of kGmgBatch outer iterations; the direction buffers alternate
     // with period 2, so every batch after the first has the same launches.
@@ -606,10 +738,10 @@ to_status launch_solve_gmg(Plan* p, to_dtype dt, const void* xphys, double penal
         double* pnew = pa;
         double* other = pb;
         for (int k = 0; k < kGmgBatch; ++k) {
-            vcycle(p, 0, r, z, done, cs);
+            vcycle<DIM>(p, 0, r, z, done, cs);
             hipLaunchKernelGGL(fcg_dots_kernel, dim3(gn), dim3(kBlock), 0, cs, n, r, rold, z, part, ctr, S,
                                (restart_first && k == 0) ? 1 : 0);
-            hipLaunchKernelGGL(fcg_dir_kernel, dim3(g0), dim3(kBlock), 0, cs, L0, z, pold, pnew, q, part, ctr, S);
+            hipLaunchKernelGGL(fcg_dir_kernel<DIM>, dim3(g0), dim3(kBlock), 0, cs, L0, z, pold, pnew, q, part, ctr, S);
             hipLaunchKernelGGL(fcg_update_kernel, dim3(gn), dim3(kBlock), 0, cs, n, pnew, q, u, r, rold, part, ctr, S);
             pold = pnew;
             std::swap(pnew, other);
@@ -648,7 +780,7 @@ to_status launch_solve_gmg(Plan* p, to_dtype dt, const void* xphys, double penal
         }
         if (h_done == 2 || h_it >= o.maxit) break;
         // confirm on the true residual; reopen (restart the directions) if it misses
-        hipLaunchKernelGGL(fcg_residual_kernel, dim3(g0), dim3(kBlock), 0, s, L0, f, u, r, part, ctr, S, 0);
+        hipLaunchKernelGGL(fcg_residual_kernel<DIM>, dim3(g0), dim3(kBlock), 0, s, L0, f, u, r, part, ctr, S, 0);
         hipLaunchKernelGGL(fcg_reopen_kernel, dim3(1), dim3(1), 0, s, S);
         TO_HIP(hipMemcpyAsync(&h_done, &S->done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         TO_HIP(hipStreamSynchronize(s));
@@ -658,6 +790,18 @@ to_status launch_solve_gmg(Plan* p, to_dtype dt, const void* xphys, double penal
     hipLaunchKernelGGL(fcg_stats_kernel, dim3(1), dim3(1), 0, s, S, st, o.rtol);
     TO_HIP(hipGetLastError());
     return TO_OK;
+}
+
+to_status launch_solve_gmg(Plan* p, to_dtype dt, const void* xphys, double penal, const double* f, double* u,
+                           const to_solve_opts& o, to_solve_stats* st, hipStream_t s) {
+    if (p->gmg.L < 2) {
+        set_error("the mesh is too small for a multigrid hierarchy");
+        return TO_EUNSUPPORTED;
+    }
+    // FP64 moduli of the design (the FP32 design promoted for TO_F32)
+    to_status r0 = launch_moduli(p, dt, xphys, penal, s, true);
+    if (r0 != TO_OK) return r0;
+    return p->dim == 2 ? solve_gmg<2>(p, f, u, o, st, s) : solve_gmg<3>(p, f, u, o, st, s);
 }
 
 }  // namespace topt

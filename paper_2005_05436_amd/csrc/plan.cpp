@@ -276,12 +276,14 @@ static Offsets layout(const Sizes& S) {
     for (int i = 0; i < 8; ++i) o.v32[i] = L.take(4 * S.n);
     o.fx64 = L.take(8 * S.m);
     o.fx32 = L.take(4 * S.m);
-    if (S.G.dim == 2) {
-        o.gs = gmg_shape(S.G.nx, S.G.ny);
+    {
+        const int dim = S.G.dim;
+        const size_t D = (size_t)dim * (dim == 2 ? 4 : 8);
+        o.gs = gmg_shape(dim, S.G.nx, S.G.ny, S.G.nz);
         for (int l = 0; l < o.gs.L; ++l) {
-            const int64_t nx = o.gs.nx[l], ny = o.gs.ny[l];
-            const int64_t n = 2 * (nx + 1) * (ny + 1);
-            o.gK[l] = l ? L.take(8 * 64 * (size_t)(nx * ny)) : 0;
+            const int64_t nx = o.gs.nx[l], ny = o.gs.ny[l], nz = o.gs.nz[l];
+            const int64_t n = gmg_dofs(dim, (int)nx, (int)ny, (int)nz);
+            o.gK[l] = l ? L.take(8 * D * D * (size_t)(nx * ny * nz)) : 0;
             o.gx[l] = l ? L.take(8 * n) : 0;
             o.gb[l] = l ? L.take(8 * n) : 0;
             o.gxt[l] = L.take(8 * n);
@@ -440,10 +442,10 @@ to_status plan_create(const to_mesh_desc* D, void* ws, size_t ws_bytes, hipStrea
     p->gmg.L = o.gs.L;
     for (int l = 0; l < o.gs.L; ++l) {
         GmgLevel& v = p->gmg.lv[l];
-        v.nx = o.gs.nx[l]; v.ny = o.gs.ny[l];
-        v.nnode = (int64_t)(v.nx + 1) * (v.ny + 1);
-        v.n = 2 * v.nnode;
-        v.m = (int64_t)v.nx * v.ny;
+        v.nx = o.gs.nx[l]; v.ny = o.gs.ny[l]; v.nz = o.gs.nz[l];
+        v.nnode = (int64_t)(v.nx + 1) * (v.ny + 1) * (S.G.dim == 3 ? v.nz + 1 : 1);
+        v.n = S.G.dim * v.nnode;
+        v.m = (int64_t)v.nx * v.ny * v.nz;
         v.K = l ? (double*)(base + o.gK[l]) : nullptr;
         v.x = l ? (double*)(base + o.gx[l]) : nullptr;
         v.b = l ? (double*)(base + o.gb[l]) : nullptr;

@@ -456,3 +456,76 @@ def test_solve_gmg_matches_oracle(kind, dims, dt, seed):
     assert abs(c - cref) <= 1e-7 * abs(cref)
     assert s.iterations < 200
     print(f"gmg {kind} {dims}: {s.iterations} iterations, residual {s.residual:.2e}")
+
+
+@pytest.mark.parametrize("dims,dt,seed", [((6, 4, 3), 1, 7), ((12, 6, 6), 0, 8), ((13, 7, 5), 1, 9),
+                                          ((24, 12, 12), 1, 10)])
+def test_solve_gmg_3d_matches_oracle(dims, dt, seed):
+    """The 3D multigrid-preconditioned CG (trilinear prolongation, 24 x 24
+    Galerkin element matrices) reaches the true residual 1e-8 and the
+    oracle's compliance within 1e-7 on the 3D cantilever, even and odd
+    sizes."""
+    from paper_2005_05436_amd import _lib as L
+    from paper_2005_05436_amd import problems
+    from paper_2005_05436_amd.driver import Plan, read_struct
+    nelx, nely, nelz = dims
+    f, fixed = problems.cantilever3d(nelx, nely, nelz)
+    P = Plan(3, nelx, nely, nelz, 1.5, "N", fixed)
+    I = P.info
+    x = W.design_field(I.m, seed, 0.05, 1.0)
+    if dt == L.TO_F32:
+        x = x.astype(np.float32).astype(np.float64)
+    M = omesh.Mesh(nelx, nely, nelz)
+    ke = oel.element_matrix(3, 0.3)
+    E = osp.simp_modulus(x, 3.0, 1.0, 1e-9)
+    free = np.ones(M.n, bool)
+    free[fixed] = False
+    if M.n <= 3000:
+        ref = osolve.solve_dense(osp.dense_global(M.cmat(), ke, E, M.n), f, free)
+    else:
+        ir = osp.reduced_index_set(M.cmat())
+        rp, ci, perm, seg = osp.csr_pattern(ir, M.n)
+        kl = osp.assemble(x, oel.lower_vector(ke), perm, seg, 3.0, 1.0, 1e-9)
+        ref, _, res, ok = osolve.solve_pcg(osp.lower_to_full(rp, ci, kl, M.n), f, free, np.zeros(M.n), 1e-12)
+        assert ok
+    xd = torch.as_tensor(x, dtype=tdt(dt)).cuda()
+    u = torch.zeros(I.n, dtype=torch.float64, device="cuda")
+    st = torch.zeros(40, dtype=torch.uint8, device="cuda")
+    opts = L.SolveOpts(1e-8, 0.1, 2000, L.TO_OP_MATFREE, L.TO_SOLVE_AUTO, 1, 0, L.TO_PREC_GMG)
+    L.to_solve(P.handle, dt, None, xd, 3.0, torch.as_tensor(f).cuda(), u, opts, st)
+    s = read_struct(st, L.SolveStats)
+    got = host(u)
+    assert s.converged and s.residual <= 1e-8, (s.residual, s.iterations)
+    c, cref = float(f @ got), float(f @ ref)
+    assert abs(c - cref) <= 1e-7 * abs(cref)
+    assert s.iterations < 200
+    print(f"gmg3d {dims}: {s.iterations} iterations, residual {s.residual:.2e}")
+
+
+def test_solve_gmg_3d_cantilever96_properties():
+    """The 3D cantilever at 96 x 48 x 48 (221,184 elements, ~6.9e5 DOFs):
+    the multigrid solve reaches the true residual 1e-8 in far fewer
+    iterations than the Jacobi-preconditioned CG on the same design, and both
+    give the same compliance."""
+    from paper_2005_05436_amd import _lib as L
+    from paper_2005_05436_amd import problems
+    from paper_2005_05436_amd.driver import Plan, read_struct
+    nelx, nely, nelz = 96, 48, 48
+    f, fixed = problems.cantilever3d(nelx, nely, nelz)
+    P = Plan(3, nelx, nely, nelz, float(np.sqrt(3.0)), "N", fixed)
+    I = P.info
+    x = W.design_field(I.m, 11, 0.05, 1.0)
+    xd = torch.as_tensor(x, dtype=torch.float64).cuda()
+    fd = torch.as_tensor(f).cuda()
+    out = {}
+    for name, pc in (("gmg", L.TO_PREC_GMG), ("jacobi", L.TO_PREC_JACOBI)):
+        u = torch.zeros(I.n, dtype=torch.float64, device="cuda")
+        st = torch.zeros(40, dtype=torch.uint8, device="cuda")
+        opts = L.SolveOpts(1e-8, 0.1, 20000, L.TO_OP_MATFREE, L.TO_SOLVE_AUTO, 1, 0, pc)
+        L.to_solve(P.handle, L.TO_F64, None, xd, 3.0, fd, u, opts, st)
+        s = read_struct(st, L.SolveStats)
+        assert s.converged and s.residual <= 1e-8, (name, s.residual, s.iterations)
+        out[name] = (s.iterations, float(f @ host(u)))
+    assert out["gmg"][0] * 5 < out["jacobi"][0], out
+    assert abs(out["gmg"][1] - out["jacobi"][1]) <= 1e-7 * abs(out["jacobi"][1])
+    print(f"cantilever96: {out}")
