@@ -58,6 +58,7 @@ struct GmgLevel {
     int nx = 0, ny = 0, nz = 1;
     int64_t nnode = 0, n = 0, m = 0;
     double* K = nullptr;           // element matrices, (dim * 2^dim)^2 each (levels >= 1)
+    double* S = nullptr;           // assembled node stencils, 3^dim * dim^2 per node, entry-major (levels >= 1)
     double *x = nullptr, *xt = nullptr, *b = nullptr, *r = nullptr, *dinv = nullptr;
 };
 struct GmgScal {

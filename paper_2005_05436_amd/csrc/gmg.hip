@@ -100,6 +100,7 @@ struct LevelArgs {
     int nx, ny, nz;
     int64_t nnode;
     const double* K;          // stored element matrices (levels >= 1), else null
+    const double* S;          // assembled node stencils (levels >= 1), else null
     const double* E;          // level 0: moduli
     const double* ke;         // level 0: element matrix
     const uint8_t* fm;        // level 0: free mask (null above)
@@ -126,79 +127,85 @@ __device__ __forceinline__ bool elem_in(int nx, int ny, int nz, int y, int x, in
 }
 
 // --- level operators ----------------------------------------------------------
-// y = A x at node nd for a level with stored element matrices (row-major D x D).
-// 2D: the 3x3 neighbourhood is gathered once and the four element rows are
-// applied from registers; 3D: element by element (gathering the 27-node
-// neighbourhood would keep 81 values live).
+// y = A x at node nd from the assembled stencil: S holds, for neighbour k of
+// the 3^DIM box (k = ((dx + 1) 3 + (dz + 1)) 3 + (dy + 1), dz absent in 2D)
+// and components (c, c2), the block entry at S[((k DIM + c) DIM + c2) nnode + nd]
+// (entry-major, so a wave reads consecutive nodes).  Each entry is read once
+// per application, where element matrices would be read by every corner node.
 template <int DIM>
-__device__ __forceinline__ void elem_apply(const double* __restrict__ K, const double* __restrict__ x, int nx, int ny,
-                                           int nz, int64_t nd, int iy, int ix, int iz, double (&out)[DIM]) {
-    if constexpr (DIM == 2) {
-        const int64_t col = ny + 1;
-        double pv[3][3][2];
+__device__ __forceinline__ void stencil_apply(const double* __restrict__ S, int64_t nnode,
+                                              const double* __restrict__ x, int nx, int ny, int nz, int64_t nd, int iy,
+                                              int ix, int iz, double (&out)[DIM]) {
 #pragma unroll
-        for (int dx = -1; dx <= 1; ++dx)
+    for (int c = 0; c < DIM; ++c) out[c] = 0.0;
+    constexpr int ZR = DIM == 3 ? 1 : 0;
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx)
+#pragma unroll
+        for (int dz = -ZR; dz <= ZR; ++dz)
 #pragma unroll
             for (int dy = -1; dy <= 1; ++dy) {
-                const bool ok = iy + dy >= 0 && iy + dy <= ny && ix + dx >= 0 && ix + dx <= nx;
-                const int64_t q = nd + dy + col * dx;
-                pv[dx + 1][dy + 1][0] = ok ? x[2 * q] : 0.0;
-                pv[dx + 1][dy + 1][1] = ok ? x[2 * q + 1] : 0.0;
-            }
-        out[0] = out[1] = 0.0;
+                const int k = DIM == 2 ? (dx + 1) * 3 + (dy + 1) : ((dx + 1) * 3 + (dz + 1)) * 3 + (dy + 1);
+                const bool ok = iy + dy >= 0 && iy + dy <= ny && ix + dx >= 0 && ix + dx <= nx &&
+                                (DIM == 2 || (iz + dz >= 0 && iz + dz <= nz));
+                if (!ok) continue;
+                const int64_t q = node_at<DIM>(ny, nz, iy + dy, ix + dx, iz + dz);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int ey = iy - kCY[a], ex = ix - kCX[a];
-            if (ey < 0 || ey >= ny || ex < 0 || ex >= nx) continue;
-            const double* Ke = K + (size_t)(ey + (int64_t)ny * ex) * 64;
+                for (int c2 = 0; c2 < DIM; ++c2) {
+                    const double xv = x[DIM * q + c2];
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const double* kr = Ke + (2 * a + c) * 8;
-                double acc = 0.0;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int dy = kCY[b] - kCY[a], dx = kCX[b] - kCX[a];
-                    acc += kr[2 * b] * pv[dx + 1][dy + 1][0] + kr[2 * b + 1] * pv[dx + 1][dy + 1][1];
+                    for (int c = 0; c < DIM; ++c) out[c] += S[((size_t)(k * DIM + c) * DIM + c2) * nnode + nd] * xv;
                 }
-                out[c] += acc;
             }
-        }
+}
+
+// plain source vector of the level-0 operator (the V-cycle's vectors are 0 on fixed DOFs)
+template <int DIM> struct SrcPlain {
+    const double* x;
+    __device__ __forceinline__ double operator()(int64_t q, int c) const { return x[DIM * q + c]; }
+};
+
+// y = A x at node nd on level 0 (matrix-free, E_e Ke) or a stored level (stencil)
+template <int DIM, bool STORED>
+__device__ __forceinline__ void level_apply(const LevelArgs& L, const double* x, int64_t nd, int iy, int ix, int iz,
+                                            double (&out)[DIM]) {
+    if constexpr (STORED) {
+        stencil_apply<DIM>(L.S, L.nnode, x, L.nx, L.ny, L.nz, nd, iy, ix, iz, out);
     } else {
-        constexpr int NC = Cell<3>::NC, D = Cell<3>::D;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) out[c] = 0.0;
-#pragma unroll 1
-        for (int a = 0; a < NC; ++a) {
-            const int ey = iy - kCY[a], ex = ix - kCX[a], ez = iz - kCZ[a];
-            if (!elem_in<3>(nx, ny, nz, ey, ex, ez)) continue;
-            const double* Ke = K + (size_t)elem_at<3>(ny, nz, ey, ex, ez) * D * D;
-            double sv[D];
-#pragma unroll
-            for (int b = 0; b < NC; ++b) {
-                const int64_t q = node_at<3>(ny, nz, ey + kCY[b], ex + kCX[b], ez + kCZ[b]);
-#pragma unroll
-                for (int c2 = 0; c2 < 3; ++c2) sv[3 * b + c2] = x[3 * q + c2];
-            }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double* kr = Ke + (3 * a + c) * D;
-                double acc = 0.0;
-#pragma unroll
-                for (int j = 0; j < D; ++j) acc += kr[j] * sv[j];
-                out[c] += acc;
-            }
-        }
+        MatFree<DIM, double> op{L.E, L.ke, L.nx, L.ny, L.nz};
+        op.apply(nd, iy, ix, iz, SrcPlain<DIM>{x}, out);
     }
 }
 
+// node stencils of a stored level from its element matrices: one thread per
+// (node, neighbour k); the element contributions are summed in corner order
 template <int DIM>
-__device__ __forceinline__ void level_apply(const LevelArgs& L, const double* x, int64_t nd, int iy, int ix, int iz,
-                                            double (&out)[DIM]) {
-    if (L.K) {
-        elem_apply<DIM>(L.K, x, L.nx, L.ny, L.nz, nd, iy, ix, iz, out);
-    } else {
-        MatFree<DIM, double> op{L.E, L.ke, L.nx, L.ny, L.nz};
-        op.apply(nd, iy, ix, iz, SrcMask<DIM, double>{x, L.fm}, out);
+__global__ __launch_bounds__(kBlock) void gmg_stencil_kernel(int nx, int ny, int nz, int64_t nnode,
+                                                             const double* __restrict__ K, double* __restrict__ S) {
+    constexpr int NC = Cell<DIM>::NC, D = Cell<DIM>::D, NS = DIM == 2 ? 9 : 27;
+    for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < nnode * NS; t += (int64_t)gridDim.x * kBlock) {
+        const int64_t nd = t / NS;
+        const int k = (int)(t % NS);
+        const int dy = k % 3 - 1;
+        const int dz = DIM == 3 ? (k / 3) % 3 - 1 : 0;
+        const int dx = (DIM == 3 ? k / 9 : k / 3) - 1;
+        int iy, ix, iz;
+        node_coords<DIM>(nd, ny, nz, iy, ix, iz);
+        double acc[DIM][DIM] = {};
+        for (int a = 0; a < NC; ++a) {
+            const int ey = iy - kCY[a], ex = ix - kCX[a], ez = iz - kCZ[a];
+            if (!elem_in<DIM>(nx, ny, nz, ey, ex, ez)) continue;
+            const int by = kCY[a] + dy, bx = kCX[a] + dx, bz = kCZ[a] + dz;
+            if (by < 0 || by > 1 || bx < 0 || bx > 1 || bz < 0 || bz > (DIM == 3 ? 1 : 0)) continue;
+            int b = 0;
+            for (int q = 0; q < NC; ++q)
+                if (kCY[q] == by && kCX[q] == bx && kCZ[q] == bz) b = q;
+            const double* Ke = K + (size_t)elem_at<DIM>(ny, nz, ey, ex, ez) * D * D;
+            for (int c = 0; c < DIM; ++c)
+                for (int c2 = 0; c2 < DIM; ++c2) acc[c][c2] += Ke[(DIM * a + c) * D + DIM * b + c2];
+        }
+        for (int c = 0; c < DIM; ++c)
+            for (int c2 = 0; c2 < DIM; ++c2) S[((size_t)(k * DIM + c) * DIM + c2) * nnode + nd] = acc[c][c2];
     }
 }
 
@@ -206,7 +213,7 @@ __device__ __forceinline__ void level_apply(const LevelArgs& L, const double* x,
 // mode 1: Chebyshev step  d = cd d + cr dinv (b - A x),  y = x + d;
 // mode 2: the first step from x = 0:  d = cr dinv b,  y = d.
 // d is updated in place (each entry by its own thread); y and x differ.
-template <int DIM>
+template <int DIM, bool STORED>
 __global__ __launch_bounds__(kBlock) void gmg_sweep_kernel(LevelArgs L, int mode, const double* __restrict__ x,
                                                            const double* __restrict__ b, const double* __restrict__ dinv,
                                                            double* __restrict__ y, double* d, double cd, double cr,
@@ -216,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void gmg_sweep_kernel(LevelArgs L, int mode
         int iy, ix, iz;
         node_coords<DIM>(nd, L.ny, L.nz, iy, ix, iz);
         double ax[DIM] = {};
-        if (mode != 2) level_apply<DIM>(L, x, nd, iy, ix, iz, ax);
+        if (mode != 2) level_apply<DIM, STORED>(L, x, nd, iy, ix, iz, ax);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const int64_t i = DIM * nd + c;
@@ -476,9 +483,16 @@ __global__ __launch_bounds__(kBlock) void gmg_coarse_solve_kernel(const double* 
                                                                   const int32_t* done) {
     if (*done) return;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        double s = 0.0;
-        for (int j = 0; j < n; ++j) s += Ainv[(size_t)j * n + i] * b[j];
-        x[i] = s;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;      // four chains: the loads overlap
+        int j = 0;
+        for (; j + 4 <= n; j += 4) {
+            s0 += Ainv[(size_t)j * n + i] * b[j];
+            s1 += Ainv[(size_t)(j + 1) * n + i] * b[j + 1];
+            s2 += Ainv[(size_t)(j + 2) * n + i] * b[j + 2];
+            s3 += Ainv[(size_t)(j + 3) * n + i] * b[j + 3];
+        }
+        for (; j < n; ++j) s0 += Ainv[(size_t)j * n + i] * b[j];
+        x[i] = (s0 + s1) + (s2 + s3);
     }
 }
 
@@ -493,7 +507,8 @@ __global__ __launch_bounds__(kBlock) void fcg_residual_kernel(LevelArgs L, const
         int iy, ix, iz;
         node_coords<DIM>(nd, L.ny, L.nz, iy, ix, iz);
         double ax[DIM];
-        level_apply<DIM>(L, u, nd, iy, ix, iz, ax);
+        MatFree<DIM, double> op{L.E, L.ke, L.nx, L.ny, L.nz};
+        op.apply(nd, iy, ix, iz, SrcMask<DIM, double>{u, L.fm}, ax);     // u may hold values on fixed DOFs
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const int64_t i = DIM * nd + c;
@@ -630,13 +645,16 @@ __global__ void fcg_reopen_kernel(GmgScal* S) {
 
 // --- host ------------------------------------------------------------------------
 static int grid_of(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + kBlock - 1) / kBlock)); }
+// kernels that end in a last-block reduction: every block arrives on one
+// counter, so fewer, fuller blocks (their arrivals serialise at one address)
+static int grid_red(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + kBlock - 1) / kBlock)); }
 
 static LevelArgs level_args(const Plan* p, int l) {
     const GmgLevel& v = p->gmg.lv[l];
     LevelArgs L{};
     L.nx = v.nx; L.ny = v.ny; L.nz = v.nz; L.nnode = v.nnode;
-    if (l == 0) { L.K = nullptr; L.E = p->E64; L.ke = p->kf64; L.fm = p->freemask; }
-    else { L.K = v.K; L.E = nullptr; L.ke = nullptr; L.fm = nullptr; }
+    if (l == 0) { L.K = nullptr; L.S = nullptr; L.E = p->E64; L.ke = p->kf64; L.fm = p->freemask; }
+    else { L.K = v.K; L.S = v.S; L.E = nullptr; L.ke = nullptr; L.fm = nullptr; }
     return L;
 }
 
@@ -651,6 +669,7 @@ static void vcycle(Plan* p, int l, const double* b, double* x, const int32_t* do
         return;
     }
     const LevelArgs L = level_args(p, l);
+    const auto sweep = l == 0 ? gmg_sweep_kernel<DIM, false> : gmg_sweep_kernel<DIM, true>;
     double* t = v.xt;     // ping-pong partner of x
     double* r = v.r;
     const int g = grid_of(v.nnode);
@@ -659,16 +678,16 @@ static void vcycle(Plan* p, int l, const double* b, double* x, const int32_t* do
     double* cur = (kGmgNu % 2 == 1) ? x : t;
     double* nxt = (kGmgNu % 2 == 1) ? t : x;
     ChebStep cs = cheb_step(0);
-    hipLaunchKernelGGL(gmg_sweep_kernel<DIM>, dim3(g), dim3(kBlock), 0, s, L, 2, (const double*)nullptr, b, v.dinv,
+    hipLaunchKernelGGL(sweep, dim3(g), dim3(kBlock), 0, s, L, 2, (const double*)nullptr, b, v.dinv,
                        cur, r, cs.cd, cs.cr, done);
     for (int k = 1; k < kGmgNu; ++k) {
         cs = cheb_step(k);
-        hipLaunchKernelGGL(gmg_sweep_kernel<DIM>, dim3(g), dim3(kBlock), 0, s, L, 1, cur, b, v.dinv, nxt, r, cs.cd,
+        hipLaunchKernelGGL(sweep, dim3(g), dim3(kBlock), 0, s, L, 1, cur, b, v.dinv, nxt, r, cs.cd,
                            cs.cr, done);
         std::swap(cur, nxt);
     }
     // residual, restriction, coarse correction, prolongation
-    hipLaunchKernelGGL(gmg_sweep_kernel<DIM>, dim3(g), dim3(kBlock), 0, s, L, 0, x, b, v.dinv, r, (double*)nullptr,
+    hipLaunchKernelGGL(sweep, dim3(g), dim3(kBlock), 0, s, L, 0, x, b, v.dinv, r, (double*)nullptr,
                        0.0, 0.0, done);
     GmgLevel& c = G.lv[l + 1];
     hipLaunchKernelGGL(gmg_restrict_kernel<DIM>, dim3(grid_of(c.nnode)), dim3(kBlock), 0, s, v.nx, v.ny, v.nz, c.nx,
@@ -681,7 +700,7 @@ static void vcycle(Plan* p, int l, const double* b, double* x, const int32_t* do
     nxt = t;
     for (int k = 0; k < kGmgNu; ++k) {
         cs = cheb_step(k);
-        hipLaunchKernelGGL(gmg_sweep_kernel<DIM>, dim3(g), dim3(kBlock), 0, s, L, 1, cur, b, v.dinv, nxt, r, cs.cd,
+        hipLaunchKernelGGL(sweep, dim3(g), dim3(kBlock), 0, s, L, 1, cur, b, v.dinv, nxt, r, cs.cd,
                            cs.cr, done);
         std::swap(cur, nxt);
     }
@@ -698,6 +717,11 @@ static to_status gmg_setup(Plan* p, hipStream_t s) {
         hipLaunchKernelGGL(gmg_galerkin_kernel<DIM>, dim3(grid_of(D * c.m)), dim3(kBlock), 0, s, f.nx, f.ny, f.nz,
                            c.nx, c.ny, c.nz, l == 0 ? p->E64 : nullptr, l == 0 ? p->kf64 : nullptr,
                            l == 0 ? p->freemask : nullptr, l == 0 ? nullptr : f.K, c.K);
+    }
+    for (int l = 1; l + 1 < G.L; ++l) {
+        const GmgLevel& v = G.lv[l];
+        hipLaunchKernelGGL(gmg_stencil_kernel<DIM>, dim3(grid_of(v.nnode * (DIM == 2 ? 9 : 27))), dim3(kBlock), 0, s,
+                           v.nx, v.ny, v.nz, v.nnode, v.K, v.S);
     }
     for (int l = 0; l + 1 < G.L; ++l) {
         const LevelArgs L = level_args(p, l);
@@ -725,7 +749,7 @@ static to_status solve_gmg(Plan* p, const double* f, double* u, const to_solve_o
     double* part = p->partial + (size_t)kMaxCoopBlocks * kPartialWidth;
     unsigned* ctr = p->bar + 12;
     const LevelArgs L0 = level_args(p, 0);
-    const int g0 = grid_of(p->info.nnode), gn = grid_of(n);
+    const int g0 = grid_red(p->info.nnode), gn = grid_red(n);
     if (o.zero_x0)
         hipLaunchKernelGGL(fill_zero_f64_kernel, dim3(gn), dim3(kBlock), 0, s, u, n);
     hipLaunchKernelGGL(fcg_init_kernel, dim3(1), dim3(1), 0, s, S, o.maxit);

@@ -242,7 +242,7 @@ struct Offsets {
         hlim, hp64, hp32, Hs64, Hs32, E64, E32, partial, ll, scal, bar, v64[8], v32[8], fx64, fx32, total;
     // multigrid hierarchy (2D)
     GmgShape gs;
-    size_t gK[kGmgMaxLevels], gx[kGmgMaxLevels], gxt[kGmgMaxLevels], gb[kGmgMaxLevels], gr[kGmgMaxLevels],
+    size_t gK[kGmgMaxLevels], gS[kGmgMaxLevels], gx[kGmgMaxLevels], gxt[kGmgMaxLevels], gb[kGmgMaxLevels], gr[kGmgMaxLevels],
         gd[kGmgMaxLevels], gAinv, gscal;
 };
 
@@ -284,6 +284,7 @@ static Offsets layout(const Sizes& S) {
             const int64_t nx = o.gs.nx[l], ny = o.gs.ny[l], nz = o.gs.nz[l];
             const int64_t n = gmg_dofs(dim, (int)nx, (int)ny, (int)nz);
             o.gK[l] = l ? L.take(8 * D * D * (size_t)(nx * ny * nz)) : 0;
+            o.gS[l] = l ? L.take(8 * (size_t)(dim == 2 ? 9 : 27) * dim * dim * (size_t)(n / dim)) : 0;
             o.gx[l] = l ? L.take(8 * n) : 0;
             o.gb[l] = l ? L.take(8 * n) : 0;
             o.gxt[l] = L.take(8 * n);
@@ -447,6 +448,7 @@ to_status plan_create(const to_mesh_desc* D, void* ws, size_t ws_bytes, hipStrea
         v.n = S.G.dim * v.nnode;
         v.m = (int64_t)v.nx * v.ny * v.nz;
         v.K = l ? (double*)(base + o.gK[l]) : nullptr;
+        v.S = l ? (double*)(base + o.gS[l]) : nullptr;
         v.x = l ? (double*)(base + o.gx[l]) : nullptr;
         v.b = l ? (double*)(base + o.gb[l]) : nullptr;
         v.xt = (double*)(base + o.gxt[l]);
