@@ -18,7 +18,10 @@ second including the Jacobi-preconditioned CG solve (the plain CG of the
 metric); roofline = the persistent PCG kernel.  Also in the line: the same
 steps with the multigrid-preconditioned CG (gmg, to_iters_per_s_gmg), with
 the learned warm start for both solvers (nn_warm_start), the 64-design
-ragged batch (batch64) and the FP64 oracle on the host (cpu_baseline).
+ragged batch (batch64), test T2 of Table 4 with and without the periodic
+Anderson extrapolation (pae_t2), the 900 x 900 frame problem (frame900), the
+96 x 48 x 48 3D cantilever with three solvers (cantilever3d) and the FP64
+oracle on the host (cpu_baseline).
 Stage times come from HIP events recorded on the stream the kernels run on.
 """
 import argparse
@@ -242,6 +245,118 @@ def train_net(args, cfg, op, sp, precond):
                  "last_train_loss": round(float(net.loss.item()), 5)}
 
 
+def pae_run(args):
+    """Test T2 of Table 4 (MBB 300 x 100, rmin 8.75, beta 2, volume-
+    preserving projection, FP64, multigrid-preconditioned CG) with the
+    periodic Anderson extrapolation (m_r = 4, q = 4, from iteration 20,
+    alpha = 0.9) until |r|_2 / sqrt(m) < 1e-6 (at most --pae-cap
+    iterations), and without it for the same number of iterations."""
+    import torch
+    import workloads as W
+    from paper_2005_05436_amd import _lib as L
+    from paper_2005_05436_amd.driver import TopOpt
+    cfg = W.PAE_T["T2"]
+    out = {"case": "T2", "paper_iterations": {"plain": "2500 (not converged)", "pae": 352}}
+    n_pae = None
+    for use in (True, False):
+        g = TopOpt(cfg, precond=L.TO_PREC_GMG,
+                   pae=dict(mr=4, q=4, q0=W.PAE_Q0["T2"], alpha=0.9, xi=1.0) if use else None)
+        cap = args.pae_cap if use else n_pae
+        ch = torch.zeros(cap, dtype=torch.float64, device=g.x.device)
+        pv = g.pst.view(torch.float64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, conv = 0, None
+        while it < cap and conv is None:
+            for _ in range(min(50, cap - it)):
+                g.step()
+                ch[it:it + 1].copy_(pv[2:3])
+                it += 1
+            if use:
+                hit = torch.nonzero(ch[:it] < 1e-6)
+                if hit.numel():
+                    conv = int(hit[0, 0]) + 1
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        n = conv or it
+        s = g.stats()
+        r = {"iterations": n, "converged": conv is not None, "residual": float(ch[n - 1].item()),
+             "compliance": s["c"], "seconds": round(wall, 2), "ms_per_iteration": round(1e3 * wall / it, 3)}
+        if use:
+            n_pae = n
+            out["pae"] = r
+        else:
+            out["plain_same_iterations"] = r
+        print(f"[bench] T2 {'with' if use else 'without'} PAE: {r}", file=sys.stderr, flush=True)
+    return out
+
+
+def frame_run(args):
+    """The frame reinforcement problem of Sec. 3.5 (900 x 900, 1.62e6 DOFs,
+    ft = 3, beta = 2, FP64, multigrid-preconditioned CG): seconds per
+    redesign iteration (the paper quotes about 10.8 s on its laptop)."""
+    import torch
+    import workloads as W
+    from paper_2005_05436_amd import _lib as L
+    from paper_2005_05436_amd.driver import TopOpt
+    g = TopOpt(W.C4, precond=L.TO_PREC_GMG)
+    for _ in range(2):
+        g.step()
+    K = args.frame_steps
+    hist = torch.zeros((K, g.sst.numel()), dtype=torch.uint8, device=g.sst.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        g.step()
+        hist[k].copy_(g.sst, non_blocking=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    h = hist.cpu().numpy()
+    st = [L.SolveStats.from_buffer_copy(h[k].tobytes()) for k in range(K)]
+    out = {"workload": W.C4.name, "dofs": int(g.plan.info.n), "iterations_timed": f"3-{2 + K}",
+           "ms_per_iteration": round(1e3 * wall / K, 2), "paper_s_per_iteration": 10.8,
+           "cg_iterations": [s.iterations for s in st], "all_converged": bool(all(s.converged for s in st)),
+           "compliance": g.stats()["c"]}
+    print(f"[bench] frame900: {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def c3d_run(args):
+    """The 3D cantilever 96 x 48 x 48 (221,184 Hex8 elements, 6.9e5 DOFs,
+    rmin sqrt(3), ft = 3, beta = 2): seconds per redesign iteration with the
+    Jacobi-preconditioned CG in FP64, with FP32 fields and the mixed-precision
+    CG (FP64 refinement), and with the multigrid-preconditioned CG (the paper's
+    Table 5 quotes 14.2 s per iteration for its code with a multigrid-
+    preconditioned CG at this size, rmin 2 sqrt(3), on its laptop)."""
+    import torch
+    import workloads as W
+    from paper_2005_05436_amd import _lib as L
+    from paper_2005_05436_amd.driver import TopOpt
+    out = {"workload": W.C2.name, "elements": W.C2.m, "paper_s_per_iteration_mgcg": 14.2}
+    for name, prec, sp, pc in (("jacobi_f64", "f64", L.TO_SOLVE_AUTO, L.TO_PREC_JACOBI),
+                               ("jacobi_f32_mixed", "f32", L.TO_SOLVE_MIXED, L.TO_PREC_JACOBI),
+                               ("gmg_f64", "f64", L.TO_SOLVE_AUTO, L.TO_PREC_GMG)):
+        g = TopOpt(W.C2, precision=prec, solve_precision=sp, precond=pc, autotune=True)
+        g.step()
+        K = args.c3d_steps
+        hist = torch.zeros((K, g.sst.numel()), dtype=torch.uint8, device=g.sst.device)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(K):
+            g.step()
+            hist[k].copy_(g.sst, non_blocking=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        h = hist.cpu().numpy()
+        st = [L.SolveStats.from_buffer_copy(h[k].tobytes()) for k in range(K)]
+        out[name] = {"ms_per_iteration": round(1e3 * wall / K, 2), "iterations_timed": f"2-{1 + K}",
+                     "cg_iterations": [s.iterations for s in st], "all_converged": bool(all(s.converged for s in st)),
+                     "max_true_residual": max(s.residual for s in st), "compliance": g.stats()["c"]}
+        print(f"[bench] cantilever 3D {name}: {out[name]}", file=sys.stderr, flush=True)
+        del g
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,6 +375,12 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=3,
                     help="redesign iterations of the 64-design ragged batch, batched (graph) and one by one "
                          "(0: skip)")
+    ap.add_argument("--pae-cap", type=int, default=2500,
+                    help="iteration cap of the T2 run with Anderson extrapolation (0: skip)")
+    ap.add_argument("--frame-steps", type=int, default=10,
+                    help="timed iterations of the 900 x 900 frame problem (0: skip)")
+    ap.add_argument("--c3d-steps", type=int, default=3,
+                    help="timed iterations of the 96 x 48 x 48 3D cantilever per solver (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size once (a counter calibration kernel)")
     args = ap.parse_args()
@@ -404,6 +525,12 @@ def main():
         line["nn_warm_start"] = out
     if args.batch_steps > 0:
         line["batch64"] = batch_run(args)
+    if args.pae_cap > 0:
+        line["pae_t2"] = pae_run(args)
+    if args.frame_steps > 0:
+        line["frame900"] = frame_run(args)
+    if args.c3d_steps > 0:
+        line["cantilever3d"] = c3d_run(args)
     if args.copy_probe_mib > 0:
         nb = args.copy_probe_mib << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device=g.sst.device)

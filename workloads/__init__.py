@@ -83,6 +83,22 @@ C4 = Config("frame900", "frame", 900, 900, volfrac=0.2, penal=3.0, rmin=8.0, ft=
 C4_SMALL = replace(C4, name="frame100", nelx=100, nely=100, rmin=2.0, iterations=8)
 
 
+# The convergence tests of Table 4 (MBB, f = 0.5, rmin = 8.75, 2,500
+# iterations at most, stop when |r|_2 / sqrt(m) < 1e-6 on the physical field):
+# T1 density filter alone; T2 volume-preserving projection with beta = 2;
+# T3 as T2 with continuation on beta (from 250, x2 every 25, up to 16) and p
+# (from 50, +0.25 every 25, 1 -> 3); T4 as T2 on 600 x 200 (rmin kept).
+# The filter boundary rule of these runs is not stated; 'D' is taken.
+PAE_T = {
+    "T1": Config("T1", "mbb", 300, 100, volfrac=0.5, rmin=8.75, ft=1, bc="D", iterations=2500),
+    "T2": Config("T2", "mbb", 300, 100, volfrac=0.5, rmin=8.75, ft=3, bc="D", beta=2.0, iterations=2500),
+    "T3": Config("T3", "mbb", 300, 100, volfrac=0.5, rmin=8.75, ft=3, bc="D", beta=2.0, penal=1.0,
+                 iterations=2500, beta_sched=(250, 16.0, 25, 2.0, "mul"), penal_sched=(50, 3.0, 25, 0.25, "add")),
+    "T4": Config("T4", "mbb", 600, 200, volfrac=0.5, rmin=8.75, ft=3, bc="D", beta=2.0, iterations=2500),
+}
+PAE_Q0 = {"T1": 20, "T2": 20, "T3": 500, "T4": 20}
+
+
 def batch_configs(count=64, seed=0):
     """Ragged batch: per instance (drawn in this order) the problem type
     (cantilever or MBB, 1/2 each), nelx uniform over even integers in
