@@ -11,6 +11,11 @@
 // and the final design are therefore exactly those of plain bisection, with
 // four times fewer grid barriers.  Volume sums are double-double, so every
 // decision agrees with an exactly rounded sum except in exact ties.
+//
+// The same kernel runs the explicit primal-dual update of Appendix A instead
+// of the bisection (TO_OC_PD).  Further down: the bisection whose volume test
+// filters and projects each candidate (Sec. 3.2) and the periodic Anderson
+// extrapolation of the OC iteration (Sec. 3.3).
 #include <cmath>
 #include <cstring>
 #include <type_traits>
@@ -508,7 +513,8 @@ static to_status run_oc_filtered(Plan* p, to_dtype dt, int ft, T* x, const T* dc
     OcfState* fs = reinterpret_cast<OcfState*>(p->scal + 32);
     double* part = p->partial + (size_t)kMaxCoopBlocks * kPartialWidth;
     unsigned* ctr = p->bar + 20;
-    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (m + kBlock - 1) / kBlock));
+    // 256 blocks: the arrivals on the last-block counter serialise at one address
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, (m + kBlock - 1) / kBlock));
     hipLaunchKernelGGL(ocf_init_kernel<T>, dim3(blocks), dim3(kBlock), 0, s, m, p->passive, x, dc, dv, volfrac,
                        p->fx64, part, ctr, fs);
     TO_HIP(hipGetLastError());

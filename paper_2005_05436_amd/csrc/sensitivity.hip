@@ -102,7 +102,8 @@ to_status launch_sensitivity(Plan* p, to_dtype dt, const void* xphys, const doub
     TO_HIP(hipGetLastError());
     if (f && c) {
         const int64_t n = p->info.n;
-        const int nb = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
+        // 256 blocks: the arrivals on the last-block counter serialise at one address
+        const int nb = (int)std::min<int64_t>(256, (n + kBlock - 1) / kBlock);
         // partial slots: the second region of the partial buffer; counter: bar[8]
         double* part = p->partial + (size_t)kMaxCoopBlocks * kPartialWidth;
         hipLaunchKernelGGL(dot_kernel, dim3(nb), dim3(kBlock), 0, s, n, f, u, part, p->bar + 8, c);

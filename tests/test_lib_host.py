@@ -183,3 +183,16 @@ def test_frame_problem_matches_oracle(nelx, nely, sign):
     np.testing.assert_array_equal(f1, f2)
     np.testing.assert_array_equal(x1, x2)
     np.testing.assert_array_equal(c1, c2)
+
+
+def test_new_entry_points_validate_before_launching(lib):
+    """The Anderson and OC-variant entry points reject a missing plan or bad
+    parameters on the host, before anything is enqueued."""
+    prm = L.PaeParams(4, 4, 20, 0, 0.9, 1.0)
+    n = C.c_size_t()
+    assert lib.to_pae_query(None, C.byref(prm), C.byref(n)) == L.TO_EINVAL
+    assert lib.to_pae_step(None, L.TO_F64, None, None, 0, C.byref(prm), None, None, None) == L.TO_EINVAL
+    st = C.c_void_p(8)
+    assert lib.to_oc_update_pd(None, L.TO_F64, None, None, None, 0.5, 0.2, st, None) == L.TO_EINVAL
+    assert lib.to_oc_update_filtered(None, L.TO_F64, 2, None, None, None, 0.5, 0.2, 2.0, None, st, None) == L.TO_EINVAL
+    assert b"plan" in lib.to_last_error()
