@@ -20,8 +20,9 @@ steps with the multigrid-preconditioned CG (gmg, to_iters_per_s_gmg), with
 the learned warm start for both solvers (nn_warm_start), the 64-design
 ragged batch (batch64), test T2 of Table 4 with and without the periodic
 Anderson extrapolation (pae_t2), the 900 x 900 frame problem (frame900), the
-96 x 48 x 48 3D cantilever with three solvers (cantilever3d) and the FP64
-oracle on the host (cpu_baseline).
+96 x 48 x 48 3D cantilever with three solvers (cantilever3d), the non-solve
+stages on a 16 times larger mesh (stage_scaling) and the FP64 oracle on the
+host (cpu_baseline).
 Stage times come from HIP events recorded on the stream the kernels run on.
 """
 import argparse
@@ -321,6 +322,55 @@ def frame_run(args):
     return out
 
 
+def stage_scaling(args):
+    """The non-solve stages on a mesh 16 times the benchmark's (MBB 4800 x 1600,
+    7.68e6 elements, rmin 3 so the filter is bandwidth-bound, FP32 fields,
+    volume-preserving projection, beta 2): per-stage time and algorithmic
+    bandwidth once the fields no longer fit in the caches (at 1200 x 400 a
+    stage's fields are a few MB and its time is launch and grid-sum latency)."""
+    import torch
+    import workloads as W
+    from paper_2005_05436_amd import _lib as L
+    from paper_2005_05436_amd.driver import TopOpt
+    cfg = W.Config("mbb4800x1600", "mbb", 4800, 1600, rmin=3.0, ft=3, bc="D", beta=2.0, penal=3.0,
+                   precision="f32")
+    g = TopOpt(cfg, autotune=True)
+    I = g.plan.info
+    h, dt, st = g.plan.handle, g.dtype, g.state
+    g.x.copy_(torch.as_tensor(W.smooth_design(cfg, 5), dtype=torch.float32))
+    g.u.copy_(torch.as_tensor(W.displacement_field(I.n, 6)))
+    stages = {
+        "filter": lambda: L.to_filter(h, dt, L.TO_FILTER_FWD, g.x, None, None, g.xtilde, None),
+        "project": lambda: L.to_project(h, dt, cfg.ft, g.xtilde, g.x, g.xphys, g.dprj, st.beta, g.eta, cfg.volfrac,
+                                        g.xphys_old, g.pst),
+        "assemble": lambda: L.to_assemble(h, dt, g.xphys, st.penal, g.kval),
+        "sensitivity": lambda: L.to_sensitivity(h, dt, g.xphys, g.u, g.f, st.penal, g.dc, g.c),
+        "backfilter": lambda: L.to_filter(h, dt, L.TO_FILTER_ADJ2, g.dc, g.dv, g.dprj, g.dcf, g.dv0),
+        "oc": lambda: L.to_oc_update(h, dt, g.x, g.dcf, g.dv0, cfg.volfrac, cfg.move, g.ost),
+    }
+    nb = stage_bytes(cfg, I, 4, "assembled", "auto")
+    out = {"workload": cfg.name, "elements": I.m, "rmin": cfg.rmin, "precision": "f32", "stages": {}}
+    reps = 5
+    for name, fn in stages.items():
+        fn()
+        a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b2.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b2) / reps
+        gbps = nb[name] / (ms * 1e-3) / 1e9
+        out["stages"][name] = {"ms": round(ms, 4), "algorithmic_bytes": nb[name], "gbps": round(gbps, 1),
+                               "hbm_frac": round(gbps * 1e9 / HBM_PEAK, 4)}
+    total = sum(v["ms"] for v in out["stages"].values())
+    out["elem_per_s"] = round(I.m / (total * 1e-3), 1)
+    print(f"[bench] stage scaling {cfg.name}: {out}", file=sys.stderr, flush=True)
+    del g
+    return out
+
+
 def c3d_run(args):
     """The 3D cantilever 96 x 48 x 48 (221,184 Hex8 elements, 6.9e5 DOFs,
     rmin sqrt(3), ft = 3, beta = 2): seconds per redesign iteration with the
@@ -379,6 +429,8 @@ def main():
                     help="iteration cap of the T2 run with Anderson extrapolation (0: skip)")
     ap.add_argument("--frame-steps", type=int, default=10,
                     help="timed iterations of the 900 x 900 frame problem (0: skip)")
+    ap.add_argument("--no-scaling", dest="scaling", action="store_false",
+                    help="skip the non-solve stages on the 4800 x 1600 mesh")
     ap.add_argument("--c3d-steps", type=int, default=3,
                     help="timed iterations of the 96 x 48 x 48 3D cantilever per solver (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -531,6 +583,8 @@ def main():
         line["frame900"] = frame_run(args)
     if args.c3d_steps > 0:
         line["cantilever3d"] = c3d_run(args)
+    if args.scaling:
+        line["stage_scaling"] = stage_scaling(args)
     if args.copy_probe_mib > 0:
         nb = args.copy_probe_mib << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device=g.sst.device)

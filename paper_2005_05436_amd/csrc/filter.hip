@@ -97,7 +97,8 @@ template <typename T, int MODE, int V, int LS>
 __global__ __launch_bounds__(64 * kFiltMaxParts) void filter2d_kernel(
     int nely, int nelx, int R, char bc, const T* __restrict__ hp, int hps, const int32_t* __restrict__ hlim,
     const T* __restrict__ Hs, const T* __restrict__ in, const T* __restrict__ in2,
-    const T* __restrict__ sc, T* __restrict__ out, T* __restrict__ out2, unsigned* ctr, const unsigned* skip) {
+    const T* __restrict__ sc, T* __restrict__ out, T* __restrict__ out2, unsigned* ctr, const unsigned* skip,
+    int chunk) {
     extern __shared__ unsigned char smem_raw[];
     __shared__ int tile_sh;
     if (skip && *skip) return;          // the whole launch is cancelled (the tile counter is untouched)
@@ -115,10 +116,16 @@ __global__ __launch_bounds__(64 * kFiltMaxParts) void filter2d_kernel(
     const int parts = blockDim.x >> 6;
     T* tile2 = tile + (size_t)ls * LX;
 
-    for (;;) {
-        if (threadIdx.x == 0) tile_sh = (int)atomicAdd(&ctr[0], 1u);
-        __syncthreads();
-        const int t = tile_sh;
+    // tiles are claimed `chunk` at a time: every claim is an atomic on one
+    // address, which at small radii (little work per tile) would serialise
+    int t = 0, t_end = 0;
+    for (;; ++t) {
+        if (t >= t_end) {
+            if (threadIdx.x == 0) tile_sh = (int)atomicAdd(&ctr[0], (unsigned)chunk);
+            __syncthreads();
+            t = tile_sh;
+            t_end = min(t + chunk, ntiles);
+        }
         if (t >= ntiles) break;
         const int y0 = (t % nty) * 64, x0 = (t / nty) * V;
         // stage the window with the boundary rule
@@ -314,8 +321,11 @@ static to_status run_filter2d_ls(Plan* p, const T* hp, const T* Hs, const T* in,
         per_cu = 1;
     const int ntiles = ((p->nely + 63) / 64) * ((p->nelx + V - 1) / V);
     const int blocks = std::max(1, std::min(ntiles, per_cu * p->num_cu));
+    // tiles per claim: about 8 claims per block at large radii (uneven work
+    // near the boundary is balanced), 2 at small radii (the claims dominate)
+    const int chunk = std::max(1, ntiles / (blocks * (W >= 16 ? 8 : 2)));
     hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * parts), lds, s, p->nely, p->nelx, R, p->bc, hp, p->hp_stride,
-                       p->hlim, Hs, in, in2, sc, out, out2, p->bar + 16, p->filt_skip);
+                       p->hlim, Hs, in, in2, sc, out, out2, p->bar + 16, p->filt_skip, chunk);
     TO_HIP(hipGetLastError());
     return TO_OK;
 }
