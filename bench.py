@@ -199,14 +199,16 @@ def batch_run(args):
             "graph_captures": info["graph_captures"]}
 
 
-def solver_run(args, cfg, op, sp, precond, net=None):
+def solver_run(args, cfg, op, sp, precond, net=None, zero_x0=False):
     """The same redesign iterations (steps warmup+1 .. warmup+K of the run)
-    with another solve set-up: the multigrid preconditioner and/or the
-    network warm start.  Returns the rate and per-step CG statistics."""
+    with another solve set-up: the multigrid preconditioner, the network warm
+    start, or every solve started from u = 0 instead of the previous
+    displacement.  Returns the rate and per-step CG statistics."""
     import torch
     from paper_2005_05436_amd import _lib as L
     from paper_2005_05436_amd.driver import TopOpt
     g = TopOpt(cfg, op=op, solve_precision=sp, autotune=True, precond=precond)
+    g.params.solve.zero_x0 = 1 if zero_x0 else 0
     for _ in range(args.warmup):
         g.step_stages(net)
     K = args.steps
@@ -319,6 +321,62 @@ def frame_run(args):
            "cg_iterations": [s.iterations for s in st], "all_converged": bool(all(s.converged for s in st)),
            "compliance": g.stats()["c"]}
     print(f"[bench] frame900: {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def stream_copy(nbytes=1 << 30, reps=5):
+    """Achievable HBM bandwidth: a device-to-device copy of nbytes (read and
+    written once), larger than the 256 MB last-level cache."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    s = a.elapsed_time(b) / reps * 1e-3
+    gbps = 2 * nbytes / s / 1e9
+    del src, dst
+    return {"bytes_read_and_written": 2 * nbytes, "gbps": round(gbps, 1), "frac_of_peak": round(gbps * 1e9 / HBM_PEAK, 4)}
+
+
+def cold_stages(g, cfg, sb, reps=5):
+    """Each non-solve stage of the benchmark workload timed alone after
+    streaming a 1 GiB buffer (the last-level cache holds none of its
+    fields), median over reps."""
+    import statistics
+    import torch
+    from paper_2005_05436_amd import _lib as L
+    h, dt, st = g.plan.handle, g.dtype, g.state
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    stages = {
+        "filter": lambda: L.to_filter(h, dt, L.TO_FILTER_FWD, g.x, None, None, g.xtilde, None),
+        "project": lambda: L.to_project(h, dt, cfg.ft, g.xtilde, g.x, g.xphys, g.dprj, st.beta, g.eta, cfg.volfrac,
+                                        g.xphys_old, g.pst),
+        "assemble": lambda: L.to_assemble(h, dt, g.xphys, st.penal, g.kval),
+        "sensitivity": lambda: L.to_sensitivity(h, dt, g.xphys, g.u, g.f, st.penal, g.dc, g.c),
+        "backfilter": lambda: L.to_filter(h, dt, L.TO_FILTER_ADJ2, g.dc, g.dv, g.dprj, g.dcf, g.dv0),
+        "oc": lambda: L.to_oc_update(h, dt, g.x, g.dcf, g.dv0, cfg.volfrac, cfg.move, g.ost),
+    }
+    out = {}
+    for name, fn in stages.items():
+        ts = []
+        for _ in range(reps):
+            flush.fill_(1.0)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        ms = statistics.median(ts)
+        gbps = sb[name] / (ms * 1e-3) / 1e9
+        out[name] = {"ms": round(ms, 4), "gbps": round(gbps, 1), "hbm_frac": round(gbps * 1e9 / HBM_PEAK, 4)}
+    del flush
     return out
 
 
@@ -445,6 +503,8 @@ def main():
                     help="iteration cap of the T2 run with Anderson extrapolation (0: skip)")
     ap.add_argument("--frame-steps", type=int, default=10,
                     help="timed iterations of the 900 x 900 frame problem (0: skip)")
+    ap.add_argument("--no-x0-zero", dest="x0_zero", action="store_false",
+                    help="skip the runs whose solves start from u = 0")
     ap.add_argument("--no-scaling", dest="scaling", action="store_false",
                     help="skip the non-solve stages on the 4800 x 1600 mesh")
     ap.add_argument("--c3d-steps", type=int, default=3,
@@ -477,6 +537,8 @@ def main():
           file=sys.stderr, flush=True)
 
     sst_hist = torch.zeros((max(args.steps, 1), g.sst.numel()), dtype=torch.uint8, device=g.sst.device)
+    pst_hist = torch.zeros((max(args.steps, 1), g.pst.numel()), dtype=torch.uint8, device=g.pst.device)
+    ost_hist = torch.zeros((max(args.steps, 1), g.ost.numel()), dtype=torch.uint8, device=g.ost.device)
 
     def timed_step(ev, k=None):
         """One redesign iteration through the single-stage entry points (the
@@ -499,8 +561,10 @@ def main():
         ev[6].record(stream)
         L.to_oc_update(h, dt, g.x, g.dcf, g.dv0, cfg.volfrac, cfg.move, g.ost)
         ev[7].record(stream)
-        if k is not None:
-            sst_hist[k].copy_(g.sst, non_blocking=True)     # device-to-device, after the timed stages
+        if k is not None:                                  # device-to-device, after the timed stages
+            sst_hist[k].copy_(g.sst, non_blocking=True)
+            pst_hist[k].copy_(g.pst, non_blocking=True)
+            ost_hist[k].copy_(g.ost, non_blocking=True)
         g.xphys_old.copy_(g.xphys)
         st.loop += 1
         st.penal = L.to_continuation(st.penal, g.params.penal_sched, st.loop)
@@ -528,6 +592,9 @@ def main():
     hist = sst_hist.cpu().numpy()
     solve_stats = [L.SolveStats.from_buffer_copy(hist[k].tobytes()) for k in range(K)]
     iters = [s.iterations for s in solve_stats]
+    ph, oh = pst_hist.cpu().numpy(), ost_hist.cpu().numpy()
+    newton = [L.ProjectStats.from_buffer_copy(ph[k].tobytes()).n_newton for k in range(K)]
+    bisect = [L.OcStats.from_buffer_copy(oh[k].tobytes()).n_bs for k in range(K)]
     last = g.stats()
     print(f"[bench] timed {K} steps in {wall:.3f} s; cg iterations per step {iters}; last: {json.dumps(last)}",
           file=sys.stderr, flush=True)
@@ -568,13 +635,27 @@ def main():
         "stage_gbps": {s: round(v, 1) for s, v in gbps.items()},
         "stage_hbm_frac": {s: round(v * 1e9 / HBM_PEAK, 4) for s, v in gbps.items()},
         "roofline": roof,
+        "loop_counts": {"cg": iters, "newton": newton, "bisection": bisect},
     }
+    sc = stream_copy()
+    line["stream_copy"] = sc
+    roof["frac_of_achievable"] = round(solve_gbps / sc["gbps"], 4)
+    line["stage_cold_cache"] = cold_stages(g, cfg, sb)
+    print(f"[bench] copy {sc}; cold-cache stages {line['stage_cold_cache']}", file=sys.stderr, flush=True)
     if I.dim == 2 and args.gmg:
         from paper_2005_05436_amd import _lib as L2
         r = solver_run(args, cfg, op, sp, L2.TO_PREC_GMG)
         print(f"[bench] multigrid run: cg iterations per step {r['cg_iterations']}", file=sys.stderr, flush=True)
         line["gmg"] = r
         line["to_iters_per_s_gmg"] = r["to_iters_per_s"]
+    if args.x0_zero and I.dim == 2:
+        from paper_2005_05436_amd import _lib as L2
+        z = {"note": "every solve started from u = 0 (the other runs warm-start from the previous displacement)"}
+        z["jacobi"] = solver_run(args, cfg, op, sp, L2.TO_PREC_JACOBI, zero_x0=True)
+        if args.gmg:
+            z["gmg"] = solver_run(args, cfg, op, sp, L2.TO_PREC_GMG, zero_x0=True)
+        print(f"[bench] x0 = 0: cg iterations per step {z['jacobi']['cg_iterations']}", file=sys.stderr, flush=True)
+        line["x0_zero"] = z
     if args.nn_train_steps > 0 and I.dim == 2:
         from paper_2005_05436_amd import _lib as L2
         out = {"note": "network trained on the first iterations of the same problem (in-sample); "
