@@ -536,7 +536,8 @@ def main():
     stream = torch.cuda.current_stream()
     t = g.tuning
     print(f"[bench] {cfg.name} m={I.m} n={I.n} nnz_lower={I.nnz_lower} precision={cfg.precision} op={args.op} "
-          f"tuning: filter columns {t.filt_v}, waves {t.filt_parts} / {t.filt_parts2}, assembly block {t.asm_block}",
+          f"tuning: filter columns {t.filt_v}, waves {t.filt_parts} / {t.filt_parts2}, matrix-core tile "
+          f"{t.filt_mfma} / {t.filt_mfma2}, assembly block {t.asm_block}",
           file=sys.stderr, flush=True)
 
     sst_hist = torch.zeros((max(args.steps, 1), g.sst.numel()), dtype=torch.uint8, device=g.sst.device)
@@ -639,6 +640,8 @@ def main():
         "stage_hbm_frac": {s: round(v * 1e9 / HBM_PEAK, 4) for s, v in gbps.items()},
         "roofline": roof,
         "loop_counts": {"cg": iters, "newton": newton, "bisection": bisect},
+        "tuning": {k: getattr(t, k) for k in ("filt_v", "filt_parts", "filt_parts2", "filt_mfma", "filt_mfma2",
+                                              "asm_block")},
     }
     sc = stream_copy()
     line["stream_copy"] = sc

@@ -396,7 +396,10 @@ to_status to_nn_train_step(to_nn* nn, to_dtype dtype, const void* xtilde, const 
 /* ---------------------------------------------------------------------------
  * Launch-shape autotuning.  to_plan_autotune times, on the plan's own arrays,
  * the candidate shapes of the 2D filter kernel (output columns per tile 4 or
- * 8; waves per block automatic or equal to the columns) and of the assembly
+ * 8; waves per block automatic or equal to the columns; for FP32 also the
+ * four tiles of the matrix-core variant, which computes the same sums with
+ * v_mfma_f32_16x16x4_f32 and falls back to the stencil kernel where its tile
+ * does not fit in LDS) and of the assembly
  * kernel (128, 256 or 512 threads per block; only when kval, a device buffer
  * of nnz_lower entries of `dtype`, is given) and keeps the fastest in the
  * plan (the waves per block separately for the one-field and the fused
@@ -410,6 +413,9 @@ typedef struct {
     int32_t asm_block;           /* 128, 256 or 512 */
     int32_t tuned;               /* 1 once autotuned */
     int32_t filt_parts2;         /* waves per block, fused double adjoint: 0 .. 16 */
+    int32_t filt_mfma;           /* 2D FP32 filter on the matrix cores, one field: 0 off, 1..4 the tile
+                                    (1: 32 x 64, 2: 16 x 64, 3: 32 x 32, 4: 16 x 32 outputs) */
+    int32_t filt_mfma2;          /* the same for the fused double adjoint */
     int32_t pad;
 } to_tuning;
 to_status to_plan_autotune(to_plan* plan, to_dtype dtype, void* kval, to_tuning* h_out, void* stream);

@@ -183,6 +183,7 @@ to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuni
         struct Cand { int v, parts; };
         const Cand cands[] = {{8, 0}, {8, 8}, {4, 0}, {4, 4}};
         float tbest = 1e30f;
+        p->tune.filt_mfma = p->tune.filt_mfma2 = best.filt_mfma = best.filt_mfma2 = 0;
         for (const Cand& c : cands) {
             p->tune.filt_v = c.v;
             p->tune.filt_parts = c.parts;
@@ -193,8 +194,21 @@ to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuni
             if (st != TO_OK) continue;          // e.g. the tile does not fit in LDS
             if (t < tbest) { tbest = t; best.filt_v = c.v; best.filt_parts = c.parts; }
         }
+        if (dt == TO_F32) {                  // the matrix-core tiles (same columns and waves otherwise)
+            p->tune.filt_v = best.filt_v;
+            p->tune.filt_parts = best.filt_parts;
+            for (int shape = 1; shape <= 4; ++shape) {
+                p->tune.filt_mfma = shape;
+                to_status st = TO_OK;
+                const float t = time_ms(s, [&] {
+                    if (st == TO_OK) st = launch_filter(p, dt, TO_FILTER_FWD, Hs, nullptr, nullptr, scratch, nullptr, s);
+                }, 3);
+                if (st == TO_OK && t < tbest) { tbest = t; best.filt_mfma = shape; }
+            }
+        }
         p->tune.filt_v = best.filt_v;
         p->tune.filt_parts = best.filt_parts;
+        p->tune.filt_mfma = best.filt_mfma;
         // fused double adjoint: waves per block with the chosen columns
         void* scratch2 = dt == TO_F64 ? (void*)p->v64[7] : (void*)p->v32[7];   // n >= m entries
         tbest = 1e30f;
@@ -207,7 +221,19 @@ to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuni
             if (st != TO_OK) continue;
             if (t < tbest) { tbest = t; best.filt_parts2 = parts; }
         }
+        if (dt == TO_F32) {
+            p->tune.filt_parts2 = best.filt_parts2;
+            for (int shape = 1; shape <= 4; ++shape) {
+                p->tune.filt_mfma2 = shape;
+                to_status st = TO_OK;
+                const float t = time_ms(s, [&] {
+                    if (st == TO_OK) st = launch_filter(p, dt, TO_FILTER_ADJ2, Hs, Hs, nullptr, scratch, scratch2, s);
+                }, 3);
+                if (st == TO_OK && t < tbest) { tbest = t; best.filt_mfma2 = shape; }
+            }
+        }
         p->tune.filt_parts2 = best.filt_parts2;
+        p->tune.filt_mfma2 = best.filt_mfma2;
     }
     if (kval) {
         float tbest = 1e30f;
@@ -230,6 +256,8 @@ to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuni
         out->asm_block = p->tune.asm_block;
         out->tuned = p->tune.tuned;
         out->filt_parts2 = p->tune.filt_parts2;
+        out->filt_mfma = p->tune.filt_mfma;
+        out->filt_mfma2 = p->tune.filt_mfma2;
         out->pad = 0;
     }
     return TO_OK;
@@ -261,9 +289,10 @@ to_status to_plan_autotune(to_plan* plan, to_dtype dtype, void* kval, to_tuning*
 to_status to_plan_set_tuning(to_plan* plan, const to_tuning* t) {
     if (!plan || !t) { set_error("to_plan_set_tuning: NULL argument"); return TO_EINVAL; }
     if ((t->filt_v != 4 && t->filt_v != 8) || t->filt_parts < 0 || t->filt_parts > 16 || t->filt_parts2 < 0 ||
-        t->filt_parts2 > 16 ||
+        t->filt_parts2 > 16 || t->filt_mfma < 0 || t->filt_mfma > 4 || t->filt_mfma2 < 0 || t->filt_mfma2 > 4 ||
         (t->asm_block != 128 && t->asm_block != 256 && t->asm_block != 512)) {
-        set_error("to_plan_set_tuning: filt_v must be 4 or 8, filt_parts 0..16, asm_block 128, 256 or 512");
+        set_error("to_plan_set_tuning: filt_v must be 4 or 8, filt_parts 0..16, filt_mfma 0..4, asm_block 128, "
+                  "256 or 512");
         return TO_EINVAL;
     }
     Plan* p = topt::P(plan);
@@ -272,6 +301,8 @@ to_status to_plan_set_tuning(to_plan* plan, const to_tuning* t) {
     p->tune.filt_parts2 = t->filt_parts2;
     p->tune.asm_block = t->asm_block;
     p->tune.tuned = t->tuned;
+    p->tune.filt_mfma = t->filt_mfma;
+    p->tune.filt_mfma2 = t->filt_mfma2;
     return TO_OK;
 }
 
@@ -283,6 +314,8 @@ to_status to_plan_get_tuning(const to_plan* plan, to_tuning* out) {
     out->filt_parts2 = p->tune.filt_parts2;
     out->asm_block = p->tune.asm_block;
     out->tuned = p->tune.tuned;
+    out->filt_mfma = p->tune.filt_mfma;
+    out->filt_mfma2 = p->tune.filt_mfma2;
     out->pad = 0;
     return TO_OK;
 }

@@ -109,6 +109,8 @@ struct Plan {
     int32_t* hlim = nullptr;                             // per (x[,z]) column: max |dy| with h > 0
     double* hp64 = nullptr;  float* hp32 = nullptr;      // 2D: row dy of non-zero taps, zero padded
     int hp_stride = 0;
+    float* hm32 = nullptr;                               // 2D: column dx of h, 16 zeros before, 19+ after
+    int hm_stride = 0;
     double* Hs64 = nullptr;  float* Hs32 = nullptr;      // m
     // scratch (device)
     double* E64 = nullptr;   float* E32 = nullptr;       // m
@@ -130,6 +132,8 @@ struct Plan {
         int filt_parts2 = 0;   // 2D filter: waves per block for the fused double adjoint
         int asm_block = 256;   // assembly: threads per block (128, 256 or 512)
         int tuned = 0;
+        int filt_mfma = 0;     // 2D FP32 filter on the matrix cores: 0 off, else the tile shape (1..4), one field
+        int filt_mfma2 = 0;    // the same for the fused double adjoint
     } tune;
 
     // host copies

@@ -224,6 +224,153 @@ __global__ __launch_bounds__(64 * kFiltMaxParts) void filter2d_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// 2D, FP32, on the matrix cores.  For one tap column dx the cone filter acts
+// along y as a banded Toeplitz matrix: out[y0+i][x] += sum_t h(dx, t-i)
+// in[y0+t][x+dx].  For 16 output rows and 16 output columns that is a
+// (16 x K) band block of weights times a (K x 16) block of the staged
+// window, K = 16 + 2 lim(dx) rounded up to 4, which v_mfma_f32_16x16x4_f32
+// takes four rows of K at a time (about 80% of the products are non-zero
+// taps at large radii).  Operand lanes: A[i][k] in lane i + 16k, B[k][j] in
+// lane j + 16k, D[4q+r][j] in register r of lane j + 16q.  Lane group k takes
+// the contiguous rows k S .. k S + S - 1 of K (S = K / 4), so the weight of
+// lane (i, k) at step s is h(dx, k S + s - lim - i), read from a per-column
+// table with 16 zeros before and 19 or more after the taps (one copy per
+// block in LDS).
+//
+// Block: 8 waves on a tile of TY = 16 MT rows by TX = 16 NB columns; wave w
+// owns the 16-row strip w % MT of the tile (NB accumulators, so each weight
+// register feeds NB products) and the tap columns dx = w / MT (mod 8 / MT);
+// the parts are added in LDS.  Tiles are claimed like the stencil kernel's.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kFmUnroll = 4;           // MFMA steps whose operand reads issue together
+
+template <int MODE, int MT, int NB>
+__global__ __launch_bounds__(512) void filter2d_mfma_kernel(
+    int nely, int nelx, int R, char bc, const float* __restrict__ hm, int hms, const int32_t* __restrict__ hlim,
+    const float* __restrict__ Hs, const float* __restrict__ in, const float* __restrict__ in2,
+    const float* __restrict__ sc, float* __restrict__ out, float* __restrict__ out2, unsigned* ctr,
+    const unsigned* skip, int chunk, int wofs) {
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ int tile_sh;
+    if (skip && *skip) return;          // the whole launch is cancelled (the tile counter is untouched)
+    constexpr int NF = MODE == M_ADJ2 ? 2 : 1;
+    constexpr int NP = 8 / MT;           // tap-column parts
+    constexpr int TY = 16 * MT, TX = 16 * NB;
+    float* tile = reinterpret_cast<float*>(smem_raw);
+    const int LY = TY + 2 * R + 3;       // rows y0-R .. y0+TY+R+2 (the last 3 meet zero weights only)
+    const int ls = LY | 1;               // odd column stride: the 16 columns of a read fall in distinct banks
+    const int LX = TX + 2 * R;
+    float* tile2 = tile + (size_t)ls * LX;
+    const int nty = (nely + TY - 1) / TY, ntiles = nty * ((nelx + TX - 1) / TX);
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int mt = w % MT, part = w / MT;
+    const int i16 = lane & 15, kq = lane >> 4;
+    float* wtab = tile + wofs;           // the weight columns -R..0 (h is even in dx), for the whole launch
+    for (int i = threadIdx.x; i < (R + 1) * hms; i += blockDim.x) wtab[i] = hm[i];
+
+    int t = 0, t_end = 0;
+    for (;; ++t) {
+        if (t >= t_end) {
+            if (threadIdx.x == 0) tile_sh = (int)atomicAdd(&ctr[0], (unsigned)chunk);
+            __syncthreads();
+            t = tile_sh;
+            t_end = min(t + chunk, ntiles);
+        }
+        if (t >= ntiles) break;
+        const int y0 = (t % nty) * TY, x0 = (t / nty) * TX;
+        for (int i = threadIdx.x; i < LY * LX; i += blockDim.x) {
+            const int ly = i % LY, lx = i / LY;
+            int gy = y0 - R + ly, gx = x0 - R + lx;
+            float v = 0.f, v2 = 0.f;
+            bool inside = gy >= 0 && gy < nely && gx >= 0 && gx < nelx;
+            if (bc == 'N' && !inside) {
+                gy = mirror_idx(gy, nely);
+                gx = mirror_idx(gx, nelx);
+                inside = true;
+            }
+            if (inside) {
+                const int64_t e = gy + (int64_t)nely * gx;
+                v = staged_value<float>(MODE, in, sc, Hs, e);
+                if (NF == 2) v2 = staged_value<float>(MODE, in2, sc, Hs, e);
+            }
+            tile[(size_t)lx * ls + ly] = v;
+            if (NF == 2) tile2[(size_t)lx * ls + ly] = v2;
+        }
+        __syncthreads();
+
+        f32x4 acc[NF][NB];
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[f][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int dxi = part; dxi <= 2 * R; dxi += NP) {
+            const int lim = hlim[dxi];
+            if (lim < 0) continue;
+            const int S = (16 + 2 * lim + 3) >> 2;
+            const float* ap = wtab + (size_t)min(dxi, 2 * R - dxi) * hms + (R + 16 - lim) + kq * S - i16;
+            const size_t b0 = (size_t)(dxi + i16) * ls + mt * 16 + R - lim + kq * S;
+            const float* bp = tile + b0;
+            const float* bp2 = tile2 + b0;
+            // MFMA is convergent, so the compiler will not unroll a loop of
+            // unknown trip count: groups of kFmUnroll steps by hand (their
+            // LDS reads issue together), then the rest one by one
+            auto step = [&](int s) {
+                const float a = ap[s];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bp[(size_t)nb * 16 * ls + s], acc[0][nb], 0, 0, 0);
+                    if (NF == 2)
+                        acc[NF - 1][nb] =
+                            __builtin_amdgcn_mfma_f32_16x16x4f32(a, bp2[(size_t)nb * 16 * ls + s], acc[NF - 1][nb], 0, 0, 0);
+                }
+            };
+            int s = 0;
+            for (; s + kFmUnroll <= S; s += kFmUnroll) {
+#pragma unroll
+                for (int u = 0; u < kFmUnroll; ++u) step(s + u);
+            }
+            for (; s < S; ++s) step(s);
+        }
+        __syncthreads();                 // the window is no longer needed
+        float* red = tile;               // [part][field][column][row], TX x TY per slab
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    red[((size_t)(part * NF + f) * TX + nb * 16 + i16) * TY + mt * 16 + 4 * kq + r] = acc[f][nb][r];
+        __syncthreads();
+        for (int o = threadIdx.x; o < TY * TX; o += blockDim.x) {
+            const int row = o % TY, col = o / TY;
+            const int gy = y0 + row, gx = x0 + col;
+            float r0 = 0.f, r1 = 0.f;
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                r0 += red[((size_t)(q * NF) * TX + col) * TY + row];
+                if (NF == 2) r1 += red[((size_t)(q * NF + 1) * TX + col) * TY + row];
+            }
+            if (gy < nely && gx < nelx) {
+                const int64_t e = gy + (int64_t)nely * gx;
+                if (MODE == M_FWD) r0 = r0 / Hs[e];
+                out[e] = r0;
+                if (NF == 2) out2[e] = r1;
+            }
+        }
+        __syncthreads();
+    }
+    // the last block to finish resets the tile counter for the next launch
+    if (threadIdx.x == 0) {
+        const unsigned done = atomicAdd(&ctr[1], 1u);
+        if (done == gridDim.x - 1) {
+            st_dev(&ctr[0], 0u);
+            st_dev(&ctr[1], 0u);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 3D: tile of 64 (y) x 4 (z) x 4 (x) outputs, each thread 4 outputs along x.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void filter3d_kernel(
@@ -343,6 +490,51 @@ static to_status run_filter2d(Plan* p, const T* hp, const T* Hs, const T* in, co
     return run_filter2d_ls<T, MODE, V, 0>(p, hp, Hs, in, in2, sc, out, out2, s);
 }
 
+// LDS bytes of the matrix-core kernel's tile shape (window or partial sums)
+static size_t mfma_lds(int R, int NF, int MT, int NB) {
+    const int TY = 16 * MT, TX = 16 * NB;
+    const size_t win = (size_t)NF * ((TY + 2 * R + 3) | 1) * (TX + 2 * R) * sizeof(float);
+    const size_t red = (size_t)(8 / MT) * NF * TY * TX * sizeof(float);
+    return std::max(win, red);
+}
+
+template <int MODE, int MT, int NB>
+static to_status run_filter2d_mfma_shape(Plan* p, const float* Hs, const float* in, const float* in2,
+                                         const float* sc, float* out, float* out2, hipStream_t s) {
+    constexpr int NF = MODE == M_ADJ2 ? 2 : 1;
+    const int R = p->R;
+    const size_t lds0 = mfma_lds(R, NF, MT, NB);
+    const size_t lds = lds0 + (size_t)(R + 1) * p->hm_stride * sizeof(float);   // + the weight table
+    if (lds > 160 * 1024 - 256) {        // the block also holds a few static words
+        set_error("filter radius too large for the matrix-core tile");
+        return TO_EUNSUPPORTED;
+    }
+    auto k = filter2d_mfma_kernel<MODE, MT, NB>;
+    TO_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, 512, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int ntiles = ((p->nely + 16 * MT - 1) / (16 * MT)) * ((p->nelx + 16 * NB - 1) / (16 * NB));
+    const int blocks = std::max(1, std::min(ntiles, per_cu * p->num_cu));
+    const int chunk = std::max(1, ntiles / (blocks * 4));
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(512), lds, s, p->nely, p->nelx, R, p->bc, p->hm32, p->hm_stride,
+                       p->hlim, Hs, in, in2, sc, out, out2, p->bar + 16, p->filt_skip, chunk, (int)(lds0 / sizeof(float)));
+    TO_HIP(hipGetLastError());
+    return TO_OK;
+}
+
+// shape 1: 32 x 64 tiles, 2: 16 x 64, 3: 32 x 32, 4: 16 x 32
+template <int MODE>
+static to_status run_filter2d_mfma(Plan* p, int shape, const float* Hs, const float* in, const float* in2,
+                                   const float* sc, float* out, float* out2, hipStream_t s) {
+    switch (shape) {
+    case 1: return run_filter2d_mfma_shape<MODE, 2, 4>(p, Hs, in, in2, sc, out, out2, s);
+    case 2: return run_filter2d_mfma_shape<MODE, 1, 4>(p, Hs, in, in2, sc, out, out2, s);
+    case 3: return run_filter2d_mfma_shape<MODE, 2, 2>(p, Hs, in, in2, sc, out, out2, s);
+    default: return run_filter2d_mfma_shape<MODE, 1, 2>(p, Hs, in, in2, sc, out, out2, s);
+    }
+}
+
 template <typename T, int MODE>
 static to_status run_filter(Plan* p, const T* h, const T* hp, const T* Hs, const T* in, const T* in2, const T* sc,
                             T* out, T* out2, hipStream_t s) {
@@ -350,6 +542,13 @@ static to_status run_filter(Plan* p, const T* h, const T* hp, const T* Hs, const
     const int R = p->R;
     const size_t lds_max = 160 * 1024;
     if (p->dim == 2) {
+        if constexpr (std::is_same<T, float>::value && MODE != M_RAW) {
+            const int shape = NF == 2 ? p->tune.filt_mfma2 : p->tune.filt_mfma;
+            if (shape > 0) {
+                const to_status st = run_filter2d_mfma<MODE>(p, shape, Hs, in, in2, sc, out, out2, s);
+                if (st != TO_EUNSUPPORTED) return st;   // else the tile does not fit: the stencil kernel below
+            }
+        }
         if (p->tune.filt_v == 4) return run_filter2d<T, MODE, 4>(p, hp, Hs, in, in2, sc, out, out2, s);
         return run_filter2d<T, MODE, kFiltV>(p, hp, Hs, in, in2, sc, out, out2, s);
     } else {
