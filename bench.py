@@ -641,7 +641,7 @@ def main():
         "roofline": roof,
         "loop_counts": {"cg": iters, "newton": newton, "bisection": bisect},
         "tuning": {k: getattr(t, k) for k in ("filt_v", "filt_parts", "filt_parts2", "filt_mfma", "filt_mfma2",
-                                              "asm_block")},
+                                              "asm_block", "coop_launch")},
     }
     sc = stream_copy()
     line["stream_copy"] = sc

@@ -416,7 +416,12 @@ typedef struct {
     int32_t filt_mfma;           /* 2D FP32 filter on the matrix cores, one field: 0 off, 1..4 the tile
                                     (1: 32 x 64, 2: 16 x 64, 3: 32 x 32, 4: 16 x 32 outputs) */
     int32_t filt_mfma2;          /* the same for the fused double adjoint */
-    int32_t pad;
+    int32_t coop_launch;         /* projection and OC kernels (their blocks meet at grid barriers):
+                                    0 = plain launch with a grid that fits the device at once (default;
+                                    the waits are bounded, a block that never arrives turns into a
+                                    barrier-timeout error), 1 = the runtime's cooperative launch (about
+                                    17 us more per launch; residency guaranteed also when other
+                                    streams run kernels on the device at the same time) */
 } to_tuning;
 to_status to_plan_autotune(to_plan* plan, to_dtype dtype, void* kval, to_tuning* h_out, void* stream);
 to_status to_plan_set_tuning(to_plan* plan, const to_tuning* h_tuning);

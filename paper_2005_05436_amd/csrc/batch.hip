@@ -258,7 +258,7 @@ to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuni
         out->filt_parts2 = p->tune.filt_parts2;
         out->filt_mfma = p->tune.filt_mfma;
         out->filt_mfma2 = p->tune.filt_mfma2;
-        out->pad = 0;
+        out->coop_launch = p->tune.coop_launch;
     }
     return TO_OK;
 }
@@ -290,9 +290,10 @@ to_status to_plan_set_tuning(to_plan* plan, const to_tuning* t) {
     if (!plan || !t) { set_error("to_plan_set_tuning: NULL argument"); return TO_EINVAL; }
     if ((t->filt_v != 4 && t->filt_v != 8) || t->filt_parts < 0 || t->filt_parts > 16 || t->filt_parts2 < 0 ||
         t->filt_parts2 > 16 || t->filt_mfma < 0 || t->filt_mfma > 4 || t->filt_mfma2 < 0 || t->filt_mfma2 > 4 ||
+        (t->coop_launch != 0 && t->coop_launch != 1) ||
         (t->asm_block != 128 && t->asm_block != 256 && t->asm_block != 512)) {
-        set_error("to_plan_set_tuning: filt_v must be 4 or 8, filt_parts 0..16, filt_mfma 0..4, asm_block 128, "
-                  "256 or 512");
+        set_error("to_plan_set_tuning: filt_v must be 4 or 8, filt_parts 0..16, filt_mfma 0..4, coop_launch 0 or 1, "
+                  "asm_block 128, 256 or 512");
         return TO_EINVAL;
     }
     Plan* p = topt::P(plan);
@@ -303,6 +304,7 @@ to_status to_plan_set_tuning(to_plan* plan, const to_tuning* t) {
     p->tune.tuned = t->tuned;
     p->tune.filt_mfma = t->filt_mfma;
     p->tune.filt_mfma2 = t->filt_mfma2;
+    p->tune.coop_launch = t->coop_launch;
     return TO_OK;
 }
 
@@ -316,7 +318,7 @@ to_status to_plan_get_tuning(const to_plan* plan, to_tuning* out) {
     out->tuned = p->tune.tuned;
     out->filt_mfma = p->tune.filt_mfma;
     out->filt_mfma2 = p->tune.filt_mfma2;
-    out->pad = 0;
+    out->coop_launch = p->tune.coop_launch;
     return TO_OK;
 }
 

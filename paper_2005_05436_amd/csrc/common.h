@@ -134,6 +134,7 @@ struct Plan {
         int tuned = 0;
         int filt_mfma = 0;     // 2D FP32 filter on the matrix cores: 0 off, else the tile shape (1..4), one field
         int filt_mfma2 = 0;    // the same for the fused double adjoint
+        int coop_launch = 0;   // projection and OC kernels: 0 plain launch, 1 cooperative launch
     } tune;
 
     // host copies
@@ -486,5 +487,11 @@ to_status launch_oc(Plan* p, to_dtype dt, void* x, const void* dc, const void* d
 to_status launch_oc_filtered(Plan* p, to_dtype dt, int ft, void* x, const void* dc, const void* dv, double volfrac,
                              double move, double beta, const double* d_eta, to_oc_stats* st, hipStream_t s);
 int coop_blocks_for(const void* kernel, int block, size_t smem, int num_cu);
+// Launch of a persistent kernel whose blocks meet at grid barriers; `blocks`
+// must not exceed coop_blocks_for (every block resident at once).  A plain
+// launch by default (a cooperative launch costs about 17 us more here); with
+// tune.coop_launch the runtime's cooperative launch, which also guarantees
+// residency when other streams share the device.
+hipError_t launch_resident(const Plan* p, const void* kernel, int blocks, int block, void** args, hipStream_t s);
 
 }  // namespace topt

@@ -304,7 +304,7 @@ static to_status run_oc(Plan* p, T* x, const T* dc, const T* dv, double volfrac,
     OcArgs<T> a = oc_args<T>(p, x, dc, dv, volfrac, move, st);
     a.method = method;
     void* args[] = {&a};
-    TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(kOcBlock), args, 0, s));
+    TO_HIP(launch_resident(p, (const void*)k, blocks, kOcBlock, args, s));
     return TO_OK;
 }
 

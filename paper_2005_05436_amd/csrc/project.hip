@@ -183,6 +183,11 @@ int coop_blocks_for(const void* kernel, int block, size_t smem, int num_cu) {
     return std::min(kMaxCoopBlocks, per_cu * num_cu);
 }
 
+hipError_t launch_resident(const Plan* p, const void* kernel, int blocks, int block, void** args, hipStream_t s) {
+    if (p->tune.coop_launch) return hipLaunchCooperativeKernel(kernel, dim3(blocks), dim3(block), args, 0, s);
+    return hipLaunchKernel(kernel, dim3(blocks), dim3(block), args, 0, s);
+}
+
 template <typename T>
 static ProjArgs<T> proj_args(Plan* p, int ft, const void* xt, const void* x, void* xphys, void* dprj, double beta,
                              double* d_eta, double target, const void* xold, to_project_stats* st) {
@@ -206,7 +211,7 @@ static to_status run_project(Plan* p, int ft, const void* xt, const void* x, voi
     int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, p->num_cu), (m + kBigBlock - 1) / kBigBlock));
     ProjArgs<T> a = proj_args<T>(p, ft, xt, x, xphys, dprj, beta, d_eta, target, xold, st);
     void* args[] = {&a};
-    TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(kBigBlock), args, 0, s));
+    TO_HIP(launch_resident(p, (const void*)k, blocks, kBigBlock, args, s));
     return TO_OK;
 }
 
