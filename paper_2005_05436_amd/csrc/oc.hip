@@ -118,9 +118,13 @@ __device__ void oc_body(const OcArgs<T>& A, int bid, int nb) {
                 hv[q] = ok ? ld_dev(&reg[b * kPartialWidth + 2 * k]) : 0.0;
                 lv[q] = ok ? ld_dev(&reg[b * kPartialWidth + 2 * k + 1]) : 0.0;
             }
+            // the chains stop at the last existing block: adding the zeros of
+            // missing blocks to a normalised pair leaves it unchanged
+            const int qn = j < nb ? (nb - j + S - 1) / S : 0;
             dd a{0.0, 0.0};
 #pragma unroll
-            for (int q = 0; q < kMaxPer; ++q) a = dd_add(a, dd{hv[q], lv[q]});
+            for (int q = 0; q < kMaxPer; ++q)
+                if (q < qn) a = dd_add(a, dd{hv[q], lv[q]});
             gsum[(k * S + j) * 2] = a.hi;
             gsum[(k * S + j) * 2 + 1] = a.lo;
         }
@@ -128,7 +132,8 @@ __device__ void oc_body(const OcArgs<T>& A, int bid, int nb) {
         if (threadIdx.x < K) {
             const int k = threadIdx.x;
             dd b{gsum[k * S * 2], gsum[k * S * 2 + 1]};
-            for (int j = 1; j < S; ++j) b = dd_add(b, dd{gsum[(k * S + j) * 2], gsum[(k * S + j) * 2 + 1]});
+            const int jn = nb < S ? nb : S;
+            for (int j = 1; j < jn; ++j) b = dd_add(b, dd{gsum[(k * S + j) * 2], gsum[(k * S + j) * 2 + 1]});
             tot[2 * k] = b.hi;
             tot[2 * k + 1] = b.lo;
         }

@@ -68,7 +68,13 @@ __device__ void project_body(const ProjArgs<T>& a, int bid, int nb) {
     const T* __restrict__ xt = a.xt;
     const T* __restrict__ x = a.x;
     const uint8_t* __restrict__ pas = a.pas;
-    double* partial = a.partial;
+    // two partial regions used in turn: a block may write the next sums while
+    // a slower one still reads the previous ones, so each grid sum needs one
+    // barrier (a block cannot write a region again before every block has
+    // passed the barrier that follows its reads)
+    double* const part0 = a.partial;
+    int region = 0;
+    auto partial_now = [&]() { return part0 + (size_t)region * kMaxCoopBlocks * kPartialWidth; };
     const int64_t stride = (int64_t)nb * NB;
     const int64_t i0 = (int64_t)bid * NB + threadIdx.x;
     double eta = *a.d_eta;
@@ -84,11 +90,11 @@ __device__ void project_body(const ProjArgs<T>& a, int bid, int nb) {
         double s = 0.0;
         for (int64_t e = i0; e < m; e += stride) s += pre_value(xt, x, pas, e);
         s = block_sum<NB>(s, sh);
-        if (threadIdx.x == 0) st_dev(&partial[bid * kPartialWidth], s);
+        if (threadIdx.x == 0) st_dev(&partial_now()[bid * kPartialWidth], s);
         alive = gb.sync();
-        grid_reduce<1, NB>(partial, red, sh, nb);
+        grid_reduce<1, NB>(partial_now(), red, sh, nb);
         target = red[0] / (double)m;
-        alive = alive && gb.sync();              // partial buffer is reused below
+        region ^= 1;
     }
 
     int steps = 0;
@@ -107,18 +113,17 @@ __device__ void project_body(const ProjArgs<T>& a, int bid, int nb) {
             sp = block_sum<NB>(sp, sh);
             sd = block_sum<NB>(sd, sh);
             if (threadIdx.x == 0) {
-                st_dev(&partial[bid * kPartialWidth + 0], sp);
-                st_dev(&partial[bid * kPartialWidth + 1], sd);
+                st_dev(&partial_now()[bid * kPartialWidth + 0], sp);
+                st_dev(&partial_now()[bid * kPartialWidth + 1], sd);
             }
             alive = gb.sync() && alive;
-            grid_reduce<2, NB>(partial, red, sh, nb);
+            grid_reduce<2, NB>(partial_now(), red, sh, nb);
+            region ^= 1;
             g = red[0] / (double)m - target;
             if (!(fabs(g) > 1e-6) || steps >= 50 || !alive) break;
             eta = eta - g / (red[1] / (double)m);
             ++steps;
-            alive = gb.sync() && alive;          // everyone has read the partials
         }
-        alive = gb.sync() && alive;
     }
     P.set(beta, eta);
     double sc = 0.0, sv = 0.0;
@@ -139,12 +144,12 @@ __device__ void project_body(const ProjArgs<T>& a, int bid, int nb) {
     sc = block_sum<NB>(sc, sh);
     sv = block_sum<NB>(sv, sh);
     if (threadIdx.x == 0) {
-        st_dev(&partial[bid * kPartialWidth + 0], sc);
-        st_dev(&partial[bid * kPartialWidth + 1], sv);
+        st_dev(&partial_now()[bid * kPartialWidth + 0], sc);
+        st_dev(&partial_now()[bid * kPartialWidth + 1], sv);
     }
     alive = gb.sync() && alive;
     if (bid == 0) {
-        grid_reduce<2, NB>(partial, red, sh, nb);
+        grid_reduce<2, NB>(partial_now(), red, sh, nb);
         if (threadIdx.x == 0) {
             to_project_stats s;
             s.eta = eta;
