@@ -57,6 +57,28 @@ def solve_path(cfg, op, solve):
     return ("assembled" if assembled else "matfree"), ("f32" if mixed else "f64")
 
 
+FP32_PEAK = 157.3e12          # flop/s, MI355X FP32 (matrix cores; also the vector rate with packed instructions)
+
+
+def filter_flops(rmin):
+    """2D cone filter work per element: (useful flops = 2 per non-zero tap,
+    flops the matrix-core kernel issues = 2,048 per v_mfma_f32_16x16x4_f32,
+    sum over the tap columns dx of ceil((16 + 2 lim(dx)) / 4) of them per
+    16 x 16 outputs, lim(dx) = the largest |dy| with a non-zero weight)."""
+    import math
+    R = math.ceil(rmin) - 1
+    taps, steps = 0, 0
+    for dx in range(-R, R + 1):
+        lim = -1
+        for dy in range(-R, R + 1):
+            if rmin - math.sqrt(dx * dx + dy * dy) > 0.0:
+                taps += 1
+                lim = max(lim, abs(dy))
+        if lim >= 0:
+            steps += (16 + 2 * lim + 3) // 4
+    return 2.0 * taps, steps * 2048.0 / 256.0
+
+
 def stage_bytes(cfg, info, dt_bytes, op, solve):
     """Algorithmic bytes per launch of each stage: every array the kernel must
     read or write counted once (no credit for caches, no charge for re-reads)."""
@@ -643,6 +665,18 @@ def main():
         "tuning": {k: getattr(t, k) for k in ("filt_v", "filt_parts", "filt_parts2", "filt_mfma", "filt_mfma2",
                                               "asm_block", "coop_launch")},
     }
+    if I.dim == 2 and cfg.precision == "f32":
+        useful, issued = filter_flops(cfg.rmin)
+        fc = {}
+        for stage, nf, shape in (("filter", 1, t.filt_mfma), ("backfilter", 2, t.filt_mfma2)):
+            sec = avg_ms[stage] * 1e-3
+            d = {"kernel": f"filter2d_mfma_kernel, tile shape {shape}" if shape else "filter2d_kernel (stencil)",
+                 "useful_tflops": round(nf * useful * I.m / sec / 1e12, 1)}
+            if shape:
+                d["issued_tflops"] = round(nf * issued * I.m / sec / 1e12, 1)
+            d["frac_of_fp32_peak"] = round(d.get("issued_tflops", d["useful_tflops"]) * 1e12 / FP32_PEAK, 4)
+            fc[stage] = d
+        line["filter_compute"] = fc
     sc = stream_copy()
     line["stream_copy"] = sc
     roof["frac_of_achievable"] = round(solve_gbps / sc["gbps"], 4)
