@@ -27,13 +27,26 @@ __global__ __launch_bounds__(NT) void assemble_kernel(int64_t nnz, const int32_t
     __shared__ T ke_s[DT];
     for (int i = threadIdx.x; i < DT; i += NT) ke_s[i] = ke[i];
     __syncthreads();
+    // a slot has at most MC contributions on a structured grid (the elements
+    // that share both nodes: 4 in 2D, 8 in 3D); their perm and E loads are all
+    // issued before the sum, which still runs in ascending t
+    constexpr int MC = DT == 36 ? 4 : 8;
     for (int64_t s = blockIdx.x * (int64_t)NT + threadIdx.x; s < nnz; s += (int64_t)gridDim.x * NT) {
         const int32_t a = seg[s], b = seg[s + 1];
+        uint32_t pk[MC];
+        T ev[MC];
+#pragma unroll
+        for (int u = 0; u < MC; ++u) pk[u] = a + u < b ? (uint32_t)perm[a + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < MC; ++u) ev[u] = a + u < b ? E[pk[u] / DT] : T(0);
         T acc = T(0);
-        for (int32_t t = a; t < b; ++t) {
-            const uint32_t pk = (uint32_t)perm[t];
-            const uint32_t e = pk / DT;
-            acc += ke_s[pk - e * DT] * E[e];
+#pragma unroll
+        for (int u = 0; u < MC; ++u)
+            if (a + u < b) acc += ke_s[pk[u] - (pk[u] / DT) * DT] * ev[u];
+        for (int32_t t = a + MC; t < b; ++t) {             // longer segments (not produced by the plan)
+            const uint32_t q = (uint32_t)perm[t];
+            const uint32_t e = q / DT;
+            acc += ke_s[q - e * DT] * E[e];
         }
         kval[s] = acc;
     }
