@@ -16,7 +16,7 @@ template <typename TX, typename T>
 __global__ __launch_bounds__(kBlock) void moduli_kernel(int64_t m, const TX* __restrict__ x, T E0, T Emin,
                                                          T penal, T* __restrict__ E) {
     for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < m; e += (int64_t)gridDim.x * kBlock)
-        E[e] = Emin + pow((T)x[e], penal) * (E0 - Emin);
+        E[e] = Emin + simp_pow((T)x[e], penal) * (E0 - Emin);
 }
 
 template <typename T, int DT, int NT>

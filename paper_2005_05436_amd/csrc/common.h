@@ -200,6 +200,17 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // double-double (error-free) accumulation for the OC volume sums
+// x^p with the small integer exponents of the SIMP continuation (0, 1, 2, 3)
+// by products, any other exponent by pow
+template <typename T>
+__device__ __forceinline__ T simp_pow(T x, T p) {
+    if (p == T(0)) return T(1);
+    if (p == T(1)) return x;
+    if (p == T(2)) return x * x;
+    if (p == T(3)) return x * x * x;
+    return pow(x, p);
+}
+
 struct dd { double hi, lo; };
 __device__ __forceinline__ dd dd_add(dd a, dd b) {
     double s = a.hi + b.hi;

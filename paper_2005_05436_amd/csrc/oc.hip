@@ -37,6 +37,23 @@ __device__ __forceinline__ double oc_clamp(double ocp, double lm, double x, doub
     return v;
 }
 
+// The same with the quotient ocp / lm formed from rlm = 1 / lm (correctly
+// rounded, once per candidate): q = ocp rlm, then the remainder ocp - q lm
+// (exact in one fma) corrects q to the correctly rounded quotient (the final
+// step of Markstein's division; no overflow or underflow in the ranges of
+// ocP and the multiplier), so the value equals oc_clamp's without a
+// division per element.
+__device__ __forceinline__ double oc_clamp_r(double ocp, double lm, double rlm, double x, double move) {
+    const double q = ocp * rlm;
+    const double r = fma(-q, lm, ocp);
+    double v = fma(r, rlm, q);
+    v = fmin(v, x + move);
+    v = fmin(v, 1.0);
+    v = fmax(v, x - move);
+    v = fmax(v, 0.0);
+    return v;
+}
+
 constexpr int kOcBlock = 512;   // 15 double-double accumulators per lane need the register room
 
 template <typename T>
@@ -232,13 +249,17 @@ __device__ void oc_body(const OcArgs<T>& A, int bid, int nb) {
             }
         }
         dd v[kCand];
+        double rmid[kCand];
 #pragma unroll
-        for (int j = 0; j < kCand; ++j) v[j] = dd{0.0, 0.0};
+        for (int j = 0; j < kCand; ++j) {
+            v[j] = dd{0.0, 0.0};
+            rmid[j] = 1.0 / mid[j];
+        }
         for (int64_t e = i0; e < m; e += stride) {
             if (pas[e] != TO_ACTIVE) continue;
             const double q = ocp_buf[e], xe = (double)x[e];
 #pragma unroll
-            for (int j = 0; j < kCand; ++j) v[j] = dd_add1(v[j], oc_clamp(q, mid[j], xe, move));
+            for (int j = 0; j < kCand; ++j) v[j] = dd_add1(v[j], oc_clamp_r(q, mid[j], rmid[j], xe, move));
         }
         double* reg = partial + (size_t)region * kMaxCoopBlocks * kPartialWidth;
         block_dd(v, std::integral_constant<int, kCand>{}, reg);
@@ -259,9 +280,11 @@ __device__ void oc_body(const OcArgs<T>& A, int bid, int nb) {
         }
     }
     // final design from the last midpoint evaluated (unchanged if none)
-    if (n_bs > 0 && alive)
+    if (n_bs > 0 && alive) {
+        const double rl = 1.0 / lmid;
         for (int64_t e = i0; e < m; e += stride)
-            if (pas[e] == TO_ACTIVE) x[e] = (T)oc_clamp(ocp_buf[e], lmid, (double)x[e], move);
+            if (pas[e] == TO_ACTIVE) x[e] = (T)oc_clamp_r(ocp_buf[e], lmid, rl, (double)x[e], move);
+    }
     if (bid == 0 && threadIdx.x == 0) {
         to_oc_stats s;
         s.lmid = lmid; s.l1 = l1; s.l2 = l2;
