@@ -10,12 +10,23 @@
 
 namespace topt {
 
+// Words of the plan's barrier array used by the compliance sum: the top
+// arrival counter and kDotGroups group counters on separate cache lines
+// (clear of the grid barrier's words).
+constexpr int kDotTop = 8, kDotGroup0 = 576, kDotGroupStride = 16, kDotGroups = 16;
+
+// With f given, the same launch also sums c = f^T u: block partials, a
+// two-level arrival (group counters, then the top counter, so no more than
+// gridDim / 16 arrivals meet at one address), and the last block sums the
+// partials in block order.
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void sensitivity_kernel(int nx, int ny, int nz, const T* __restrict__ xphys,
                                                               const uint8_t* __restrict__ pas,
                                                               const double* __restrict__ u,
                                                               const double* __restrict__ ke, double penal,
-                                                              double E0, double Emin, T* __restrict__ dc) {
+                                                              double E0, double Emin, T* __restrict__ dc,
+                                                              const double* __restrict__ f, int64_t n,
+                                                              double* partial, unsigned* bar, double* c_out) {
     constexpr int NC = DIM == 2 ? 4 : 8, D = DIM * NC;
     constexpr int CY[8] = {1, 1, 0, 0, 1, 1, 0, 0};
     constexpr int CX[8] = {0, 1, 1, 0, 0, 1, 1, 0};
@@ -46,25 +57,29 @@ __global__ __launch_bounds__(kBlock) void sensitivity_kernel(int nx, int ny, int
         if (pas[e] == TO_ACTIVE) out = -penal * (E0 - Emin) * pow((double)xphys[e], penal - 1.0) * ce;
         dc[e] = (T)out;
     }
-}
-
-// c = f^T u: block partials, then the last block to finish sums them in order.
-__global__ __launch_bounds__(kBlock) void dot_kernel(int64_t n, const double* __restrict__ a,
-                                                     const double* __restrict__ b, double* partial,
-                                                     unsigned* counter, double* out) {
+    if (f == nullptr) return;
     __shared__ double sh[kWaves];
     __shared__ int last;
-    double s = 0.0;
+    double sd = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-        s += a[i] * b[i];
-    s = block_sum(s, sh);
-    // partials are exchanged with device-coherent accesses, so the arrival
+        sd += f[i] * u[i];
+    sd = block_sum(sd, sh);
+    // partials are exchanged with device-coherent accesses, so an arrival
     // needs only the block's own stores to have completed (no L2 writeback)
     if (threadIdx.x == 0) {
-        st_dev(&partial[blockIdx.x], s);
+        st_dev(&partial[blockIdx.x], sd);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        unsigned done = atomicAdd(counter, 1u);
-        last = done == gridDim.x - 1;
+        const unsigned nb = gridDim.x;
+        const unsigned G = nb < (unsigned)kDotGroups ? nb : (unsigned)kDotGroups;
+        const unsigned g = blockIdx.x % G;
+        const unsigned ng = nb / G + (g < nb % G ? 1u : 0u);
+        unsigned* grp = &bar[kDotGroup0 + kDotGroupStride * g];
+        int is_last = 0;
+        if (atomicAdd(grp, 1u) == ng - 1) {
+            st_dev(grp, 0u);
+            is_last = atomicAdd(&bar[kDotTop], 1u) == G - 1;
+        }
+        last = is_last;
     }
     __syncthreads();
     if (last) {
@@ -72,43 +87,43 @@ __global__ __launch_bounds__(kBlock) void dot_kernel(int64_t n, const double* __
         for (int b2 = threadIdx.x; b2 < (int)gridDim.x; b2 += kBlock) t += ld_acq(&partial[b2]);
         t = block_sum(t, sh);
         if (threadIdx.x == 0) {
-            *out = t;
-            st_dev(counter, 0u);
+            *c_out = t;
+            st_dev(&bar[kDotTop], 0u);
         }
     }
 }
 
 to_status launch_sensitivity(Plan* p, to_dtype dt, const void* xphys, const double* u, const double* f,
                              double penal, void* dc, double* c, hipStream_t s) {
-    const int64_t m = p->info.m;
-    const int blocks = (int)std::min<int64_t>(8192, (m + kBlock - 1) / kBlock);
+    const int64_t m = p->info.m, n = p->info.n;
+    const bool dot = f && c;
+    // with the compliance sum: at most 1024 blocks (64 arrivals per group
+    // counter); partial slots in the second region of the partial buffer
+    const int64_t work = dot ? std::max(m, n) : m;
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(dot ? 1024 : 8192, (work + kBlock - 1) / kBlock));
+    double* part = p->partial + (size_t)kMaxCoopBlocks * kPartialWidth;
+    const double* fd = dot ? f : nullptr;
+    const int nz = p->dim == 2 ? 1 : p->nelz;
     if (p->dim == 2) {
         if (dt == TO_F64)
-            hipLaunchKernelGGL((sensitivity_kernel<2, double>), dim3(blocks), dim3(kBlock), 0, s, p->nelx, p->nely, 1,
-                               (const double*)xphys, p->passive, u, p->kf64, penal, p->E0, p->Emin, (double*)dc);
+            hipLaunchKernelGGL((sensitivity_kernel<2, double>), dim3(blocks), dim3(kBlock), 0, s, p->nelx, p->nely, nz,
+                               (const double*)xphys, p->passive, u, p->kf64, penal, p->E0, p->Emin, (double*)dc, fd,
+                               n, part, p->bar, c);
         else
-            hipLaunchKernelGGL((sensitivity_kernel<2, float>), dim3(blocks), dim3(kBlock), 0, s, p->nelx, p->nely, 1,
-                               (const float*)xphys, p->passive, u, p->kf64, penal, p->E0, p->Emin, (float*)dc);
+            hipLaunchKernelGGL((sensitivity_kernel<2, float>), dim3(blocks), dim3(kBlock), 0, s, p->nelx, p->nely, nz,
+                               (const float*)xphys, p->passive, u, p->kf64, penal, p->E0, p->Emin, (float*)dc, fd,
+                               n, part, p->bar, c);
     } else {
         if (dt == TO_F64)
-            hipLaunchKernelGGL((sensitivity_kernel<3, double>), dim3(blocks), dim3(kBlock), 0, s, p->nelx, p->nely,
-                               p->nelz, (const double*)xphys, p->passive, u, p->kf64, penal, p->E0, p->Emin,
-                               (double*)dc);
+            hipLaunchKernelGGL((sensitivity_kernel<3, double>), dim3(blocks), dim3(kBlock), 0, s, p->nelx, p->nely, nz,
+                               (const double*)xphys, p->passive, u, p->kf64, penal, p->E0, p->Emin, (double*)dc, fd,
+                               n, part, p->bar, c);
         else
-            hipLaunchKernelGGL((sensitivity_kernel<3, float>), dim3(blocks), dim3(kBlock), 0, s, p->nelx, p->nely,
-                               p->nelz, (const float*)xphys, p->passive, u, p->kf64, penal, p->E0, p->Emin,
-                               (float*)dc);
+            hipLaunchKernelGGL((sensitivity_kernel<3, float>), dim3(blocks), dim3(kBlock), 0, s, p->nelx, p->nely, nz,
+                               (const float*)xphys, p->passive, u, p->kf64, penal, p->E0, p->Emin, (float*)dc, fd,
+                               n, part, p->bar, c);
     }
     TO_HIP(hipGetLastError());
-    if (f && c) {
-        const int64_t n = p->info.n;
-        // 256 blocks: the arrivals on the last-block counter serialise at one address
-        const int nb = (int)std::min<int64_t>(256, (n + kBlock - 1) / kBlock);
-        // partial slots: the second region of the partial buffer; counter: bar[8]
-        double* part = p->partial + (size_t)kMaxCoopBlocks * kPartialWidth;
-        hipLaunchKernelGGL(dot_kernel, dim3(nb), dim3(kBlock), 0, s, n, f, u, part, p->bar + 8, c);
-        TO_HIP(hipGetLastError());
-    }
     return TO_OK;
 }
 
