@@ -199,7 +199,6 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return s;
 }
 
-// double-double (error-free) accumulation for the OC volume sums
 // x^p with the small integer exponents of the SIMP continuation (0, 1, 2, 3)
 // by products, any other exponent by pow
 template <typename T>
@@ -211,6 +210,7 @@ __device__ __forceinline__ T simp_pow(T x, T p) {
     return pow(x, p);
 }
 
+// double-double (error-free) accumulation for the OC volume sums
 struct dd { double hi, lo; };
 __device__ __forceinline__ dd dd_add(dd a, dd b) {
     double s = a.hi + b.hi;

@@ -15,22 +15,27 @@
 namespace topt {
 
 struct ProjCoef {
-    double beta, eta, den, tbe, csch;
+    double beta, eta, den, tbe, csch, chb;
     __device__ void set(double b, double e) {
         beta = b; eta = e;
         tbe = tanh(b * e);
         den = tbe + tanh(b * (1.0 - e));
         csch = 1.0 / sinh(b);
+        chb = cosh(b);
     }
-    __device__ double prj(double v) const { return (tbe + tanh(beta * (v - eta))) / den; }
-    __device__ double dprj(double v) const {
-        double t = tanh(beta * (v - eta));
-        return beta * (1.0 - t * t) / den;
+    // t(v) = tanh(beta (v - eta)), shared by the projection and both derivatives
+    __device__ double th(double v) const { return tanh(beta * (v - eta)); }
+    __device__ double prj_t(double t) const { return (tbe + t) / den; }
+    __device__ double dprj_t(double t) const { return beta * (1.0 - t * t) / den; }
+    // d prj / d eta of the codes, -beta csch(beta) sinh(v beta) sinh((1-v) beta)
+    // / cosh^2(beta (v - eta)), with sinh a sinh b = (cosh(a+b) - cosh(a-b)) / 2
+    // and 1 / cosh^2 = 1 - tanh^2: one more hyperbolic function per element
+    // instead of three
+    __device__ double deta_t(double v, double t) const {
+        return -beta * csch * (1.0 - t * t) * 0.5 * (chb - cosh(beta * (2.0 * v - 1.0)));
     }
-    __device__ double deta(double v) const {
-        double c = cosh(beta * (v - eta));
-        return -beta * csch / (c * c) * sinh(v * beta) * sinh((1.0 - v) * beta);
-    }
+    __device__ double prj(double v) const { return prj_t(th(v)); }
+    __device__ double dprj(double v) const { return dprj_t(th(v)); }
 };
 
 template <typename T>
@@ -106,9 +111,10 @@ __device__ void project_body(const ProjArgs<T>& a, int bid, int nb) {
             double sp = 0.0, sd = 0.0;
             if (alive)
                 for (int64_t e = i0; e < m; e += stride) {
-                    double v = pre_value(xt, x, pas, e);
-                    sp += P.prj(v);
-                    sd += P.deta(v);
+                    const double v = pre_value(xt, x, pas, e);
+                    const double t = P.th(v);
+                    sp += P.prj_t(t);
+                    sd += P.deta_t(v, t);
                 }
             sp = block_sum<NB>(sp, sh);
             sd = block_sum<NB>(sd, sh);
@@ -129,9 +135,14 @@ __device__ void project_body(const ProjArgs<T>& a, int bid, int nb) {
     double sc = 0.0, sv = 0.0;
     if (alive)
         for (int64_t e = i0; e < m; e += stride) {
-            double v = pre_value(xt, x, pas, e);
-            double xp = ft >= 2 ? P.prj(v) : v;
-            double dp = ft >= 2 ? P.dprj((double)xt[e]) : 1.0;
+            const double v = pre_value(xt, x, pas, e);
+            const double xte = (double)xt[e];
+            double xp = v, dp = 1.0;
+            if (ft >= 2) {
+                const double t = P.th(v);            // for active elements v is xtilde: one tanh serves both
+                xp = P.prj_t(t);
+                dp = P.dprj_t(v == xte ? t : P.th(xte));
+            }
             T xpT = (T)xp;
             a.xphys[e] = xpT;
             a.dprj[e] = (T)dp;
