@@ -129,8 +129,10 @@ __global__ __launch_bounds__(64 * kFiltMaxParts) void filter2d_kernel(
         if (t >= ntiles) break;
         const int y0 = (t % nty) * 64, x0 = (t / nty) * V;
         // stage the window with the boundary rule
+        // (ly, lx) of element i = ly + LY lx, advanced without a division per element
+        const int step_x = (int)blockDim.x / LY, step_y = (int)blockDim.x % LY;
+        int ly = (int)threadIdx.x % LY, lx = (int)threadIdx.x / LY;
         for (int i = threadIdx.x; i < LY * LX; i += blockDim.x) {
-            const int ly = i % LY, lx = i / LY;
             int gy = y0 - R + ly, gx = x0 - R + lx;
             T v = T(0), v2 = T(0);
             bool inside = gy >= 0 && gy < nely && gx >= 0 && gx < nelx;
@@ -147,6 +149,9 @@ __global__ __launch_bounds__(64 * kFiltMaxParts) void filter2d_kernel(
             }
             tile[(size_t)lx * ls + ly] = v;
             if (NF == 2) tile2[(size_t)lx * ls + ly] = v2;
+            ly += step_y;
+            lx += step_x;
+            if (ly >= LY) { ly -= LY; ++lx; }
         }
         __syncthreads();
 
@@ -279,8 +284,10 @@ __global__ __launch_bounds__(512) void filter2d_mfma_kernel(
         }
         if (t >= ntiles) break;
         const int y0 = (t % nty) * TY, x0 = (t / nty) * TX;
+        // (ly, lx) of element i = ly + LY lx, advanced without a division per element
+        const int step_x = (int)blockDim.x / LY, step_y = (int)blockDim.x % LY;
+        int ly = (int)threadIdx.x % LY, lx = (int)threadIdx.x / LY;
         for (int i = threadIdx.x; i < LY * LX; i += blockDim.x) {
-            const int ly = i % LY, lx = i / LY;
             int gy = y0 - R + ly, gx = x0 - R + lx;
             float v = 0.f, v2 = 0.f;
             bool inside = gy >= 0 && gy < nely && gx >= 0 && gx < nelx;
@@ -296,6 +303,9 @@ __global__ __launch_bounds__(512) void filter2d_mfma_kernel(
             }
             tile[(size_t)lx * ls + ly] = v;
             if (NF == 2) tile2[(size_t)lx * ls + ly] = v2;
+            ly += step_y;
+            lx += step_x;
+            if (ly >= LY) { ly -= LY; ++lx; }
         }
         __syncthreads();
 
