@@ -80,7 +80,9 @@ __device__ __forceinline__ dd wave_dd_sum16(const dd (&v)[16], int lane) {
     return dd_add(u, dd_xor(u, 1));
 }
 
-constexpr int kOcBlock = 512;   // 15 double-double accumulators per lane need the register room
+constexpr int kOcBlock = 512;
+// value-major partials (2 words per value, kMaxCoopBlocks blocks each) fit a partial region
+static_assert(2 * kCand <= kPartialWidth, "OC partials exceed a partial region");   // 15 double-double accumulators per lane need the register room
 
 template <typename T>
 struct OcArgs {
@@ -146,8 +148,10 @@ __device__ void oc_body(const OcArgs<T>& A, int bid, int nb) {
             const int k = threadIdx.x;
             dd b{wsum[k * 2], wsum[k * 2 + 1]};
             for (int i = 1; i < NW; ++i) b = dd_add(b, dd{wsum[(i * K + k) * 2], wsum[(i * K + k) * 2 + 1]});
-            st_dev(&reg[bid * kPartialWidth + 2 * k], b.hi);
-            st_dev(&reg[bid * kPartialWidth + 2 * k + 1], b.lo);
+            // value-major: the words of one value from all blocks are
+            // consecutive, so the grid sum's reads of a value coalesce
+            st_dev(&reg[(size_t)(2 * k) * kMaxCoopBlocks + bid], b.hi);
+            st_dev(&reg[(size_t)(2 * k + 1) * kMaxCoopBlocks + bid], b.lo);
         }
         __syncthreads();
     };
@@ -167,8 +171,8 @@ __device__ void oc_body(const OcArgs<T>& A, int bid, int nb) {
             for (int q = 0; q < kMaxPer; ++q) {
                 const int b = j + q * S;
                 const bool ok = b < nb;
-                hv[q] = ok ? ld_dev(&reg[b * kPartialWidth + 2 * k]) : 0.0;
-                lv[q] = ok ? ld_dev(&reg[b * kPartialWidth + 2 * k + 1]) : 0.0;
+                hv[q] = ok ? ld_dev(&reg[(size_t)(2 * k) * kMaxCoopBlocks + b]) : 0.0;
+                lv[q] = ok ? ld_dev(&reg[(size_t)(2 * k + 1) * kMaxCoopBlocks + b]) : 0.0;
             }
             // the chains stop at the last existing block: adding the zeros of
             // missing blocks to a normalised pair leaves it unchanged
