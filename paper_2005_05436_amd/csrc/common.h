@@ -315,7 +315,8 @@ struct GridBar {
     }
 };
 
-// Sum of K partial columns written by every block: partial[b*kPartialWidth + k].
+// Sum of K partial columns written by every block: partial[k*kMaxCoopBlocks + b]
+// (value-major, so a wave's reads of one value from consecutive blocks coalesce).
 // Every block computes the identical result (same data, same order).
 // All loads are issued before the additions (one memory latency per
 // reduction, not one per block); gridDim.x <= 4 * NB.
@@ -327,7 +328,7 @@ __device__ __forceinline__ void grid_reduce(const double* partial, double* out_s
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int b = threadIdx.x + q * NB;
-            v[k][q] = b < nblocks ? ld_acq(&partial[b * kPartialWidth + k]) : 0.0;
+            v[k][q] = b < nblocks ? ld_acq(&partial[(size_t)k * kMaxCoopBlocks + b]) : 0.0;
         }
 #pragma unroll
     for (int k = 0; k < K; ++k) {

@@ -95,7 +95,7 @@ __device__ void project_body(const ProjArgs<T>& a, int bid, int nb) {
         double s = 0.0;
         for (int64_t e = i0; e < m; e += stride) s += pre_value(xt, x, pas, e);
         s = block_sum<NB>(s, sh);
-        if (threadIdx.x == 0) st_dev(&partial_now()[bid * kPartialWidth], s);
+        if (threadIdx.x == 0) st_dev(&partial_now()[bid], s);
         alive = gb.sync();
         grid_reduce<1, NB>(partial_now(), red, sh, nb);
         target = red[0] / (double)m;
@@ -119,8 +119,8 @@ __device__ void project_body(const ProjArgs<T>& a, int bid, int nb) {
             sp = block_sum<NB>(sp, sh);
             sd = block_sum<NB>(sd, sh);
             if (threadIdx.x == 0) {
-                st_dev(&partial_now()[bid * kPartialWidth + 0], sp);
-                st_dev(&partial_now()[bid * kPartialWidth + 1], sd);
+                st_dev(&partial_now()[bid], sp);
+                st_dev(&partial_now()[kMaxCoopBlocks + bid], sd);
             }
             alive = gb.sync() && alive;
             grid_reduce<2, NB>(partial_now(), red, sh, nb);
@@ -155,8 +155,8 @@ __device__ void project_body(const ProjArgs<T>& a, int bid, int nb) {
     sc = block_sum<NB>(sc, sh);
     sv = block_sum<NB>(sv, sh);
     if (threadIdx.x == 0) {
-        st_dev(&partial_now()[bid * kPartialWidth + 0], sc);
-        st_dev(&partial_now()[bid * kPartialWidth + 1], sv);
+        st_dev(&partial_now()[bid], sc);
+        st_dev(&partial_now()[kMaxCoopBlocks + bid], sv);
     }
     alive = gb.sync() && alive;
     if (bid == 0) {
