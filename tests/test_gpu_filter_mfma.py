@@ -73,13 +73,21 @@ def test_mfma_filter_matches_oracle(dims, rmin, bc, shape):
     assert rel_inf(host(out2), F.adjoint(host(g2d), host(sd))) < TOL32
 
 
-@pytest.mark.parametrize("shape", [1, 3])
-def test_mfma_filter_full_size_sampled(shape):
+def _mirror(k, n):
+    """Half-sample symmetric reflection into [0, n) (period 2 n)."""
+    k = np.mod(k, 2 * n)
+    return np.where(k >= n, 2 * n - 1 - k, k)
+
+
+@pytest.mark.parametrize("shape,bc", [(1, "D"), (3, "D"), (2, "N")])
+def test_mfma_filter_full_size_sampled(shape, bc):
     """1200 x 400 at rmin 40 (the benchmark filter): sampled outputs summed
-    directly from eq. (2), and the whole field against the stencil kernel."""
+    directly from eq. (2) with the boundary rule ('D': the window cut at the
+    mesh edge, 'N': mirrored), and the whole field against the stencil
+    kernel."""
     from paper_2005_05436_amd import _lib as L
     cfg = W.C1[1200]
-    P = plan((cfg.nelx, cfg.nely), cfg.rmin, "D", shape)
+    P = plan((cfg.nelx, cfg.nely), cfg.rmin, bc, shape)
     M = omesh.Mesh(cfg.nelx, cfg.nely)
     xd = torch.as_tensor(W.smooth_design(cfg, 5), dtype=torch.float32).cuda()
     out = torch.zeros(M.m, dtype=torch.float32, device="cuda")
@@ -90,10 +98,15 @@ def test_mfma_filter_full_size_sampled(shape):
     rng = np.random.default_rng(0)
     for e in np.concatenate([[0, M.m - 1, cfg.nely - 1], rng.integers(0, M.m, 200)]):
         iy, ix = e % cfg.nely, e // cfg.nely
-        y0, y1 = max(0, iy - R), min(cfg.nely, iy + R + 1)
-        x0, x1 = max(0, ix - R), min(cfg.nelx, ix + R + 1)
-        w = h[y0 - iy + R:y1 - iy + R, x0 - ix + R:x1 - ix + R]
-        ref = (w * xi[y0:y1, x0:x1]).sum() / w.sum()
+        if bc == "D":
+            y0, y1 = max(0, iy - R), min(cfg.nely, iy + R + 1)
+            x0, x1 = max(0, ix - R), min(cfg.nelx, ix + R + 1)
+            w = h[y0 - iy + R:y1 - iy + R, x0 - ix + R:x1 - ix + R]
+            ref = (w * xi[y0:y1, x0:x1]).sum() / w.sum()
+        else:
+            ys = _mirror(np.arange(iy - R, iy + R + 1), cfg.nely)
+            xs = _mirror(np.arange(ix - R, ix + R + 1), cfg.nelx)
+            ref = (h * xi[np.ix_(ys, xs)]).sum() / h.sum()
         assert abs(got[e] - ref) <= TOL32, (e, got[e], ref)
     L.to_plan_set_tuning(P.handle, 8, 0, 256, 1, filt_mfma=0)
     ref = torch.zeros_like(out)
