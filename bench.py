@@ -559,7 +559,7 @@ def main():
     t = g.tuning
     print(f"[bench] {cfg.name} m={I.m} n={I.n} nnz_lower={I.nnz_lower} precision={cfg.precision} op={args.op} "
           f"tuning: filter columns {t.filt_v}, waves {t.filt_parts} / {t.filt_parts2}, matrix-core tile "
-          f"{t.filt_mfma} / {t.filt_mfma2}, assembly block {t.asm_block}",
+          f"{t.filt_mfma} / {t.filt_mfma2}, assembly block {t.asm_block}, rows {t.asm_rows}",
           file=sys.stderr, flush=True)
 
     sst_hist = torch.zeros((max(args.steps, 1), g.sst.numel()), dtype=torch.uint8, device=g.sst.device)
@@ -663,7 +663,7 @@ def main():
         "roofline": roof,
         "loop_counts": {"cg": iters, "newton": newton, "bisection": bisect},
         "tuning": {k: getattr(t, k) for k in ("filt_v", "filt_parts", "filt_parts2", "filt_mfma", "filt_mfma2",
-                                              "asm_block", "coop_launch")},
+                                              "asm_block", "asm_rows", "coop_launch")},
     }
     if I.dim == 2 and cfg.precision == "f32":
         useful, issued = filter_flops(cfg.rmin)

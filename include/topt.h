@@ -400,7 +400,7 @@ to_status to_nn_train_step(to_nn* nn, to_dtype dtype, const void* xtilde, const 
  * four tiles of the matrix-core variant, which computes the same sums with
  * v_mfma_f32_16x16x4_f32 and falls back to the stencil kernel where its tile
  * does not fit in LDS) and of the assembly
- * kernel (128, 256 or 512 threads per block; only when kval, a device buffer
+ * kernel (either form, 128, 256 or 512 threads per block; only when kval, a device buffer
  * of nnz_lower entries of `dtype`, is given) and keeps the fastest in the
  * plan (the waves per block separately for the one-field and the fused
  * two-field filter).  It synchronises `stream` and overwrites the plan's scratch arrays
@@ -422,6 +422,10 @@ typedef struct {
                                     barrier-timeout error), 1 = the runtime's cooperative launch (about
                                     17 us more per launch; residency guaranteed also when other
                                     streams run kernels on the device at the same time) */
+    int32_t asm_rows;            /* assembly kernel: 0 = segmented sum over the permutation of I_r,
+                                    1 = one thread per slot, the row from row_ptr and the contributing
+                                    elements from the grid (same terms in the same order: identical
+                                    values) */
 } to_tuning;
 to_status to_plan_autotune(to_plan* plan, to_dtype dtype, void* kval, to_tuning* h_out, void* stream);
 to_status to_plan_set_tuning(to_plan* plan, const to_tuning* h_tuning);

@@ -107,7 +107,7 @@ class PaeParams(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("filt_v", C.c_int32), ("filt_parts", C.c_int32), ("asm_block", C.c_int32), ("tuned", C.c_int32),
                 ("filt_parts2", C.c_int32), ("filt_mfma", C.c_int32), ("filt_mfma2", C.c_int32),
-                ("coop_launch", C.c_int32)]
+                ("coop_launch", C.c_int32), ("asm_rows", C.c_int32)]
 
 
 def load():
@@ -338,11 +338,11 @@ def to_plan_autotune(plan, dtype, kval=None, stream=None):
 
 
 def to_plan_set_tuning(plan, filt_v=8, filt_parts=0, asm_block=256, tuned=0, filt_parts2=None, filt_mfma=0,
-                       filt_mfma2=None, coop_launch=0):
+                       filt_mfma2=None, coop_launch=0, asm_rows=0):
     p2 = filt_parts if filt_parts2 is None else filt_parts2
     m2 = filt_mfma if filt_mfma2 is None else filt_mfma2
     check(load().to_plan_set_tuning(plan, C.byref(Tuning(filt_v, filt_parts, asm_block, tuned, p2, filt_mfma, m2,
-                                                         coop_launch))))
+                                                         coop_launch, asm_rows))))
 
 
 def to_plan_get_tuning(plan):

@@ -7,7 +7,9 @@
 // pairs of an element).  The segmented reduction runs one slot per thread:
 // the slots of a wave are consecutive, so their perm ranges form one
 // contiguous stretch of memory and the wave's reads coalesce in L1/L2; Ke
-// (d~ values) is staged in LDS.
+// (d~ values) is staged in LDS.  A second kernel forms the same sums from the
+// grid instead of the permutation, one thread per slot (the plan's tuning
+// chooses).
 #include "common.h"
 
 namespace topt {
@@ -52,6 +54,108 @@ __global__ __launch_bounds__(NT) void assemble_kernel(int64_t nnz, const int32_t
     }
 }
 
+// The same sums without the permutation.  On the structured grid the pairs t
+// that land in slot (r, c) are those of the elements holding both nodes,
+// and t = e * d~ + (local pair) grows with the element index e, so visiting
+// those elements in ascending index and taking Ke at the lower-triangle
+// position of the local pair adds the same terms in the same order as the
+// segmented sum: the two kernels give identical values.  Reads: row_ptr and
+// col_idx (4 B per slot) instead of seg_ptr and perm (about 12 B per slot),
+// and the gathers of E.
+// Node coordinates of a node index (32-bit: the plan keeps n below 2^31).
+template <int DIM>
+__device__ __forceinline__ void node_coords(uint32_t q, uint32_t ny1, uint32_t nz1, int& y, int& x, int& z) {
+    const uint32_t rest = q / ny1;
+    y = (int)(q - rest * ny1);
+    if (DIM == 2) { x = (int)rest; z = 0; }
+    else { const uint32_t xx = rest / nz1; x = (int)xx; z = (int)(rest - xx * nz1); }
+}
+
+// Value of slot (r, c), row r at node coordinates (iy, ix, iz) and DOF
+// component cr.
+template <typename T, int DIM>
+__device__ __forceinline__ T grid_slot_value(int iy, int ix, int iz, int cr, int32_t c, int nelx, int nely, int nelz,
+                                             const T* ke_s, const T* __restrict__ E) {
+    constexpr int D = DIM == 2 ? 8 : 24;
+    const uint32_t qc = (uint32_t)c / DIM;
+    const int cc = (int)((uint32_t)c - qc * DIM);
+    int jy, jx, jz;
+    node_coords<DIM>(qc, nely + 1, nelz + 1, jy, jx, jz);
+    // elements holding both nodes: e.x in [max(ix, jx) - 1, min(ix, jx)] within the
+    // grid, likewise y and z; ascending element index = x outer, then z, then y
+    const int x0 = max(max(ix, jx) - 1, 0), x1 = min(min(ix, jx), nelx - 1);
+    const int y0 = max(max(iy, jy) - 1, 0), y1 = min(min(iy, jy), nely - 1);
+    const int z0 = DIM == 2 ? 0 : max(max(iz, jz) - 1, 0), z1 = DIM == 2 ? 0 : min(min(iz, jz), nelz - 1);
+    T acc = T(0);
+    for (int ex = x0; ex <= x1; ++ex)
+        for (int ez = z0; ez <= z1; ++ez)
+            for (int ey = y0; ey <= y1; ++ey) {
+                // corner of a node at offset (dy, dx, dz) in {0,1}^3 from the element's
+                // origin: corners 0..3 at (1,0), (1,1), (0,1), (0,0) in (y, x), +4 at z + 1
+                const int dyr = iy - ey, dxr = ix - ex, dyc = jy - ey, dxc = jx - ex;
+                int br = dyr ? dxr : 3 - dxr, bc = dyc ? dxc : 3 - dxc;
+                if (DIM == 3) { br += 4 * (iz - ez); bc += 4 * (jz - ez); }
+                const int a = DIM * br + cr, b = DIM * bc + cc;
+                const int j = min(a, b), i = max(a, b);
+                const int k = j * D - ((j * (j - 1)) >> 1) + (i - j);
+                const uint32_t e = (uint32_t)ey + (uint32_t)nely * (uint32_t)(DIM == 2 ? ex : ez + nelz * ex);
+                acc += ke_s[k] * E[e];
+            }
+    return acc;
+}
+
+// One thread per slot: a block takes RB consecutive rows, stages their
+// row_ptr entries and node coordinates in LDS, and every thread finds the row of its slot by a
+// binary search there, so the slots (and the stores of kval) of a wave are
+// consecutive.
+template <typename T, int DIM, int NT>
+__global__ __launch_bounds__(NT) void assemble_grid_kernel(int nelx, int nely, int nelz, int64_t n,
+                                                            const int32_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ ci,
+                                                            const T* __restrict__ ke, const T* __restrict__ E,
+                                                            T* __restrict__ kval) {
+    constexpr int D = DIM == 2 ? 8 : 24, DT = D * (D + 1) / 2;
+    constexpr int RB = NT / (DIM == 2 ? 8 : 32);   // about 9.5 (2D) and 38 (3D) slots per row
+    __shared__ T ke_s[DT];
+    __shared__ int32_t rps[RB + 1];
+    __shared__ int32_t ry[RB], rx[RB], rz[RB];
+    for (int i = threadIdx.x; i < DT; i += NT) ke_s[i] = ke[i];
+    for (int64_t R0 = blockIdx.x * (int64_t)RB; R0 < n; R0 += (int64_t)gridDim.x * RB) {
+        const int nr = (int)std::min<int64_t>(RB, n - R0);
+        __syncthreads();   // ke_s written; the previous group's rows no longer read
+        if (threadIdx.x <= nr) rps[threadIdx.x] = rp[R0 + threadIdx.x];
+        if (threadIdx.x < nr) {
+            const uint32_t r = (uint32_t)(R0 + threadIdx.x);
+            int y, x, z;
+            node_coords<DIM>(r / DIM, nely + 1, nelz + 1, y, x, z);
+            ry[threadIdx.x] = y;
+            rx[threadIdx.x] = x;
+            rz[threadIdx.x] = z;
+        }
+        __syncthreads();
+        const int32_t S0 = rps[0], S1 = rps[nr];
+        for (int32_t s = S0 + (int32_t)threadIdx.x; s < S1; s += NT) {
+            int lo = 0, hi = nr;   // rps[lo] <= s < rps[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (rps[mid] <= s) lo = mid;
+                else hi = mid;
+            }
+            const int cr = (int)((uint32_t)(R0 + lo) % DIM);
+            kval[s] = grid_slot_value<T, DIM>(ry[lo], rx[lo], rz[lo], cr, ci[s], nelx, nely, nelz, ke_s, E);
+        }
+    }
+}
+
+template <typename T, int DIM, int NT>
+static void assemble_grid_nt(Plan* p, const T* ke, const T* E, T* kval, hipStream_t s) {
+    constexpr int RB = NT / (DIM == 2 ? 8 : 32);
+    const int64_t n = p->info.n;
+    const int blocks = (int)std::min<int64_t>(1 << 16, (n + RB - 1) / RB);
+    hipLaunchKernelGGL((assemble_grid_kernel<T, DIM, NT>), dim3(blocks), dim3(NT), 0, s, p->nelx, p->nely,
+                       DIM == 2 ? 1 : p->nelz, n, p->row_ptr, p->col_idx, ke, E, kval);
+}
+
 template <typename T, int DT, int NT>
 static void assemble_nt(Plan* p, int64_t nnz, const T* ke, const T* E, T* kval, hipStream_t s) {
     const int blocks = (int)std::min<int64_t>(1 << 16, (nnz + NT - 1) / NT);
@@ -60,6 +164,15 @@ static void assemble_nt(Plan* p, int64_t nnz, const T* ke, const T* E, T* kval, 
 
 template <typename T, int DT>
 static void assemble_t(Plan* p, int64_t nnz, const T* ke, const T* E, T* kval, hipStream_t s) {
+    constexpr int DIM = DT == 36 ? 2 : 3;
+    if (p->tune.asm_rows) {
+        switch (p->tune.asm_block) {
+        case 128: assemble_grid_nt<T, DIM, 128>(p, ke, E, kval, s); break;
+        case 512: assemble_grid_nt<T, DIM, 512>(p, ke, E, kval, s); break;
+        default: assemble_grid_nt<T, DIM, 256>(p, ke, E, kval, s); break;
+        }
+        return;
+    }
     switch (p->tune.asm_block) {
     case 128: assemble_nt<T, DT, 128>(p, nnz, ke, E, kval, s); break;
     case 512: assemble_nt<T, DT, 512>(p, nnz, ke, E, kval, s); break;

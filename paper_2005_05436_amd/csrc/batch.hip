@@ -237,15 +237,18 @@ to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuni
     }
     if (kval) {
         float tbest = 1e30f;
-        for (int nt : {128, 256, 512}) {
-            p->tune.asm_block = nt;
-            to_status st = TO_OK;
-            const float t = time_ms(s, [&] {
-                if (st == TO_OK) st = launch_assemble(p, dt, Hs, 3.0, kval, s);
-            }, 3);
-            if (st == TO_OK && t < tbest) { tbest = t; best.asm_block = nt; }
-        }
+        for (int rows : {0, 1})
+            for (int nt : {128, 256, 512}) {
+                p->tune.asm_rows = rows;
+                p->tune.asm_block = nt;
+                to_status st = TO_OK;
+                const float t = time_ms(s, [&] {
+                    if (st == TO_OK) st = launch_assemble(p, dt, Hs, 3.0, kval, s);
+                }, 3);
+                if (st == TO_OK && t < tbest) { tbest = t; best.asm_block = nt; best.asm_rows = rows; }
+            }
         p->tune.asm_block = best.asm_block;
+        p->tune.asm_rows = best.asm_rows;
     }
     p->tune.tuned = 1;
     TO_HIP(hipStreamSynchronize(s));
@@ -259,6 +262,7 @@ to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuni
         out->filt_mfma = p->tune.filt_mfma;
         out->filt_mfma2 = p->tune.filt_mfma2;
         out->coop_launch = p->tune.coop_launch;
+        out->asm_rows = p->tune.asm_rows;
     }
     return TO_OK;
 }
@@ -290,10 +294,10 @@ to_status to_plan_set_tuning(to_plan* plan, const to_tuning* t) {
     if (!plan || !t) { set_error("to_plan_set_tuning: NULL argument"); return TO_EINVAL; }
     if ((t->filt_v != 4 && t->filt_v != 8) || t->filt_parts < 0 || t->filt_parts > 16 || t->filt_parts2 < 0 ||
         t->filt_parts2 > 16 || t->filt_mfma < 0 || t->filt_mfma > 4 || t->filt_mfma2 < 0 || t->filt_mfma2 > 4 ||
-        (t->coop_launch != 0 && t->coop_launch != 1) ||
+        (t->coop_launch != 0 && t->coop_launch != 1) || (t->asm_rows != 0 && t->asm_rows != 1) ||
         (t->asm_block != 128 && t->asm_block != 256 && t->asm_block != 512)) {
         set_error("to_plan_set_tuning: filt_v must be 4 or 8, filt_parts 0..16, filt_mfma 0..4, coop_launch 0 or 1, "
-                  "asm_block 128, 256 or 512");
+                  "asm_rows 0 or 1, asm_block 128, 256 or 512");
         return TO_EINVAL;
     }
     Plan* p = topt::P(plan);
@@ -305,6 +309,7 @@ to_status to_plan_set_tuning(to_plan* plan, const to_tuning* t) {
     p->tune.filt_mfma = t->filt_mfma;
     p->tune.filt_mfma2 = t->filt_mfma2;
     p->tune.coop_launch = t->coop_launch;
+    p->tune.asm_rows = t->asm_rows;
     return TO_OK;
 }
 
@@ -319,6 +324,7 @@ to_status to_plan_get_tuning(const to_plan* plan, to_tuning* out) {
     out->filt_mfma = p->tune.filt_mfma;
     out->filt_mfma2 = p->tune.filt_mfma2;
     out->coop_launch = p->tune.coop_launch;
+    out->asm_rows = p->tune.asm_rows;
     return TO_OK;
 }
 

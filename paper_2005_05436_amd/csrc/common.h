@@ -135,6 +135,7 @@ struct Plan {
         int filt_mfma = 0;     // 2D FP32 filter on the matrix cores: 0 off, else the tile shape (1..4), one field
         int filt_mfma2 = 0;    // the same for the fused double adjoint
         int coop_launch = 0;   // projection and OC kernels: 0 plain launch, 1 cooperative launch
+        int asm_rows = 0;      // assembly: 0 segmented sum over perm, 1 slots from the grid (no perm)
     } tune;
 
     // host copies
