@@ -429,7 +429,10 @@ def stage_scaling(args):
         "oc": lambda: L.to_oc_update(h, dt, g.x, g.dcf, g.dv0, cfg.volfrac, cfg.move, g.ost),
     }
     nb = stage_bytes(cfg, I, 4, "assembled", "auto")
-    out = {"workload": cfg.name, "elements": I.m, "rmin": cfg.rmin, "precision": "f32", "stages": {}}
+    t = g.tuning
+    out = {"workload": cfg.name, "elements": I.m, "rmin": cfg.rmin, "precision": "f32", "stages": {},
+           "tuning": {k: getattr(t, k) for k in ("filt_v", "filt_parts", "filt_parts2", "filt_mfma", "filt_mfma2",
+                                                 "asm_block", "asm_rows")}}
     reps = 5
     for name, fn in stages.items():
         fn()
