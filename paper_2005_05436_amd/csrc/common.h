@@ -246,14 +246,23 @@ __device__ __forceinline__ void st_dev(T* p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ double ld_acq(const double* p) { return ld_dev(p); }
+
+// Wait until every global access this wave has issued has completed.  On gfx9
+// the vector memory counter covers stores as well as loads, and a completed
+// device-scope store (st_dev) is visible at the device coherence point.  A
+// workgroup-scope release does not wait for it here (the waves of a block
+// share one CU), so every wave that published data for other blocks waits
+// before the block's arrival is signalled.  The "memory" clobber keeps the
+// compiler from moving accesses across the wait.
+__device__ __forceinline__ void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 __device__ __forceinline__ unsigned ld_acq_u(const unsigned* p) { return ld_dev(p); }
 
 // Grid-wide barrier for cooperatively launched kernels (all blocks resident).
 //
 // Data that crosses blocks is written and read with st_dev / ld_dev, so the
-// barrier only has to order it: every wave waits for its own stores
-// (workgroup-scope release = wait for the store counters) before the block
-// arrives, and the arrival and release are relaxed device-scope atomics.
+// barrier only has to order it: every wave waits for its own stores to
+// complete (wait_stores) before the block arrives, and the arrival and
+// release are relaxed device-scope atomics.
 // Same-address atomics serialise, so arrivals are split over kBarGroups
 // counters on separate cache lines (group = blockIdx % kBarGroups); the last
 // arrival of a group resets it and arrives at the top word, whose low 20 bits
@@ -279,7 +288,7 @@ struct GridBar {
     // persistent loops leave and every wave reaches the kernel's end).
     __device__ __forceinline__ bool sync() {
         __shared__ int ok_sh;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        wait_stores();
         __syncthreads();
         if (threadIdx.x == 0) {
             int ok = 1;
@@ -378,7 +387,9 @@ struct FlagReduce {
             const double s = wave_sum(v[k]);
             if (lane == 0) shA[w][k] = s;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        // data the waves stored for other blocks (the halo band) must be
+        // complete before this block's flagged words can be seen
+        wait_stores();
         __syncthreads();
         if (threadIdx.x == 0) {
 #pragma unroll

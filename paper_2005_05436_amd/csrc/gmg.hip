@@ -69,7 +69,7 @@ __device__ __forceinline__ bool last_block_sums(const double (&v)[K], double* pa
         if (threadIdx.x == 0) st_dev(&partial[blockIdx.x * 8 + k], s);
     }
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        wait_stores();
         const unsigned done = atomicAdd(counter, 1u);
         last = done == gridDim.x - 1;
     }

@@ -448,7 +448,7 @@ __device__ __forceinline__ bool last_block_dd2(dd a, dd b, double* partial, unsi
     if (threadIdx.x == 0) {
         double* q = partial + (size_t)blockIdx.x * 4;
         st_dev(q, a.hi); st_dev(q + 1, a.lo); st_dev(q + 2, b.hi); st_dev(q + 3, b.lo);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        wait_stores();
         last = atomicAdd(counter, 1u) == gridDim.x - 1;
     }
     __syncthreads();

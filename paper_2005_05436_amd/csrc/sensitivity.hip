@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void sensitivity_kernel(int nx, int ny, int
     // needs only the block's own stores to have completed (no L2 writeback)
     if (threadIdx.x == 0) {
         st_dev(&partial[blockIdx.x], sd);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        wait_stores();
         const unsigned nb = gridDim.x;
         const unsigned G = nb < (unsigned)kDotGroups ? nb : (unsigned)kDotGroups;
         const unsigned g = blockIdx.x % G;

@@ -650,7 +650,7 @@ __global__ __launch_bounds__(kBlock) void galerkin_kernel(Geo g, MatFree<DIM, do
         if (threadIdx.x == 0) st_dev(&partial[blockIdx.x * 8 + k], s);
     }
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        wait_stores();
         const unsigned done = atomicAdd(counter, 1u);
         last = done == gridDim.x - 1;
     }

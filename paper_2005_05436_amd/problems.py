@@ -41,7 +41,7 @@ def cantilever3d(nelx, nely, nelz):
     n = 3 * (nelx + 1) * (nely + 1) * (nelz + 1)
     f = np.zeros(n)
     iy = np.arange(nely + 1)
-    f[3 * _node3(nely, nelz, iy, nelx, 0) + 2] = -np.sin(np.pi * iy / nely)
+    f[3 * _node3(nely, nelz, iy, nelx, 0) + 2] = -np.sin(iy / nely * np.pi)
     nodes = np.arange((nely + 1) * (nelz + 1))          # ix = 0 face: the first nodes
     fixed = (3 * nodes[:, None] + np.arange(3)[None, :]).reshape(-1).astype(np.int32)
     return f, fixed

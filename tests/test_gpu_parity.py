@@ -283,14 +283,15 @@ def test_oc_update(m, seed, passive, dt):
     L.to_oc_update(P.handle, dt, xd, dcd, dvd, 0.4, 0.2, st)
     s = read_struct(st, L.OcStats)
     xo, so = ooc.oc_update(xin, dci, dvi, pas == 0, 0.4, 0.2)
+    # FP32 fields: the candidates and volume sums are formed in FP64 from the
+    # promoted inputs on both sides, so the decisions are the oracle's and
+    # the design differs only by its final rounding to FP32
+    assert s.n_bs == so["n_bs"]
+    assert s.lmid == so["lmid"]
     if dt == 1:
-        assert s.n_bs == so["n_bs"]
-        assert s.lmid == so["lmid"]
         np.testing.assert_array_equal(host(xd), xo)       # bit-exact: same decisions, same arithmetic
     else:
-        assert abs(s.n_bs - so["n_bs"]) <= 1
-        assert abs(s.lmid - so["lmid"]) <= 2e-4 * so["lmid"]
-        assert rel_inf(host(xd), xo) < 1e-3
+        np.testing.assert_array_equal(host(xd), xo.astype(np.float32).astype(np.float64))
 
 
 # --- solve ------------------------------------------------------------------

@@ -189,3 +189,73 @@ def test_frame_problem_matches_section_3_5():
     np.testing.assert_array_equal(f2[0::2], -fx)
     with pytest.raises(ValueError):
         mesh.frame(mesh.Mesh(120, 100))
+
+
+# --- loads and supports (block PRE.3 of both codes) ------------------------
+def _node_nrs_2d(nelx, nely):
+    """The 2D code's nodeNrs: 1-based node numbers filled column-major into a
+    (1 + nely) x (1 + nelx) array (block PRE.2)."""
+    return np.arange(1, (nelx + 1) * (nely + 1) + 1).reshape((nely + 1, nelx + 1), order="F")
+
+
+def _node_nrs_3d(nelx, nely, nelz):
+    """The 3D code's nodeNrs: (1 + nely) x (1 + nelz) x (1 + nelx), column-major."""
+    n = (nelx + 1) * (nely + 1) * (nelz + 1)
+    return np.arange(1, n + 1).reshape((nely + 1, nelz + 1, nelx + 1), order="F")
+
+
+@pytest.mark.parametrize("nelx,nely", [(4, 2), (7, 3), (60, 20), (300, 100)])
+def test_mbb_matches_listing_pre3(nelx, nely):
+    """Block PRE.3 of the 2D code, transcribed with its 1-based indices:
+    lcDof = 2 nodeNrs(1, 1); fixed = union(1:2:2(nely+1), 2 nodeNrs(end, end));
+    F(lcDof) = -1.  The oracle's 0-based arrays are these minus one."""
+    N = _node_nrs_2d(nelx, nely)
+    lc = 2 * N[0, 0]
+    fixed1 = np.union1d(np.arange(1, 2 * (nely + 1) + 1, 2), [2 * N[-1, -1]])
+    M = mesh.Mesh(nelx, nely)
+    f, fixed = mesh.mbb(M)
+    F = np.zeros(M.n)
+    F[lc - 1] = -1.0
+    np.testing.assert_array_equal(f, F)
+    np.testing.assert_array_equal(fixed, fixed1 - 1)
+
+
+@pytest.mark.parametrize("nelx,nely,load_ix", [(10, 5, 0), (10, 5, 3), (40, 20, 39)])
+def test_mbb_moved_load_is_top_edge_node(nelx, nely, load_ix):
+    """Ragged-batch reading of the MBB load: the same unit downward load at the
+    top node of column load_ix, i.e. DOF 2 nodeNrs(1, load_ix + 1) in the
+    listing's indexing; supports unchanged."""
+    N = _node_nrs_2d(nelx, nely)
+    M = mesh.Mesh(nelx, nely)
+    f, fixed = mesh.mbb(M, load_ix)
+    assert np.flatnonzero(f).tolist() == [2 * N[0, load_ix] - 1] and f.sum() == -1.0
+    np.testing.assert_array_equal(fixed, mesh.mbb(M)[1])
+
+
+@pytest.mark.parametrize("nelx,nely,nelz", [(4, 2, 3), (6, 3, 3), (12, 6, 6), (96, 48, 48)])
+def test_cantilever3d_matches_listing_pre3(nelx, nely, nelz):
+    """Block PRE.3 of the 3D code, transcribed with its 1-based indices:
+    lcDof = 3 nodeNrs(1:nely+1, 1, nelx+1); fixed = 1 : 3(nely+1)(nelz+1);
+    F(lcDof) = -sin((0:nely)/nely pi)."""
+    N = _node_nrs_3d(nelx, nely, nelz)
+    lc = 3 * N[:, 0, nelx]
+    F = np.zeros(3 * N.size)
+    F[lc - 1] = -np.sin(np.arange(nely + 1) / nely * np.pi)
+    fixed1 = np.arange(1, 3 * (nely + 1) * (nelz + 1) + 1)
+    M = mesh.Mesh(nelx, nely, nelz)
+    f, fixed = mesh.cantilever3d(M)
+    np.testing.assert_array_equal(f, F)
+    np.testing.assert_array_equal(fixed, fixed1 - 1)
+
+
+@pytest.mark.parametrize("nelx,nely,load_iy", [(10, 5, 0), (10, 5, 5), (40, 20, 7)])
+def test_cantilever2d_reading(nelx, nely, load_iy):
+    """The 2D cantilever of the ragged batch (no listing of its own; read in
+    the 2D code's indexing): fixed = 1 : 2(nely+1), the two DOFs of every
+    node of the left edge; a unit downward load on DOF 2 nodeNrs(load_iy+1,
+    nelx+1), a node of the free right edge."""
+    N = _node_nrs_2d(nelx, nely)
+    M = mesh.Mesh(nelx, nely)
+    f, fixed = mesh.cantilever2d(M, load_iy)
+    np.testing.assert_array_equal(fixed, np.arange(1, 2 * (nely + 1) + 1) - 1)
+    assert np.flatnonzero(f).tolist() == [2 * N[load_iy, nelx] - 1] and f.sum() == -1.0

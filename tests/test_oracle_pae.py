@@ -28,10 +28,11 @@ def test_correction_is_the_least_squares_solution():
     act = np.ones(m, bool)
     P = pae.PAE(m, mr=4, q=4, q0=0, alpha=0.9, xi=1.0)
     xs = [rng.uniform(0.3, 0.7, m)]
-    for loop in range(0, 6):
+    uses = []
+    for loop in range(0, 10):
         x_post = np.clip(xs[-1] + 0.05 * rng.standard_normal(m), 0, 1)
-        x_prev_R = (P.R.copy(), P.X.copy())
         out, used = P.step(xs[-1], x_post, act, loop)
+        uses.append(used)
         if used:
             r = x_post - xs[-1]
             R, X = P.R[:, :used], P.X[:, :used]
@@ -40,7 +41,10 @@ def test_correction_is_the_least_squares_solution():
             want = np.clip(xs[-1] + mix * r - (X + mix * R) @ g, 0, 1)
             assert np.allclose(out, want, atol=1e-10)
         xs.append(out)
-    assert used == 4 or True
+    # with q0 = 0 the step counter is it = loop; corrections at it > 1 with
+    # (it - 1) mod q = 0, i.e. it = 5 and 9, each with min(it, m_r) = 4
+    # history columns (written at it = 2, 3, 4, 5 and then 6 .. 9)
+    assert uses == [0, 0, 0, 0, 0, 4, 0, 0, 0, 4]
 
 
 def test_solve_pivot_matches_library_and_handles_singular():
