@@ -125,6 +125,23 @@ const char* to_status_string(to_status s);
 const char* to_last_error(void);
 
 /* ---------------------------------------------------------------------------
+ * to_init_state -- the initial state of a run (Sec. 3, block PRE.6 of both
+ * codes), on the device:
+ *   x_e = (volfrac (m - |P0|) - |P1|) / |A| on active elements, 1 on passive
+ *         solid, 0 on passive void (the mean of x over all m elements is
+ *         volfrac);
+ *   xphys = x;  xphys_old = 1 (every element);
+ *   dv_e = 1 / (m volfrac) on active elements, 0 on passive ones (the codes'
+ *         constant volume derivative, which carries the 1/volfrac scale);
+ *   u = 0.
+ * x: device, m values of `dtype` (required); xphys, xphys_old, dv: device, m
+ * values of `dtype`, each nullable (not written); u: device double n,
+ * nullable.  Returns TO_EINVAL when volfrac is outside (0, 1), the plan has no
+ * active element, or the active value falls outside [0, 1]. */
+to_status to_init_state(const to_plan* plan, to_dtype dtype, double volfrac, void* x, void* xphys,
+                        void* xphys_old, void* dv, double* u, void* stream);
+
+/* ---------------------------------------------------------------------------
  * to_filter -- density filter, eq. (2), and its adjoint, eq. (8) read as the
  * chain rule (the 2D code's back-filter).
  *   mode TO_FILTER_FWD:  out = (h * in) / Hs                         (s unused)
@@ -167,7 +184,8 @@ to_status to_assemble(const to_plan* plan, to_dtype dtype, const void* xphys, do
                       void* kval, void* stream);
 
 /* ---------------------------------------------------------------------------
- * to_solve -- K(free, free) u = f (eq. (5)) by Jacobi-preconditioned CG.
+ * to_solve -- K(free, free) u = f (eq. (5)) by Jacobi-preconditioned CG
+ * (or the multigrid-preconditioned flexible CG, precond TO_PREC_GMG).
  * Fixed DOFs hold u = 0.  The stop test is on the 2-norm over free DOFs:
  * |f - K u| <= rtol |f|, checked on the recursive residual and confirmed on a
  * recomputed one (CG restarts from the recomputed residual otherwise).
@@ -188,16 +206,21 @@ to_status to_assemble(const to_plan* plan, to_dtype dtype, const void* xphys, do
  *                 stop improving (3 replacements without halving the best),
  *                 grow, or half of maxit is spent, the solve restarts from the
  *                 best iterate with FP64 matrix-free PCG (flagged in the stats).
- * kval: device, nnz_lower values of dtype (needed for op TO_OP_ASSEMBLED and
- * for TO_F32); xphys: device m values of dtype (moduli for the matrix-free
+ *   dtype TO_F64, op TO_OP_HYBRID: FP64 PCG on the matrix-free operator with
+ *                 the Jacobi diagonal read from the FP64 assembled kval.
+ * kval: device, nnz_lower values of dtype (needed unless op is
+ * TO_OP_MATFREE); xphys: device m values of dtype (moduli for the matrix-free
  * operator); f, u: device double n; u holds the initial guess on entry. */
-enum { TO_OP_ASSEMBLED = 0, TO_OP_MATFREE = 1 };
+enum { TO_OP_ASSEMBLED = 0, TO_OP_MATFREE = 1, TO_OP_HYBRID = 2 };
 enum { TO_SOLVE_AUTO = 0, TO_SOLVE_F64 = 1, TO_SOLVE_MIXED = 2 };
 typedef struct {
     double rtol;                 /* default 1e-8 */
     double inner_rtol;           /* mixed precision replacement factor, default 0.1 */
     int32_t maxit;               /* total CG iteration cap, default 200000 */
-    int32_t op;                  /* TO_OP_ASSEMBLED | TO_OP_MATFREE */
+    int32_t op;                  /* TO_OP_ASSEMBLED | TO_OP_MATFREE | TO_OP_HYBRID: the FP64
+                                    matrix-free operator with the Jacobi diagonal read from the
+                                    assembled kval (either field dtype; the mixed scheme takes it as
+                                    TO_OP_ASSEMBLED) */
     int32_t precision;           /* TO_SOLVE_AUTO or TO_SOLVE_F64: FP64 PCG (for TO_F32 fields the
                                     operator is the FP64 matrix-free one built from the FP32
                                     design, and with op TO_OP_ASSEMBLED the Jacobi diagonal is
@@ -209,6 +232,17 @@ typedef struct {
     int32_t precond;             /* TO_PREC_JACOBI (default) or TO_PREC_GMG: geometric multigrid
                                     V-cycle (2D and 3D meshes; FP64 vectors and operators for
                                     either field precision; op and precision are then ignored) */
+    int32_t budget;              /* TO_PREC_GMG only.  0: the host reads the device stop flag after
+                                    every 8 outer iterations and stops once convergence is confirmed
+                                    (synchronises the stream; not capturable).  > 0: enqueue-only --
+                                    `budget` outer iterations (rounded up to a multiple of 8) are
+                                    enqueued, each predicated on the device stop flag (after
+                                    convergence they return at once), with no host synchronisation;
+                                    capturable into a caller's graph.  If the budget ends before
+                                    convergence, the stats say converged = 0 (call again from u to
+                                    continue).  Ignored by the Jacobi PCG, which is enqueue-only
+                                    always.  0 .. 1,000,000. */
+    int32_t pad;
 } to_solve_opts;
 enum { TO_PREC_JACOBI = 0, TO_PREC_GMG = 1 };
 typedef struct {
@@ -335,7 +369,7 @@ to_status to_step(const to_plan* plan, to_dtype dtype, to_step_state* h_state,
 double to_continuation(double par, const to_sched* sched, int32_t loop);
 
 /* ---------------------------------------------------------------------------
- * Learned warm start of the state solve (2D meshes).  The paper has no
+ * Learned warm start of the state solve (2D and 3D meshes).  The paper has no
  * network; the prediction only seeds the PCG of eq. (5), whose own true
  * residual still decides convergence.
  *
@@ -350,19 +384,24 @@ to_status to_warm_start(const to_plan* plan, to_dtype dtype, const void* xphys, 
                         const double* f, const double* uhat, const double* uprev, double* u,
                         double* d_coef, void* stream);
 
-/* The network: a U-Net on the node grid (rows ix, columns iy, padded to
- * multiples of 8) from (mean filtered density around the node, f_x, f_y) to
- * the displacement divided by its RMS, with bfloat16 weights and
- * activations on the matrix cores and FP32 accumulation (15 layers of 3x3
- * convolutions, leaky ReLU of slope 1/8, 2x2 average pooling, nearest
- * upsampling, additive skips; 4 levels).  Parameters: an FP32 vector of
- * to_nn_query's n_params entries, per layer W[t][co][ci] (t = 3 (dr + 1) +
- * (dc + 1) for the offset (dr, dc) in (row, column)) then b[co]; layers in the
+/* The network: a U-Net on the node grid, bfloat16 weights and activations on
+ * the matrix cores with FP32 accumulation, 15 layers of 3x3 (3D: 3x3x3)
+ * convolutions, leaky ReLU of slope 1/8, 2x2 (2x2x2) average pooling,
+ * nearest upsampling, additive skips, 4 levels.  2D: image rows ix, columns
+ * iy (padded to multiples of 8), inputs (mean filtered density around the
+ * node, f_x, f_y), outputs the two displacement components divided by the
+ * RMS of u; channels 16, 32, 64, 128 (293,922 parameters).  3D: image planes
+ * ix, rows iz, columns iy, inputs (density, f_x, f_y, f_z), three outputs;
+ * channels 8, 16, 32, 64 (221,267 parameters).  Parameters: an FP32 vector
+ * of to_nn_query's n_params entries, per layer W[t][co][ci] (2D: t = 3 (dr +
+ * 1) + (dc + 1) for the offset (dr, dc) in (row, column); 3D: t = 9 (dp + 1)
+ * + 3 (dr + 1) + (dc + 1) for (plane, row, column)) then b[co]; layers in the
  * order e1a e1b e2a e2b e3a e3b ba bb d3a d3b d2a d2b d1a d1b out.
  *
- * to_nn_query: workspace bytes for a mesh, and the parameter count.
- * to_nn_create: binds a 2D plan (mesh size, free mask) and a caller-owned
- *   device workspace (256-byte aligned); TO_EUNSUPPORTED for 3D plans.
+ * to_nn_query: workspace bytes for a mesh (dim 2 or 3; nelz ignored in 2D),
+ *   and the parameter count.
+ * to_nn_create: binds a plan (mesh size, free mask) and a caller-owned
+ *   device workspace (256-byte aligned) of to_nn_query's size.
  * to_nn_set_params: copies device FP32 parameters in, clears the Adam moments.
  * to_nn_forward: xtilde (m, dtype) and f (n, FP64) -> uhat (n, FP64, zero on
  *   fixed DOFs; may be NULL to keep the output image only).
@@ -372,16 +411,18 @@ to_status to_warm_start(const to_plan* plan, to_dtype dtype, const void* xphys, 
  * to_nn_adam: one Adam step (bias-corrected) with the last gradient.
  * to_nn_train_step: forward, backward and Adam (0.9, 0.999, 1e-8) on one sample.
  * to_nn_get: copies to device memory `out` the parameters or the gradient
- *   (n_params floats), the output image (rows x columns x 16 floats), the
- *   bfloat16 output of layer i < 14 (TO_NN_ACT + i: rows_l x columns_l x
- *   c_out padded to 16, raw 16-bit values; level l images are 2^l times
- *   smaller) or, for the three layers with a skip, the activation before the
- *   skip is added (TO_NN_PRESKIP + i).
- * Weight gradients are summed with FP32 atomics (their last bits vary run to
- * run); everything else is deterministic. */
+ *   (n_params floats), the output image (pixels x 16 floats), the bfloat16
+ *   output of layer i < 14 (TO_NN_ACT + i: pixels_l x c_out padded to 16,
+ *   raw 16-bit values; level l images are 2^l times smaller along each axis)
+ *   or, for the three layers with a skip, the activation before the skip is
+ *   added (TO_NN_PRESKIP + i).
+ * Every sum of the backward pass (weight and bias gradients, the loss and
+ * the target scale) is taken in a fixed order: training is bitwise
+ * repeatable. */
 typedef struct to_nn to_nn;
 enum { TO_NN_PARAMS = 0, TO_NN_GRAD = 1, TO_NN_OUTPUT = 2, TO_NN_ACT = 16, TO_NN_PRESKIP = 32 };
-to_status to_nn_query(int32_t nelx, int32_t nely, size_t* ws_bytes, int64_t* n_params);
+to_status to_nn_query(int32_t dim, int32_t nelx, int32_t nely, int32_t nelz, size_t* ws_bytes,
+                      int64_t* n_params);
 to_status to_nn_create(const to_plan* plan, void* ws, size_t ws_bytes, to_nn** out);
 void to_nn_destroy(to_nn* nn);
 to_status to_nn_set_params(to_nn* nn, const float* params, void* stream);

@@ -96,16 +96,17 @@ def cantilever2d(mesh, load_iy):
     return f, np.array(sorted(fixed), dtype=np.int64)
 
 
-def cantilever3d(mesh):
+def cantilever3d(mesh, load_iz=0):
     """3D cantilever (Sec. 4, Fig. 7a, App. C block PRE.3): the face x = 0 is
     clamped; a line load along y on the bottom edge (iz = 0) of the free end
     x = nelx acts on u_z with magnitude sin((iy/nely)*pi), downward (the
     argument rounded in the code's order: the ratio first, then the
-    product with pi)."""
+    product with pi).  load_iz moves the line up the free end (the random
+    training instances of the learned warm start; 0 is the paper's case)."""
     assert mesh.dim == 3
     f = np.zeros(mesh.n)
     for iy in range(mesh.nely + 1):
-        f[3 * mesh.node(iy, mesh.nelx, 0) + 2] = -np.sin(iy / mesh.nely * np.pi)
+        f[3 * mesh.node(iy, mesh.nelx, load_iz) + 2] = -np.sin(iy / mesh.nely * np.pi)
     fixed = [3 * mesh.node(iy, 0, iz) + c for iy in range(mesh.nely + 1)
              for iz in range(mesh.nelz + 1) for c in range(3)]
     return f, np.array(sorted(fixed), dtype=np.int64)

@@ -100,7 +100,7 @@ def problem_from_config(cfg):
     passive = None
     if cfg.nelz:
         M = _mesh.Mesh(cfg.nelx, cfg.nely, cfg.nelz)
-        f, fixed = _mesh.cantilever3d(M)
+        f, fixed = _mesh.cantilever3d(M, cfg.load)
     else:
         M = _mesh.Mesh(cfg.nelx, cfg.nely)
         if cfg.kind == "mbb":

@@ -32,6 +32,15 @@ two products of the backward pass.  All sums stay in FP64.
 
 Weights: flat FP64 vector, per layer W[t][co][ci] (t = 3 (dr + 1) + (dc + 1),
 offset (dr, dc) along rows and columns) then b[co].
+
+The 3D network (for Hex8 meshes) has the same structure with 3x3x3
+cross-correlations, 2x2x2 average pooling and nearest 2x upsampling along
+all three axes, half the channels (8, 16, 32, 64; about 2.2e5 parameters),
+four input channels (density, f_x, f_y, f_z) and three outputs.  Its image
+is [ix][iz][iy] (planes, rows, columns), each padded to a multiple of 8, so
+pixel (ix, iz, iy) is node iy + (nely + 1) (iz + (nelz + 1) ix); tap
+t = 9 (dp + 1) + 3 (dr + 1) + (dc + 1) for the offset (dp, dr, dc).  Every
+function below takes 2D images [H, W, C] and 3D images [D, H, W, C] alike.
 """
 import numpy as np
 
@@ -57,17 +66,52 @@ LAYERS = [
 ]
 
 
-def layer_offsets():
+LAYERS3 = [
+    ("e1a", 4, 8, 0, True, "prev", None),
+    ("e1b", 8, 8, 0, True, "prev", None),
+    ("e2a", 8, 16, 1, True, "pool", None),
+    ("e2b", 16, 16, 1, True, "prev", None),
+    ("e3a", 16, 32, 2, True, "pool", None),
+    ("e3b", 32, 32, 2, True, "prev", None),
+    ("ba", 32, 64, 3, True, "pool", None),
+    ("bb", 64, 32, 3, True, "prev", None),
+    ("d3a", 32, 32, 2, True, "up", "e3b"),
+    ("d3b", 32, 16, 2, True, "prev", None),
+    ("d2a", 16, 16, 1, True, "up", "e2b"),
+    ("d2b", 16, 8, 1, True, "prev", None),
+    ("d1a", 8, 8, 0, True, "up", "e1b"),
+    ("d1b", 8, 8, 0, True, "prev", None),
+    ("out", 8, 3, 0, False, "prev", None),
+]
+
+
+def layers(dim=2):
+    return LAYERS if dim == 2 else LAYERS3
+
+
+def taps(dim=2):
+    return 9 if dim == 2 else 27
+
+
+def offsets(dim):
+    """Tap offsets in tap order: (dr, dc) in 2D, (dp, dr, dc) in 3D."""
+    if dim == 2:
+        return [(t // 3 - 1, t % 3 - 1) for t in range(9)]
+    return [(t // 9 - 1, (t // 3) % 3 - 1, t % 3 - 1) for t in range(27)]
+
+
+def layer_offsets(dim=2):
     """Offsets of each layer's W and b in the flat parameter vector."""
     offs, o = [], 0
-    for (_, ci, co, *_rest) in LAYERS:
-        offs.append((o, o + 9 * co * ci))
-        o += 9 * co * ci + co
+    T = taps(dim)
+    for (_, ci, co, *_rest) in layers(dim):
+        offs.append((o, o + T * co * ci))
+        o += T * co * ci + co
     return offs, o
 
 
-def n_params():
-    return layer_offsets()[1]
+def n_params(dim=2):
+    return layer_offsets(dim)[1]
 
 
 def bf16_round(a):
@@ -84,16 +128,21 @@ def _rnd(a, on):
     return bf16_round(a) if on else a
 
 
+def _shifted(x, o):
+    """The zero-padded image x shifted by the offset o: out[p] = x[p + o]."""
+    sp = x.shape[:-1]
+    xp = np.zeros(tuple(n + 2 for n in sp) + (x.shape[-1],))
+    xp[tuple(slice(1, -1) for _ in sp)] = x
+    return xp[tuple(slice(1 + d, 1 + d + n) for d, n in zip(o, sp))]
+
+
 def conv3x3(x, W, b=None):
-    """'same' 3x3 cross-correlation with zero padding: x [H, W, Ci],
-    W [9, Co, Ci] -> [H, W, Co]."""
-    H, Wd, _ = x.shape
-    xp = np.zeros((H + 2, Wd + 2, x.shape[2]))
-    xp[1:-1, 1:-1] = x
-    y = np.zeros((H, Wd, W.shape[1]))
-    for t in range(9):
-        dr, dc = t // 3 - 1, t % 3 - 1
-        y += xp[1 + dr:1 + dr + H, 1 + dc:1 + dc + Wd] @ W[t].T
+    """'same' 3x3 (3x3x3) cross-correlation with zero padding: x [H, W, Ci]
+    (or [D, H, W, Ci]), W [T, Co, Ci] -> [H, W, Co] (or [D, H, W, Co])."""
+    dim = x.ndim - 1
+    y = np.zeros(x.shape[:-1] + (W.shape[1],))
+    for t, o in enumerate(offsets(dim)):
+        y += _shifted(x, o) @ W[t].T
     if b is not None:
         y += b
     return y
@@ -101,30 +150,53 @@ def conv3x3(x, W, b=None):
 
 def conv3x3_wgrad(x, dz):
     """d loss / d W for y = conv3x3(x, W): sum over pixels of x(p + o_t) dz(p)."""
-    H, Wd, _ = x.shape
-    xp = np.zeros((H + 2, Wd + 2, x.shape[2]))
-    xp[1:-1, 1:-1] = x
-    g = np.zeros((9, dz.shape[2], x.shape[2]))
-    for t in range(9):
-        dr, dc = t // 3 - 1, t % 3 - 1
-        xs = xp[1 + dr:1 + dr + H, 1 + dc:1 + dc + Wd].reshape(-1, x.shape[2])
-        g[t] = dz.reshape(-1, dz.shape[2]).T @ xs
+    dim = x.ndim - 1
+    offs = offsets(dim)
+    g = np.zeros((len(offs), dz.shape[-1], x.shape[-1]))
+    for t, o in enumerate(offs):
+        xs = _shifted(x, o).reshape(-1, x.shape[-1])
+        g[t] = dz.reshape(-1, dz.shape[-1]).T @ xs
     return g
 
 
 def conv3x3_dgrad(dz, W):
     """d loss / d x for y = conv3x3(x, W): the correlation of dz with the
     flipped, transposed kernel."""
-    Wt = np.stack([W[8 - t].T for t in range(9)])
+    T = W.shape[0]
+    Wt = np.stack([W[T - 1 - t].T for t in range(T)])
     return conv3x3(dz, Wt)
 
 
+def _corners(x):
+    """The 2^dim sub-images x[a::2, b::2, ...] of the even/odd corners."""
+    dim = x.ndim - 1
+    out = []
+    for k in range(2 ** dim):
+        out.append(x[tuple(slice((k >> (dim - 1 - a)) & 1, None, 2) for a in range(dim))])
+    return out
+
+
 def pool2(x):
-    return 0.25 * (x[0::2, 0::2] + x[0::2, 1::2] + x[1::2, 0::2] + x[1::2, 1::2])
+    c = _corners(x)
+    s = c[0]
+    for t in c[1:]:
+        s = s + t
+    return s / len(c)
 
 
 def up2(x):
-    return np.repeat(np.repeat(x, 2, axis=0), 2, axis=1)
+    for a in range(x.ndim - 1):
+        x = np.repeat(x, 2, axis=a)
+    return x
+
+
+def sum2(x):
+    """Sum over each 2x2 (2x2x2) block: the adjoint of up2."""
+    c = _corners(x)
+    s = c[0]
+    for t in c[1:]:
+        s = s + t
+    return s
 
 
 def leaky(z):
@@ -136,21 +208,24 @@ def leaky_grad(y):
     return np.where(y > 0, 1.0, SLOPE)
 
 
-def unpack(params):
-    offs, _ = layer_offsets()
+def unpack(params, dim=2):
+    offs, _ = layer_offsets(dim)
+    T = taps(dim)
     out = []
-    for (name, ci, co, *_r), (ow, ob) in zip(LAYERS, offs):
-        out.append((params[ow:ob].reshape(9, co, ci), params[ob:ob + co]))
+    for (name, ci, co, *_r), (ow, ob) in zip(layers(dim), offs):
+        out.append((params[ow:ob].reshape(T, co, ci), params[ob:ob + co]))
     return out
 
 
 def forward(params, img, bf16=False):
-    """Returns the output image [H, W, 2] and the cache for backward()."""
-    wb = unpack(params)
-    cache = {"in": _rnd(img, bf16)}
+    """Returns the output image ([H, W, 2] in 2D, [D, H, W, 3] in 3D) and the
+    cache for backward()."""
+    dim = img.ndim - 1
+    wb = unpack(params, dim)
+    cache = {"in": _rnd(img, bf16), "dim": dim}
     x = cache["in"]
     act = {}
-    for (name, ci, co, lev, use_act, src, skip), (W, b) in zip(LAYERS, wb):
+    for (name, ci, co, lev, use_act, src, skip), (W, b) in zip(layers(dim), wb):
         W = _rnd(W, bf16)
         if src == "pool":
             x = _rnd(pool2(x), bf16)
@@ -173,16 +248,17 @@ def forward(params, img, bf16=False):
 
 def backward(params, cache, dout, bf16=False):
     """Gradient of a loss with d loss / d output = dout, for every weight."""
-    wb = unpack(params)
-    offs, P = layer_offsets()
+    dim = cache.get("dim", 2)
+    LY = layers(dim)
+    wb = unpack(params, dim)
+    offs, P = layer_offsets(dim)
     grad = np.zeros(P)
     G = {"out": dout}
-    by_name = {L[0]: i for i, L in enumerate(LAYERS)}
     prev = {}
-    for i, L in enumerate(LAYERS):
-        prev[L[0]] = LAYERS[i - 1][0] if i > 0 else None
-    for i in range(len(LAYERS) - 1, -1, -1):
-        name, ci, co, lev, use_act, src, skip = LAYERS[i]
+    for i, L in enumerate(LY):
+        prev[L[0]] = LY[i - 1][0] if i > 0 else None
+    for i in range(len(LY) - 1, -1, -1):
+        name, ci, co, lev, use_act, src, skip = LY[i]
         W, _ = wb[i]
         W = _rnd(W, bf16)
         g = G.pop(name)
@@ -193,25 +269,26 @@ def backward(params, cache, dout, bf16=False):
         ow, ob = offs[i]
         x = cache[name + ".x"]
         grad[ow:ob] = conv3x3_wgrad(x, dz).ravel()
-        grad[ob:ob + co] = dz.sum(axis=(0, 1))
+        grad[ob:ob + co] = dz.sum(axis=tuple(range(dim)))
         if i == 0:
             break
         gx = conv3x3_dgrad(dz, W)
         p = prev[name]
         if src == "pool":
-            gx = up2(gx) * 0.25
+            gx = up2(gx) / 2 ** dim
         elif src == "up":
-            gx = gx[0::2, 0::2] + gx[0::2, 1::2] + gx[1::2, 0::2] + gx[1::2, 1::2]
+            gx = sum2(gx)
         G[p] = G.get(p, 0.0) + gx
     return grad
 
 
 def loss_and_grad(params, img, target, mask, bf16=False):
-    """Mean squared error over the masked pixels (both channels) and its
-    gradient."""
+    """Mean squared error over the masked pixels (every output channel) and
+    its gradient."""
     out, cache = forward(params, img, bf16)
-    cnt = 2.0 * mask.sum()
-    diff = (out[..., :2] - target) * mask[..., None]
+    nc = target.shape[-1]
+    cnt = nc * mask.sum()
+    diff = (out[..., :nc] - target) * mask[..., None]
     loss = float((diff * diff).sum() / cnt)
     dout = 2.0 * diff / cnt
     return loss, backward(params, cache, dout, bf16)
@@ -296,3 +373,52 @@ def galerkin_start(K, f, uh, up):
     if not cands:
         return np.zeros_like(f)
     return min(cands, key=lambda c: c[0])[1]
+
+
+# --- the 3D image ([ix][iz][iy], node iy + (nely + 1) (iz + (nelz + 1) ix)) --
+
+def image_shape3(nelx, nely, nelz):
+    p8 = lambda n: (n + 1 + 7) // 8 * 8
+    return (p8(nelx), p8(nelz), p8(nely))
+
+
+def features3(nelx, nely, nelz, xtilde, f):
+    """Input image of the 3D network: mean filtered density of the (1 to 8)
+    elements around each node, and the nodal load (three components)."""
+    D, H, Wd = image_shape3(nelx, nely, nelz)
+    img = np.zeros((D, H, Wd, 4))
+    # element e = iy + nely (iz + nelz ix)  ->  [ix, iz, iy]
+    xe = np.asarray(xtilde, dtype=np.float64).reshape(nelx, nelz, nely)
+    s = np.zeros((nelx + 1, nelz + 1, nely + 1))
+    c = np.zeros((nelx + 1, nelz + 1, nely + 1))
+    for a in (0, 1):
+        for b in (0, 1):
+            for d in (0, 1):
+                s[a:a + nelx, b:b + nelz, d:d + nely] += xe
+                c[a:a + nelx, b:b + nelz, d:d + nely] += 1.0
+    img[:nelx + 1, :nelz + 1, :nely + 1, 0] = s / c
+    fn = np.asarray(f, dtype=np.float64).reshape(nelx + 1, nelz + 1, nely + 1, 3)
+    img[:nelx + 1, :nelz + 1, :nely + 1, 1:4] = fn
+    return img
+
+
+def node_mask3(nelx, nely, nelz):
+    mk = np.zeros(image_shape3(nelx, nely, nelz))
+    mk[:nelx + 1, :nelz + 1, :nely + 1] = 1.0
+    return mk
+
+
+def target3(nelx, nely, nelz, u):
+    """u normalised by its RMS over the real DOFs, as a 3D image."""
+    u = np.asarray(u, dtype=np.float64)
+    rms = np.sqrt(np.mean(u * u))
+    t = np.zeros(image_shape3(nelx, nely, nelz) + (3,))
+    t[:nelx + 1, :nelz + 1, :nely + 1] = (u / rms if rms > 0 else u).reshape(nelx + 1, nelz + 1, nely + 1, 3)
+    return t
+
+
+def prediction3(nelx, nely, nelz, out, free):
+    """3D network output as a DOF vector (zero on fixed DOFs)."""
+    u = out[:nelx + 1, :nelz + 1, :nely + 1, :3].reshape(-1).copy()
+    u[~np.asarray(free, bool)] = 0.0
+    return u

@@ -20,13 +20,13 @@ TO_ACTIVE, TO_SOLID, TO_VOID = 0, 1, 2
 (TO_X_PAIRS, TO_X_PERM, TO_X_SEGPTR, TO_X_ROWPTR, TO_X_COLIDX, TO_X_HS, TO_X_KE, TO_X_FREE,
  TO_X_KERNEL) = range(9)
 TO_FILTER_FWD, TO_FILTER_ADJ, TO_FILTER_ADJ2 = 0, 1, 2
-TO_OP_ASSEMBLED, TO_OP_MATFREE = 0, 1
+TO_OP_ASSEMBLED, TO_OP_MATFREE, TO_OP_HYBRID = 0, 1, 2
 TO_SOLVE_AUTO, TO_SOLVE_F64, TO_SOLVE_MIXED = 0, 1, 2
 TO_OC_BISECT, TO_OC_PD, TO_OC_FILTERED = 0, 1, 2
 
 EXPORTED = ["to_plan_query", "to_plan_create", "to_plan_destroy", "to_plan_get_info", "to_plan_export",
             "to_plan_build_host",
-            "to_status_string", "to_last_error", "to_filter", "to_project", "to_assemble", "to_solve",
+            "to_status_string", "to_last_error", "to_init_state", "to_filter", "to_project", "to_assemble", "to_solve",
             "to_sensitivity", "to_oc_update", "to_oc_update_pd", "to_oc_update_filtered", "to_step", "to_continuation", "to_warm_start",
             "to_nn_query", "to_nn_create", "to_nn_destroy", "to_nn_set_params", "to_nn_get", "to_nn_forward",
             "to_nn_backward", "to_nn_adam", "to_nn_train_step", "to_plan_autotune", "to_plan_set_tuning",
@@ -65,7 +65,7 @@ TO_PREC_JACOBI, TO_PREC_GMG = 0, 1
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("inner_rtol", C.c_double), ("maxit", C.c_int32),
                 ("op", C.c_int32), ("precision", C.c_int32), ("zero_x0", C.c_int32),
-                ("grid_blocks", C.c_int32), ("precond", C.c_int32)]
+                ("grid_blocks", C.c_int32), ("precond", C.c_int32), ("budget", C.c_int32), ("pad", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -129,6 +129,7 @@ def load():
         "to_plan_build_host": (S, [C.POINTER(MeshDesc), C.c_int, P, C.c_size_t]),
         "to_status_string": (C.c_char_p, [S]),
         "to_last_error": (C.c_char_p, []),
+        "to_init_state": (S, [P, S, C.c_double, P, P, P, P, P, P]),
         "to_filter": (S, [P, S, C.c_int, P, P, P, P, P, P]),
         "to_project": (S, [P, S, C.c_int, P, P, P, P, C.c_double, P, C.c_double, P, P, P]),
         "to_assemble": (S, [P, S, P, C.c_double, P, P]),
@@ -150,7 +151,7 @@ def load():
         "to_batch_destroy": (None, [P]),
         "to_pae_query": (S, [P, C.POINTER(PaeParams), C.POINTER(C.c_size_t)]),
         "to_pae_step": (S, [P, S, P, P, C.c_int32, C.POINTER(PaeParams), P, P, P]),
-        "to_nn_query": (S, [C.c_int32, C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_int64)]),
+        "to_nn_query": (S, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_int64)]),
         "to_nn_create": (S, [P, P, C.c_size_t, C.POINTER(P)]),
         "to_nn_destroy": (None, [P]),
         "to_nn_set_params": (S, [P, P, P]),
@@ -244,6 +245,11 @@ def to_solve(plan, dtype, kval, xphys, penal, f, u, opts, d_stats, stream=None):
                           C.byref(opts) if opts is not None else None, ptr(d_stats), stream_ptr(stream)))
 
 
+def to_init_state(plan, dtype, volfrac, x, xphys, xphys_old, dv, u, stream=None):
+    check(load().to_init_state(plan, dtype, volfrac, ptr(x), ptr(xphys), ptr(xphys_old), ptr(dv), ptr(u),
+                               stream_ptr(stream)))
+
+
 def to_sensitivity(plan, dtype, xphys, u, f, penal, dc, d_compliance, stream=None):
     check(load().to_sensitivity(plan, dtype, ptr(xphys), ptr(u), ptr(f), penal, ptr(dc), ptr(d_compliance),
                                 stream_ptr(stream)))
@@ -291,9 +297,10 @@ def to_pae_step(plan, dtype, x, x_pre, loop, params, ws, d_gamma=None, stream=No
 TO_NN_PARAMS, TO_NN_GRAD, TO_NN_OUTPUT, TO_NN_ACT, TO_NN_PRESKIP = 0, 1, 2, 16, 32
 
 
-def to_nn_query(nelx, nely):
-    ws, npar = C.c_size_t(0), C.c_int64(0)
-    check(load().to_nn_query(nelx, nely, C.byref(ws), C.byref(npar)))
+def to_nn_query(dim, nelx, nely, nelz=1):
+    ws = C.c_size_t(0)
+    npar = C.c_int64(0)
+    check(load().to_nn_query(dim, nelx, nely, nelz, C.byref(ws), C.byref(npar)))
     return ws.value, npar.value
 
 

@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libtopt.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.cpp", "plan.cpp", "filter.hip", "project.hip", "assemble.hip", "solve.hip",
-           "sensitivity.hip", "oc.hip", "nn.hip", "batch.hip", "gmg.hip"]
+           "sensitivity.hip", "oc.hip", "nn.hip", "batch.hip", "gmg.hip", "state.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -127,6 +127,7 @@ static to_solve_opts default_opts() {
     to_solve_opts o;
     o.rtol = 1e-8; o.inner_rtol = 0.1; o.maxit = 200000; o.op = TO_OP_ASSEMBLED;
     o.precision = TO_SOLVE_AUTO; o.zero_x0 = 0; o.grid_blocks = 0; o.precond = TO_PREC_JACOBI;
+    o.budget = 0; o.pad = 0;
     return o;
 }
 
@@ -137,12 +138,12 @@ to_status to_solve(const to_plan* plan, to_dtype dtype, const void* kval, const 
     NEED(f, "f"); NEED(u, "u"); NEED(d_stats, "d_stats");
     to_solve_opts o = h_opts ? *h_opts : default_opts();
     if (!(o.rtol > 0) || !(o.inner_rtol > 0 && o.inner_rtol < 1) || o.maxit < 0 || o.grid_blocks < 0 ||
-        (o.op != TO_OP_ASSEMBLED && o.op != TO_OP_MATFREE) ||
+        (o.op != TO_OP_ASSEMBLED && o.op != TO_OP_MATFREE && o.op != TO_OP_HYBRID) ||
         (o.precision != TO_SOLVE_AUTO && o.precision != TO_SOLVE_F64 && o.precision != TO_SOLVE_MIXED) ||
-        (o.precision == TO_SOLVE_MIXED && dtype == TO_F64) || (o.precond != TO_PREC_JACOBI && o.precond != TO_PREC_GMG)) {
+        (o.precision == TO_SOLVE_MIXED && dtype == TO_F64) || (o.precond != TO_PREC_JACOBI && o.precond != TO_PREC_GMG) || o.budget < 0 || o.budget > 1000000) {
         set_error("bad solve options"); return TO_EINVAL;
     }
-    if ((o.op == TO_OP_MATFREE || dtype == TO_F32) && !xphys) { set_error("xphys is NULL"); return TO_EINVAL; }
+    if ((o.op != TO_OP_ASSEMBLED || dtype == TO_F32) && !xphys) { set_error("xphys is NULL"); return TO_EINVAL; }
     if ((const void*)f == (const void*)u) { set_error("f and u may not alias"); return TO_EINVAL; }
     TO_GUARD(launch_solve(P(plan), dtype, kval, xphys, penal, f, u, o, d_stats, S(stream)));
 }
@@ -156,6 +157,22 @@ to_status to_warm_start(const to_plan* plan, to_dtype dtype, const void* xphys, 
         set_error("u may alias uprev only"); return TO_EINVAL;
     }
     TO_GUARD(launch_warm_start(P(plan), dtype, xphys, penal, f, uhat, uprev, u, d_coef, S(stream)));
+}
+
+to_status to_init_state(const to_plan* plan, to_dtype dtype, double volfrac, void* x, void* xphys, void* xphys_old,
+                        void* dv, double* u, void* stream) {
+    NEED(plan, "plan");
+    if (check_dtype(dtype)) return TO_EINVAL;
+    NEED(x, "x");
+    if (!(volfrac > 0 && volfrac < 1)) { set_error("volfrac must be in (0, 1)"); return TO_EINVAL; }
+    const to_plan_info& I = P(plan)->info;
+    if (I.n_active == 0) { set_error("the plan has no active element"); return TO_EINVAL; }
+    const double xa = (volfrac * (double)(I.m - I.n_void) - (double)I.n_solid) / (double)I.n_active;
+    if (!(xa >= 0.0 && xa <= 1.0)) {
+        set_error("volfrac cannot be met with designs in [0, 1] on the active set (passive elements fix too much)");
+        return TO_EINVAL;
+    }
+    TO_GUARD(launch_init_state(P(plan), dtype, volfrac, x, xphys, xphys_old, dv, u, S(stream)));
 }
 
 to_status to_sensitivity(const to_plan* plan, to_dtype dtype, const void* xphys, const double* u, const double* f,
@@ -238,10 +255,11 @@ to_status to_step(const to_plan* plan, to_dtype dtype, to_step_state* st, const 
     NEED(st->pstats, "pstats"); NEED(st->sstats, "sstats"); NEED(st->ostats, "ostats");
     if (prm->ft < 1 || prm->ft > 3) { set_error("ft must be 1, 2 or 3"); return TO_EINVAL; }
     if (prm->oc < TO_OC_BISECT || prm->oc > TO_OC_FILTERED) { set_error("oc must be TO_OC_BISECT, TO_OC_PD or TO_OC_FILTERED"); return TO_EINVAL; }
-    // op TO_OP_ASSEMBLED: K^(s) is assembled every iteration; it is the CG
-    // operator (FP64 fields, or the mixed scheme) or, for the FP64 solve of
-    // FP32 fields, the source of the FP32 Jacobi preconditioner
-    const bool assembled = prm->solve.op == TO_OP_ASSEMBLED;
+    // op TO_OP_ASSEMBLED or TO_OP_HYBRID: K^(s) is assembled every
+    // iteration; it is the CG operator (TO_OP_ASSEMBLED with FP64 fields, or
+    // the mixed scheme) or the source of the Jacobi preconditioner of the
+    // matrix-free FP64 solve (TO_OP_HYBRID; TO_OP_ASSEMBLED with FP32 fields)
+    const bool assembled = prm->solve.op != TO_OP_MATFREE;
     if (assembled) NEED(st->kval, "kval");
     try {
         Plan* p = P(plan);

@@ -84,7 +84,14 @@ struct Batch {
     hipGraphExec_t exec = nullptr;
     std::vector<double> key;
     int graph_captures = 0, graph_launches = 0;
+    // multigrid solves: one enqueue-only solve per design, spread over side
+    // streams that fork from and join the batch's stream (parallel branches
+    // when captured)
+    bool gmg = false;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev;     // ev[0] fork, ev[1 + j] join of side[j]
 };
+constexpr int kBatchSideStreams = 4;
 
 struct BatchLayout {
     size_t proj, oc, solve, dyn, maps, total;
@@ -133,13 +140,29 @@ static to_status batch_enqueue(Batch* b, const to_step_state* st, const to_step_
         hipLaunchKernelGGL(batch_dyn_kernel, dim3(1), dim3(4 * kDynChunk), 0, s, b->dyn, d);
     }
     if ((r = launch_project_batch(dt, b->proj_tab, b->mp_proj, s))) return r;
-    for (int i = 0; i < b->n; ++i) {
-        if (b->solve.op == TO_OP_ASSEMBLED &&
-            (r = launch_assemble(b->plans[i], dt, st[i].xphys, st[i].penal, st[i].kval, s)))
-            return r;
-        if ((r = solve_prepare(b->plans[i], dt, st[i].xphys, st[i].penal, b->solve, s))) return r;
+    if (b->gmg) {
+        // per design: FP64 moduli, hierarchy set-up and a fixed budget of
+        // predicated outer iterations (no host synchronisation)
+        const int k = (int)b->side.size();
+        TO_HIP(hipEventRecord(b->ev[0], s));
+        for (int j = 0; j < k; ++j) TO_HIP(hipStreamWaitEvent(b->side[j], b->ev[0], 0));
+        for (int i = 0; i < b->n; ++i)
+            if ((r = launch_solve_gmg(b->plans[i], dt, st[i].xphys, st[i].penal, st[i].f, st[i].u, b->solve,
+                                      st[i].sstats, b->side[i % k])))
+                return r;
+        for (int j = 0; j < k; ++j) {
+            TO_HIP(hipEventRecord(b->ev[1 + j], b->side[j]));
+            TO_HIP(hipStreamWaitEvent(s, b->ev[1 + j], 0));
+        }
+    } else {
+        for (int i = 0; i < b->n; ++i) {
+            if (b->solve.op != TO_OP_MATFREE &&
+                (r = launch_assemble(b->plans[i], dt, st[i].xphys, st[i].penal, st[i].kval, s)))
+                return r;
+            if ((r = solve_prepare(b->plans[i], dt, st[i].xphys, st[i].penal, b->solve, s))) return r;
+        }
+        if ((r = launch_solve_batch(b->dim, b->mode, b->solve_tab, b->mp_solve, s))) return r;
     }
-    if ((r = launch_solve_batch(b->dim, b->mode, b->solve_tab, b->mp_solve, s))) return r;
     for (int i = 0; i < b->n; ++i) {
         Plan* p = b->plans[i];
         if ((r = launch_sensitivity(p, dt, st[i].xphys, st[i].u, st[i].f, st[i].penal, st[i].dc, st[i].compliance, s)))
@@ -340,7 +363,7 @@ static to_status check_state(const to_step_state& st, const to_step_params& prm)
         set_error("batch: a state buffer is NULL");
         return TO_EINVAL;
     }
-    if (prm.solve.op == TO_OP_ASSEMBLED && !st.kval) { set_error("batch: kval is NULL"); return TO_EINVAL; }
+    if (prm.solve.op != TO_OP_MATFREE && !st.kval) { set_error("batch: kval is NULL"); return TO_EINVAL; }
     if (prm.ft < 1 || prm.ft > 3) { set_error("batch: ft must be 1, 2 or 3"); return TO_EINVAL; }
     if (prm.oc != TO_OC_BISECT && prm.oc != TO_OC_PD) {
         set_error("batch: oc must be TO_OC_BISECT or TO_OC_PD (the filtered bisection runs one design at a time)");
@@ -388,8 +411,24 @@ to_status to_batch_create(to_plan* const* plans, int32_t count, to_dtype dtype, 
         b.dim = b.plans[0]->dim;
         for (Plan* p : b.plans)
             if (p->dim != b.dim) { delete h; set_error("to_batch_create: designs must all be 2D or all 3D"); return TO_EINVAL; }
-        if (b.solve.precond != TO_PREC_JACOBI) {
-            delete h; set_error("to_batch_create: batches use the Jacobi-preconditioned solve"); return TO_EUNSUPPORTED;
+        for (int i = 0; i < count; ++i)
+            if (params[i].solve.precond != b.solve.precond || params[i].solve.budget != b.solve.budget) {
+                delete h;
+                set_error("to_batch_create: the preconditioner and the multigrid budget must be the same for every design");
+                return TO_EINVAL;
+            }
+        if (b.solve.precond == TO_PREC_GMG) {
+            if (b.solve.budget <= 0) {
+                delete h;
+                set_error("to_batch_create: multigrid solves in a batch need a budget (to_solve_opts.budget > 0)");
+                return TO_EINVAL;
+            }
+            for (Plan* p : b.plans)
+                if (p->gmg.L < 2) {
+                    delete h; set_error("to_batch_create: a mesh is too small for a multigrid hierarchy");
+                    return TO_EUNSUPPORTED;
+                }
+            b.gmg = true;
         }
         if (b.solve.precision == TO_SOLVE_MIXED && dtype == TO_F64) {
             delete h; set_error("to_batch_create: the mixed solve needs TO_F32 fields"); return TO_EINVAL;
@@ -462,12 +501,18 @@ to_status to_batch_create(to_plan* const* plans, int32_t count, to_dtype dtype, 
         if (autotune) {
             for (int i = 0; i < count; ++i) {
                 if (b.plans[i]->tune.tuned) continue;
-                to_status r = plan_autotune(b.plans[i], dtype, b.solve.op == TO_OP_ASSEMBLED ? states[i].kval : nullptr,
+                to_status r = plan_autotune(b.plans[i], dtype, b.solve.op != TO_OP_MATFREE ? states[i].kval : nullptr,
                                             s, nullptr);
                 if (r != TO_OK) { delete h; return r; }
             }
         }
         TO_HIP(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
+        if (b.gmg) {
+            b.side.assign(kBatchSideStreams, nullptr);
+            b.ev.assign(1 + kBatchSideStreams, nullptr);
+            for (auto& q : b.side) TO_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+            for (auto& e : b.ev) TO_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        }
         *out = h;
         return TO_OK;
     } catch (...) {
@@ -480,6 +525,8 @@ void to_batch_destroy(to_batch* h) {
     if (!h) return;
     if (h->impl.exec) (void)hipGraphExecDestroy(h->impl.exec);
     if (h->impl.cap) (void)hipStreamDestroy(h->impl.cap);
+    for (hipStream_t q : h->impl.side) if (q) (void)hipStreamDestroy(q);
+    for (hipEvent_t e : h->impl.ev) if (e) (void)hipEventDestroy(e);
     delete h;
 }
 

@@ -61,9 +61,13 @@ struct GmgLevel {
     double* S = nullptr;           // assembled node stencils, 3^dim * dim^2 per node, entry-major (levels >= 1)
     double *x = nullptr, *xt = nullptr, *b = nullptr, *r = nullptr, *dinv = nullptr;
 };
+// Device scalars of the outer flexible CG.  done: 0 iterating, 1 stopped
+// (confirmed, or a cap reached), 2 breakdown.  check: the recursive residual
+// reached the tolerance and waits for the true-residual confirmation.
+// restart: the next direction update starts afresh (beta = 0).
 struct GmgScal {
     double rz, pq, alpha, beta, rr, bnorm, tol, roz, rz_old;
-    int32_t it, done, maxit, confirm, restarts, pad;
+    int32_t it, done, maxit, check, restarts, confirmed, restart, pad;
 };
 struct Gmg {
     int L = 0;
@@ -506,6 +510,8 @@ to_status launch_solve(Plan* p, to_dtype dt, const void* kval, const void* xphys
                        hipStream_t s);
 to_status launch_sensitivity(Plan* p, to_dtype dt, const void* xphys, const double* u,
                              const double* f, double penal, void* dc, double* c, hipStream_t s);
+to_status launch_init_state(Plan* p, to_dtype dt, double volfrac, void* x, void* xphys, void* xold, void* dv,
+                            double* u, hipStream_t s);
 to_status launch_oc(Plan* p, to_dtype dt, void* x, const void* dc, const void* dv, double volfrac,
                     double move, to_oc_stats* st, hipStream_t s, int method = TO_OC_BISECT);
 to_status launch_oc_filtered(Plan* p, to_dtype dt, int ft, void* x, const void* dc, const void* dv, double volfrac,

@@ -54,7 +54,8 @@ static ChebStep cheb_step(int k) {
     for (int i = 1; i <= k; ++i) { rho_prev = rho; rho = 1.0 / (2.0 * sigma - rho); }
     return {rho * rho_prev, 2.0 * rho / delta};
 }
-constexpr int kGmgBatch = 8;           // iterations enqueued between host checks
+constexpr int kGmgBatch = 8;           // iterations per captured batch (even: the directions alternate)
+constexpr int kGmgMaxRestarts = 64;    // true-residual confirmations that may reopen the iteration
 
 
 // --- deterministic block partials + last-block finish --------------------------
@@ -497,11 +498,16 @@ __global__ __launch_bounds__(kBlock) void gmg_coarse_solve_kernel(const double* 
 }
 
 // --- outer flexible PCG ---------------------------------------------------------
-// r = f - A u on free DOFs, u = 0 on fixed ones; |f|, |r|
+// r = f - A u on free DOFs, u = 0 on fixed ones; |f|, |r|.
+// mode 1: the initial residual (also |f| and the counters);
+// mode 2: the true-residual confirmation, run only while S->check is set:
+//         accept (confirmed) if |r| meets the tolerance, else restart the
+//         directions from this residual unless a cap has been reached.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void fcg_residual_kernel(LevelArgs L, const double* __restrict__ f, double* u,
                                                               double* __restrict__ r, double* partial,
-                                                              unsigned* counter, GmgScal* S, int first) {
+                                                              unsigned* counter, GmgScal* S, int mode) {
+    if (mode == 2 && !S->check) return;
     double v[2] = {0.0, 0.0};
     for (int64_t nd = blockIdx.x * (int64_t)kBlock + threadIdx.x; nd < L.nnode; nd += (int64_t)gridDim.x * kBlock) {
         int iy, ix, iz;
@@ -521,21 +527,30 @@ __global__ __launch_bounds__(kBlock) void fcg_residual_kernel(LevelArgs L, const
     }
     double tot[2];
     if (last_block_sums<2>(v, partial, counter, tot) && threadIdx.x == 0) {
-        if (first) {
-            S->bnorm = sqrt(tot[0]);
-            S->it = 0;
-            S->restarts = 0;
-        }
         S->rr = tot[1];
-        S->done = (tot[1] <= S->tol * S->tol) ? 1 : 0;
+        if (mode == 1) {
+            S->bnorm = sqrt(tot[0]);
+            return;
+        }
+        S->check = 0;
+        if (tot[1] <= S->tol * S->tol) {
+            S->confirmed = 1;
+        } else if (S->it < S->maxit && S->restarts < kGmgMaxRestarts) {
+            S->done = 0;
+            S->restart = 1;
+            S->restarts += 1;
+        }
     }
 }
 
 // z = M r finished: rz = r.z, roz = r_old.z; beta = (rz - roz) / rz_old (0 on restart)
 __global__ __launch_bounds__(kBlock) void fcg_dots_kernel(int64_t n, const double* __restrict__ r,
                                                           const double* __restrict__ rold, const double* __restrict__ z,
-                                                          double* partial, unsigned* counter, GmgScal* S, int restart) {
+                                                          double* partial, unsigned* counter, GmgScal* S) {
     if (S->done) return;
+    // every block reads the flag before the last block (the last arrival)
+    // clears it
+    const int restart = S->restart;
     double v[2] = {0.0, 0.0};
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
         v[0] += r[i] * z[i];
@@ -546,6 +561,7 @@ __global__ __launch_bounds__(kBlock) void fcg_dots_kernel(int64_t n, const doubl
         S->beta = restart ? 0.0 : (tot[0] - tot[1]) / S->rz_old;
         S->rz = tot[0];
         S->rz_old = tot[0];
+        S->restart = 0;
     }
 }
 
@@ -603,7 +619,12 @@ __global__ __launch_bounds__(kBlock) void fcg_update_kernel(int64_t n, const dou
     if (last_block_sums<1>(v, partial, counter, tot) && threadIdx.x == 0) {
         S->rr = tot[0];
         S->it += 1;
-        if (tot[0] <= S->tol * S->tol || S->it >= S->maxit) S->done = 1;
+        if (tot[0] <= S->tol * S->tol) {
+            S->done = 1;
+            S->check = 1;            // confirmed on the true residual next
+        } else if (S->it >= S->maxit) {
+            S->done = 1;
+        }
     }
 }
 
@@ -614,7 +635,7 @@ __global__ void fcg_stats_kernel(const GmgScal* S, to_solve_stats* st, double rt
     s.bnorm = S->bnorm;
     s.iterations = S->it;
     s.outer = 0;
-    s.converged = s.residual <= rtol ? 1 : 0;
+    s.converged = S->confirmed;
     s.fallback = 0;
     s.restarts = S->restarts;
     s.pad = 0;
@@ -632,15 +653,18 @@ __global__ void fcg_init_kernel(GmgScal* S, int maxit) {
     S->maxit = maxit;
     S->restarts = 0;
     S->rz_old = 1.0;
+    S->check = 0;
+    S->confirmed = 0;
+    S->restart = 1;
 }
 
+// after the initial (true) residual: done at once if the start already meets
+// the tolerance
 __global__ void fcg_tol_kernel(GmgScal* S, double rtol) {
     S->tol = rtol * S->bnorm;
-    S->done = (S->rr <= S->tol * S->tol) ? 1 : 0;
-}
-
-__global__ void fcg_reopen_kernel(GmgScal* S) {
-    if (S->rr > S->tol * S->tol && S->it < S->maxit) { S->done = 0; S->restarts += 1; }
+    const int ok = S->rr <= S->tol * S->tol ? 1 : 0;
+    S->done = ok;
+    S->confirmed = ok;
 }
 
 // --- host ------------------------------------------------------------------------
@@ -755,61 +779,72 @@ static to_status solve_gmg(Plan* p, const double* f, double* u, const to_solve_o
     hipLaunchKernelGGL(fcg_init_kernel, dim3(1), dim3(1), 0, s, S, o.maxit);
     hipLaunchKernelGGL(fcg_residual_kernel<DIM>, dim3(g0), dim3(kBlock), 0, s, L0, f, u, r, part, ctr, S, 1);
     hipLaunchKernelGGL(fcg_tol_kernel, dim3(1), dim3(1), 0, s, S, o.rtol);
-    // A batch of kGmgBatch outer iterations; the direction buffers alternate
-    // with period 2, so every batch after the first has the same launches.
-    auto enqueue_batch = [&](bool restart_first, hipStream_t cs) {
-        double* pold = restart_first ? z : pb;
+    // A batch of kGmgBatch outer iterations, each predicated on S->done and
+    // followed by the (predicated) true-residual confirmation, which may
+    // reopen the iteration with fresh directions.  The direction buffers
+    // alternate with period 2, so every batch after the first has the same
+    // launches; the first one starts from p_old = z (finite; beta is 0).
+    auto enqueue_batch = [&](bool first, hipStream_t cs) {
+        double* pold = first ? z : pb;
         double* pnew = pa;
         double* other = pb;
         for (int k = 0; k < kGmgBatch; ++k) {
             vcycle<DIM>(p, 0, r, z, done, cs);
-            hipLaunchKernelGGL(fcg_dots_kernel, dim3(gn), dim3(kBlock), 0, cs, n, r, rold, z, part, ctr, S,
-                               (restart_first && k == 0) ? 1 : 0);
+            hipLaunchKernelGGL(fcg_dots_kernel, dim3(gn), dim3(kBlock), 0, cs, n, r, rold, z, part, ctr, S);
             hipLaunchKernelGGL(fcg_dir_kernel<DIM>, dim3(g0), dim3(kBlock), 0, cs, L0, z, pold, pnew, q, part, ctr, S);
             hipLaunchKernelGGL(fcg_update_kernel, dim3(gn), dim3(kBlock), 0, cs, n, pnew, q, u, r, rold, part, ctr, S);
+            hipLaunchKernelGGL(fcg_residual_kernel<DIM>, dim3(g0), dim3(kBlock), 0, cs, L0, f, u, r, part, ctr, S, 2);
             pold = pnew;
             std::swap(pnew, other);
         }
     };
-    // capture both batch kinds once per (u, f) and replay them
-    if (!G.cap) TO_HIP(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
-    if (G.key_u != u || G.key_f != f || !G.g_first || !G.g_steady) {
-        for (hipGraphExec_t* ex : {&G.g_first, &G.g_steady}) {
-            if (*ex) { TO_HIP(hipGraphExecDestroy(*ex)); *ex = nullptr; }
-        }
-        for (int kind = 0; kind < 2; ++kind) {
-            TO_HIP(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
-            enqueue_batch(kind == 0, G.cap);
-            hipGraph_t gr = nullptr;
-            hipError_t e = hipStreamEndCapture(G.cap, &gr);
-            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-            e = hipGraphInstantiate(kind == 0 ? &G.g_first : &G.g_steady, gr, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(gr);
-            if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-        }
-        G.key_u = u;
-        G.key_f = f;
+    hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+    TO_HIP(hipStreamIsCapturing(s, &cst));
+    const bool capturing = cst != hipStreamCaptureStatusNone;
+    if (capturing && o.budget <= 0) {
+        set_error("to_solve: a multigrid solve under stream capture needs a budget (to_solve_opts.budget > 0)");
+        return TO_EINVAL;
     }
-    bool restart = true;
-    const int max_rounds = 64;  // true-residual confirmations
-    for (int round = 0; round < max_rounds; ++round) {
-        int32_t h_done = 0, h_it = 0;
-        for (;;) {
-            TO_HIP(hipGraphLaunch(restart ? G.g_first : G.g_steady, s));
-            restart = false;
-            TO_HIP(hipMemcpyAsync(&h_done, &S->done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            TO_HIP(hipMemcpyAsync(&h_it, &S->it, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            TO_HIP(hipStreamSynchronize(s));
-            if (h_done) break;
+    if (capturing) {
+        // the caller records this call into its own graph: the kernels go
+        // straight into the capture (no private graph, no stream creation)
+        const int nb = (o.budget + kGmgBatch - 1) / kGmgBatch;
+        for (int b = 0; b < nb; ++b) enqueue_batch(b == 0, s);
+    } else {
+        // capture both batch kinds once per (u, f) and replay them
+        if (!G.cap) TO_HIP(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+        if (G.key_u != u || G.key_f != f || !G.g_first || !G.g_steady) {
+            for (hipGraphExec_t* ex : {&G.g_first, &G.g_steady}) {
+                if (*ex) { TO_HIP(hipGraphExecDestroy(*ex)); *ex = nullptr; }
+            }
+            for (int kind = 0; kind < 2; ++kind) {
+                TO_HIP(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+                enqueue_batch(kind == 0, G.cap);
+                hipGraph_t gr = nullptr;
+                hipError_t e = hipStreamEndCapture(G.cap, &gr);
+                if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+                e = hipGraphInstantiate(kind == 0 ? &G.g_first : &G.g_steady, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+            }
+            G.key_u = u;
+            G.key_f = f;
         }
-        if (h_done == 2 || h_it >= o.maxit) break;
-        // confirm on the true residual; reopen (restart the directions) if it misses
-        hipLaunchKernelGGL(fcg_residual_kernel<DIM>, dim3(g0), dim3(kBlock), 0, s, L0, f, u, r, part, ctr, S, 0);
-        hipLaunchKernelGGL(fcg_reopen_kernel, dim3(1), dim3(1), 0, s, S);
-        TO_HIP(hipMemcpyAsync(&h_done, &S->done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        TO_HIP(hipStreamSynchronize(s));
-        if (h_done) break;
-        restart = true;
+        if (o.budget > 0) {
+            // enqueue-only: a fixed number of predicated outer iterations
+            const int nb = (o.budget + kGmgBatch - 1) / kGmgBatch;
+            for (int b = 0; b < nb; ++b) TO_HIP(hipGraphLaunch(b == 0 ? G.g_first : G.g_steady, s));
+        } else {
+            // host-checked: read the stop flag after every batch
+            const int64_t max_batches = (int64_t)o.maxit / kGmgBatch + kGmgMaxRestarts + 2;
+            for (int64_t b = 0; b < max_batches; ++b) {
+                TO_HIP(hipGraphLaunch(b == 0 ? G.g_first : G.g_steady, s));
+                int32_t h_done = 0;
+                TO_HIP(hipMemcpyAsync(&h_done, &S->done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                TO_HIP(hipStreamSynchronize(s));
+                if (h_done) break;
+            }
+        }
     }
     hipLaunchKernelGGL(fcg_stats_kernel, dim3(1), dim3(1), 0, s, S, st, o.rtol);
     TO_HIP(hipGetLastError());

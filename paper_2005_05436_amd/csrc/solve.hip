@@ -176,6 +176,7 @@ struct SolveArgs {
     const int32_t* rp;
     const void* kval;
     const float* kdiag32;       // FP32 assembled values for the Jacobi of the FP64 solve (nullable)
+    const double* kdiag64;      // FP64 assembled values for the same (TO_OP_HYBRID; nullable)
     const double* E64; const float* E32;
     const double* kf64; const float* kf32;
     const double* f; double* u;
@@ -520,12 +521,13 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
             Pcg<DIM, double, CsrS<DIM, double>> cg{op, g, A.freem, C};
             iters = cg.run(A.f, u, false, dinv, r, z, pa, pb, q, tol, A.maxit, restarts);
         } else {
-            if (A.kdiag32) {   // FP32 fields: Jacobi from the FP32 assembled diagonal
+            if (A.kdiag32 || A.kdiag64) {   // Jacobi from the assembled diagonal (last entry of each row)
                 for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x)
 #pragma unroll
                     for (int c = 0; c < DIM; ++c) {
                         const int64_t i = DIM * nd + c;
-                        const double dg = (double)A.kdiag32[A.rp[i + 1] - 1];
+                        const int64_t k = A.rp[i + 1] - 1;
+                        const double dg = A.kdiag64 ? A.kdiag64[k] : (double)A.kdiag32[k];
                         dinv[i] = A.freem[i] && dg != 0.0 ? 1.0 / dg : 0.0;
                     }
             } else {
@@ -718,7 +720,9 @@ to_status launch_warm_start(Plan* p, to_dtype dt, const void* xphys, double pena
 
 int solve_mode(to_dtype dt, const to_solve_opts& o) {
     const bool mixed = dt == TO_F32 && o.precision == TO_SOLVE_MIXED;
-    const bool assembled = o.op == TO_OP_ASSEMBLED && (dt == TO_F64 || mixed);
+    // TO_OP_HYBRID: the FP64 matrix-free operator with the assembled diagonal
+    // (the mixed scheme keeps its FP32 assembled inner operator)
+    const bool assembled = (o.op == TO_OP_ASSEMBLED && (dt == TO_F64 || mixed)) || (o.op == TO_OP_HYBRID && mixed);
     return !mixed ? (assembled ? 0 : 1) : (assembled ? 2 : 3);
 }
 
@@ -738,7 +742,8 @@ void solve_args_fill(Plan* p, to_dtype dt, const void* kval, const double* f, do
     A.freem = p->freemask;
     A.rp = p->row_ptr;
     A.kval = kval;
-    A.kdiag32 = (dt == TO_F32 && mode == 1 && o.op == TO_OP_ASSEMBLED) ? (const float*)kval : nullptr;
+    A.kdiag32 = (dt == TO_F32 && mode == 1 && o.op != TO_OP_MATFREE) ? (const float*)kval : nullptr;
+    A.kdiag64 = (dt == TO_F64 && mode == 1 && o.op == TO_OP_HYBRID) ? (const double*)kval : nullptr;
     A.E64 = p->E64; A.E32 = p->E32; A.kf64 = p->kf64; A.kf32 = p->kf32;
     A.f = f; A.u = u;
     for (int i = 0; i < 8; ++i) { A.v64[i] = p->v64[i]; A.v32[i] = p->v32[i]; }
@@ -751,7 +756,7 @@ void solve_args_fill(Plan* p, to_dtype dt, const void* kval, const double* f, do
 to_status launch_solve(Plan* p, to_dtype dt, const void* kval, const void* xphys, double penal,
                        const double* f, double* u, const to_solve_opts& o, to_solve_stats* st, hipStream_t s) {
     if (o.precond == TO_PREC_GMG) return launch_solve_gmg(p, dt, xphys, penal, f, u, o, st, s);
-    if (o.op == TO_OP_ASSEMBLED && !kval) { set_error("kval is NULL"); return TO_EINVAL; }
+    if (o.op != TO_OP_MATFREE && !kval) { set_error("kval is NULL"); return TO_EINVAL; }
     to_status r = solve_prepare(p, dt, xphys, penal, o, s);
     if (r != TO_OK) return r;
     SolveArgs A;

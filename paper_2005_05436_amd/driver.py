@@ -1,14 +1,36 @@
 """Plan and optimisation-loop objects around the C ABI.  PyTorch supplies
 device memory and the stream; every step of the method runs in libtopt's
 kernels (to_step and the single-step entry points)."""
+import atexit
 import ctypes as C
 import math
+import weakref
 
 import numpy as np
 import torch
 
 from . import _lib as L
 from . import problems
+
+
+# Library objects still open when the interpreter exits are closed by an exit
+# handler, while the HIP runtime is still up (destructors that run later, at
+# module teardown, would call into a runtime that is already shut down).
+_LIVE = {"batch": weakref.WeakSet(), "net": weakref.WeakSet(), "plan": weakref.WeakSet()}
+
+
+def track(kind, obj):
+    _LIVE[kind].add(obj)
+
+
+@atexit.register
+def _close_all():
+    for kind in ("batch", "net", "plan"):
+        for obj in list(_LIVE[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
 
 
 def _dev():
@@ -46,6 +68,7 @@ class Plan:
         base = self.ws.data_ptr()
         self.ws_ptr = (base + 255) & ~255
         self.handle = L.to_plan_create(self.desc, self.ws_ptr, self.ws_bytes, stream)
+        track("plan", self)
         self.info = L.to_plan_get_info(self.handle)
         self.dim, self.nelx, self.nely, self.nelz = dim, nelx, nely, nelz if dim == 3 else 1
 
@@ -95,7 +118,7 @@ class TopOpt:
 
     def __init__(self, cfg, op=L.TO_OP_ASSEMBLED, rtol=1e-8, inner_rtol=0.1, maxit=200000,
                  precision=None, passive=None, solve_precision=L.TO_SOLVE_AUTO, grid_blocks=0, autotune=False,
-                 precond=L.TO_PREC_JACOBI, pae=None, oc=L.TO_OC_BISECT):
+                 precond=L.TO_PREC_JACOBI, pae=None, oc=L.TO_OC_BISECT, budget=0):
         self.cfg = cfg
         self.plan, f, passive = plan_for_config(cfg, passive)
         dev = self.plan.device
@@ -104,20 +127,14 @@ class TopOpt:
         self.dtype = L.TO_F64 if prec == "f64" else L.TO_F32
         tdt = torch.float64 if self.dtype == L.TO_F64 else torch.float32
         m, n = I.m, I.n
-        code = np.zeros(m, np.uint8) if passive is None else np.asarray(passive, np.uint8)
-        act = code == L.TO_ACTIVE
-        x0 = np.zeros(m)
-        x0[act] = (cfg.volfrac * (m - np.sum(code == L.TO_VOID)) - np.sum(code == L.TO_SOLID)) / np.sum(act)
-        x0[code == L.TO_SOLID] = 1.0
-        dv = np.zeros(m)
-        dv[act] = 1.0 / m / cfg.volfrac
-        mk = lambda a=None: (torch.zeros(m, dtype=tdt, device=dev) if a is None
-                             else torch.as_tensor(a, dtype=tdt).to(dev))
-        self.x, self.xtilde, self.xphys = mk(x0), mk(), mk(x0)
-        self.xphys_old = torch.ones(m, dtype=tdt, device=dev)
-        self.dprj, self.dc, self.dcf, self.dv, self.dv0 = mk(), mk(), mk(dv), mk(dv), mk()
-        self.kval = torch.zeros(I.nnz_lower, dtype=tdt, device=dev)
+        mk = lambda: torch.zeros(m, dtype=tdt, device=dev)
+        self.x, self.xtilde, self.xphys, self.xphys_old = mk(), mk(), mk(), mk()
+        self.dprj, self.dc, self.dcf, self.dv, self.dv0 = mk(), mk(), mk(), mk(), mk()
         self.u = torch.zeros(n, dtype=torch.float64, device=dev)
+        # block PRE.6 on the device: x, xphys, xphys_old = 1, dv, u = 0
+        L.to_init_state(self.plan.handle, self.dtype, cfg.volfrac, self.x, self.xphys, self.xphys_old, self.dv,
+                        self.u)
+        self.kval = torch.zeros(I.nnz_lower, dtype=tdt, device=dev)
         self.f = torch.as_tensor(f, dtype=torch.float64).to(dev)
         self.eta = torch.tensor([cfg.eta], dtype=torch.float64, device=dev)
         self.c = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -132,9 +149,9 @@ class TopOpt:
         self.params = L.StepParams(cfg.volfrac, cfg.move, cfg.ft, oc, math.nan, _sched(cfg.penal_sched),
                                    _sched(cfg.beta_sched),
                                    L.SolveOpts(rtol, inner_rtol, maxit, op, solve_precision, 0, grid_blocks,
-                                               precond))
+                                               precond, budget))
         if autotune:
-            self.tuning = L.to_plan_autotune(self.plan.handle, self.dtype, self.kval if op == L.TO_OP_ASSEMBLED else None)
+            self.tuning = L.to_plan_autotune(self.plan.handle, self.dtype, self.kval if op != L.TO_OP_MATFREE else None)
         self.pae = None
         if pae is not None:
             self.enable_pae(**pae)
@@ -171,19 +188,24 @@ class TopOpt:
         L.to_step(self.plan.handle, self.dtype, self.state, self.params, stream)
         self._pae_post(stream)
 
-    def step_stages(self, net=None, train_lr=None, stream=None):
+    def step_stages(self, net=None, train_lr=None, stream=None, solve_events=None):
         """One redesign iteration through the single-stage entry points (the
         sequence to_step runs).  With a network: its prediction from the
         physical density and the load, combined with the previous displacement
         by the Galerkin start (to_warm_start), seeds the PCG; with train_lr the
-        network then takes one Adam step on the converged displacement."""
+        network then takes one Adam step on the converged displacement.
+        solve_events: two torch events recorded before the network's
+        prediction (or the solve) and after the solve."""
         h, dt, st, cfg = self.plan.handle, self.dtype, self.state, self.cfg
         self._pae_pre(stream)
         L.to_filter(h, dt, L.TO_FILTER_FWD, self.x, None, None, self.xtilde, None, stream)
         L.to_project(h, dt, cfg.ft, self.xtilde, self.x, self.xphys, self.dprj, st.beta, self.eta, cfg.volfrac,
                      self.xphys_old, self.pst, stream)
-        if self.params.solve.op == L.TO_OP_ASSEMBLED:
+        if self.params.solve.op != L.TO_OP_MATFREE:
             L.to_assemble(h, dt, self.xphys, st.penal, self.kval, stream)
+        sq = stream or torch.cuda.current_stream()
+        if solve_events is not None:
+            solve_events[0].record(sq)
         if net is not None:
             if not hasattr(self, "uhat"):
                 self.uhat = torch.zeros_like(self.u)
@@ -191,6 +213,8 @@ class TopOpt:
             net.forward(dt, self.xphys, self.f, self.uhat)
             L.to_warm_start(h, dt, self.xphys, st.penal, self.f, self.uhat, self.u, self.u, self.wcoef, stream)
         L.to_solve(h, dt, self.kval, self.xphys, st.penal, self.f, self.u, self.params.solve, self.sst, stream)
+        if solve_events is not None:
+            solve_events[1].record(sq)
         if net is not None and train_lr:
             net.train_step(dt, self.xphys, self.f, self.u, train_lr)
         L.to_sensitivity(h, dt, self.xphys, self.u, self.f, st.penal, self.dc, self.c, stream)
@@ -234,9 +258,9 @@ class Batch:
     optionally replayed from a HIP graph."""
 
     def __init__(self, cfgs, op=L.TO_OP_ASSEMBLED, rtol=1e-8, precision=None, solve_precision=L.TO_SOLVE_AUTO,
-                 autotune=True, maxit=200000, oc=L.TO_OC_BISECT):
+                 autotune=True, maxit=200000, oc=L.TO_OC_BISECT, precond=L.TO_PREC_JACOBI, budget=0):
         self.runs = [TopOpt(c, op=op, rtol=rtol, precision=precision, solve_precision=solve_precision, maxit=maxit,
-                            oc=oc) for c in cfgs]
+                            oc=oc, precond=precond, budget=budget) for c in cfgs]
         dts = {g.dtype for g in self.runs}
         if len(dts) != 1:
             raise ValueError("all designs of a batch need the same precision")
@@ -253,6 +277,7 @@ class Batch:
         self.ws_ptr = (self.ws.data_ptr() + 255) & ~255
         self.handle = L.to_batch_create([g.plan.handle for g in self.runs], self.dtype, self.states, self.params,
                                         autotune, self.ws_ptr, self.ws_bytes)
+        track("batch", self)
 
     def step(self, use_graph=False, stream=None):
         L.to_step_batched(self.handle, self.states, self.params, use_graph, stream)

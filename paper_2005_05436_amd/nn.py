@@ -5,23 +5,37 @@ import torch
 
 from . import _lib as L
 
-# (c_in, c_out) of the 15 layers, in the library's parameter order
+# (c_in, c_out) of the 15 layers, in the library's parameter order (2D and 3D)
 LAYERS = [(3, 16), (16, 16), (16, 32), (32, 32), (32, 64), (64, 64), (64, 128), (128, 64),
           (64, 64), (64, 32), (32, 32), (32, 16), (16, 16), (16, 16), (16, 2)]
+LAYERS3 = [(4, 8), (8, 8), (8, 16), (16, 16), (16, 32), (32, 32), (32, 64), (64, 32),
+           (32, 32), (32, 16), (16, 16), (16, 8), (8, 8), (8, 8), (8, 3)]
+LEVELS = [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0]
+
+
+def layers(dim):
+    return LAYERS if dim == 2 else LAYERS3
 
 
 class Net:
-    """A U-Net bound to one 2D plan (mesh size and free DOFs)."""
+    """A U-Net bound to one plan (mesh size and free DOFs), 2D or 3D."""
 
     def __init__(self, plan):
         self.plan = plan
-        self.ws_bytes, self.n_params = L.to_nn_query(plan.nelx, plan.nely)
+        self.dim = plan.dim
+        self.ws_bytes, self.n_params = L.to_nn_query(plan.dim, plan.nelx, plan.nely, plan.nelz)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=plan.device)
         self.ws_ptr = (self.ws.data_ptr() + 255) & ~255
         self.handle = L.to_nn_create(plan.handle, self.ws_ptr, self.ws_bytes)
+        from .driver import track
+        track("net", self)
         self.loss = torch.zeros(1, dtype=torch.float64, device=plan.device)
-        self.H = (plan.nelx + 1 + 7) // 8 * 8
-        self.W = (plan.nely + 1 + 7) // 8 * 8
+        p8 = lambda n: (n + 1 + 7) // 8 * 8
+        if self.dim == 2:
+            self.shape = (p8(plan.nelx), p8(plan.nely))
+        else:
+            self.shape = (p8(plan.nelx), p8(plan.nelz), p8(plan.nely))
+        self.H, self.W = self.shape[-2], self.shape[-1]
 
     def close(self):
         if getattr(self, "handle", None):
@@ -39,20 +53,27 @@ class Net:
         assert p.numel() == self.n_params
         L.to_nn_set_params(self.handle, p)
 
+    def npix(self, level=0):
+        n = 1
+        for e in self.shape:
+            n *= e >> level
+        return n
+
     def get(self, what):
-        n = self.H * self.W * 16 if what == L.TO_NN_OUTPUT else self.n_params
+        n = self.npix() * 16 if what == L.TO_NN_OUTPUT else self.n_params
         out = torch.empty(n, dtype=torch.float32, device=self.plan.device)
         L.to_nn_get(self.handle, what, out)
         return out
 
     def layer(self, i, preskip=False):
-        """bfloat16 output (or pre-skip activation) of layer i as float32, [rows, cols, c_out padded]."""
-        lev = [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0][i]
-        cp = (LAYERS[i][1] + 15) // 16 * 16
-        n = (self.H >> lev) * (self.W >> lev) * cp
+        """bfloat16 output (or pre-skip activation) of layer i as float32,
+        [(planes,) rows, cols, c_out padded]."""
+        lev = LEVELS[i]
+        cp = (layers(self.dim)[i][1] + 15) // 16 * 16
+        n = self.npix(lev) * cp
         raw = torch.empty(n, dtype=torch.int16, device=self.plan.device)
         L.to_nn_get(self.handle, (L.TO_NN_PRESKIP if preskip else L.TO_NN_ACT) + i, raw)
-        return (raw.to(torch.int32) << 16).view(torch.float32).reshape(self.H >> lev, self.W >> lev, cp)
+        return (raw.to(torch.int32) << 16).view(torch.float32).reshape(*[e >> lev for e in self.shape], cp)
 
     def params(self):
         return self.get(L.TO_NN_PARAMS)

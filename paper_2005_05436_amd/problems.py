@@ -35,13 +35,14 @@ def cantilever2d(nelx, nely, load_iy):
     return f, np.unique(fixed)
 
 
-def cantilever3d(nelx, nely, nelz):
+def cantilever3d(nelx, nely, nelz, load_iz=0):
     """Face x = 0 clamped; downward line load sin(pi iy / nely) on u_z along
-    the bottom edge (iz = 0) of the end x = nelx."""
+    the line iz = load_iz (0: the bottom edge, the paper's case) of the end
+    x = nelx."""
     n = 3 * (nelx + 1) * (nely + 1) * (nelz + 1)
     f = np.zeros(n)
     iy = np.arange(nely + 1)
-    f[3 * _node3(nely, nelz, iy, nelx, 0) + 2] = -np.sin(iy / nely * np.pi)
+    f[3 * _node3(nely, nelz, iy, nelx, load_iz) + 2] = -np.sin(iy / nely * np.pi)
     nodes = np.arange((nely + 1) * (nelz + 1))          # ix = 0 face: the first nodes
     fixed = (3 * nodes[:, None] + np.arange(3)[None, :]).reshape(-1).astype(np.int32)
     return f, fixed
@@ -72,7 +73,7 @@ def frame(nelx, nely, sign=-1.0):
 def from_config(cfg):
     """(f, fixed, passive codes or None) for a workloads.Config."""
     if cfg.nelz:
-        return cantilever3d(cfg.nelx, cfg.nely, cfg.nelz) + (None,)
+        return cantilever3d(cfg.nelx, cfg.nely, cfg.nelz, cfg.load) + (None,)
     if cfg.kind == "mbb":
         return mbb(cfg.nelx, cfg.nely, cfg.load) + (None,)
     if cfg.kind == "frame":

@@ -214,15 +214,15 @@ def test_warm_start_matches_oracle(case):
         assert np.abs(got - ustar).max() <= 1e-8 * np.abs(ustar).max()
 
 
-def test_trained_network_warm_start_gain():
+def test_trained_network_warm_start():
     """The network trained on the GPU on (design, displacement) pairs from
     optimiser runs of seeded random MBB instances, then used as the warm start
-    on held-out instances: the held-out prediction error falls with training,
-    every warm-started solve still reaches the true residual 1e-8, and the CG
-    iterations are reported against the plain warm start from the previous
-    displacement (the gain at rtol 1e-8 is small: the previous displacement is
-    already a good start, and a prediction accurate in the smooth modes still
-    leaves a rough residual)."""
+    on held-out instances: the held-out prediction error falls at least
+    fivefold with training, every warm-started solve still reaches the true
+    residual 1e-8, and the warm start costs at most 3% more CG iterations than
+    the plain warm start from the previous displacement.  This is not a gain
+    test: at rtol 1e-8 the measured difference is within a few tenths of a
+    percent either way (the CG iterations are printed)."""
     from paper_2005_05436_amd import _lib as L
     from paper_2005_05436_amd.driver import TopOpt, read_struct
     from paper_2005_05436_amd.nn import LAYERS, Net
@@ -267,3 +267,135 @@ def test_trained_network_warm_start_gain():
         print(f"{cfg.name}: CG iterations plain {sum(its['plain'])} warm-started {sum(its['nn'])} "
               f"(gain {100 * gain:.2f}%), first iteration {its['plain'][0]} vs {its['nn'][0]}")
         assert sum(its["nn"]) <= 1.03 * sum(its["plain"])
+
+
+# --- the 3D network (Hex8 meshes) --------------------------------------------
+def make3(nelx, nely, nelz, seed, load_iz=0):
+    from paper_2005_05436_amd import problems
+    from paper_2005_05436_amd.driver import Plan
+    from paper_2005_05436_amd.nn import LAYERS3, Net
+    f, fixed = problems.cantilever3d(nelx, nely, nelz, load_iz)
+    plan = Plan(3, nelx, nely, nelz, 1.5, "N", fixed)
+    net = Net(plan)
+    params = W.network_params(LAYERS3, seed, taps=27)
+    net.set_params(params)
+    return plan, net, f, fixed, params
+
+
+def gpu_inputs3(net, dims, xin, f):
+    """gpu_inputs for the 3D network."""
+    names = [Ly[0] for Ly in unet.LAYERS3]
+    ys = [host(net.layer(i))[..., :unet.LAYERS3[i][2]] for i in range(len(names) - 1)]
+    xs = []
+    for i, (name, ci, co, lev, act, src, skip) in enumerate(unet.LAYERS3):
+        if i == 0:
+            x = unet.bf16_round(unet.features3(*dims, xin, f))
+        elif src == "pool":
+            x = unet.bf16_round(unet.pool2(ys[i - 1]))
+        elif src == "up":
+            x = unet.up2(ys[i - 1])
+        else:
+            x = ys[i - 1]
+        xs.append(x)
+    return names, ys, xs
+
+
+@pytest.mark.parametrize("dims,dt,seed", [((6, 4, 3), 1, 31), ((13, 6, 7), 0, 32)])
+def test_nn3d_forward_layers_match_bf16_oracle(dims, dt, seed):
+    """Every layer of the 3D network (3x3x3 convolutions, 2x2x2 pooling)
+    against the oracle layer applied to the GPU's own input, as in 2D; the
+    DOF vector is the output at the real nodes, zero on fixed DOFs."""
+    from paper_2005_05436_amd import _lib as L
+    nelx, nely, nelz = dims
+    plan, net, f, fixed, params = make3(nelx, nely, nelz, seed, load_iz=nelz // 2)
+    m = nelx * nely * nelz
+    x = W.design_field(m, 5, 0.0, 1.0)
+    T = torch.float64 if dt == L.TO_F64 else torch.float32
+    uh = torch.zeros(f.size, dtype=torch.float64, device="cuda")
+    net.forward(dt, torch.as_tensor(x, dtype=T).cuda(), torch.as_tensor(f).cuda(), uh)
+    out = host(net.get(L.TO_NN_OUTPUT)).reshape(*net.shape, 16)
+    xin = x if dt == L.TO_F64 else x.astype(np.float32).astype(np.float64)
+    p64 = params.astype(np.float32).astype(np.float64)
+    wb = unet.unpack(p64, 3)
+    names, ys, xs = gpu_inputs3(net, dims, xin, f)
+    print(f"3D network {dims}: image {net.shape}", flush=True)
+    for i, (name, ci, co, lev, act, src, skip) in enumerate(unet.LAYERS3):
+        Wt, b = wb[i]
+        z = unet.conv3x3(xs[i], unet.bf16_round(Wt), b)
+        if not act:
+            assert np.abs(out[..., :3] - z).max() <= 1e-5 * np.abs(z).max()
+            continue
+        a = unet.leaky(z)
+        y = a + ys[names.index(skip)] if skip else a
+        nd, within = count_flips(ys[i], unet.bf16_round(y))
+        assert within, name
+        assert nd <= max(3, 2e-3 * y.size), (name, nd, y.size)
+    assert np.all(out[..., 3:] == 0.0)
+    ref, _ = unet.forward(p64, unet.features3(*dims, xin, f), bf16=True)
+    assert np.linalg.norm(out[..., :3] - ref) <= 3e-2 * np.linalg.norm(ref)
+    free = np.ones(f.size, bool)
+    free[fixed] = False
+    np.testing.assert_array_equal(host(uh), unet.prediction3(*dims, out, free))
+
+
+def test_nn3d_gradient_matches_bf16_oracle():
+    """3D weight gradients against the oracle's bfloat16 backward pass on the
+    GPU's own forward activations (1% per layer in the 2-norm, cosine
+    >= 0.9999), and the loss against its definition."""
+    from paper_2005_05436_amd import _lib as L
+    dims = (9, 6, 5)
+    plan, net, f, fixed, params = make3(*dims, 33)
+    x = W.design_field(dims[0] * dims[1] * dims[2], 6, 0.0, 1.0)
+    u = W.displacement_field(f.size, 7)
+    u[fixed] = 0.0
+    net.forward(L.TO_F64, torch.as_tensor(x).cuda(), torch.as_tensor(f).cuda(), None)
+    net.backward(torch.as_tensor(u).cuda())
+    g = host(net.get(L.TO_NN_GRAD))
+    loss = float(host(net.loss)[0])
+    out = host(net.get(L.TO_NN_OUTPUT)).reshape(*net.shape, 16)[..., :3]
+    p64 = params.astype(np.float32).astype(np.float64)
+    names, ys, xs = gpu_inputs3(net, dims, x, f)
+    cache = {"dim": 3}
+    for i, name in enumerate(names):
+        cache[name + ".x"] = xs[i]
+        if unet.LAYERS3[i][4]:
+            cache[name + ".a"] = host(net.layer(i, preskip=True))[..., :unet.LAYERS3[i][2]] if unet.LAYERS3[i][6] \
+                else ys[i]
+    tgt, mk = unet.target3(*dims, u), unet.node_mask3(*dims)
+    cnt = 3.0 * mk.sum()
+    diff = (out - tgt) * mk[..., None]
+    assert abs(loss - (diff * diff).sum() / cnt) <= 1e-6 * loss
+    rg = unet.backward(p64, cache, 2.0 * diff / cnt, bf16=True)
+    offs, _ = unet.layer_offsets(3)
+    for (ow, ob), Ly in zip(offs, unet.LAYERS3):
+        sl = slice(ow, ob + Ly[2])
+        assert np.linalg.norm(g[sl] - rg[sl]) <= 1e-2 * np.linalg.norm(rg[sl]), Ly[0]
+    cos = g @ rg / (np.linalg.norm(g) * np.linalg.norm(rg))
+    print(f"3D gradient cosine {cos:.7f}", flush=True)
+    assert cos >= 0.9999
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_nn_training_is_bitwise_repeatable(dim):
+    """Two identical training sequences (3 Adam steps from the same
+    parameters on the same samples) end with bit-identical parameters: every
+    sum of the backward pass is taken in a fixed order."""
+    from paper_2005_05436_amd import _lib as L
+    if dim == 2:
+        plan, net, f, fixed, params = make(40, 16, 41)
+        m = 40 * 16
+    else:
+        plan, net, f, fixed, params = make3(10, 6, 6, 41)
+        m = 10 * 6 * 6
+    xd = torch.as_tensor(W.design_field(m, 42, 0.0, 1.0)).cuda()
+    fd = torch.as_tensor(f).cuda()
+    ud = torch.as_tensor(W.displacement_field(f.size, 43)).cuda()
+    runs = []
+    for rep in range(2):
+        net.set_params(params)
+        for _ in range(3):
+            net.train_step(L.TO_F64, xd, fd, ud, 1e-3)
+        runs.append((host(net.params()), host(net.get(L.TO_NN_GRAD)), float(host(net.loss)[0])))
+    np.testing.assert_array_equal(runs[0][0], runs[1][0])
+    np.testing.assert_array_equal(runs[0][1], runs[1][1])
+    assert runs[0][2] == runs[1][2]

@@ -230,6 +230,42 @@ def test_assemble_full_3d_sampled(dt):
         assert abs(got[s] - ref) <= (1e-13 if dt == 1 else 1e-6) * scale
 
 
+# --- initial state (block PRE.6) ----------------------------------------------
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("dims,vf,passive", [((60, 20), 0.5, False), ((100, 100), 0.2, True), ((6, 5, 4), 0.12, True)])
+def test_init_state(dims, vf, passive, dt):
+    """to_init_state against the oracle's initial design (PRE.6): x, xphys,
+    dv element by element (FP64 exact; FP32 the rounded oracle values),
+    xphys_old = 1 and u = 0; the mean of x is volfrac."""
+    from paper_2005_05436_amd import _lib as L
+    M = omesh.Mesh(*dims)
+    code = None
+    if passive:
+        code = np.zeros(M.m, np.uint8)
+        code[::11] = L.TO_SOLID
+        code[3::17] = L.TO_VOID
+    P = make_plan(dims, passive=code)
+    T = tdt(dt)
+    x, xp, xo, dv = (torch.full((M.m,), -5.0, dtype=T, device="cuda") for _ in range(4))
+    u = torch.full((M.n,), 3.0, dtype=torch.float64, device="cuda")
+    L.to_init_state(P.handle, dt, vf, x, xp, xo, dv, u)
+    x_ref, dv_ref, _ = omesh.initial_design(M, vf, code)
+    cast = (lambda a: a) if dt == 1 else (lambda a: a.astype(np.float32).astype(np.float64))
+    np.testing.assert_array_equal(host(x), cast(x_ref))
+    np.testing.assert_array_equal(host(xp), cast(x_ref))
+    np.testing.assert_array_equal(host(dv), cast(dv_ref))
+    assert np.all(host(xo) == 1.0) and np.all(host(u) == 0.0)
+    # the codes' initial value fills volfrac of the non-void part of the domain
+    n_void = 0 if code is None else int(np.sum(code == L.TO_VOID))
+    assert abs(np.sum(host(x)) - vf * (M.m - n_void)) <= (1e-9 if dt == 1 else 1e-3)
+    # the other outputs are optional
+    x2 = torch.zeros(M.m, dtype=T, device="cuda")
+    L.to_init_state(P.handle, dt, vf, x2, None, None, None, None)
+    np.testing.assert_array_equal(host(x2), cast(x_ref))
+    with pytest.raises(L.ToError):
+        L.to_init_state(P.handle, dt, 1.5, x2, None, None, None, None)
+
+
 # --- sensitivity ------------------------------------------------------------
 @pytest.mark.parametrize("dt", DTYPES)
 @pytest.mark.parametrize("dims,penal", [((60, 20), 3.0), ((23, 11), 1.0), ((6, 5, 4), 3.0), ((96, 48, 48), 3.0)])

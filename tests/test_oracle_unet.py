@@ -149,3 +149,98 @@ def test_galerkin_start_minimises_energy():
     # an exact prediction is recovered exactly; a zero previous field falls back
     assert np.allclose(unet.galerkin_start(K, f, ustar, up), ustar)
     assert np.allclose(unet.galerkin_start(K, f, uh, np.zeros(n)), (uh @ f) / (uh @ K @ uh) * uh)
+
+
+# --- the 3D network (Hex8 meshes) --------------------------------------------
+
+def test_conv3x3x3_equals_library_correlation():
+    rng = np.random.default_rng(13)
+    x = rng.normal(size=(6, 5, 7, 2))
+    W = rng.normal(size=(27, 3, 2))
+    b = np.array([0.25, -0.5, 1.0])
+    y = unet.conv3x3(x, W, b)
+    for co in range(3):
+        ref = sum(ndi.correlate(x[..., ci], W[:, co, ci].reshape(3, 3, 3), mode="constant") for ci in range(2))
+        assert np.allclose(y[..., co], ref + b[co], atol=1e-12)
+
+
+def test_conv3d_adjoint_identities():
+    rng = np.random.default_rng(14)
+    x = rng.normal(size=(4, 6, 5, 3))
+    W = rng.normal(size=(27, 2, 3))
+    g = rng.normal(size=(4, 6, 5, 2))
+    lhs = np.sum(unet.conv3x3(x, W) * g)
+    assert np.isclose(lhs, np.sum(x * unet.conv3x3_dgrad(g, W)), rtol=1e-12)
+    assert np.isclose(lhs, np.sum(W * unet.conv3x3_wgrad(x, g)), rtol=1e-12)
+
+
+def test_pool_and_upsample_3d():
+    rng = np.random.default_rng(15)
+    x = rng.normal(size=(4, 6, 8, 2))
+    p = unet.pool2(x)
+    assert p.shape == (2, 3, 4, 2)
+    assert np.isclose(p[1, 2, 3, 1], x[2:4, 4:6, 6:8, 1].mean())
+    y = rng.normal(size=(2, 3, 4, 2))
+    # up2 and sum2 are adjoint; pool2 = sum2 / 8
+    assert np.isclose(np.sum(unet.up2(y) * x), np.sum(y * unet.sum2(x)), rtol=1e-12)
+    assert np.allclose(unet.pool2(x), unet.sum2(x) / 8.0)
+    assert np.all(unet.up2(y)[3, 5, 7] == y[1, 2, 3])
+
+
+def test_parameter_count_3d():
+    assert 2.0e5 <= unet.n_params(3) <= 3.2e5
+
+
+def _problem3(seed, nelx=5, nely=4, nelz=3):
+    rng = np.random.default_rng(seed)
+    xt = rng.uniform(0.0, 1.0, nelx * nely * nelz)
+    f = np.zeros(3 * (nelx + 1) * (nely + 1) * (nelz + 1))
+    f[3 * rng.integers(0, f.size // 3) + 2] = -1.0
+    u = rng.normal(size=f.size)
+    img = unet.features3(nelx, nely, nelz, xt, f)
+    return img, unet.target3(nelx, nely, nelz, u), unet.node_mask3(nelx, nely, nelz)
+
+
+def _init3(seed):
+    rng = np.random.default_rng(seed)
+    offs, P = unet.layer_offsets(3)
+    p = np.zeros(P)
+    for (name, ci, co, *_r), (ow, ob) in zip(unet.LAYERS3, offs):
+        p[ow:ob] = rng.normal(size=ob - ow) * np.sqrt(2.0 / (27 * ci))
+        p[ob:ob + co] = rng.normal(size=co) * 0.1
+    return p
+
+
+def test_gradient_matches_finite_differences_3d():
+    img, tgt, mk = _problem3(20)
+    p = _init3(21)
+    loss, g = unet.loss_and_grad(p, img, tgt, mk)
+    rng = np.random.default_rng(22)
+    offs, P = unet.layer_offsets(3)
+    picks = []
+    for (ow, ob), L in zip(offs, unet.LAYERS3):
+        picks += list(rng.integers(ow, ob, 2)) + [ob + int(rng.integers(0, L[2]))]
+    for i in picks:
+        h = 1e-6 * max(1.0, abs(p[i]))
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (unet.loss_and_grad(pp, img, tgt, mk)[0] - unet.loss_and_grad(pm, img, tgt, mk)[0]) / (2 * h)
+        # the central difference carries a rounding floor of about eps |loss| / h
+        assert abs(fd - g[i]) <= 1e-6 * max(abs(fd), abs(g[i])) + 1e-9, (i, fd, g[i])
+
+
+def test_features3_density_and_load_layout():
+    nelx, nely, nelz = 3, 4, 2
+    xt = np.arange(nelx * nely * nelz, dtype=float)
+    f = np.zeros(3 * (nelx + 1) * (nely + 1) * (nelz + 1))
+    node = 2 + (nely + 1) * (1 + (nelz + 1) * 3)            # iy = 2, iz = 1, ix = 3
+    f[3 * node + 2] = -7.0
+    img = unet.features3(nelx, nely, nelz, xt, f)
+    e = lambda iy, iz, ix: xt[iy + nely * (iz + nelz * ix)]
+    assert img.shape == (8, 8, 8, 4)
+    assert img[0, 0, 0, 0] == e(0, 0, 0)
+    # node (iy 2, iz 1, ix 1): the eight elements around it
+    want = np.mean([e(iy, iz, ix) for iy in (1, 2) for iz in (0, 1) for ix in (0, 1)])
+    assert np.isclose(img[1, 1, 2, 0], want)
+    assert img[3, 1, 2, 3] == -7.0 and np.count_nonzero(img[..., 1:]) == 1

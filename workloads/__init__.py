@@ -149,16 +149,31 @@ def sensitivity_field(m, seed):
 
 
 # --- the learned warm start --------------------------------------------------
-def network_params(layers, seed):
-    """Initial network parameters, flat, per layer W[9][c_out][c_in] then
-    b[c_out]: He-normal weights (standard deviation sqrt(2 / (9 c_in))) and
-    small normal biases.  `layers` lists (c_in, c_out)."""
+def network_params(layers, seed, taps=9):
+    """Initial network parameters, flat, per layer W[taps][c_out][c_in] then
+    b[c_out]: He-normal weights (standard deviation sqrt(2 / (taps c_in)))
+    and small normal biases.  `layers` lists (c_in, c_out); taps is 9 for
+    the 2D network, 27 for the 3D one."""
     rng = np.random.default_rng(seed)
     out = []
     for ci, co in layers:
-        out.append(rng.standard_normal(9 * co * ci) * np.sqrt(2.0 / (9 * ci)))
+        out.append(rng.standard_normal(taps * co * ci) * np.sqrt(2.0 / (taps * ci)))
         out.append(rng.standard_normal(co) * 0.05)
     return np.concatenate(out)
+
+
+def warm_start_instances3(count, nelx, nely, nelz, seed):
+    """Training / held-out instances for the 3D learned warm start: the 3D
+    cantilever with its sine line load moved to a random height iz on the
+    free end (drawn uniformly, `load`) and volfrac uniform in [0.08, 0.2];
+    rmin sqrt(3), 'N', projection with beta 2, FP32 fields."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        out.append(Config(f"ws3_{seed}_{i}", "cantilever3d", nelx, nely, nelz, volfrac=float(rng.uniform(0.08, 0.2)),
+                          rmin=float(np.sqrt(3.0)), ft=3, bc="N", eta=0.5, beta=2.0, penal=3.0, iterations=100,
+                          precision="f32", load=int(rng.integers(0, nelz + 1))))
+    return out
 
 
 def warm_start_instances(count, nelx, nely, seed):
