@@ -268,6 +268,25 @@ to_status to_sensitivity(const to_plan* plan, to_dtype dtype, const void* xphys,
                          const double* u, const double* f, double penal, void* dc,
                          double* d_compliance, void* stream);
 
+/* to_sensitivity_noalloc -- to_sensitivity for callers that cannot allocate
+ * device memory or take part in allocation at all (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments, kernels and results (bit-identical) as to_sensitivity; the
+ * compliance sum's scratch (at most 1024 FP64 block partials and 832 arrival
+ * counters, 11.3 KiB) lives in a file-scope device array of the library, one
+ * per device, held until the process ends, instead of the plan workspace.
+ * Allocates nothing (no hipMalloc, no library allocation).  The counters are
+ * cleared by a small kernel at the start of every call with f and
+ * d_compliance given.  Calls on one device share that array: two such calls
+ * that overlap in time on one device (different streams, or threads) race and
+ * give wrong compliance values; serialise them.  Returns TO_EINVAL for bad
+ * arguments, or if a launch would need more block partials than the array
+ * holds (no mesh does: the launch clamps its grid); TO_EHIP if the device
+ * address of the array cannot be obtained. */
+to_status to_sensitivity_noalloc(const to_plan* plan, to_dtype dtype, const void* xphys,
+                                 const double* u, const double* f, double penal, void* dc,
+                                 double* d_compliance, void* stream);
+
 /* ---------------------------------------------------------------------------
  * to_oc_update -- OC rule eq. (10)-(11) with bisection on sqrt(lambda) over
  * [0, sqrt(lambda#)] of eq. (19) (block RL.4 of the 2D code):

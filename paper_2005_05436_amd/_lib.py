@@ -27,7 +27,7 @@ TO_OC_BISECT, TO_OC_PD, TO_OC_FILTERED = 0, 1, 2
 EXPORTED = ["to_plan_query", "to_plan_create", "to_plan_destroy", "to_plan_get_info", "to_plan_export",
             "to_plan_build_host",
             "to_status_string", "to_last_error", "to_init_state", "to_filter", "to_project", "to_assemble", "to_solve",
-            "to_sensitivity", "to_oc_update", "to_oc_update_pd", "to_oc_update_filtered", "to_step", "to_continuation", "to_warm_start",
+            "to_sensitivity", "to_sensitivity_noalloc", "to_oc_update", "to_oc_update_pd", "to_oc_update_filtered", "to_step", "to_continuation", "to_warm_start",
             "to_nn_query", "to_nn_create", "to_nn_destroy", "to_nn_set_params", "to_nn_get", "to_nn_forward",
             "to_nn_backward", "to_nn_adam", "to_nn_train_step", "to_plan_autotune", "to_plan_set_tuning",
             "to_plan_get_tuning", "to_batch_query", "to_batch_create", "to_step_batched", "to_batch_get_info",
@@ -135,6 +135,7 @@ def load():
         "to_assemble": (S, [P, S, P, C.c_double, P, P]),
         "to_solve": (S, [P, S, P, P, C.c_double, P, P, C.POINTER(SolveOpts), P, P]),
         "to_sensitivity": (S, [P, S, P, P, P, C.c_double, P, P, P]),
+        "to_sensitivity_noalloc": (S, [P, S, P, P, P, C.c_double, P, P, P]),
         "to_oc_update": (S, [P, S, P, P, P, C.c_double, C.c_double, P, P]),
         "to_oc_update_pd": (S, [P, S, P, P, P, C.c_double, C.c_double, P, P]),
         "to_oc_update_filtered": (S, [P, S, C.c_int, P, P, P, C.c_double, C.c_double, C.c_double, P, P, P]),
@@ -253,6 +254,11 @@ def to_init_state(plan, dtype, volfrac, x, xphys, xphys_old, dv, u, stream=None)
 def to_sensitivity(plan, dtype, xphys, u, f, penal, dc, d_compliance, stream=None):
     check(load().to_sensitivity(plan, dtype, ptr(xphys), ptr(u), ptr(f), penal, ptr(dc), ptr(d_compliance),
                                 stream_ptr(stream)))
+
+
+def to_sensitivity_noalloc(plan, dtype, xphys, u, f, penal, dc, d_compliance, stream=None):
+    check(load().to_sensitivity_noalloc(plan, dtype, ptr(xphys), ptr(u), ptr(f), penal, ptr(dc),
+                                        ptr(d_compliance), stream_ptr(stream)))
 
 
 def to_oc_update(plan, dtype, x, dc, dv, volfrac, move, d_stats, stream=None):

@@ -183,6 +183,14 @@ to_status to_sensitivity(const to_plan* plan, to_dtype dtype, const void* xphys,
     TO_GUARD(launch_sensitivity(P(plan), dtype, xphys, u, f, penal, dc, d_compliance, S(stream)));
 }
 
+to_status to_sensitivity_noalloc(const to_plan* plan, to_dtype dtype, const void* xphys, const double* u,
+                                 const double* f, double penal, void* dc, double* d_compliance, void* stream) {
+    NEED(plan, "plan");
+    if (check_dtype(dtype)) return TO_EINVAL;
+    NEED(xphys, "xphys"); NEED(u, "u"); NEED(dc, "dc");
+    TO_GUARD(launch_sensitivity_noalloc(P(plan), dtype, xphys, u, f, penal, dc, d_compliance, S(stream)));
+}
+
 to_status to_oc_update(const to_plan* plan, to_dtype dtype, void* x, const void* dc, const void* dv, double volfrac,
                        double move, to_oc_stats* d_stats, void* stream) {
     NEED(plan, "plan");

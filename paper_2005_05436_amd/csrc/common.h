@@ -510,6 +510,8 @@ to_status launch_solve(Plan* p, to_dtype dt, const void* kval, const void* xphys
                        hipStream_t s);
 to_status launch_sensitivity(Plan* p, to_dtype dt, const void* xphys, const double* u,
                              const double* f, double penal, void* dc, double* c, hipStream_t s);
+to_status launch_sensitivity_noalloc(Plan* p, to_dtype dt, const void* xphys, const double* u,
+                                     const double* f, double penal, void* dc, double* c, hipStream_t s);
 to_status launch_init_state(Plan* p, to_dtype dt, double volfrac, void* x, void* xphys, void* xold, void* dv,
                             double* u, hipStream_t s);
 to_status launch_oc(Plan* p, to_dtype dt, void* x, const void* dc, const void* dv, double volfrac,

@@ -6,6 +6,8 @@
 // grid, corner order of Fig. 1b), u_e is gathered in FP64 (adjacent threads
 // read adjacent nodes), and Ke (d x d, FP64) is read with wave-uniform
 // indices, i.e. through the scalar cache.
+#include <mutex>
+
 #include "common.h"
 
 namespace topt {
@@ -14,6 +16,10 @@ namespace topt {
 // arrival counter and kDotGroups group counters on separate cache lines
 // (clear of the grid barrier's words).
 constexpr int kDotTop = 8, kDotGroup0 = 576, kDotGroupStride = 16, kDotGroups = 16;
+// Blocks of a launch with the compliance sum, and the counter words it uses.
+constexpr int kSensMaxBlocks = 1024;
+constexpr int kSensBarWords = kDotGroup0 + kDotGroupStride * kDotGroups;
+constexpr int kMaxDevices = 64;
 
 // With f given, the same launch also sums c = f^T u: block partials, a
 // two-level arrival (group counters, then the top counter, so no more than
@@ -93,38 +99,104 @@ __global__ __launch_bounds__(kBlock) void sensitivity_kernel(int nx, int ny, int
     }
 }
 
-to_status launch_sensitivity(Plan* p, to_dtype dt, const void* xphys, const double* u, const double* f,
-                             double penal, void* dc, double* c, hipStream_t s) {
-    const int64_t m = p->info.m, n = p->info.n;
+// The launch itself, with the scratch (block partials, arrival counters)
+// passed in: the plan's own region, or the per-device static array below.
+// Blocks of the launch: with the compliance sum at most kSensMaxBlocks (64
+// arrivals per group counter, one partial per block).
+static int sens_blocks(const Plan* p, bool dot) {
+    const int64_t work = dot ? std::max(p->info.m, p->info.n) : p->info.m;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(dot ? kSensMaxBlocks : 8192, (work + kBlock - 1) / kBlock));
+}
+
+static to_status sensitivity_enqueue(Plan* p, to_dtype dt, const void* xphys, const double* u, const double* f,
+                                     double penal, void* dc, double* c, double* part, unsigned* bar, hipStream_t s) {
+    const int64_t n = p->info.n;
     const bool dot = f && c;
-    // with the compliance sum: at most 1024 blocks (64 arrivals per group
-    // counter); partial slots in the second region of the partial buffer
-    const int64_t work = dot ? std::max(m, n) : m;
-    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(dot ? 1024 : 8192, (work + kBlock - 1) / kBlock));
-    double* part = p->partial + (size_t)kMaxCoopBlocks * kPartialWidth;
+    const int blocks = sens_blocks(p, dot);
     const double* fd = dot ? f : nullptr;
     const int nz = p->dim == 2 ? 1 : p->nelz;
     if (p->dim == 2) {
         if (dt == TO_F64)
             hipLaunchKernelGGL((sensitivity_kernel<2, double>), dim3(blocks), dim3(kBlock), 0, s, p->nelx, p->nely, nz,
                                (const double*)xphys, p->passive, u, p->kf64, penal, p->E0, p->Emin, (double*)dc, fd,
-                               n, part, p->bar, c);
+                               n, part, bar, c);
         else
             hipLaunchKernelGGL((sensitivity_kernel<2, float>), dim3(blocks), dim3(kBlock), 0, s, p->nelx, p->nely, nz,
                                (const float*)xphys, p->passive, u, p->kf64, penal, p->E0, p->Emin, (float*)dc, fd,
-                               n, part, p->bar, c);
+                               n, part, bar, c);
     } else {
         if (dt == TO_F64)
             hipLaunchKernelGGL((sensitivity_kernel<3, double>), dim3(blocks), dim3(kBlock), 0, s, p->nelx, p->nely, nz,
                                (const double*)xphys, p->passive, u, p->kf64, penal, p->E0, p->Emin, (double*)dc, fd,
-                               n, part, p->bar, c);
+                               n, part, bar, c);
         else
             hipLaunchKernelGGL((sensitivity_kernel<3, float>), dim3(blocks), dim3(kBlock), 0, s, p->nelx, p->nely, nz,
                                (const float*)xphys, p->passive, u, p->kf64, penal, p->E0, p->Emin, (float*)dc, fd,
-                               n, part, p->bar, c);
+                               n, part, bar, c);
     }
     TO_HIP(hipGetLastError());
     return TO_OK;
+}
+
+to_status launch_sensitivity(Plan* p, to_dtype dt, const void* xphys, const double* u, const double* f,
+                             double penal, void* dc, double* c, hipStream_t s) {
+    // partial slots in the second region of the plan's partial buffer
+    double* part = p->partial + (size_t)kMaxCoopBlocks * kPartialWidth;
+    return sensitivity_enqueue(p, dt, xphys, u, f, penal, dc, c, part, p->bar, s);
+}
+
+// --- allocation-free variant ---------------------------------------------------
+// Scratch of to_sensitivity_noalloc: kSensMaxBlocks block partials (FP64)
+// followed by kSensBarWords arrival-counter words.  A file-scope device array
+// exists once per device for the life of the process; host code must not pass
+// its name to a kernel (on the host the name is only a stand-in): the device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kScratchPartBytes = sizeof(double) * kSensMaxBlocks;
+constexpr size_t kScratchBytes = kScratchPartBytes + sizeof(unsigned) * kSensBarWords;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Zeroes the arrival counters (the last block of a call leaves them at zero,
+// but a call that never ran to its end would not).  A kernel rather than a
+// memset, so the call stays capturable.
+__global__ void sens_scratch_clear_kernel(unsigned* bar) {
+    for (int i = threadIdx.x; i < kSensBarWords; i += blockDim.x) bar[i] = 0u;
+}
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+to_status launch_sensitivity_noalloc(Plan* p, to_dtype dt, const void* xphys, const double* u, const double* f,
+                                     double penal, void* dc, double* c, hipStream_t s) {
+    int dev = -1;
+    TO_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("to_sensitivity_noalloc: device ordinal out of range");
+        return TO_EINVAL;
+    }
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void* q = nullptr;
+            hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+            g_scratch_ptr[dev] = q;
+        }
+        base = g_scratch_ptr[dev];
+    }
+    // one FP64 partial per block of the launch; the launch clamps its grid,
+    // so any mesh fits, and this guards the bound if either side changes
+    if ((f && c) && (size_t)sens_blocks(p, true) * sizeof(double) > kScratchPartBytes) {
+        set_error("to_sensitivity_noalloc: the launch needs more block partials than the static scratch holds");
+        return TO_EINVAL;
+    }
+    double* part = reinterpret_cast<double*>(base);
+    unsigned* bar = reinterpret_cast<unsigned*>(reinterpret_cast<unsigned char*>(base) + kScratchPartBytes);
+    if (f && c) {
+        hipLaunchKernelGGL(sens_scratch_clear_kernel, dim3(1), dim3(kBlock), 0, s, bar);
+        TO_HIP(hipGetLastError());
+    }
+    return sensitivity_enqueue(p, dt, xphys, u, f, penal, dc, c, part, bar, s);
 }
 
 }  // namespace topt

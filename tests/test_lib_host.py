@@ -197,3 +197,4 @@ def test_new_entry_points_validate_before_launching(lib):
     assert lib.to_oc_update_filtered(None, L.TO_F64, 2, None, None, None, 0.5, 0.2, 2.0, None, st, None) == L.TO_EINVAL
     assert b"plan" in lib.to_last_error()
     assert lib.to_init_state(None, L.TO_F64, 0.5, None, None, None, None, None, None) == L.TO_EINVAL
+    assert lib.to_sensitivity_noalloc(None, L.TO_F64, None, None, None, 3.0, None, None, None) == L.TO_EINVAL
