@@ -484,8 +484,9 @@ typedef struct {
                                     streams run kernels on the device at the same time) */
     int32_t asm_rows;            /* assembly kernel: 0 = segmented sum over the permutation of I_r,
                                     1 = one thread per slot, the row from row_ptr and the contributing
-                                    elements from the grid (same terms in the same order: identical
-                                    values) */
+                                    elements from the grid, 2 = (2D) one thread per node, its two rows
+                                    from the moduli of the elements around it (3D meshes take 0); the
+                                    same terms in the same order: identical values */
 } to_tuning;
 to_status to_plan_autotune(to_plan* plan, to_dtype dtype, void* kval, to_tuning* h_out, void* stream);
 to_status to_plan_set_tuning(to_plan* plan, const to_tuning* h_tuning);

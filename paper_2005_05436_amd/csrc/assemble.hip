@@ -147,6 +147,91 @@ __global__ __launch_bounds__(NT) void assemble_grid_kernel(int nelx, int nely, i
     }
 }
 
+// 2D, one thread per node: the node's two rows of K^(s) (up to 9 + 10
+// slots) from the moduli of the (up to four) elements around it.  Row 2n
+// holds the columns of the lower neighbours (iy-1, ix-1), (iy, ix-1),
+// (iy+1, ix-1), (iy-1, ix) (both components each) and 2n itself; row 2n+1
+// the same and 2n+1: the plan's ascending column order.  A slot's value
+// sums, over the elements holding both nodes in ascending element index,
+// Ke at the lower-triangle position of the local pair times E, so it equals
+// the segmented sum bit for bit.  Every index is resolved at compile time
+// except the boundary tests.  The values of a block's nodes are gathered in
+// LDS and written out as one contiguous, coalesced stretch of kval (a
+// block's nodes are consecutive, so their rows are).
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void assemble_node2d_kernel(int nelx, int nely, int64_t nnode,
+                                                              const int32_t* __restrict__ rp,
+                                                              const T* __restrict__ ke, const T* __restrict__ E,
+                                                              T* __restrict__ kval) {
+    constexpr int D = 8;
+    __shared__ T ke_s[36];
+    __shared__ T out_s[NT * 19];
+    for (int i = threadIdx.x; i < 36; i += NT) ke_s[i] = ke[i];
+    const int ny1 = nely + 1;
+    for (int64_t n0 = blockIdx.x * (int64_t)NT; n0 < nnode; n0 += (int64_t)gridDim.x * NT) {
+        const int64_t nend = n0 + NT < nnode ? n0 + NT : nnode;
+        const int64_t nd = n0 + threadIdx.x;
+        __syncthreads();   // ke_s written; the previous stretch written out
+        const int32_t base = rp[2 * n0], top = rp[2 * nend];
+        if (nd < nend) {
+            const int ix = (int)((uint32_t)nd / (uint32_t)ny1), iy = (int)nd - ix * ny1;
+            // moduli of the elements (iy - 1 + ay, ix - 1 + bx), ay, bx in {0, 1}
+            T Ev[2][2];
+            bool ok[2][2];
+#pragma unroll
+            for (int ay = 0; ay < 2; ++ay)
+#pragma unroll
+                for (int bx = 0; bx < 2; ++bx) {
+                    const int ey = iy - 1 + ay, ex = ix - 1 + bx;
+                    ok[ay][bx] = ey >= 0 && ey < nely && ex >= 0 && ex < nelx;
+                    Ev[ay][bx] = ok[ay][bx] ? E[ey + (int64_t)nely * ex] : T(0);
+                }
+            int pos = rp[2 * nd] - base;
+#pragma unroll
+            for (int cr = 0; cr < 2; ++cr)
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    // lower neighbour q at offset (a, b) in (y, x), ascending node index
+                    const int a = q < 3 ? q - 1 : q - 4, b = q < 3 ? -1 : 0;
+                    if (iy + a < 0 || iy + a > nely || ix + b < 0) continue;
+#pragma unroll
+                    for (int cc = 0; cc < 2; ++cc) {
+                        if (q == 4 && cc > cr) continue;          // upper triangle of the diagonal block
+                        T acc = T(0);
+                        // shared elements, ascending element index: x outer, then y
+#pragma unroll
+                        for (int bx = 0; bx < 2; ++bx) {
+                            if (b == -1 && bx == 1) continue;
+#pragma unroll
+                            for (int ay = 0; ay < 2; ++ay) {
+                                if ((a == -1 && ay == 1) || (a == 1 && ay == 0)) continue;
+                                if (!ok[ay][bx]) continue;
+                                const int dyr = 1 - ay, dxr = 1 - bx;              // this node in the element
+                                const int dyc = 1 - ay + a, dxc = 1 - bx + b;      // the neighbour
+                                const int br = dyr ? dxr : 3 - dxr, bc = dyc ? dxc : 3 - dxc;
+                                const int la = 2 * br + cr, lb = 2 * bc + cc;
+                                const int j = la < lb ? la : lb, i = la < lb ? lb : la;
+                                const int k = j * D - ((j * (j - 1)) >> 1) + (i - j);
+                                acc += ke_s[k] * Ev[ay][bx];
+                            }
+                        }
+                        out_s[pos++] = acc;
+                    }
+                }
+        }
+        __syncthreads();
+        for (int32_t i = (int32_t)threadIdx.x; i < top - base; i += NT) kval[base + i] = out_s[i];
+    }
+}
+
+template <typename T, int NT>
+static void assemble_node2d_nt(Plan* p, const T* ke, const T* E, T* kval, hipStream_t s) {
+    const int64_t nn = p->info.nnode;
+    const int blocks = (int)std::min<int64_t>(1 << 16, (nn + NT - 1) / NT);
+    hipLaunchKernelGGL((assemble_node2d_kernel<T, NT>), dim3(blocks), dim3(NT), 0, s, p->nelx, p->nely, nn,
+                       p->row_ptr, ke, E, kval);
+}
+
 template <typename T, int DIM, int NT>
 static void assemble_grid_nt(Plan* p, const T* ke, const T* E, T* kval, hipStream_t s) {
     constexpr int RB = NT / (DIM == 2 ? 8 : 32);
@@ -165,6 +250,14 @@ static void assemble_nt(Plan* p, int64_t nnz, const T* ke, const T* E, T* kval, 
 template <typename T, int DT>
 static void assemble_t(Plan* p, int64_t nnz, const T* ke, const T* E, T* kval, hipStream_t s) {
     constexpr int DIM = DT == 36 ? 2 : 3;
+    if (DIM == 2 && p->tune.asm_rows == 2) {
+        switch (p->tune.asm_block) {
+        case 128: assemble_node2d_nt<T, 128>(p, ke, E, kval, s); break;
+        case 512: assemble_node2d_nt<T, 512>(p, ke, E, kval, s); break;
+        default: assemble_node2d_nt<T, 256>(p, ke, E, kval, s); break;
+        }
+        return;
+    }
     if (p->tune.asm_rows) {
         switch (p->tune.asm_block) {
         case 128: assemble_grid_nt<T, DIM, 128>(p, ke, E, kval, s); break;

@@ -217,7 +217,7 @@ to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuni
             if (st != TO_OK) continue;          // e.g. the tile does not fit in LDS
             if (t < tbest) { tbest = t; best.filt_v = c.v; best.filt_parts = c.parts; }
         }
-        if (dt == TO_F32) {                  // the matrix-core tiles (same columns and waves otherwise)
+        {                                    // the matrix-core tiles (same columns and waves otherwise)
             p->tune.filt_v = best.filt_v;
             p->tune.filt_parts = best.filt_parts;
             for (int shape = 1; shape <= 4; ++shape) {
@@ -244,7 +244,7 @@ to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuni
             if (st != TO_OK) continue;
             if (t < tbest) { tbest = t; best.filt_parts2 = parts; }
         }
-        if (dt == TO_F32) {
+        {
             p->tune.filt_parts2 = best.filt_parts2;
             for (int shape = 1; shape <= 4; ++shape) {
                 p->tune.filt_mfma2 = shape;
@@ -260,8 +260,9 @@ to_status plan_autotune(Plan* p, to_dtype dt, void* kval, hipStream_t s, to_tuni
     }
     if (kval) {
         float tbest = 1e30f;
-        for (int rows : {0, 1})
+        for (int rows : {0, 1, 2})
             for (int nt : {128, 256, 512}) {
+                if (rows == 2 && p->dim != 2) continue;
                 p->tune.asm_rows = rows;
                 p->tune.asm_block = nt;
                 to_status st = TO_OK;
@@ -317,10 +318,10 @@ to_status to_plan_set_tuning(to_plan* plan, const to_tuning* t) {
     if (!plan || !t) { set_error("to_plan_set_tuning: NULL argument"); return TO_EINVAL; }
     if ((t->filt_v != 4 && t->filt_v != 8) || t->filt_parts < 0 || t->filt_parts > 16 || t->filt_parts2 < 0 ||
         t->filt_parts2 > 16 || t->filt_mfma < 0 || t->filt_mfma > 4 || t->filt_mfma2 < 0 || t->filt_mfma2 > 4 ||
-        (t->coop_launch != 0 && t->coop_launch != 1) || (t->asm_rows != 0 && t->asm_rows != 1) ||
+        (t->coop_launch != 0 && t->coop_launch != 1) || (t->asm_rows < 0 || t->asm_rows > 2) ||
         (t->asm_block != 128 && t->asm_block != 256 && t->asm_block != 512)) {
         set_error("to_plan_set_tuning: filt_v must be 4 or 8, filt_parts 0..16, filt_mfma 0..4, coop_launch 0 or 1, "
-                  "asm_rows 0 or 1, asm_block 128, 256 or 512");
+                  "asm_rows 0, 1 or 2, asm_block 128, 256 or 512");
         return TO_EINVAL;
     }
     Plan* p = topt::P(plan);
@@ -461,7 +462,7 @@ to_status to_batch_create(to_plan* const* plans, int32_t count, to_dtype dtype, 
             // solve work goes as (nodes)^1.5
             wn[i] = std::pow((double)p->info.nnode, 1.5);
             cap_p[i] = (int)std::min<int64_t>(num_cu, (p->info.m + kBigBlock - 1) / kBigBlock);
-            cap_o[i] = (int)std::min<int64_t>(1024, (p->info.m + 511) / 512);
+            cap_o[i] = (int)std::min<int64_t>(512, (p->info.m + 511) / 512);
             const int sb = solve_block_size(b.dim, b.mode);
             cap_s[i] = (int)std::min<int64_t>(kMaxCoopBlocks, (p->info.nnode + sb - 1) / sb);
         }

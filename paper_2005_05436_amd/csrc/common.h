@@ -114,6 +114,7 @@ struct Plan {
     double* hp64 = nullptr;  float* hp32 = nullptr;      // 2D: row dy of non-zero taps, zero padded
     int hp_stride = 0;
     float* hm32 = nullptr;                               // 2D: column dx of h, 16 zeros before, 19+ after
+    double* hm64 = nullptr;                              // the same in FP64
     int hm_stride = 0;
     double* Hs64 = nullptr;  float* Hs32 = nullptr;      // m
     // scratch (device)

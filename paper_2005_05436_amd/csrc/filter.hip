@@ -93,8 +93,14 @@ __device__ __forceinline__ void filt_chunk(const T* __restrict__ hrow, int k, co
 // LS: the LDS column stride when known at compile time (0: 64 + 2R at run
 // time); a compile-time stride turns the V column reads of a chunk into one
 // base address with immediate offsets.
+// At most 16 waves per block in FP32; in FP64 at most 8, so the launch bound
+// leaves 256 registers per lane (the ring, the weights and the accumulators
+// of FP64 values take twice the registers).
+template <typename T>
+constexpr int filt_max_parts() { return sizeof(T) == 8 ? 8 : kFiltMaxParts; }
+
 template <typename T, int MODE, int V, int LS>
-__global__ __launch_bounds__(64 * kFiltMaxParts) void filter2d_kernel(
+__global__ __launch_bounds__(64 * filt_max_parts<T>()) void filter2d_kernel(
     int nely, int nelx, int R, char bc, const T* __restrict__ hp, int hps, const int32_t* __restrict__ hlim,
     const T* __restrict__ Hs, const T* __restrict__ in, const T* __restrict__ in2,
     const T* __restrict__ sc, T* __restrict__ out, T* __restrict__ out2, unsigned* ctr, const unsigned* skip,
@@ -229,12 +235,12 @@ __global__ __launch_bounds__(64 * kFiltMaxParts) void filter2d_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// 2D, FP32, on the matrix cores.  For one tap column dx the cone filter acts
+// 2D, on the matrix cores (FP32 or FP64).  For one tap column dx the cone filter acts
 // along y as a banded Toeplitz matrix: out[y0+i][x] += sum_t h(dx, t-i)
 // in[y0+t][x+dx].  For 16 output rows and 16 output columns that is a
 // (16 x K) band block of weights times a (K x 16) block of the staged
 // window, K = 16 + 2 lim(dx) rounded up to 4, which v_mfma_f32_16x16x4_f32
-// takes four rows of K at a time (about 80% of the products are non-zero
+// (v_mfma_f64_16x16x4_f64 for FP64 fields) takes four rows of K at a time (about 80% of the products are non-zero
 // taps at large radii).  Operand lanes: A[i][k] in lane i + 16k, B[k][j] in
 // lane j + 16k, D[4q+r][j] in register r of lane j + 16q.  Lane group k takes
 // the contiguous rows k S .. k S + S - 1 of K (S = K / 4), so the weight of
@@ -247,13 +253,29 @@ __global__ __launch_bounds__(64 * kFiltMaxParts) void filter2d_kernel(
 // register feeds NB products) and the tap columns dx = w / MT (mod 8 / MT);
 // the parts are added in LDS.  Tiles are claimed like the stencil kernel's.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kFmUnroll = 4;           // MFMA steps whose operand reads issue together
 
-template <int MODE, int MT, int NB>
+// The 16 x 16 x 4 products in FP32 and FP64: the same operand layout
+// (A[i][k] in lane i + 16k, B[k][j] in lane j + 16k); the results differ:
+// D[4q+r][j] (FP32) and D[q+4r][j] (FP64) in register r of lane j + 16q.
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+    using acc = f32x4;
+    __device__ static acc step(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int q, int r) { return 4 * q + r; }
+};
+template <> struct Mfma<double> {
+    using acc = f64x4;
+    __device__ static acc step(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int q, int r) { return q + 4 * r; }
+};
+
+template <typename T, int MODE, int MT, int NB>
 __global__ __launch_bounds__(512) void filter2d_mfma_kernel(
-    int nely, int nelx, int R, char bc, const float* __restrict__ hm, int hms, const int32_t* __restrict__ hlim,
-    const float* __restrict__ Hs, const float* __restrict__ in, const float* __restrict__ in2,
-    const float* __restrict__ sc, float* __restrict__ out, float* __restrict__ out2, unsigned* ctr,
+    int nely, int nelx, int R, char bc, const T* __restrict__ hm, int hms, const int32_t* __restrict__ hlim,
+    const T* __restrict__ Hs, const T* __restrict__ in, const T* __restrict__ in2,
+    const T* __restrict__ sc, T* __restrict__ out, T* __restrict__ out2, unsigned* ctr,
     const unsigned* skip, int chunk, int wofs) {
     extern __shared__ unsigned char smem_raw[];
     __shared__ int tile_sh;
@@ -261,17 +283,18 @@ __global__ __launch_bounds__(512) void filter2d_mfma_kernel(
     constexpr int NF = MODE == M_ADJ2 ? 2 : 1;
     constexpr int NP = 8 / MT;           // tap-column parts
     constexpr int TY = 16 * MT, TX = 16 * NB;
-    float* tile = reinterpret_cast<float*>(smem_raw);
+    using Acc = typename Mfma<T>::acc;
+    T* tile = reinterpret_cast<T*>(smem_raw);
     const int LY = TY + 2 * R + 3;       // rows y0-R .. y0+TY+R+2 (the last 3 meet zero weights only)
     const int ls = LY | 1;               // odd column stride: the 16 columns of a read fall in distinct banks
     const int LX = TX + 2 * R;
-    float* tile2 = tile + (size_t)ls * LX;
+    T* tile2 = tile + (size_t)ls * LX;
     const int nty = (nely + TY - 1) / TY, ntiles = nty * ((nelx + TX - 1) / TX);
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int mt = w % MT, part = w / MT;
     const int i16 = lane & 15, kq = lane >> 4;
-    float* wtab = tile + wofs;           // the weight columns -R..0 (h is even in dx), for the whole launch
+    T* wtab = tile + wofs;           // the weight columns -R..0 (h is even in dx), for the whole launch
     for (int i = threadIdx.x; i < (R + 1) * hms; i += blockDim.x) wtab[i] = hm[i];
 
     int t = 0, t_end = 0;
@@ -289,7 +312,7 @@ __global__ __launch_bounds__(512) void filter2d_mfma_kernel(
         int ly = (int)threadIdx.x % LY, lx = (int)threadIdx.x / LY;
         for (int i = threadIdx.x; i < LY * LX; i += blockDim.x) {
             int gy = y0 - R + ly, gx = x0 - R + lx;
-            float v = 0.f, v2 = 0.f;
+            T v = T(0), v2 = T(0);
             bool inside = gy >= 0 && gy < nely && gx >= 0 && gx < nelx;
             if (bc == 'N' && !inside) {
                 gy = mirror_idx(gy, nely);
@@ -298,8 +321,8 @@ __global__ __launch_bounds__(512) void filter2d_mfma_kernel(
             }
             if (inside) {
                 const int64_t e = gy + (int64_t)nely * gx;
-                v = staged_value<float>(MODE, in, sc, Hs, e);
-                if (NF == 2) v2 = staged_value<float>(MODE, in2, sc, Hs, e);
+                v = staged_value<T>(MODE, in, sc, Hs, e);
+                if (NF == 2) v2 = staged_value<T>(MODE, in2, sc, Hs, e);
             }
             tile[(size_t)lx * ls + ly] = v;
             if (NF == 2) tile2[(size_t)lx * ls + ly] = v2;
@@ -309,30 +332,28 @@ __global__ __launch_bounds__(512) void filter2d_mfma_kernel(
         }
         __syncthreads();
 
-        f32x4 acc[NF][NB];
+        Acc acc[NF][NB];
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[f][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int nb = 0; nb < NB; ++nb) acc[f][nb] = Acc{T(0), T(0), T(0), T(0)};
         for (int dxi = part; dxi <= 2 * R; dxi += NP) {
             const int lim = hlim[dxi];
             if (lim < 0) continue;
             const int S = (16 + 2 * lim + 3) >> 2;
-            const float* ap = wtab + (size_t)min(dxi, 2 * R - dxi) * hms + (R + 16 - lim) + kq * S - i16;
+            const T* ap = wtab + (size_t)min(dxi, 2 * R - dxi) * hms + (R + 16 - lim) + kq * S - i16;
             const size_t b0 = (size_t)(dxi + i16) * ls + mt * 16 + R - lim + kq * S;
-            const float* bp = tile + b0;
-            const float* bp2 = tile2 + b0;
+            const T* bp = tile + b0;
+            const T* bp2 = tile2 + b0;
             // MFMA is convergent, so the compiler will not unroll a loop of
             // unknown trip count: groups of kFmUnroll steps by hand (their
             // LDS reads issue together), then the rest one by one
             auto step = [&](int s) {
-                const float a = ap[s];
+                const T a = ap[s];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bp[(size_t)nb * 16 * ls + s], acc[0][nb], 0, 0, 0);
-                    if (NF == 2)
-                        acc[NF - 1][nb] =
-                            __builtin_amdgcn_mfma_f32_16x16x4f32(a, bp2[(size_t)nb * 16 * ls + s], acc[NF - 1][nb], 0, 0, 0);
+                    acc[0][nb] = Mfma<T>::step(a, bp[(size_t)nb * 16 * ls + s], acc[0][nb]);
+                    if (NF == 2) acc[NF - 1][nb] = Mfma<T>::step(a, bp2[(size_t)nb * 16 * ls + s], acc[NF - 1][nb]);
                 }
             };
             int s = 0;
@@ -343,19 +364,20 @@ __global__ __launch_bounds__(512) void filter2d_mfma_kernel(
             for (; s < S; ++s) step(s);
         }
         __syncthreads();                 // the window is no longer needed
-        float* red = tile;               // [part][field][column][row], TX x TY per slab
+        T* red = tile;                   // [part][field][column][row], TX x TY per slab
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    red[((size_t)(part * NF + f) * TX + nb * 16 + i16) * TY + mt * 16 + 4 * kq + r] = acc[f][nb][r];
+                    red[((size_t)(part * NF + f) * TX + nb * 16 + i16) * TY + mt * 16 + Mfma<T>::row(kq, r)] =
+                        acc[f][nb][r];
         __syncthreads();
         for (int o = threadIdx.x; o < TY * TX; o += blockDim.x) {
             const int row = o % TY, col = o / TY;
             const int gy = y0 + row, gx = x0 + col;
-            float r0 = 0.f, r1 = 0.f;
+            T r0 = T(0), r1 = T(0);
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
                 r0 += red[((size_t)(q * NF) * TX + col) * TY + row];
@@ -463,9 +485,10 @@ static to_status run_filter2d_ls(Plan* p, const T* hp, const T* Hs, const T* in,
     const int W = 2 * R + 1;
     // waves per block: at least V (wave q finishes output column q); by
     // default 16 when there are enough tap rows to split, else V
-    int parts = W >= 16 ? kFiltMaxParts : V;
+    constexpr int maxp = filt_max_parts<T>();
+    int parts = W >= 16 ? maxp : V;
     const int ptune = NF == 2 ? p->tune.filt_parts2 : p->tune.filt_parts;
-    if (ptune > 0) parts = std::max(V, std::min(kFiltMaxParts, ptune));
+    if (ptune > 0) parts = std::max(V, std::min(maxp, ptune));
     const int ls = LS ? LS : 64 + 2 * R;
     size_t lds = (size_t)NF * ls * (V + 2 * R + V) * sizeof(T);
     lds = std::max(lds, (size_t)parts * NF * V * 64 * sizeof(T));   // partial-sum reuse
@@ -501,25 +524,27 @@ static to_status run_filter2d(Plan* p, const T* hp, const T* Hs, const T* in, co
 }
 
 // LDS bytes of the matrix-core kernel's tile shape (window or partial sums)
-static size_t mfma_lds(int R, int NF, int MT, int NB) {
+static size_t mfma_lds(int R, int NF, int MT, int NB, size_t tsz) {
     const int TY = 16 * MT, TX = 16 * NB;
-    const size_t win = (size_t)NF * ((TY + 2 * R + 3) | 1) * (TX + 2 * R) * sizeof(float);
-    const size_t red = (size_t)(8 / MT) * NF * TY * TX * sizeof(float);
+    const size_t win = (size_t)NF * ((TY + 2 * R + 3) | 1) * (TX + 2 * R) * tsz;
+    const size_t red = (size_t)(8 / MT) * NF * TY * TX * tsz;
     return std::max(win, red);
 }
 
-template <int MODE, int MT, int NB>
-static to_status run_filter2d_mfma_shape(Plan* p, const float* Hs, const float* in, const float* in2,
-                                         const float* sc, float* out, float* out2, hipStream_t s) {
+template <typename T, int MODE, int MT, int NB>
+static to_status run_filter2d_mfma_shape(Plan* p, const T* Hs, const T* in, const T* in2,
+                                         const T* sc, T* out, T* out2, hipStream_t s) {
     constexpr int NF = MODE == M_ADJ2 ? 2 : 1;
     const int R = p->R;
-    const size_t lds0 = mfma_lds(R, NF, MT, NB);
-    const size_t lds = lds0 + (size_t)(R + 1) * p->hm_stride * sizeof(float);   // + the weight table
+    const size_t lds0 = mfma_lds(R, NF, MT, NB, sizeof(T));
+    const size_t lds = lds0 + (size_t)(R + 1) * p->hm_stride * sizeof(T);   // + the weight table
     if (lds > 160 * 1024 - 256) {        // the block also holds a few static words
         set_error("filter radius too large for the matrix-core tile");
         return TO_EUNSUPPORTED;
     }
-    auto k = filter2d_mfma_kernel<MODE, MT, NB>;
+    auto k = filter2d_mfma_kernel<T, MODE, MT, NB>;
+    const T* hm;
+    if constexpr (sizeof(T) == 8) hm = p->hm64; else hm = p->hm32;
     TO_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, 512, lds) != hipSuccess || per_cu < 1)
@@ -527,21 +552,21 @@ static to_status run_filter2d_mfma_shape(Plan* p, const float* Hs, const float* 
     const int ntiles = ((p->nely + 16 * MT - 1) / (16 * MT)) * ((p->nelx + 16 * NB - 1) / (16 * NB));
     const int blocks = std::max(1, std::min(ntiles, per_cu * p->num_cu));
     const int chunk = std::max(1, ntiles / (blocks * 4));
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(512), lds, s, p->nely, p->nelx, R, p->bc, p->hm32, p->hm_stride,
-                       p->hlim, Hs, in, in2, sc, out, out2, p->bar + 16, p->filt_skip, chunk, (int)(lds0 / sizeof(float)));
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(512), lds, s, p->nely, p->nelx, R, p->bc, hm, p->hm_stride,
+                       p->hlim, Hs, in, in2, sc, out, out2, p->bar + 16, p->filt_skip, chunk, (int)(lds0 / sizeof(T)));
     TO_HIP(hipGetLastError());
     return TO_OK;
 }
 
 // shape 1: 32 x 64 tiles, 2: 16 x 64, 3: 32 x 32, 4: 16 x 32
-template <int MODE>
-static to_status run_filter2d_mfma(Plan* p, int shape, const float* Hs, const float* in, const float* in2,
-                                   const float* sc, float* out, float* out2, hipStream_t s) {
+template <typename T, int MODE>
+static to_status run_filter2d_mfma(Plan* p, int shape, const T* Hs, const T* in, const T* in2,
+                                   const T* sc, T* out, T* out2, hipStream_t s) {
     switch (shape) {
-    case 1: return run_filter2d_mfma_shape<MODE, 2, 4>(p, Hs, in, in2, sc, out, out2, s);
-    case 2: return run_filter2d_mfma_shape<MODE, 1, 4>(p, Hs, in, in2, sc, out, out2, s);
-    case 3: return run_filter2d_mfma_shape<MODE, 2, 2>(p, Hs, in, in2, sc, out, out2, s);
-    default: return run_filter2d_mfma_shape<MODE, 1, 2>(p, Hs, in, in2, sc, out, out2, s);
+    case 1: return run_filter2d_mfma_shape<T, MODE, 2, 4>(p, Hs, in, in2, sc, out, out2, s);
+    case 2: return run_filter2d_mfma_shape<T, MODE, 1, 4>(p, Hs, in, in2, sc, out, out2, s);
+    case 3: return run_filter2d_mfma_shape<T, MODE, 2, 2>(p, Hs, in, in2, sc, out, out2, s);
+    default: return run_filter2d_mfma_shape<T, MODE, 1, 2>(p, Hs, in, in2, sc, out, out2, s);
     }
 }
 
@@ -552,10 +577,10 @@ static to_status run_filter(Plan* p, const T* h, const T* hp, const T* Hs, const
     const int R = p->R;
     const size_t lds_max = 160 * 1024;
     if (p->dim == 2) {
-        if constexpr (std::is_same<T, float>::value && MODE != M_RAW) {
+        if constexpr (MODE != M_RAW) {
             const int shape = NF == 2 ? p->tune.filt_mfma2 : p->tune.filt_mfma;
             if (shape > 0) {
-                const to_status st = run_filter2d_mfma<MODE>(p, shape, Hs, in, in2, sc, out, out2, s);
+                const to_status st = run_filter2d_mfma<T, MODE>(p, shape, Hs, in, in2, sc, out, out2, s);
                 if (st != TO_EUNSUPPORTED) return st;   // else the tile does not fit: the stencil kernel below
             }
         }

@@ -24,8 +24,8 @@
 
 namespace topt {
 
-constexpr int kLevels = 4;
-constexpr int kCand = (1 << kLevels) - 1;   // 15 midpoints per sweep
+constexpr int kLevels = 5;
+constexpr int kCand = (1 << kLevels) - 1;   // 31 midpoints per sweep
 
 __device__ __forceinline__ double oc_clamp(double ocp, double lm, double x, double move) {
     // max(max(min(min(ocP/lmid, xU), 1), xL), 0) with xU = x + move, xL = x - move
@@ -80,9 +80,36 @@ __device__ __forceinline__ dd wave_dd_sum16(const dd (&v)[16], int lane) {
     return dd_add(u, dd_xor(u, 1));
 }
 
+// Wave sums of 32 FP64 values at once by the same halving butterfly (lane
+// bits 5, 4, 3, 2, 1 halve the set, bit 0 sums the last value): 32
+// cross-lane exchanges instead of 32 x 6.  Lane 2 j ends with the sum of
+// value j.  The order of the additions is fixed.
+__device__ __forceinline__ double f64_sel(bool c, double a, double b) { return c ? a : b; }
+__device__ __forceinline__ double wave_sum32(const double (&v)[32], int lane) {
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
+    double u1[16], u2[8], u3[4], u4[2];
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        u1[j] = f64_sel(b5, v[16 + j], v[j]) + __shfl_xor(f64_sel(b5, v[j], v[16 + j]), 32, 64);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        u2[j] = f64_sel(b4, u1[8 + j], u1[j]) + __shfl_xor(f64_sel(b4, u1[j], u1[8 + j]), 16, 64);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        u3[j] = f64_sel(b3, u2[4 + j], u2[j]) + __shfl_xor(f64_sel(b3, u2[j], u2[4 + j]), 8, 64);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+        u4[j] = f64_sel(b2, u3[2 + j], u3[j]) + __shfl_xor(f64_sel(b2, u3[j], u3[2 + j]), 4, 64);
+    double u = f64_sel(b1, u4[1], u4[0]) + __shfl_xor(f64_sel(b1, u4[0], u4[1]), 2, 64);
+    return u + __shfl_xor(u, 1, 64);
+}
+
 constexpr int kOcBlock = 512;
+constexpr int kMaxOcBlocks = 512;          // blocks of one design's OC launch (the grid sums gather this many)
 // value-major partials (2 words per value, kMaxCoopBlocks blocks each) fit a partial region
-static_assert(2 * kCand <= kPartialWidth, "OC partials exceed a partial region");   // 15 double-double accumulators per lane need the register room
+// value-major partials: 31 FP64 values (the candidate sweeps) or 3 double-double
+// values (the first sweep) per block fit a partial region
+static_assert(kCand <= kPartialWidth && 6 <= kPartialWidth, "OC partials exceed a partial region");
 
 template <typename T>
 struct OcArgs {
@@ -107,6 +134,7 @@ __device__ void oc_body(const OcArgs<T>& A, int bid, int nb) {
     __shared__ double wsum[NW * kCand * 2];
     __shared__ double gsum[NB * 2];
     __shared__ double tot[2 * kCand];
+    __shared__ double smid[kCand], srmid[kCand];
     const int64_t m = A.m;
     const uint8_t* __restrict__ pas = A.pas;
     T* __restrict__ x = A.x;
@@ -165,7 +193,7 @@ __device__ void oc_body(const OcArgs<T>& A, int bid, int nb) {
             const int k = threadIdx.x / S, j = threadIdx.x % S;
             // all loads issued before the (dependent) additions: one memory
             // latency instead of one per block (at most kMaxPer blocks each)
-            constexpr int kMaxPer = 32;
+            constexpr int kMaxPer = (kMaxOcBlocks + S - 1) / S;
             double hv[kMaxPer], lv[kMaxPer];
 #pragma unroll
             for (int q = 0; q < kMaxPer; ++q) {
@@ -192,6 +220,52 @@ __device__ void oc_body(const OcArgs<T>& A, int bid, int nb) {
             for (int j = 1; j < jn; ++j) b = dd_add(b, dd{gsum[(k * S + j) * 2], gsum[(k * S + j) * 2 + 1]});
             tot[2 * k] = b.hi;
             tot[2 * k + 1] = b.lo;
+        }
+        __syncthreads();
+    };
+
+    // The same for K plain FP64 values (the candidate volumes): each wave
+    // reduces 32 values with the halving butterfly, thread k adds the waves'
+    // sums of value k in wave order; the grid sum is ordered as in grid_dd.
+    auto block_f64 = [&](const double (&v)[32], double* reg) {
+        const double sw = wave_sum32(v, lane);
+        const int k = lane >> 1;
+        if ((lane & 1) == 0 && k < kCand) wsum[w * kCand + k] = sw;
+        __syncthreads();
+        if (threadIdx.x < kCand) {
+            const int k2 = threadIdx.x;
+            double b = wsum[k2];
+            for (int i = 1; i < NW; ++i) b += wsum[i * kCand + k2];
+            st_dev(&reg[(size_t)k2 * kMaxCoopBlocks + bid], b);
+        }
+        __syncthreads();
+    };
+    auto grid_f64 = [&](const double* reg) {
+        constexpr int K = kCand;
+        constexpr int S = NB / K;
+        if (threadIdx.x < K * S) {
+            const int k = threadIdx.x / S, j = threadIdx.x % S;
+            constexpr int kMaxPer = (kMaxOcBlocks + S - 1) / S;
+            double hv[kMaxPer];
+#pragma unroll
+            for (int q = 0; q < kMaxPer; ++q) {
+                const int b = j + q * S;
+                hv[q] = b < nb ? ld_dev(&reg[(size_t)k * kMaxCoopBlocks + b]) : 0.0;
+            }
+            const int qn = j < nb ? (nb - j + S - 1) / S : 0;
+            double a = 0.0;
+#pragma unroll
+            for (int q = 0; q < kMaxPer; ++q)
+                if (q < qn) a += hv[q];
+            gsum[k * S + j] = a;
+        }
+        __syncthreads();
+        if (threadIdx.x < K) {
+            const int k = threadIdx.x;
+            double b = gsum[k * S];
+            const int jn = nb < S ? nb : S;
+            for (int j = 1; j < jn; ++j) b += gsum[k * S + j];
+            tot[k] = b;
         }
         __syncthreads();
     };
@@ -275,45 +349,88 @@ __device__ void oc_body(const OcArgs<T>& A, int bid, int nb) {
     const int cap = 200;
     auto more = [&]() { return (l1 + l2) > 0.0 && (l2 - l1) / (l2 + l1) > 1e-4 && n_bs < cap; };
 
+    // Rounding-error bound of the FP64 candidate sums: every term (x >= 0)
+    // passes through at most d additions (its thread's elements, the wave
+    // butterfly, the block's waves, the grid gather and the final
+    // combination), so |sum - exact| <= d u exact / (1 - d u) <= err * sum.
+    const int64_t per_thread = (m + stride - 1) / stride;
+    const double err = (double)(per_thread + 6 + NW + (kMaxOcBlocks + NB / kCand - 1) / (NB / kCand) + NB / kCand + 4) *
+                       0x1p-53 * (1.0 + 0x1p-20);
     while (alive && more()) {
-        // candidate brackets of the next four levels (node j: children 2j+1 = "l1 = mid", 2j+2 = "l2 = mid")
-        double lo[kCand], hi[kCand], mid[kCand];
-        lo[0] = l1; hi[0] = l2;
-#pragma unroll
-        for (int j = 0; j < kCand; ++j) {
-            mid[j] = 0.5 * (lo[j] + hi[j]);
-            if (2 * j + 2 < kCand) {
-                lo[2 * j + 1] = mid[j]; hi[2 * j + 1] = hi[j];
-                lo[2 * j + 2] = lo[j];  hi[2 * j + 2] = mid[j];
+        // candidate brackets of the next five levels (node j: children
+        // 2j+1 = "l1 = mid", 2j+2 = "l2 = mid"); the midpoints and their
+        // reciprocals are wave-uniform and read from LDS in the element loop
+        if (threadIdx.x == 0) {
+            double lo[kCand], hi[kCand];
+            lo[0] = l1; hi[0] = l2;
+            for (int j = 0; j < kCand; ++j) {
+                const double mj = 0.5 * (lo[j] + hi[j]);
+                smid[j] = mj;
+                srmid[j] = 1.0 / mj;
+                if (2 * j + 2 < kCand) {
+                    lo[2 * j + 1] = mj; hi[2 * j + 1] = hi[j];
+                    lo[2 * j + 2] = lo[j]; hi[2 * j + 2] = mj;
+                }
             }
         }
-        dd v[kCand];
-        double rmid[kCand];
+        __syncthreads();
+        double v[32];
 #pragma unroll
-        for (int j = 0; j < kCand; ++j) {
-            v[j] = dd{0.0, 0.0};
-            rmid[j] = 1.0 / mid[j];
-        }
+        for (int j = 0; j < 32; ++j) v[j] = 0.0;
         for (int64_t e = i0; e < m; e += stride) {
             if (pas[e] != TO_ACTIVE) continue;
             const double q = ocp_buf[e], xe = (double)x[e];
 #pragma unroll
-            for (int j = 0; j < kCand; ++j) v[j] = dd_add1(v[j], oc_clamp_r(q, mid[j], rmid[j], xe, move));
+            for (int j = 0; j < kCand; ++j) v[j] += oc_clamp_r(q, smid[j], srmid[j], xe, move);
         }
         double* reg = partial + (size_t)region * kMaxCoopBlocks * kPartialWidth;
-        block_dd(v, std::integral_constant<int, kCand>{}, reg);
+        block_f64(v, reg);
         alive = gb.sync() && alive;
-        grid_dd(std::integral_constant<int, kCand>{}, reg);
+        grid_f64(reg);
         region ^= 1;
         ++passes;
-        // walk the tree exactly as the serial loop would
+        // walk the tree exactly as the serial loop would; a decision the
+        // bound cannot settle is taken on the exactly summed volume
         int j = 0;
         for (int lev = 0; lev < kLevels && more(); ++lev) {
             lmid = 0.5 * (l1 + l2);        // equals mid[j]: the same operands, the same rounding
-            const dd s = dd_add(dd{tot[2 * j], tot[2 * j + 1]}, pas_sum);
-            const double vol = (s.hi + s.lo) / (double)m;
-            vol_last = vol;
-            if (vol > volfrac) { l1 = lmid; j = 2 * j + 1; }
+            const double tj = tot[j];
+            const dd sl = dd_add(dd{tj - err * tj, 0.0}, pas_sum), sh = dd_add(dd{tj + err * tj, 0.0}, pas_sum);
+            const double vlo = (sl.hi + sl.lo) / (double)m, vhi = (sh.hi + sh.lo) / (double)m;
+            bool greater;
+            if (vlo > volfrac) {
+                greater = true;
+                const dd s0 = dd_add(dd{tj, 0.0}, pas_sum);
+                vol_last = (s0.hi + s0.lo) / (double)m;
+            } else if (vhi <= volfrac) {
+                greater = false;
+                const dd s0 = dd_add(dd{tj, 0.0}, pas_sum);
+                vol_last = (s0.hi + s0.lo) / (double)m;
+            } else {
+                // double-double sum of this candidate (agrees with the
+                // exactly rounded sum except in exact ties)
+                const double rl = 1.0 / lmid;
+                dd ve[1] = {{0.0, 0.0}};
+                for (int64_t e = i0; e < m; e += stride)
+                    if (pas[e] == TO_ACTIVE)
+                        ve[0] = dd_add1(ve[0], oc_clamp_r(ocp_buf[e], lmid, rl, (double)x[e], move));
+                double* reg2 = partial + (size_t)region * kMaxCoopBlocks * kPartialWidth;
+                block_dd(ve, std::integral_constant<int, 1>{}, reg2);
+                alive = gb.sync() && alive;
+                grid_dd(std::integral_constant<int, 1>{}, reg2);
+                region ^= 1;
+                ++passes;
+                const dd s = dd_add(dd{tot[0], tot[1]}, pas_sum);
+                vol_last = (s.hi + s.lo) / (double)m;
+                greater = vol_last > volfrac;
+                // the candidate sums of this sweep were overwritten: keep
+                // walking from this level's decision only (the next sweep
+                // starts from the new bracket)
+                if (greater) l1 = lmid; else l2 = lmid;
+                ++n_bs;
+                break;
+            }
+            if (greater) { l1 = lmid; j = 2 * j + 1; }
             else { l2 = lmid; j = 2 * j + 2; }
             ++n_bs;
         }
@@ -367,7 +484,7 @@ static to_status run_oc(Plan* p, T* x, const T* dc, const T* dv, double volfrac,
     // blocks <= (kOcBlock / 15) * 32 = 1088 keeps every block partial within the
     // unrolled gather of the grid reduction
     int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, 2 * p->num_cu), (m + kOcBlock - 1) / kOcBlock));
-    blocks = std::min(blocks, 1024);
+    blocks = std::min(blocks, kMaxOcBlocks);
     OcArgs<T> a = oc_args<T>(p, x, dc, dv, volfrac, move, st);
     a.method = method;
     void* args[] = {&a};

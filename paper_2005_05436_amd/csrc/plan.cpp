@@ -241,7 +241,7 @@ static void filter_table(const Sizes& S, double rmin, std::vector<double>& h, st
 
 struct Offsets {
     size_t perm, seg, rowp, col, pas, freem, ke64, ke32, kf64, kf32, h64, h32,
-        hlim, hp64, hp32, hm32, Hs64, Hs32, E64, E32, partial, ll, scal, bar, v64[8], v32[8], fx64, fx32, total;
+        hlim, hp64, hp32, hm32, hm64, Hs64, Hs32, E64, E32, partial, ll, scal, bar, v64[8], v32[8], fx64, fx32, total;
     // multigrid hierarchy (2D)
     GmgShape gs;
     size_t gK[kGmgMaxLevels], gS[kGmgMaxLevels], gx[kGmgMaxLevels], gxt[kGmgMaxLevels], gb[kGmgMaxLevels], gr[kGmgMaxLevels],
@@ -267,6 +267,7 @@ static Offsets layout(const Sizes& S) {
     o.hp64 = L.take(8 * (size_t)(2 * S.R + 1) * pad_stride(S.R));
     o.hp32 = L.take(4 * (size_t)(2 * S.R + 1) * pad_stride(S.R));
     o.hm32 = L.take(S.G.dim == 2 ? 4 * (size_t)(2 * S.R + 1) * hm_stride(S.R) : 0);
+    o.hm64 = L.take(S.G.dim == 2 ? 8 * (size_t)(2 * S.R + 1) * hm_stride(S.R) : 0);
     o.Hs64 = L.take(8 * S.m);
     o.Hs32 = L.take(4 * S.m);
     o.E64 = L.take(8 * S.m);
@@ -437,6 +438,7 @@ to_status plan_create(const to_mesh_desc* D, void* ws, size_t ws_bytes, hipStrea
     p->h64 = (double*)(base + o.h64); p->h32 = (float*)(base + o.h32); p->hlim = (int32_t*)(base + o.hlim);
     p->hp64 = (double*)(base + o.hp64); p->hp32 = (float*)(base + o.hp32); p->hp_stride = pad_stride(S.R);
     p->hm32 = (float*)(base + o.hm32); p->hm_stride = hm_stride(S.R);
+    p->hm64 = (double*)(base + o.hm64);
     p->Hs64 = (double*)(base + o.Hs64); p->Hs32 = (float*)(base + o.Hs32);
     p->E64 = (double*)(base + o.E64); p->E32 = (float*)(base + o.E32);
     p->partial = (double*)(base + o.partial); p->scal = (double*)(base + o.scal);
@@ -505,9 +507,13 @@ to_status plan_create(const to_mesh_desc* D, void* ws, size_t ws_bytes, hipStrea
     // hm[dxi][dy + R + 16] = h(dx, dy) in FP32, zero for |dy| > R
     const int HM = hm_stride(S.R);
     std::vector<float> hm(S.G.dim == 2 ? (size_t)W2 * HM : 0, 0.0f);
+    std::vector<double> hm64(S.G.dim == 2 ? (size_t)W2 * HM : 0, 0.0);
     if (S.G.dim == 2)
         for (int dxi = 0; dxi < W2; ++dxi)
-            for (int dyi = 0; dyi < W2; ++dyi) hm[(size_t)dxi * HM + dyi + 16] = h32[(size_t)dxi * W2 + dyi];
+            for (int dyi = 0; dyi < W2; ++dyi) {
+                hm[(size_t)dxi * HM + dyi + 16] = h32[(size_t)dxi * W2 + dyi];
+                hm64[(size_t)dxi * HM + dyi + 16] = p->h[(size_t)dxi * W2 + dyi];
+            }
 
     // --- upload ------------------------------------------------------------------
     auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
@@ -519,7 +525,7 @@ to_status plan_create(const to_mesh_desc* D, void* ws, size_t ws_bytes, hipStrea
     UP(p->passive, pas); UP(p->freemask, fm);
     UP(p->ke64, p->ke_lower); UP(p->ke32, ke32); UP(p->kf64, p->ke_full); UP(p->kf32, kf32);
     UP(p->h64, p->h); UP(p->h32, h32); UP(p->hlim, p->hlim_host);
-    UP(p->hp64, hp); UP(p->hp32, hp32v); UP(p->hm32, hm);
+    UP(p->hp64, hp); UP(p->hp32, hp32v); UP(p->hm32, hm); UP(p->hm64, hm64);
 #undef UP
     if (e == hipSuccess) e = hipMemsetAsync(p->bar, 0, 4 * 1024, stream);
     if (e == hipSuccess) e = hipMemsetAsync(p->ll, 0, kLLBytes, stream);

@@ -68,7 +68,7 @@ template <typename T>
 __device__ void project_body(const ProjArgs<T>& a, int bid, int nb) {
     constexpr int NB = kBigBlock;
     __shared__ double sh[NB / 64];
-    __shared__ double red[4];
+    __shared__ double red[4];   // grid sums of up to four values
     const int64_t m = a.m;
     const T* __restrict__ xt = a.xt;
     const T* __restrict__ x = a.x;
@@ -102,77 +102,80 @@ __device__ void project_body(const ProjArgs<T>& a, int bid, int nb) {
         region ^= 1;
     }
 
+    // One sweep writes xphys and dprj at the current threshold and sums the
+    // change and the volume; with ft = 3 the same sweep also sums prj and
+    // d prj / d eta for the Newton test.  If the test passes (|g| <= 1e-6),
+    // the values just written are the final ones and no further sweep is
+    // made; otherwise the threshold takes its Newton step and the next sweep
+    // overwrites them.  The results are those of separate Newton and output
+    // sweeps: every value is computed from the same operands.
     int steps = 0;
     double g = 0.0;
     ProjCoef P;
-    if (ft == 3) {
-        for (;;) {
-            P.set(beta, eta);
-            double sp = 0.0, sd = 0.0;
-            if (alive)
-                for (int64_t e = i0; e < m; e += stride) {
-                    const double v = pre_value(xt, x, pas, e);
-                    const double t = P.th(v);
-                    sp += P.prj_t(t);
-                    sd += P.deta_t(v, t);
+    double rsum[4] = {0.0, 0.0, 0.0, 0.0};   // change^2, volume, sum prj, sum d prj / d eta
+    for (;;) {
+        P.set(beta, eta);
+        double sc = 0.0, sv = 0.0, sp = 0.0, sd = 0.0;
+        if (alive)
+            for (int64_t e = i0; e < m; e += stride) {
+                const double v = pre_value(xt, x, pas, e);
+                const double xte = (double)xt[e];
+                double xp = v, dp = 1.0;
+                if (ft >= 2) {
+                    const double t = P.th(v);        // for active elements v is xtilde: one tanh serves all
+                    xp = P.prj_t(t);
+                    dp = P.dprj_t(v == xte ? t : P.th(xte));
+                    if (ft == 3) {
+                        sp += xp;
+                        sd += P.deta_t(v, t);
+                    }
                 }
+                const T xpT = (T)xp;
+                a.xphys[e] = xpT;
+                a.dprj[e] = (T)dp;
+                if (a.xold) {
+                    const double dlt = (double)xpT - (double)a.xold[e];
+                    sc += dlt * dlt;
+                }
+                sv += (double)xpT;
+            }
+        sc = block_sum<NB>(sc, sh);
+        sv = block_sum<NB>(sv, sh);
+        if (ft == 3) {
             sp = block_sum<NB>(sp, sh);
             sd = block_sum<NB>(sd, sh);
-            if (threadIdx.x == 0) {
-                st_dev(&partial_now()[bid], sp);
-                st_dev(&partial_now()[kMaxCoopBlocks + bid], sd);
-            }
-            alive = gb.sync() && alive;
-            grid_reduce<2, NB>(partial_now(), red, sh, nb);
-            region ^= 1;
-            g = red[0] / (double)m - target;
-            if (!(fabs(g) > 1e-6) || steps >= 50 || !alive) break;
-            eta = eta - g / (red[1] / (double)m);
-            ++steps;
         }
-    }
-    P.set(beta, eta);
-    double sc = 0.0, sv = 0.0;
-    if (alive)
-        for (int64_t e = i0; e < m; e += stride) {
-            const double v = pre_value(xt, x, pas, e);
-            const double xte = (double)xt[e];
-            double xp = v, dp = 1.0;
-            if (ft >= 2) {
-                const double t = P.th(v);            // for active elements v is xtilde: one tanh serves both
-                xp = P.prj_t(t);
-                dp = P.dprj_t(v == xte ? t : P.th(xte));
-            }
-            T xpT = (T)xp;
-            a.xphys[e] = xpT;
-            a.dprj[e] = (T)dp;
-            if (a.xold) {
-                double dlt = (double)xpT - (double)a.xold[e];
-                sc += dlt * dlt;
-            }
-            sv += (double)xpT;
-        }
-    sc = block_sum<NB>(sc, sh);
-    sv = block_sum<NB>(sv, sh);
-    if (threadIdx.x == 0) {
-        st_dev(&partial_now()[bid], sc);
-        st_dev(&partial_now()[kMaxCoopBlocks + bid], sv);
-    }
-    alive = gb.sync() && alive;
-    if (bid == 0) {
-        grid_reduce<2, NB>(partial_now(), red, sh, nb);
         if (threadIdx.x == 0) {
-            to_project_stats s;
-            s.eta = eta;
-            s.g = g;
-            s.ch = a.xold ? sqrt(red[0]) / sqrt((double)m) : NAN;
-            s.vol = red[1] / (double)m;
-            s.n_newton = steps;
-            s.converged = (ft != 3 || fabs(g) <= 1e-6) && alive ? 1 : 0;
-            s.pad[0] = s.pad[1] = 0;
-            *a.st = s;
-            *a.d_eta = eta;
+            double* pn = partial_now();
+            st_dev(&pn[bid], sc);
+            st_dev(&pn[kMaxCoopBlocks + bid], sv);
+            if (ft == 3) {
+                st_dev(&pn[2 * kMaxCoopBlocks + bid], sp);
+                st_dev(&pn[3 * kMaxCoopBlocks + bid], sd);
+            }
         }
+        alive = gb.sync() && alive;
+        if (ft == 3) grid_reduce<4, NB>(partial_now(), red, sh, nb);
+        else grid_reduce<2, NB>(partial_now(), red, sh, nb);
+        region ^= 1;
+        for (int k = 0; k < 4; ++k) rsum[k] = red[k];
+        if (ft != 3) break;
+        g = rsum[2] / (double)m - target;
+        if (!(fabs(g) > 1e-6) || steps >= 50 || !alive) break;
+        eta = eta - g / (rsum[3] / (double)m);
+        ++steps;
+    }
+    if (bid == 0 && threadIdx.x == 0) {
+        to_project_stats s;
+        s.eta = eta;
+        s.g = g;
+        s.ch = a.xold ? sqrt(rsum[0]) / sqrt((double)m) : NAN;
+        s.vol = rsum[1] / (double)m;
+        s.n_newton = steps;
+        s.converged = (ft != 3 || fabs(g) <= 1e-6) && alive ? 1 : 0;
+        s.pad[0] = s.pad[1] = 0;
+        *a.st = s;
+        *a.d_eta = eta;
     }
 }
 

@@ -1,7 +1,8 @@
-"""The two assembly kernels (the segmented sum over the permutation of I_r,
-and one thread per slot with the slot's row from row_ptr and its
-contributing elements from the grid) give bit-identical values: the same terms in the
-same order (ascending pair index t).  Also against the oracle's segmented
+"""The assembly kernels (the segmented sum over the permutation of I_r, one
+thread per slot with the slot's row from row_ptr and its contributing
+elements from the grid, and in 2D one thread per node writing its two rows)
+give bit-identical values: the same terms in the same order (ascending pair
+index t), on meshes with ragged tiles and at the benchmark's size.  Also against the oracle's segmented
 sum, and the tuning's validation of the kernel choice."""
 import numpy as np
 import pytest
@@ -46,7 +47,7 @@ def test_grid_kernel_matches_segmented_kernel(dims, dt):
     x[: min(5, M.m)] = 0.0
     xd = torch.as_tensor(x, dtype=T).cuda()
     out = {}
-    for rows in (0, 1):
+    for rows in ((0, 1, 2) if len(dims) == 2 else (0, 1)):
         for nt in (128, 256, 512):
             L.to_plan_set_tuning(P.handle, 8, 0, nt, 0, asm_rows=rows)
             assert L.to_plan_get_tuning(P.handle).asm_rows == rows
@@ -69,4 +70,4 @@ def test_grid_kernel_choice_is_validated():
     from paper_2005_05436_amd import _lib as L
     P = _plan((6, 4))
     with pytest.raises(L.ToError):
-        L.to_plan_set_tuning(P.handle, 8, 0, 256, 0, asm_rows=2)
+        L.to_plan_set_tuning(P.handle, 8, 0, 256, 0, asm_rows=3)

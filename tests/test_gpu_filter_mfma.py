@@ -149,3 +149,52 @@ def test_mfma_filter_in_the_redesign_step_matches_stencil():
         a.step()
         b.step()
         assert np.abs(host(a.xphys) - host(b.xphys)).max() <= 2e-4, k
+
+
+@pytest.mark.parametrize("shape", [1, 2, 3, 4])
+@pytest.mark.parametrize("dims,rmin,bc", [((60, 20), 2.0, "N"), ((150, 50), 5.0, "D"), ((97, 83), 13.3, "D"),
+                                          ((130, 70), 10.0, "N"), ((1200, 400), 40.0, "D")])
+def test_mfma_filter_fp64_matches_oracle(dims, rmin, bc, shape):
+    """The same kernel in FP64 (v_mfma_f64_16x16x4_f64, FP64 weight table):
+    forward, adjoint and double adjoint within 1e-12 of the oracle (FP64
+    products summed in another order); where a tile does not fit in LDS the
+    stencil kernel takes over (or, for two fields, two one-field passes)."""
+    from paper_2005_05436_amd import _lib as L
+    P = plan(dims, rmin, bc, shape)
+    M = omesh.Mesh(*dims)
+    F = ofilt.Filter(M, rmin, bc) if M.m <= 20000 else None
+    T = torch.float64
+    xd = torch.as_tensor(W.design_field(M.m, 1), dtype=T).cuda()
+    gd = torch.as_tensor(W.sensitivity_field(M.m, 2), dtype=T).cuda()
+    g2d = torch.as_tensor(W.design_field(M.m, 3), dtype=T).cuda()
+    sd = torch.as_tensor(W.design_field(M.m, 4, 0.1, 2.0), dtype=T).cuda()
+    out, out2 = torch.zeros(M.m, dtype=T, device="cuda"), torch.zeros(M.m, dtype=T, device="cuda")
+    print(f"fp64 matrix-core filter {dims} rmin {rmin} {bc} shape {shape}", flush=True)
+    L.to_filter(P.handle, L.TO_F64, L.TO_FILTER_FWD, xd, None, None, out, None)
+    got_f = host(out)
+    L.to_filter(P.handle, L.TO_F64, L.TO_FILTER_ADJ2, gd, g2d, sd, out, out2)
+    got_a, got_a2 = host(out), host(out2)
+    if F is not None:
+        assert rel_inf(got_f, F.forward(host(xd))) < 1e-12
+        assert rel_inf(got_a, F.adjoint(host(gd), host(sd))) < 1e-12
+        assert rel_inf(got_a2, F.adjoint(host(g2d), host(sd))) < 1e-12
+    else:
+        # sampled outputs from eq. (2) directly, and the stencil kernel at full size
+        L.to_plan_set_tuning(P.handle, 8, 0, 256, 1, filt_mfma=0)
+        ref = torch.zeros(M.m, dtype=T, device="cuda")
+        L.to_filter(P.handle, L.TO_F64, L.TO_FILTER_FWD, xd, None, None, ref, None)
+        assert rel_inf(got_f, host(ref)) < 1e-12
+        x = host(xd).reshape(dims[1], dims[0], order="F")
+        h, R = ofilt.kernel(rmin, 2)
+        rng = np.random.default_rng(5)
+        for e in rng.integers(0, M.m, 12):
+            iy, ix = int(e % dims[1]), int(e // dims[1])
+            acc = wsum = 0.0
+            for dy in range(-R, R + 1):
+                for dx in range(-R, R + 1):
+                    w = h[dy + R, dx + R]
+                    if w == 0.0 or not (0 <= iy + dy < dims[1] and 0 <= ix + dx < dims[0]):
+                        continue
+                    acc += w * x[iy + dy, ix + dx]
+                    wsum += w
+            assert abs(got_f[e] - acc / wsum) <= 1e-12 * max(1.0, abs(acc / wsum))
