@@ -498,7 +498,10 @@ to_status to_plan_get_tuning(const to_plan* plan, to_tuning* h_out);
  * The projection (with its threshold Newton), the PCG state solve and the OC
  * bisection each run as ONE cooperative launch for the whole batch, its
  * blocks split into per-design groups in proportion to the design sizes; the
- * filter, assembly and sensitivity stages are launched per design.  With
+ * moduli, the 2D assembly and the sensitivities are one ordinary launch each
+ * with per-design block groups, and each 2D filter pass is one launch over
+ * the tiles of every design (3D designs filter and assemble per design; a
+ * multigrid solve runs per design on side streams).  With
  * use_graph the iteration is captured into a HIP graph on first use and
  * replayed while every design's (penal, beta, volfrac, move, target, ft)
  * stay the same; any change recaptures it.
@@ -514,8 +517,11 @@ to_status to_plan_get_tuning(const to_plan* plan, to_tuning* h_out);
  *   co-resident for a stage.
  * to_step_batched: one iteration of every design on `stream`; updates each
  *   state's host fields (loop, penal, beta) as to_step does.
- * to_batch_get_info: int32[6] = designs, blocks of the projection, solve and
- *   OC launches, graph captures, graph launches. */
+ * to_batch_get_info: int32[8] = designs, blocks of the projection, solve and
+ *   OC launches, graph captures, graph launches, blocks of the moduli /
+ *   assembly / sensitivity launches, and 1 if each 2D stencil pass is one
+ *   launch for the whole batch (0: one launch per design, as for 3D designs
+ *   or when the largest radius's tile does not fit the LDS). */
 typedef struct to_batch to_batch;
 to_status to_batch_query(int32_t count, size_t* ws_bytes);
 to_status to_batch_create(to_plan* const* plans, int32_t count, to_dtype dtype, const to_step_state* states,

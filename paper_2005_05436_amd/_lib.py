@@ -385,10 +385,10 @@ def to_step_batched(batch, states, params, use_graph=False, stream=None):
 
 
 def to_batch_get_info(batch):
-    out = (C.c_int32 * 6)()
+    out = (C.c_int32 * 8)()
     check(load().to_batch_get_info(batch, out))
     return dict(designs=out[0], project_blocks=out[1], solve_blocks=out[2], oc_blocks=out[3],
-                graph_captures=out[4], graph_launches=out[5])
+                graph_captures=out[4], graph_launches=out[5], element_blocks=out[6], filter_batched=bool(out[7]))
 
 
 def to_batch_destroy(batch):

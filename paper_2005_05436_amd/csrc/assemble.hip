@@ -10,6 +10,8 @@
 // (d~ values) is staged in LDS.  A second kernel forms the same sums from the
 // grid instead of the permutation, one thread per slot (the plan's tuning
 // chooses).
+#include <cstring>
+
 #include "common.h"
 
 namespace topt {
@@ -159,16 +161,15 @@ __global__ __launch_bounds__(NT) void assemble_grid_kernel(int nelx, int nely, i
 // LDS and written out as one contiguous, coalesced stretch of kval (a
 // block's nodes are consecutive, so their rows are).
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void assemble_node2d_kernel(int nelx, int nely, int64_t nnode,
-                                                              const int32_t* __restrict__ rp,
-                                                              const T* __restrict__ ke, const T* __restrict__ E,
-                                                              T* __restrict__ kval) {
+__device__ __forceinline__ void node2d_body(int nelx, int nely, int64_t nnode, const int32_t* __restrict__ rp,
+                                            const T* __restrict__ ke, const T* __restrict__ E,
+                                            T* __restrict__ kval, int bid, int nb) {
     constexpr int D = 8;
     __shared__ T ke_s[36];
     __shared__ T out_s[NT * 19];
     for (int i = threadIdx.x; i < 36; i += NT) ke_s[i] = ke[i];
     const int ny1 = nely + 1;
-    for (int64_t n0 = blockIdx.x * (int64_t)NT; n0 < nnode; n0 += (int64_t)gridDim.x * NT) {
+    for (int64_t n0 = bid * (int64_t)NT; n0 < nnode; n0 += (int64_t)nb * NT) {
         const int64_t nend = n0 + NT < nnode ? n0 + NT : nnode;
         const int64_t nd = n0 + threadIdx.x;
         __syncthreads();   // ke_s written; the previous stretch written out
@@ -222,6 +223,14 @@ __global__ __launch_bounds__(NT) void assemble_node2d_kernel(int nelx, int nely,
         __syncthreads();
         for (int32_t i = (int32_t)threadIdx.x; i < top - base; i += NT) kval[base + i] = out_s[i];
     }
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void assemble_node2d_kernel(int nelx, int nely, int64_t nnode,
+                                                              const int32_t* __restrict__ rp,
+                                                              const T* __restrict__ ke, const T* __restrict__ E,
+                                                              T* __restrict__ kval) {
+    node2d_body<T, NT>(nelx, nely, nnode, rp, ke, E, kval, blockIdx.x, gridDim.x);
 }
 
 template <typename T, int NT>
@@ -296,6 +305,11 @@ to_status launch_moduli(Plan* p, to_dtype dt, const void* xphys, double penal, h
 to_status launch_assemble(Plan* p, to_dtype dt, const void* xphys, double penal, void* kval, hipStream_t s) {
     to_status st = launch_moduli(p, dt, xphys, penal, s, false);
     if (st != TO_OK) return st;
+    return launch_assemble_from_moduli(p, dt, kval, s);
+}
+
+// The sums alone, from the moduli already in the plan's E array.
+to_status launch_assemble_from_moduli(Plan* p, to_dtype dt, void* kval, hipStream_t s) {
     const int64_t nnz = p->info.nnz_lower;
     if (dt == TO_F64) {
         if (p->dim == 2) assemble_t<double, 36>(p, nnz, p->ke64, p->E64, (double*)kval, s);
@@ -304,6 +318,98 @@ to_status launch_assemble(Plan* p, to_dtype dt, const void* xphys, double penal,
         if (p->dim == 2) assemble_t<float, 36>(p, nnz, p->ke32, p->E32, (float*)kval, s);
         else assemble_t<float, 300>(p, nnz, p->ke32, p->E32, (float*)kval, s);
     }
+    TO_HIP(hipGetLastError());
+    return TO_OK;
+}
+
+// --- batches -----------------------------------------------------------------
+// Arguments of one design: its moduli (E in the field type, and with the
+// FP64 operator of the mixed solve also E64) and, for 2D designs, the
+// node-centric sums.
+template <typename T>
+struct AsmArgs {
+    int nelx, nely;
+    int64_t m, nnode;
+    const T* x;
+    T* E;
+    double* E64;
+    const int32_t* rp;
+    const T* ke;
+    T* kval;
+    double E0, Emin;
+};
+
+size_t asm_args_bytes() {
+    static_assert(sizeof(AsmArgs<double>) == sizeof(AsmArgs<float>), "one table layout for both types");
+    return sizeof(AsmArgs<double>);
+}
+
+void asm_args_fill(Plan* p, to_dtype dt, const void* xphys, void* kval, void* dst) {
+    if (dt == TO_F64) {
+        const AsmArgs<double> A{p->nelx, p->nely, p->info.m, p->info.nnode, (const double*)xphys, p->E64, p->E64,
+                                p->row_ptr, p->ke64, (double*)kval, p->E0, p->Emin};
+        std::memcpy(dst, &A, sizeof A);
+    } else {
+        const AsmArgs<float> A{p->nelx, p->nely, p->info.m, p->info.nnode, (const float*)xphys, p->E32, p->E64,
+                               p->row_ptr, p->ke32, (float*)kval, p->E0, p->Emin};
+        std::memcpy(dst, &A, sizeof A);
+    }
+}
+
+// The moduli of every design (same arithmetic as moduli_kernel: the field
+// type's pow and constants; with ALSO64 the FP64 moduli from the same x).
+template <typename T, bool ALSO64>
+__global__ __launch_bounds__(kBlock) void moduli_batch_kernel(const AsmArgs<T>* __restrict__ tab,
+                                                               const double* __restrict__ dyn, int stride,
+                                                               const int32_t* __restrict__ inst,
+                                                               const int32_t* __restrict__ first,
+                                                               const int32_t* __restrict__ count) {
+    const int i = __builtin_amdgcn_readfirstlane(inst[blockIdx.x]);
+    const AsmArgs<T> A = tab[i];
+    const double penal = dyn[(size_t)stride * i + 4];
+    const int bid = (int)blockIdx.x - first[i], nb = count[i];
+    const T E0 = (T)A.E0, Emin = (T)A.Emin, pt = (T)penal;
+    for (int64_t e = bid * (int64_t)kBlock + threadIdx.x; e < A.m; e += (int64_t)nb * kBlock) {
+        const T x = A.x[e];
+        A.E[e] = Emin + simp_pow(x, pt) * (E0 - Emin);
+        if (ALSO64) A.E64[e] = A.Emin + simp_pow((double)x, penal) * (A.E0 - A.Emin);
+    }
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void assemble_node2d_batch_kernel(const AsmArgs<T>* __restrict__ tab,
+                                                                    const int32_t* __restrict__ inst,
+                                                                    const int32_t* __restrict__ first,
+                                                                    const int32_t* __restrict__ count) {
+    const int i = __builtin_amdgcn_readfirstlane(inst[blockIdx.x]);
+    const AsmArgs<T> A = tab[i];
+    node2d_body<T, NT>(A.nelx, A.nely, A.nnode, A.rp, A.ke, A.E, A.kval, (int)blockIdx.x - first[i], count[i]);
+}
+
+to_status launch_moduli_batch(to_dtype dt, const void* tab, const double* dyn, int dyn_stride, const BatchMap& mp,
+                              bool also64, hipStream_t s) {
+    if (dt == TO_F64)
+        hipLaunchKernelGGL((moduli_batch_kernel<double, false>), dim3(mp.blocks), dim3(kBlock), 0, s,
+                           (const AsmArgs<double>*)tab, dyn, dyn_stride, mp.inst, mp.first, mp.count);
+    else if (also64)
+        hipLaunchKernelGGL((moduli_batch_kernel<float, true>), dim3(mp.blocks), dim3(kBlock), 0, s,
+                           (const AsmArgs<float>*)tab, dyn, dyn_stride, mp.inst, mp.first, mp.count);
+    else
+        hipLaunchKernelGGL((moduli_batch_kernel<float, false>), dim3(mp.blocks), dim3(kBlock), 0, s,
+                           (const AsmArgs<float>*)tab, dyn, dyn_stride, mp.inst, mp.first, mp.count);
+    TO_HIP(hipGetLastError());
+    return TO_OK;
+}
+
+// 2D designs: the node-centric sums of every design in one launch (bit-identical
+// to every other assembly kernel of this file).
+to_status launch_assemble_batch2d(to_dtype dt, const void* tab, const BatchMap& mp, hipStream_t s) {
+    if (dt == TO_F64)
+        hipLaunchKernelGGL((assemble_node2d_batch_kernel<double, kAsmBatchBlock>), dim3(mp.blocks),
+                           dim3(kAsmBatchBlock), 0, s, (const AsmArgs<double>*)tab, mp.inst, mp.first, mp.count);
+    else
+        hipLaunchKernelGGL((assemble_node2d_batch_kernel<float, kAsmBatchBlock>), dim3(mp.blocks),
+                           dim3(kAsmBatchBlock), 0, s, (const AsmArgs<float>*)tab, mp.inst, mp.first, mp.count);
     TO_HIP(hipGetLastError());
     return TO_OK;
 }

@@ -8,8 +8,14 @@
 // group synchronises and reduces on its own design's barrier words and
 // partial buffers, so designs never wait for one another inside a stage and
 // the solve of a small design does not hold back a large one until the
-// launch ends.  The stencil, assembly and sensitivity stages are ordinary
-// launches per design.  Optionally the whole iteration is captured once into
+// launch ends.  The other stages are one ordinary launch each for the whole
+// batch: the moduli, the 2D assembly and the sensitivities with per-design
+// block groups of a fourth map, and the two 2D stencil passes over one list
+// of the tiles of every design (3D designs filter and assemble per design).
+// Every stage reads its per-design arguments from tables written once at
+// creation, and the scalars that change during a run (beta, the threshold
+// target, volfrac, move, penal) from a small device array refreshed at the
+// start of each iteration.  Optionally the whole iteration is captured once into
 // a HIP graph and replayed while every design's scalars (penal, beta,
 // volfrac, move, threshold target) stay the same; a change recaptures it.
 //
@@ -26,14 +32,15 @@
 namespace topt {
 
 constexpr int kDynChunk = 64;
+constexpr int kDynStride = 5;    // beta, target, volfrac, move, penal
 struct BatchDyn {
     int32_t first, n;
-    double v[kDynChunk][4];      // beta, target, volfrac, move
+    double v[kDynChunk][kDynStride];
 };
 
 __global__ void batch_dyn_kernel(double* dyn, BatchDyn d) {
     const int t = threadIdx.x;
-    if (t < 4 * d.n) dyn[4 * (size_t)d.first + t] = d.v[t / 4][t % 4];
+    if (t < kDynStride * d.n) dyn[kDynStride * (size_t)d.first + t] = d.v[t / kDynStride][t % kDynStride];
 }
 
 // Splits `blocks` among designs in proportion to `work`, at least one and at
@@ -80,6 +87,18 @@ struct Batch {
     char* solve_tab = nullptr;
     double* dyn = nullptr;
     BatchMap mp_proj{}, mp_oc{}, mp_solve{};
+    // the stencil, moduli, assembly and sensitivity stages: one launch each
+    // for the whole batch (filter and assembly for 2D designs; 3D designs
+    // filter and assemble per design)
+    char* filt_fwd = nullptr;
+    char* filt_adj = nullptr;
+    int32_t* tile0 = nullptr;
+    int ntiles = 0, rmax = 0;
+    bool filt_batched = false;
+    unsigned* ctr = nullptr;
+    char* asm_tab = nullptr;
+    char* sens_tab = nullptr;
+    BatchMap mp_elem{};
     hipStream_t cap = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<double> key;
@@ -94,8 +113,9 @@ struct Batch {
 constexpr int kBatchSideStreams = 4;
 
 struct BatchLayout {
-    size_t proj, oc, solve, dyn, maps, total;
+    size_t proj, oc, solve, dyn, maps, filt, tile0, asmt, sens, ctr, total;
 };
+constexpr int kBatchMaps = 4;
 
 static BatchLayout batch_layout(int count) {
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
@@ -106,8 +126,13 @@ static BatchLayout batch_layout(int count) {
     L.proj = o; o += al(pa * count);
     L.oc = o; o += al(oa * count);
     L.solve = o; o += al(solve_args_bytes() * count);
-    L.dyn = o; o += al(sizeof(double) * 4 * count);
-    L.maps = o; o += al(3 * sizeof(int32_t) * ((size_t)kMaxCoopBlocks + 2 * (size_t)count));
+    L.dyn = o; o += al(sizeof(double) * kDynStride * count);
+    L.maps = o; o += al(kBatchMaps * sizeof(int32_t) * ((size_t)kMaxCoopBlocks + 2 * (size_t)count));
+    L.filt = o; o += al(2 * filter_batch_entry_bytes() * count);
+    L.tile0 = o; o += al(sizeof(int32_t) * (count + 1));
+    L.asmt = o; o += al(asm_args_bytes() * count);
+    L.sens = o; o += al(sens_args_bytes() * count);
+    L.ctr = o; o += 256;
     L.total = o;
     return L;
 }
@@ -123,9 +148,6 @@ static bool same_state(const to_step_state& a, const to_step_state& b) {
 static to_status batch_enqueue(Batch* b, const to_step_state* st, const to_step_params* prm, hipStream_t s) {
     to_status r;
     const to_dtype dt = b->dt;
-    for (int i = 0; i < b->n; ++i)
-        if ((r = launch_filter(b->plans[i], dt, TO_FILTER_FWD, st[i].x, nullptr, nullptr, st[i].xtilde, nullptr, s)))
-            return r;
     for (int c0 = 0; c0 < b->n; c0 += kDynChunk) {
         BatchDyn d{};
         d.first = c0;
@@ -136,8 +158,20 @@ static to_status batch_enqueue(Batch* b, const to_step_state* st, const to_step_
             d.v[k][1] = std::isnan(p.target) ? p.volfrac : p.target;
             d.v[k][2] = p.volfrac;
             d.v[k][3] = p.move;
+            d.v[k][4] = st[c0 + k].penal;
         }
-        hipLaunchKernelGGL(batch_dyn_kernel, dim3(1), dim3(4 * kDynChunk), 0, s, b->dyn, d);
+        hipLaunchKernelGGL(batch_dyn_kernel, dim3(1), dim3(kDynStride * kDynChunk), 0, s, b->dyn, d);
+    }
+    const int num_cu = b->plans[0]->num_cu;
+    if (b->filt_batched) {
+        if ((r = launch_filter_batch(dt, TO_FILTER_FWD, b->filt_fwd, b->tile0, b->n, b->ntiles, b->rmax, num_cu,
+                                     b->ctr, s)))
+            return r;
+    } else {
+        for (int i = 0; i < b->n; ++i)
+            if ((r = launch_filter(b->plans[i], dt, TO_FILTER_FWD, st[i].x, nullptr, nullptr, st[i].xtilde, nullptr,
+                                   s)))
+                return r;
     }
     if ((r = launch_project_batch(dt, b->proj_tab, b->mp_proj, s))) return r;
     if (b->gmg) {
@@ -155,20 +189,34 @@ static to_status batch_enqueue(Batch* b, const to_step_state* st, const to_step_
             TO_HIP(hipStreamWaitEvent(s, b->ev[1 + j], 0));
         }
     } else {
-        for (int i = 0; i < b->n; ++i) {
-            if (b->solve.op != TO_OP_MATFREE &&
-                (r = launch_assemble(b->plans[i], dt, st[i].xphys, st[i].penal, st[i].kval, s)))
+        // the moduli (and the FP64 ones the mixed and hybrid operators use),
+        // then the sums of K^(s)
+        const bool assembled = b->solve.op != TO_OP_MATFREE;
+        if (assembled || b->mode != 0) {
+            if ((r = launch_moduli_batch(dt, b->asm_tab, b->dyn, kDynStride, b->mp_elem,
+                                         dt == TO_F32 && b->mode != 0, s)))
                 return r;
-            if ((r = solve_prepare(b->plans[i], dt, st[i].xphys, st[i].penal, b->solve, s))) return r;
+        }
+        if (assembled) {
+            if (b->dim == 2) {
+                if ((r = launch_assemble_batch2d(dt, b->asm_tab, b->mp_elem, s))) return r;
+            } else {
+                for (int i = 0; i < b->n; ++i)
+                    if ((r = launch_assemble_from_moduli(b->plans[i], dt, st[i].kval, s))) return r;
+            }
         }
         if ((r = launch_solve_batch(b->dim, b->mode, b->solve_tab, b->mp_solve, s))) return r;
     }
-    for (int i = 0; i < b->n; ++i) {
-        Plan* p = b->plans[i];
-        if ((r = launch_sensitivity(p, dt, st[i].xphys, st[i].u, st[i].f, st[i].penal, st[i].dc, st[i].compliance, s)))
+    if ((r = launch_sensitivity_batch(b->dim, dt, b->sens_tab, b->dyn, kDynStride, b->mp_elem, s))) return r;
+    if (b->filt_batched) {
+        if ((r = launch_filter_batch(dt, TO_FILTER_ADJ2, b->filt_adj, b->tile0, b->n, b->ntiles, b->rmax, num_cu,
+                                     b->ctr, s)))
             return r;
-        if ((r = launch_filter(p, dt, TO_FILTER_ADJ2, st[i].dc, st[i].dv, st[i].dprj, st[i].dcf, st[i].dv0, s)))
-            return r;
+    } else {
+        for (int i = 0; i < b->n; ++i)
+            if ((r = launch_filter(b->plans[i], dt, TO_FILTER_ADJ2, st[i].dc, st[i].dv, st[i].dprj, st[i].dcf,
+                                   st[i].dv0, s)))
+                return r;
     }
     if ((r = launch_oc_batch(dt, b->oc_tab, b->mp_oc, s))) return r;
     for (int i = 0; i < b->n; ++i) {
@@ -444,17 +492,34 @@ to_status to_batch_create(to_plan* const* plans, int32_t count, to_dtype dtype, 
         // host images of the tables and maps
         const size_t pa = project_args_bytes(dtype), oa = oc_args_bytes(dtype), sa = solve_args_bytes();
         std::vector<char> hp(pa * count), ho(oa * count), hs(sa * count);
+        const size_t aa = asm_args_bytes(), sn = sens_args_bytes(), fe = filter_batch_entry_bytes();
+        std::vector<char> hasm(aa * count), hsens(sn * count), hfilt(2 * fe * count);
+        std::vector<int32_t> tile0(count + 1, 0);
+        b.filt_fwd = base + Ly.filt;
+        b.filt_adj = base + Ly.filt + fe * count;
+        b.tile0 = (int32_t*)(base + Ly.tile0);
+        b.asm_tab = base + Ly.asmt;
+        b.sens_tab = base + Ly.sens;
+        b.ctr = (unsigned*)(base + Ly.ctr);
         for (int i = 0; i < count; ++i) {
             Plan* p = b.plans[i];
             const to_step_state& st = states[i];
-            double* dyn = b.dyn + 4 * (size_t)i;
+            double* dyn = b.dyn + kDynStride * (size_t)i;
             project_args_fill(p, dtype, params[i].ft, st.xtilde, st.x, st.xphys, st.dprj, st.eta, st.xphys_old,
                               st.pstats, dyn, hp.data() + pa * i);
             oc_args_fill(p, dtype, st.x, st.dcf, st.dv0, st.ostats, dyn, params[i].oc, ho.data() + oa * i);
             solve_args_fill(p, dtype, st.kval, st.f, st.u, b.solve, st.sstats, hs.data() + sa * i);
+            asm_args_fill(p, dtype, st.xphys, st.kval, hasm.data() + aa * i);
+            sens_args_fill(p, dtype, st.xphys, st.u, st.f, st.dc, st.compliance, hsens.data() + sn * i);
+            filter_batch_fill(p, dtype, st.x, nullptr, nullptr, st.xtilde, nullptr, hfilt.data() + fe * i);
+            filter_batch_fill(p, dtype, st.dc, st.dv, st.dprj, st.dcf, st.dv0, hfilt.data() + fe * (count + i));
+            tile0[i + 1] = tile0[i] + (b.dim == 2 ? filter_batch_tiles(p) : 0);
+            b.rmax = std::max(b.rmax, p->R);
         }
+        b.ntiles = tile0[count];
+        b.filt_batched = b.dim == 2 && filter_batch_fits(dtype, b.rmax);
         std::vector<double> wm(count), wn(count);
-        std::vector<int> cap_p(count), cap_o(count), cap_s(count);
+        std::vector<int> cap_p(count), cap_o(count), cap_s(count), cap_e(count);
         for (int i = 0; i < count; ++i) {
             const Plan* p = b.plans[i];
             wm[i] = (double)p->info.m;
@@ -465,6 +530,9 @@ to_status to_batch_create(to_plan* const* plans, int32_t count, to_dtype dtype, 
             cap_o[i] = (int)std::min<int64_t>(512, (p->info.m + 511) / 512);
             const int sb = solve_block_size(b.dim, b.mode);
             cap_s[i] = (int)std::min<int64_t>(kMaxCoopBlocks, (p->info.nnode + sb - 1) / sb);
+            // moduli, assembly and sensitivity blocks (one compliance partial
+            // per block: at most sens_batch_cap)
+            cap_e[i] = (int)std::min<int64_t>(sens_batch_cap(p), (p->info.m + kBlock - 1) / kBlock);
         }
         const int gp = std::min(project_batch_capacity(dtype, num_cu), kMaxCoopBlocks);
         const int go = std::min(oc_batch_capacity(dtype, num_cu), kMaxCoopBlocks);
@@ -494,10 +562,16 @@ to_status to_batch_create(to_plan* const* plans, int32_t count, to_dtype dtype, 
         add_map(wm, cap_p, gp, b.mp_proj, dmaps);
         add_map(wm, cap_o, go, b.mp_oc, dmaps);
         add_map(wn, cap_s, gs, b.mp_solve, dmaps);
+        add_map(wm, cap_e, std::max(count, std::min(kMaxCoopBlocks, 8 * num_cu)), b.mp_elem, dmaps);
         TO_HIP(hipMemcpyAsync(b.proj_tab, hp.data(), hp.size(), hipMemcpyHostToDevice, s));
         TO_HIP(hipMemcpyAsync(b.oc_tab, ho.data(), ho.size(), hipMemcpyHostToDevice, s));
         TO_HIP(hipMemcpyAsync(b.solve_tab, hs.data(), hs.size(), hipMemcpyHostToDevice, s));
         TO_HIP(hipMemcpyAsync(dmaps, maps.data(), maps.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        TO_HIP(hipMemcpyAsync(b.asm_tab, hasm.data(), hasm.size(), hipMemcpyHostToDevice, s));
+        TO_HIP(hipMemcpyAsync(b.sens_tab, hsens.data(), hsens.size(), hipMemcpyHostToDevice, s));
+        TO_HIP(hipMemcpyAsync(b.filt_fwd, hfilt.data(), hfilt.size(), hipMemcpyHostToDevice, s));
+        TO_HIP(hipMemcpyAsync(b.tile0, tile0.data(), tile0.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        TO_HIP(hipMemsetAsync(b.ctr, 0, 256, s));
         TO_HIP(hipStreamSynchronize(s));
         if (autotune) {
             for (int i = 0; i < count; ++i) {
@@ -604,6 +678,8 @@ to_status to_batch_get_info(const to_batch* h, int32_t* h_out) {
     h_out[3] = b.mp_oc.blocks;
     h_out[4] = b.graph_captures;
     h_out[5] = b.graph_launches;
+    h_out[6] = b.mp_elem.blocks;
+    h_out[7] = b.filt_batched ? 1 : 0;
     return TO_OK;
 }
 

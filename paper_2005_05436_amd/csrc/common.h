@@ -498,6 +498,29 @@ int solve_batch_capacity(int dim, int mode, int num_cu);
 int solve_block_size(int dim, int mode);
 to_status launch_solve_batch(int dim, int mode, const void* tab, const BatchMap& mp, hipStream_t s);
 
+// Stage launches covering every design of a batch (tables built once at
+// batch creation; penal is the design's device scalar dyn[stride * i + 4]).
+constexpr int kAsmBatchBlock = 256;
+size_t filter_batch_entry_bytes();
+int filter_batch_tiles(const Plan* p);
+bool filter_batch_fits(to_dtype dt, int rmax);
+void filter_batch_fill(Plan* p, to_dtype dt, const void* in, const void* in2, const void* sc, void* out, void* out2,
+                       void* dst);
+to_status launch_filter_batch(to_dtype dt, int mode, const void* tab, const int32_t* tile0, int n, int ntiles,
+                              int rmax, int num_cu, unsigned* ctr, hipStream_t s);
+size_t asm_args_bytes();
+void asm_args_fill(Plan* p, to_dtype dt, const void* xphys, void* kval, void* dst);
+to_status launch_moduli_batch(to_dtype dt, const void* tab, const double* dyn, int dyn_stride, const BatchMap& mp,
+                              bool also64, hipStream_t s);
+to_status launch_assemble_batch2d(to_dtype dt, const void* tab, const BatchMap& mp, hipStream_t s);
+to_status launch_assemble_from_moduli(Plan* p, to_dtype dt, void* kval, hipStream_t s);
+size_t sens_args_bytes();
+int sens_batch_cap(const Plan* p);
+void sens_args_fill(Plan* p, to_dtype dt, const void* xphys, const double* u, const double* f, void* dc, double* c,
+                    void* dst);
+to_status launch_sensitivity_batch(int dim, to_dtype dt, const void* tab, const double* dyn, int dyn_stride,
+                                   const BatchMap& mp, hipStream_t s);
+
 size_t pae_workspace_bytes(int64_t m, int mr);
 to_status launch_pae(Plan* p, to_dtype dt, void* x, const void* xpre, int32_t loop, const to_pae_params& prm,
                      void* ws, double* d_gamma, hipStream_t s);

@@ -14,6 +14,8 @@
 //        FWD  out = (h * in) / Hs
 //        ADJ  out = h * (in . s / Hs)
 //        ADJ2 out = h * (in . s / Hs), out2 = h * (in2 . s / Hs)  (one pass)
+#include <cstring>
+
 #include "common.h"
 
 namespace topt {
@@ -99,29 +101,150 @@ __device__ __forceinline__ void filt_chunk(const T* __restrict__ hrow, int k, co
 template <typename T>
 constexpr int filt_max_parts() { return sizeof(T) == 8 ? 8 : kFiltMaxParts; }
 
+// One 64 x V tile t of one field set: stage the window with the boundary
+// rule, run the tap rows of this wave's part, combine the parts in LDS and
+// write the outputs.  Ends with a block barrier (the tile buffer is free
+// again).
+template <typename T>
+struct Filt2dArgs {
+    int nely, nelx, R;
+    char bc;
+    const T* hp;
+    int hps;
+    const int32_t* hlim;
+    const T* Hs;
+    const T* in;
+    const T* in2;
+    const T* sc;
+    T* out;
+    T* out2;
+};
+
 template <typename T, int MODE, int V, int LS>
-__global__ __launch_bounds__(64 * filt_max_parts<T>()) void filter2d_kernel(
-    int nely, int nelx, int R, char bc, const T* __restrict__ hp, int hps, const int32_t* __restrict__ hlim,
-    const T* __restrict__ Hs, const T* __restrict__ in, const T* __restrict__ in2,
-    const T* __restrict__ sc, T* __restrict__ out, T* __restrict__ out2, unsigned* ctr, const unsigned* skip,
-    int chunk) {
-    extern __shared__ unsigned char smem_raw[];
-    __shared__ int tile_sh;
-    if (skip && *skip) return;          // the whole launch is cancelled (the tile counter is untouched)
-    T* tile = reinterpret_cast<T*>(smem_raw);
+__device__ __forceinline__ void filter2d_tile(const Filt2dArgs<T>& fa, int t, T* tile, int lane, int part, int parts) {
     constexpr int NF = MODE == M_ADJ2 ? 2 : 1;
+    const int nely = fa.nely, nelx = fa.nelx, R = fa.R;
+    const char bc = fa.bc;
+    const T* __restrict__ hp = fa.hp;
+    const int hps = fa.hps;
+    const int32_t* __restrict__ hlim = fa.hlim;
+    const T* __restrict__ Hs = fa.Hs;
+    const T* __restrict__ in = fa.in;
+    const T* __restrict__ in2 = fa.in2;
+    const T* __restrict__ sc = fa.sc;
+    T* __restrict__ out = fa.out;
+    T* __restrict__ out2 = fa.out2;
     const int W = 2 * R + 1;
     const int LY = 64 + 2 * R;           // staged rows (y, contiguous)
     const int ls = LS ? LS : LY;         // column stride
     const int LX = V + 2 * R + V;        // LDS columns (x), V spare
-    const int nty = (nely + 63) / 64, ntiles = nty * ((nelx + V - 1) / V);
+    const int nty = (nely + 63) / 64;
+    T* tile2 = tile + (size_t)ls * LX;
+    const int y0 = (t % nty) * 64, x0 = (t / nty) * V;
+    // stage the window with the boundary rule
+    // (ly, lx) of element i = ly + LY lx, advanced without a division per element
+    const int step_x = (int)blockDim.x / LY, step_y = (int)blockDim.x % LY;
+    int ly = (int)threadIdx.x % LY, lx = (int)threadIdx.x / LY;
+    for (int i = threadIdx.x; i < LY * LX; i += blockDim.x) {
+        int gy = y0 - R + ly, gx = x0 - R + lx;
+        T v = T(0), v2 = T(0);
+        bool inside = gy >= 0 && gy < nely && gx >= 0 && gx < nelx;
+        if (bc == 'N' && !inside) {
+            gy = mirror_idx(gy, nely);
+            gx = mirror_idx(gx, nelx);
+            inside = true;
+        }
+        if (inside) {
+            const int64_t e = gy + (int64_t)nely * gx;
+            if (MODE == M_RAW) v = T(1);
+            else v = staged_value<T>(MODE, in, sc, Hs, e);
+            if (NF == 2) v2 = staged_value<T>(MODE, in2, sc, Hs, e);
+        }
+        tile[(size_t)lx * ls + ly] = v;
+        if (NF == 2) tile2[(size_t)lx * ls + ly] = v2;
+        ly += step_y;
+        lx += step_x;
+        if (ly >= LY) { ly -= LY; ++lx; }
+    }
+    __syncthreads();
+
+    T acc[V], acc2[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) { acc[v] = T(0); acc2[v] = T(0); }
+    for (int dyi = part; dyi < W; dyi += parts) {
+        const int lim = hlim[dyi];
+        if (lim < 0) continue;
+        // hrow[t] = h(dy, t - lim), zero past 2 lim; read per lane (see filt_chunk)
+        int zero;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+        const T* hrow = hp + (size_t)dyi * hps + zero;
+        // column R - lim of this lane's LDS row at this dy: output 0 at dx = -lim
+        const T* col0 = tile + lane + dyi + (size_t)(R - lim) * ls;
+        const T* col0b = tile2 + lane + dyi + (size_t)(R - lim) * ls;
+        const int nch = (2 * lim + 1 + V - 1) / V;
+        T A[V], B[V], C[V], A2[V], B2[V], C2[V], WA[V], WB[V], WC[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            A[u] = col0[(size_t)u * ls];
+            B[u] = col0[(size_t)(V + u) * ls];
+            if (NF == 2) {
+                A2[u] = col0b[(size_t)u * ls];
+                B2[u] = col0b[(size_t)(V + u) * ls];
+            }
+            WA[u] = hrow[u];
+        }
+        // three buffers of columns and of weights rotate, so no register moves are needed
+        for (int k = 0; k < nch; k += 3) {
+            filt_chunk<T, NF, V, LS>(hrow, k, col0, col0b, ls, nch, A, B, C, A2, B2, C2, WA, WB, acc, acc2);
+            if (k + 1 < nch)
+                filt_chunk<T, NF, V, LS>(hrow, k + 1, col0, col0b, ls, nch, B, C, A, B2, C2, A2, WB, WC, acc,
+                                         acc2);
+            if (k + 2 < nch)
+                filt_chunk<T, NF, V, LS>(hrow, k + 2, col0, col0b, ls, nch, C, A, B, C2, A2, B2, WC, WA, acc,
+                                         acc2);
+        }
+    }
+    // combine the parts' partial sums (the window is no longer needed)
+    __syncthreads();
+    T* red = tile;                                      // [part][field][v][lane]
+    const int slab = NF * V * 64;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        red[part * slab + v * 64 + lane] = acc[v];
+        if (NF == 2) red[part * slab + V * 64 + v * 64 + lane] = acc2[v];
+    }
+    __syncthreads();
+    // wave q finishes output column q of the tile (q < V)
+    if (part < V) {
+        const int gy = y0 + lane, gx = x0 + part;
+        T r = T(0), r2 = T(0);
+        for (int q = 0; q < parts; ++q) {
+            r += red[q * slab + part * 64 + lane];
+            if (NF == 2) r2 += red[q * slab + V * 64 + part * 64 + lane];
+        }
+        if (gy < nely && gx < nelx) {
+            const int64_t e = gy + (int64_t)nely * gx;
+            if (MODE == M_FWD) r = r / Hs[e];
+            out[e] = r;
+            if (NF == 2) out2[e] = r2;
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int MODE, int V, int LS>
+__global__ __launch_bounds__(64 * filt_max_parts<T>()) void filter2d_kernel(Filt2dArgs<T> A, unsigned* ctr,
+                                                                          const unsigned* skip, int chunk) {
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ int tile_sh;
+    if (skip && *skip) return;          // the whole launch is cancelled (the tile counter is untouched)
+    T* tile = reinterpret_cast<T*>(smem_raw);
+    const int nty = (A.nely + 63) / 64, ntiles = nty * ((A.nelx + V - 1) / V);
     const int lane = threadIdx.x & 63;
     // wave index made provably wave-uniform, so the tap loop's bounds and
     // weights are scalar loads (SGPRs) rather than per-lane loads
     const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int parts = blockDim.x >> 6;
-    T* tile2 = tile + (size_t)ls * LX;
-
     // tiles are claimed `chunk` at a time: every claim is an atomic on one
     // address, which at small radii (little work per tile) would serialise
     int t = 0, t_end = 0;
@@ -133,98 +256,49 @@ __global__ __launch_bounds__(64 * filt_max_parts<T>()) void filter2d_kernel(
             t_end = min(t + chunk, ntiles);
         }
         if (t >= ntiles) break;
-        const int y0 = (t % nty) * 64, x0 = (t / nty) * V;
-        // stage the window with the boundary rule
-        // (ly, lx) of element i = ly + LY lx, advanced without a division per element
-        const int step_x = (int)blockDim.x / LY, step_y = (int)blockDim.x % LY;
-        int ly = (int)threadIdx.x % LY, lx = (int)threadIdx.x / LY;
-        for (int i = threadIdx.x; i < LY * LX; i += blockDim.x) {
-            int gy = y0 - R + ly, gx = x0 - R + lx;
-            T v = T(0), v2 = T(0);
-            bool inside = gy >= 0 && gy < nely && gx >= 0 && gx < nelx;
-            if (bc == 'N' && !inside) {
-                gy = mirror_idx(gy, nely);
-                gx = mirror_idx(gx, nelx);
-                inside = true;
-            }
-            if (inside) {
-                const int64_t e = gy + (int64_t)nely * gx;
-                if (MODE == M_RAW) v = T(1);
-                else v = staged_value<T>(MODE, in, sc, Hs, e);
-                if (NF == 2) v2 = staged_value<T>(MODE, in2, sc, Hs, e);
-            }
-            tile[(size_t)lx * ls + ly] = v;
-            if (NF == 2) tile2[(size_t)lx * ls + ly] = v2;
-            ly += step_y;
-            lx += step_x;
-            if (ly >= LY) { ly -= LY; ++lx; }
-        }
-        __syncthreads();
-
-        T acc[V], acc2[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) { acc[v] = T(0); acc2[v] = T(0); }
-        for (int dyi = part; dyi < W; dyi += parts) {
-            const int lim = hlim[dyi];
-            if (lim < 0) continue;
-            // hrow[t] = h(dy, t - lim), zero past 2 lim; read per lane (see filt_chunk)
-            int zero;
-            asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
-            const T* hrow = hp + (size_t)dyi * hps + zero;
-            // column R - lim of this lane's LDS row at this dy: output 0 at dx = -lim
-            const T* col0 = tile + lane + dyi + (size_t)(R - lim) * ls;
-            const T* col0b = tile2 + lane + dyi + (size_t)(R - lim) * ls;
-            const int nch = (2 * lim + 1 + V - 1) / V;
-            T A[V], B[V], C[V], A2[V], B2[V], C2[V], WA[V], WB[V], WC[V];
-#pragma unroll
-            for (int u = 0; u < V; ++u) {
-                A[u] = col0[(size_t)u * ls];
-                B[u] = col0[(size_t)(V + u) * ls];
-                if (NF == 2) {
-                    A2[u] = col0b[(size_t)u * ls];
-                    B2[u] = col0b[(size_t)(V + u) * ls];
-                }
-                WA[u] = hrow[u];
-            }
-            // three buffers of columns and of weights rotate, so no register moves are needed
-            for (int k = 0; k < nch; k += 3) {
-                filt_chunk<T, NF, V, LS>(hrow, k, col0, col0b, ls, nch, A, B, C, A2, B2, C2, WA, WB, acc, acc2);
-                if (k + 1 < nch)
-                    filt_chunk<T, NF, V, LS>(hrow, k + 1, col0, col0b, ls, nch, B, C, A, B2, C2, A2, WB, WC, acc,
-                                             acc2);
-                if (k + 2 < nch)
-                    filt_chunk<T, NF, V, LS>(hrow, k + 2, col0, col0b, ls, nch, C, A, B, C2, A2, B2, WC, WA, acc,
-                                             acc2);
-            }
-        }
-        // combine the parts' partial sums (the window is no longer needed)
-        __syncthreads();
-        T* red = tile;                                      // [part][field][v][lane]
-        const int slab = NF * V * 64;
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            red[part * slab + v * 64 + lane] = acc[v];
-            if (NF == 2) red[part * slab + V * 64 + v * 64 + lane] = acc2[v];
-        }
-        __syncthreads();
-        // wave q finishes output column q of the tile (q < V)
-        if (part < V) {
-            const int gy = y0 + lane, gx = x0 + part;
-            T r = T(0), r2 = T(0);
-            for (int q = 0; q < parts; ++q) {
-                r += red[q * slab + part * 64 + lane];
-                if (NF == 2) r2 += red[q * slab + V * 64 + part * 64 + lane];
-            }
-            if (gy < nely && gx < nelx) {
-                const int64_t e = gy + (int64_t)nely * gx;
-                if (MODE == M_FWD) r = r / Hs[e];
-                out[e] = r;
-                if (NF == 2) out2[e] = r2;
-            }
-        }
-        __syncthreads();
+        filter2d_tile<T, MODE, V, LS>(A, t, tile, lane, part, parts);
     }
     // the last block to finish resets the tile counter for the next launch
+    if (threadIdx.x == 0) {
+        const unsigned done = atomicAdd(&ctr[1], 1u);
+        if (done == gridDim.x - 1) {
+            st_dev(&ctr[0], 0u);
+            st_dev(&ctr[1], 0u);
+        }
+    }
+}
+
+// Many designs in one launch: the tiles of all designs form one list (design
+// i owns tiles tile0[i] .. tile0[i+1]-1) claimed from one counter; each tile
+// is filtered with its own design's arguments (a block-uniform lookup, so the
+// table reads are scalar loads).
+template <typename T, int MODE, int V, int LS>
+__global__ __launch_bounds__(64 * filt_max_parts<T>()) void filter2d_batch_kernel(
+    const Filt2dArgs<T>* __restrict__ tab, const int32_t* __restrict__ tile0, int ndesign, unsigned* ctr, int chunk) {
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ int tile_sh;
+    T* tile = reinterpret_cast<T*>(smem_raw);
+    const int ntiles = tile0[ndesign];
+    const int lane = threadIdx.x & 63;
+    const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int parts = blockDim.x >> 6;
+    int t = 0, t_end = 0;
+    for (;; ++t) {
+        if (t >= t_end) {
+            if (threadIdx.x == 0) tile_sh = (int)atomicAdd(&ctr[0], (unsigned)chunk);
+            __syncthreads();
+            t = __builtin_amdgcn_readfirstlane(tile_sh);
+            t_end = min(t + chunk, ntiles);
+        }
+        if (t >= ntiles) break;
+        int lo = 0, hi = ndesign;            // tile0[lo] <= t < tile0[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (tile0[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+        filter2d_tile<T, MODE, V, LS>(tab[lo], t - tile0[lo], tile, lane, part, parts);
+    }
     if (threadIdx.x == 0) {
         const unsigned done = atomicAdd(&ctr[1], 1u);
         if (done == gridDim.x - 1) {
@@ -504,8 +578,8 @@ static to_status run_filter2d_ls(Plan* p, const T* hp, const T* Hs, const T* in,
     // tiles per claim: about 8 claims per block at large radii (uneven work
     // near the boundary is balanced), 2 at small radii (the claims dominate)
     const int chunk = std::max(1, ntiles / (blocks * (W >= 16 ? 8 : 2)));
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * parts), lds, s, p->nely, p->nelx, R, p->bc, hp, p->hp_stride,
-                       p->hlim, Hs, in, in2, sc, out, out2, p->bar + 16, p->filt_skip, chunk);
+    Filt2dArgs<T> A{p->nely, p->nelx, R, p->bc, hp, p->hp_stride, p->hlim, Hs, in, in2, sc, out, out2};
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * parts), lds, s, A, p->bar + 16, p->filt_skip, chunk);
     TO_HIP(hipGetLastError());
     return TO_OK;
 }
@@ -638,6 +712,87 @@ to_status launch_filter(Plan* p, to_dtype dt, int mode, const void* in, const vo
         if (st == TO_OK) st = run_filter<float, M_ADJ>(p, p->h32, p->hp32, p->Hs32, b, nullptr, c, o2, nullptr, s);
     }
     return st;
+}
+
+// --- batches of 2D designs --------------------------------------------------
+size_t filter_batch_entry_bytes() {
+    static_assert(sizeof(Filt2dArgs<double>) == sizeof(Filt2dArgs<float>), "one table layout for both types");
+    return sizeof(Filt2dArgs<double>);
+}
+
+int filter_batch_tiles(const Plan* p) { return ((p->nely + 63) / 64) * ((p->nelx + kFiltV - 1) / kFiltV); }
+
+void filter_batch_fill(Plan* p, to_dtype dt, const void* in, const void* in2, const void* sc, void* out, void* out2,
+                       void* dst) {
+    if (dt == TO_F64) {
+        Filt2dArgs<double> A{p->nely, p->nelx, p->R, p->bc, p->hp64, p->hp_stride, p->hlim, p->Hs64,
+                             (const double*)in, (const double*)in2, (const double*)sc, (double*)out, (double*)out2};
+        std::memcpy(dst, &A, sizeof A);
+    } else {
+        Filt2dArgs<float> A{p->nely, p->nelx, p->R, p->bc, p->hp32, p->hp_stride, p->hlim, p->Hs32,
+                            (const float*)in, (const float*)in2, (const float*)sc, (float*)out, (float*)out2};
+        std::memcpy(dst, &A, sizeof A);
+    }
+}
+
+// LDS bytes of the batched stencil launch for the largest radius of a batch
+template <typename T, int NF>
+static size_t filter_batch_lds(int rmax) {
+    constexpr int V = kFiltV;
+    const int parts = 2 * rmax + 1 >= 16 ? filt_max_parts<T>() : V;
+    const int ly = 64 + 2 * rmax;
+    const int ls = ly <= 96 ? 96 : ly <= 160 ? 160 : ly <= 224 ? 224 : ly;
+    const size_t lds = (size_t)NF * ls * (V + 2 * rmax + V) * sizeof(T);
+    return std::max(lds, (size_t)parts * NF * V * 64 * sizeof(T));
+}
+
+bool filter_batch_fits(to_dtype dt, int rmax) {
+    const size_t lds = dt == TO_F64 ? filter_batch_lds<double, 2>(rmax) : filter_batch_lds<float, 2>(rmax);
+    return lds <= 160 * 1024;
+}
+
+template <typename T, int MODE, int LS>
+static to_status run_filter_batch_ls(const void* tab, const int32_t* tile0, int n, int ntiles, int rmax, int num_cu,
+                                     unsigned* ctr, hipStream_t s) {
+    constexpr int NF = MODE == M_ADJ2 ? 2 : 1, V = kFiltV;
+    constexpr int maxp = filt_max_parts<T>();
+    const int W = 2 * rmax + 1;
+    const int parts = W >= 16 ? maxp : V;
+    // the largest radius sets the tile buffer (smaller radii use a part of it)
+    const size_t lds = filter_batch_lds<T, NF>(rmax);
+    if (lds > 160 * 1024) { set_error("filter radius too large for the LDS tile"); return TO_EUNSUPPORTED; }
+    auto k = filter2d_batch_kernel<T, MODE, V, LS>;
+    TO_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, 64 * parts, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const int blocks = std::max(1, std::min(ntiles, per_cu * num_cu));
+    const int chunk = std::max(1, ntiles / (blocks * (W >= 16 ? 8 : 2)));
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * parts), lds, s, (const Filt2dArgs<T>*)tab, tile0, n, ctr, chunk);
+    TO_HIP(hipGetLastError());
+    return TO_OK;
+}
+
+// the LDS column stride as a compile-time constant where the largest radius allows
+template <typename T, int MODE>
+static to_status run_filter_batch(const void* tab, const int32_t* tile0, int n, int ntiles, int rmax, int num_cu,
+                                  unsigned* ctr, hipStream_t s) {
+    const int ly = 64 + 2 * rmax;
+    if (ly <= 96) return run_filter_batch_ls<T, MODE, 96>(tab, tile0, n, ntiles, rmax, num_cu, ctr, s);
+    if (ly <= 160) return run_filter_batch_ls<T, MODE, 160>(tab, tile0, n, ntiles, rmax, num_cu, ctr, s);
+    if (ly <= 224) return run_filter_batch_ls<T, MODE, 224>(tab, tile0, n, ntiles, rmax, num_cu, ctr, s);
+    return run_filter_batch_ls<T, MODE, 0>(tab, tile0, n, ntiles, rmax, num_cu, ctr, s);
+}
+
+to_status launch_filter_batch(to_dtype dt, int mode, const void* tab, const int32_t* tile0, int n, int ntiles,
+                              int rmax, int num_cu, unsigned* ctr, hipStream_t s) {
+    if (dt == TO_F64) {
+        if (mode == TO_FILTER_FWD) return run_filter_batch<double, M_FWD>(tab, tile0, n, ntiles, rmax, num_cu, ctr, s);
+        return run_filter_batch<double, M_ADJ2>(tab, tile0, n, ntiles, rmax, num_cu, ctr, s);
+    }
+    if (mode == TO_FILTER_FWD) return run_filter_batch<float, M_FWD>(tab, tile0, n, ntiles, rmax, num_cu, ctr, s);
+    return run_filter_batch<float, M_ADJ2>(tab, tile0, n, ntiles, rmax, num_cu, ctr, s);
 }
 
 }  // namespace topt

@@ -179,3 +179,70 @@ def test_batch64_ragged_configuration():
         gs.step()
         cb, cs = float(host(b.runs[i].c)[0]), float(host(gs.c)[0])
         assert abs(cb - cs) <= 1e-5 * abs(cs), (i, cb, cs)
+
+
+def _stage_check(b, x_before, penal):
+    """Every stage a batched iteration ran through its batch-wide launches
+    equals the single-design entry point on the same inputs: the stencil
+    passes and the moduli / assembly / sensitivity fields bit for bit (same
+    arithmetic per output), the compliance sum to rounding (another block
+    split)."""
+    from paper_2005_05436_amd import _lib as L
+    for g, x0 in zip(b.runs, x_before):
+        P, dt = g.plan.handle, g.dtype
+        xt = torch.zeros_like(g.xtilde)
+        L.to_filter(P, dt, L.TO_FILTER_FWD, x0, None, None, xt, None)
+        np.testing.assert_array_equal(host(xt), host(g.xtilde), err_msg=g.cfg.name)
+        kv = torch.zeros_like(g.kval)
+        L.to_assemble(P, dt, g.xphys, penal, kv)
+        np.testing.assert_array_equal(host(kv), host(g.kval), err_msg=g.cfg.name)
+        dc = torch.zeros_like(g.dc)
+        c = torch.zeros(1, dtype=torch.float64, device="cuda")
+        L.to_sensitivity(P, dt, g.xphys, g.u, g.f, penal, dc, c)
+        np.testing.assert_array_equal(host(dc), host(g.dc), err_msg=g.cfg.name)
+        cs, cb = float(host(c)[0]), float(host(g.c)[0])
+        assert abs(cs - cb) <= 1e-13 * abs(cs), (g.cfg.name, cs, cb)
+        o1, o2 = torch.zeros_like(g.dcf), torch.zeros_like(g.dv0)
+        L.to_filter(P, dt, L.TO_FILTER_ADJ2, g.dc, g.dv, g.dprj, o1, o2)
+        np.testing.assert_array_equal(host(o1), host(g.dcf), err_msg=g.cfg.name)
+        np.testing.assert_array_equal(host(o2), host(g.dv0), err_msg=g.cfg.name)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch_stage_launches_match_single_entry_points(precision):
+    """2D: the filter passes, moduli, assembly and sensitivities are one
+    launch each for the whole batch; each design's outputs equal the
+    single-design calls (eager and graph-replayed steps)."""
+    from paper_2005_05436_amd.driver import Batch
+    cfgs = ragged(precision)
+    b = Batch(cfgs, autotune=False)
+    info = b.info()
+    assert info["filter_batched"] and info["element_blocks"] >= len(cfgs)
+    for k in range(3):
+        x_before = [g.x.clone() for g in b.runs]
+        b.step(use_graph=(k > 0))
+        torch.cuda.synchronize()
+        _stage_check(b, x_before, 3.0)
+
+
+def test_batch_3d_designs():
+    """3D designs: per-design filter and assembly launches, batch-wide moduli
+    and sensitivities; stages equal the single-design calls, and the designs
+    follow their single runs to rounding."""
+    from paper_2005_05436_amd.driver import Batch, TopOpt
+    cfgs = [replace(W.C2_SMALL, name=f"b3_{i}", nelx=nx, nely=ny, nelz=nz, load=ld, rmin=rm)
+            for i, (nx, ny, nz, ld, rm) in enumerate([(12, 6, 6, 0, 1.5), (16, 8, 4, 2, 2.0), (10, 6, 8, 5, 1.8)])]
+    b = Batch(cfgs, autotune=False)
+    assert not b.info()["filter_batched"]
+    singles = [TopOpt(c) for c in cfgs]
+    for k in range(3):
+        x_before = [g.x.clone() for g in b.runs]
+        b.step()
+        for g in singles:
+            g.step()
+        torch.cuda.synchronize()
+        _stage_check(b, x_before, 3.0)
+        for gb, gs in zip(b.runs, singles):
+            cb, cs = float(host(gb.c)[0]), float(host(gs.c)[0])
+            assert abs(cb - cs) <= 1e-7 * abs(cs), (gb.cfg.name, k, cb, cs)
+            assert np.abs(host(gb.x) - host(gs.x)).max() <= 1e-6
