@@ -14,7 +14,7 @@ namespace topt {
 
 constexpr int kBlock = 256;             // threads per block (4 wave64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kBigBlock = 1024;         // persistent design-field kernels (16 wave64)
+constexpr int kBigBlock = 512;          // persistent design-field kernels (8 wave64: 256 registers, no spills)
 constexpr int kMaxCoopBlocks = 4096;    // partial-sum slots reserved per reduction
 constexpr int kPartialWidth = 32;       // doubles per block in the partial buffer
 constexpr unsigned kSpinLimit = 1u << 27;   // grid-barrier spin cap (~several seconds)

@@ -3,14 +3,16 @@
 // launched kernel.
 //
 // Bisection is a chain of decisions mean(x(lmid)) > volfrac.  Instead of one
-// grid-wide reduction per step, each sweep over the design evaluates the 15
-// midpoints of the next four levels of the bisection tree (each candidate's
+// grid-wide reduction per step, each sweep over the design evaluates the 31
+// midpoints of the next five levels of the bisection tree (each candidate's
 // bracket follows from (l1, l2) by the same midpoint arithmetic the serial
-// loop would do) and sums the candidate volumes; the blocks then walk the tree
-// with the same stop test as the serial loop.  The decisions, the midpoints
-// and the final design are therefore exactly those of plain bisection, with
-// four times fewer grid barriers.  Volume sums are double-double, so every
-// decision agrees with an exactly rounded sum except in exact ties.
+// loop would do) and sums the candidate volumes in FP64 together with a
+// rigorous bound on their rounding error; the blocks then walk the tree with
+// the same stop test as the serial loop.  A decision the bound cannot settle
+// is taken on a double-double sum of that one candidate (one more sweep), so
+// every decision agrees with the exactly rounded sum except in exact ties.
+// The decisions, the midpoints and the final design are therefore exactly
+// those of plain bisection, with up to five times fewer grid barriers.
 //
 // The same kernel runs the explicit primal-dual update of Appendix A instead
 // of the bisection (TO_OC_PD).  Further down: the bisection whose volume test

@@ -184,6 +184,8 @@ struct SolveArgs {
     float* v32[8];
     double rtol, inner_rtol;
     int maxit, zero_x0;
+    int stage;                  // 2D FP64 matrix-free: nodes of the LDS window of the SpMV source (0: off)
+    int pad;
     double* partial; unsigned* bar;
     unsigned long long* ll;
     to_solve_stats* st;
@@ -207,12 +209,24 @@ struct Ctx {
     }
 };
 
+// Source of the 2D SpMV read from the block's LDS window: nodes wlo ..
+// wlo + wn - 1 (the block's own range and the band on either side), two
+// values per node.
+template <typename T>
+struct SrcLds {
+    const T* w;
+    int64_t wlo;
+    __device__ __forceinline__ T operator()(int64_t q, int c) const { return w[2 * (q - wlo) + c]; }
+};
+
 template <int DIM, typename T, class Op>
 struct Pcg {
     const Op& op;
     const Geo& g;
     const uint8_t* __restrict__ fm;
     Ctx& C;
+    T* win = nullptr;            // LDS window of the direction (2D; nullptr: gather from memory)
+    int64_t wlo = 0, wn = 0;
 
     // r = b - A x (x = 0: r = b), z = dinv r; returns (r.z, r.r) in C.res
     __device__ void residual(const T* b, const T* x, bool x_zero, const T* dinv, T* r, T* z) {
@@ -271,19 +285,44 @@ struct Pcg {
             // phase A: pnew = z + beta pold; q = A pnew
             double v1[1] = {0.0};
             const SrcZP<DIM, T> src{z, pold, (T)beta, o};
-            for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
-                int iy, ix, iz;
-                g.coords(nd, iy, ix, iz, DIM);
-                T ap[DIM];
-                op.apply(nd, iy, ix, iz, src, ap);
+            if (DIM == 2 && win) {
+                // the direction over the window, staged once with coalesced
+                // loads (the band from the neighbouring blocks' stores), then
+                // the SpMV gathers from LDS
+                for (int64_t i = threadIdx.x; i < 2 * wn; i += (int64_t)blockDim.x)
+                    win[i] = src(wlo + (i >> 1), (int)(i & 1));
+                __syncthreads();
+                const SrcLds<T> sl{win, wlo};
+                for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
+                    int iy, ix, iz;
+                    g.coords(nd, iy, ix, iz, DIM);
+                    T ap[DIM];
+                    op.apply(nd, iy, ix, iz, sl, ap);
 #pragma unroll
-                for (int c = 0; c < DIM; ++c) {
-                    const int64_t i = DIM * nd + c;
-                    const T pi = src(nd, c);
-                    const T qi = fm[i] ? ap[c] : T(0);
-                    o.st(pnew, nd, i, pi);
-                    q[i] = qi;
-                    v1[0] += (double)pi * (double)qi;
+                    for (int c = 0; c < DIM; ++c) {
+                        const int64_t i = DIM * nd + c;
+                        const T pi = sl(nd, c);
+                        const T qi = fm[i] ? ap[c] : T(0);
+                        o.st(pnew, nd, i, pi);
+                        q[i] = qi;
+                        v1[0] += (double)pi * (double)qi;
+                    }
+                }
+            } else {
+                for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
+                    int iy, ix, iz;
+                    g.coords(nd, iy, ix, iz, DIM);
+                    T ap[DIM];
+                    op.apply(nd, iy, ix, iz, src, ap);
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        const int64_t i = DIM * nd + c;
+                        const T pi = src(nd, c);
+                        const T qi = fm[i] ? ap[c] : T(0);
+                        o.st(pnew, nd, i, pi);
+                        q[i] = qi;
+                        v1[0] += (double)pi * (double)qi;
+                    }
                 }
             }
             C.reduce<1>(v1);
@@ -534,6 +573,13 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
                 jacobi<DIM, double>(mf64, g, C.o, A.freem, dinv);
             }
             Pcg<DIM, double, MatFree<DIM, double>> cg{mf64, g, A.freem, C};
+            if (DIM == 2 && A.stage > 0) {
+                extern __shared__ double solve_win[];
+                cg.wlo = o.lo - o.band > 0 ? o.lo - o.band : 0;
+                const int64_t whi = o.hi + o.band < g.nnode ? o.hi + o.band : g.nnode;
+                cg.wn = whi - cg.wlo;
+                if (cg.wn <= A.stage) cg.win = solve_win;     // else (never, by the launch's sizing) gather
+            }
             iters = cg.run(A.f, u, false, dinv, r, z, pa, pb, q, tol, A.maxit, restarts);
         }
         resid = sqrt(C.res[1]) / (bnorm > 0 ? bnorm : 1.0);
@@ -585,6 +631,7 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
 // registers, so a block of 16 waves (one block per CU) hides the gather
 // latency without adding blocks to every grid reduction; the others use 4.
 constexpr int solve_block(int dim, int mode) { return dim == 2 && mode <= 1 ? 1024 : 256; }
+constexpr size_t kSolveWindowBytes = 96 * 1024;
 
 template <int DIM, int MODE>
 __global__ __launch_bounds__(solve_block(DIM, MODE)) void solve_kernel(SolveArgs A) {
@@ -610,8 +657,21 @@ static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream
     int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, p->num_cu), want));
     if (req_blocks > 0) blocks = std::min(req_blocks, maxb);
     blocks = std::min(blocks, kMaxCoopBlocks);
+    // 2D matrix-free FP64: the direction's window (own nodes and the band on
+    // either side) in LDS when it fits beside one block per CU
+    size_t lds = 0;
+    A.stage = 0;
+    if (DIM == 2 && MODE == 1) {
+        const int64_t chunk = (A.geo.nnode + blocks - 1) / blocks;
+        const int64_t wn = std::min<int64_t>(A.geo.nnode, chunk + 2 * ((int64_t)A.geo.ny + 2));
+        const size_t bytes = (size_t)wn * 2 * sizeof(double);
+        if (bytes <= kSolveWindowBytes && coop_blocks_for((const void*)k, SB, bytes, p->num_cu) >= blocks) {
+            A.stage = (int)wn;
+            lds = bytes;
+        }
+    }
     void* args[] = {&A};
-    TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(SB), args, 0, s));
+    TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(SB), args, lds, s));
     return TO_OK;
 }
 
