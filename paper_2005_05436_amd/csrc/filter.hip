@@ -235,7 +235,7 @@ __device__ __forceinline__ void filter2d_tile(const Filt2dArgs<T>& fa, int t, T*
 template <typename T, int MODE, int V, int LS>
 __global__ __launch_bounds__(64 * filt_max_parts<T>()) void filter2d_kernel(Filt2dArgs<T> A, unsigned* ctr,
                                                                           const unsigned* skip, int chunk) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];   // 16-byte aligned: FP64 and wide LDS accesses
     __shared__ int tile_sh;
     if (skip && *skip) return;          // the whole launch is cancelled (the tile counter is untouched)
     T* tile = reinterpret_cast<T*>(smem_raw);
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(64 * filt_max_parts<T>()) void filter2d_kernel(Filt
 template <typename T, int MODE, int V, int LS>
 __global__ __launch_bounds__(64 * filt_max_parts<T>()) void filter2d_batch_kernel(
     const Filt2dArgs<T>* __restrict__ tab, const int32_t* __restrict__ tile0, int ndesign, unsigned* ctr, int chunk) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];   // 16-byte aligned: FP64 and wide LDS accesses
     __shared__ int tile_sh;
     T* tile = reinterpret_cast<T*>(smem_raw);
     const int ntiles = tile0[ndesign];
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(512) void filter2d_mfma_kernel(
     const T* __restrict__ Hs, const T* __restrict__ in, const T* __restrict__ in2,
     const T* __restrict__ sc, T* __restrict__ out, T* __restrict__ out2, unsigned* ctr,
     const unsigned* skip, int chunk, int wofs) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];   // 16-byte aligned: FP64 and wide LDS accesses
     __shared__ int tile_sh;
     if (skip && *skip) return;          // the whole launch is cancelled (the tile counter is untouched)
     constexpr int NF = MODE == M_ADJ2 ? 2 : 1;
@@ -484,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void filter3d_kernel(
     const int32_t* __restrict__ hlim, const T* __restrict__ Hs, const T* __restrict__ in,
     const T* __restrict__ in2, const T* __restrict__ sc, T* __restrict__ out, T* __restrict__ out2,
     const unsigned* skip) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];   // 16-byte aligned: FP64 and wide LDS accesses
     if (skip && *skip) return;          // the whole launch is cancelled
     T* tile = reinterpret_cast<T*>(smem_raw);
     constexpr int NF = MODE == M_ADJ2 ? 2 : 1;
