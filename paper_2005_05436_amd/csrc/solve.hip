@@ -357,6 +357,159 @@ struct Pcg {
         if (confirm && !fresh && C.alive) residual(b, x, false, dinv, r, z);   // report the true residual
         return it;
     }
+
+    // The same solve with ONE grid sum per iteration (the Chronopoulos-Gear
+    // arrangement of preconditioned CG; 2D, the SpMV source in the LDS
+    // window).  With u = M^-1 r and w = A u, the recurrences
+    //   p = u + beta p,  s = w + beta s  (s = A p),
+    //   x += alpha p,    r -= alpha s,   u = M^-1 r,   w = A u,
+    //   gamma = (r, u),  delta = (w, u),
+    //   beta = gamma / gamma_old,  alpha = gamma / (delta - beta gamma / alpha_old)
+    // give the iterates of PCG in exact arithmetic, and the three dot
+    // products of an iteration (gamma, delta, |r|^2) are summed together.
+    // The new u of the band nodes (owned by neighbouring blocks, which write
+    // their new r and s meanwhile) is formed here from their previous r, w
+    // and s, so r, w and s are double-buffered by iteration parity; the
+    // operations are those of the owner, so every block sees the same u.
+    // Convergence is confirmed on the recomputed residual b - A x, and a
+    // failed confirmation restarts from x, as in run.
+    __device__ int run1(const T* b, T* x, const T* dinv, T* R0, T* R1, T* W0, T* W1, T* S0, T* S1, T* P, double tol,
+                        int maxit, int& restarts) {
+        const Own& o = C.o;
+        const int64_t whi = wlo + wn;
+        const int64_t nlo = 2 * (o.lo - wlo), nh = nlo + 2 * (whi - o.hi);   // band values below / in total
+        int it = 0;
+        while (C.alive) {
+            // (re)start: r = b - A x (the true residual), then u, w = A u
+            {
+                double v[2] = {0.0, 0.0};
+                for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
+                    int iy, ix, iz;
+                    g.coords(nd, iy, ix, iz, 2);
+                    T ax[2];
+                    op.apply(nd, iy, ix, iz, Src1<2, T>{x, o}, ax);
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int64_t i = 2 * nd + c;
+                        const T ri = fm[i] ? b[i] - ax[c] : T(0);
+                        o.st(R0, nd, i, ri);
+                        v[0] += (double)ri * (double)(dinv[i] * ri);
+                        v[1] += (double)ri * (double)ri;
+                    }
+                }
+                C.reduce<2>(v);
+            }
+            double rr = C.res[1];
+            if (rr <= tol * tol || !C.alive) break;       // a fresh residual needs no confirmation
+            {
+                for (int64_t t = threadIdx.x; t < 2 * wn; t += (int64_t)blockDim.x) {
+                    const int64_t q = wlo + (t >> 1), i = 2 * q + (t & 1);
+                    win[t] = o.ld(dinv, q, i) * o.ld(R0, q, i);
+                }
+                __syncthreads();
+                const SrcLds<T> sl{win, wlo};
+                double v[2] = {0.0, 0.0};
+                for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
+                    int iy, ix, iz;
+                    g.coords(nd, iy, ix, iz, 2);
+                    T aw[2];
+                    op.apply(nd, iy, ix, iz, sl, aw);
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int64_t i = 2 * nd + c;
+                        const T ui = sl(nd, c), wi = fm[i] ? aw[c] : T(0);
+                        o.st(W0, nd, i, wi);
+                        v[0] += (double)R0[i] * (double)ui;
+                        v[1] += (double)wi * (double)ui;
+                    }
+                }
+                C.reduce<2>(v);
+            }
+            double gamma = C.res[0], delta = C.res[1], gamma_old = 1.0, alpha_old = 1.0;
+            int k = 0;
+            bool ok = true;
+            while (C.alive && rr > tol * tol && it < maxit) {
+                double beta = 0.0, alpha;
+                if (k == 0) {
+                    alpha = gamma / delta;
+                } else {
+                    beta = gamma / gamma_old;
+                    alpha = gamma / (delta - beta * gamma / alpha_old);
+                }
+                if (!(alpha > 0.0) || !(alpha < INFINITY)) { ok = false; break; }   // breakdown
+                const bool odd = k & 1;
+                const T* Rk = odd ? R1 : R0;
+                T* Rn = odd ? R0 : R1;
+                const T* Wk = odd ? W1 : W0;
+                T* Wn = odd ? W0 : W1;
+                T* Sk = odd ? S1 : S0;
+                const T* So = odd ? S0 : S1;
+                const T a = (T)alpha, bt = (T)beta;
+                double v[3] = {0.0, 0.0, 0.0};        // gamma, delta, |r|^2
+                for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int64_t i = 2 * nd + c;
+                        const T di = dinv[i], rk = Rk[i], wk = Wk[i];
+                        const T ui = di * rk;
+                        const T pi = k == 0 ? ui : fma(bt, P[i], ui);
+                        const T si = k == 0 ? wk : fma(bt, So[i], wk);
+                        const T rn = fma(-a, si, rk);
+                        const T un = di * rn;
+                        P[i] = pi;
+                        o.st(x, nd, i, fma(a, pi, x[i]));
+                        o.st(Sk, nd, i, si);
+                        o.st(Rn, nd, i, rn);
+                        win[2 * (nd - wlo) + c] = un;
+                        v[0] += (double)rn * (double)un;
+                        v[2] += (double)rn * (double)rn;
+                    }
+                }
+                for (int64_t t = threadIdx.x; t < nh; t += (int64_t)blockDim.x) {
+                    const int64_t j = t < nlo ? t : t - nlo + 2 * (o.hi - wlo);   // window value index
+                    const int64_t q = wlo + (j >> 1), i = 2 * q + (j & 1);
+                    const T di = o.ld(dinv, q, i), rk = o.ld(Rk, q, i), wk = o.ld(Wk, q, i);
+                    const T si = k == 0 ? wk : fma(bt, o.ld(So, q, i), wk);
+                    const T rn = fma(-a, si, rk);
+                    win[j] = di * rn;
+                }
+                __syncthreads();
+                const SrcLds<T> sl{win, wlo};
+                for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
+                    int iy, ix, iz;
+                    g.coords(nd, iy, ix, iz, 2);
+                    T aw[2];
+                    op.apply(nd, iy, ix, iz, sl, aw);
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int64_t i = 2 * nd + c;
+                        const T wi = fm[i] ? aw[c] : T(0);
+                        o.st(Wn, nd, i, wi);
+                        v[1] += (double)wi * (double)sl(nd, c);
+                    }
+                }
+                C.reduce<3>(v);
+                gamma_old = gamma;
+                alpha_old = alpha;
+                gamma = C.res[0];
+                delta = C.res[1];
+                rr = C.res[2];
+                ++k;
+                ++it;
+            }
+            if (!C.alive) break;
+            if (ok && rr <= tol * tol) {
+                // confirm on the recomputed residual; a failure restarts
+                residual(b, x, false, dinv, R0, S1);
+                if (C.res[1] <= tol * tol) break;
+                ++restarts;
+                continue;
+            }
+            residual(b, x, false, dinv, R0, S1);          // breakdown or budget spent: report the true residual
+            break;
+        }
+        return it;
+    }
 };
 
 template <int DIM, typename T, class Op>
@@ -369,7 +522,7 @@ __device__ void jacobi(const Op& op, const Geo& g, const Own& o, const uint8_t* 
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const int64_t i = DIM * nd + c;
-            dinv[i] = fm[i] && dg[c] != T(0) ? T(1) / dg[c] : T(0);
+            o.st(dinv, nd, i, fm[i] && dg[c] != T(0) ? T(1) / dg[c] : T(0));
         }
     }
 }
@@ -509,7 +662,10 @@ __device__ bool mixed_cg(Ctx& C, const Geo& g, const SolveArgs& A, const Op32& o
 }
 
 // MODE 0: FP64, assembled operator; 1: FP64, matrix-free;
-//      2: mixed, FP32 assembled inner; 3: mixed, FP32 matrix-free inner.
+//      2: mixed, FP32 assembled inner; 3: mixed, FP32 matrix-free inner;
+//      kModeWindow: 2D FP64 matrix-free with the SpMV source in an LDS window
+//      and one grid sum per iteration (Pcg::run1).
+constexpr int kModeWindow = 4;
 template <int DIM, int MODE>
 __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
     __shared__ double sh[16];
@@ -552,7 +708,7 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
     double resid = 0.0;
 
     MatFree<DIM, double> mf64{A.E64, A.kf64, g.nx, g.ny, g.nz};
-    if (MODE <= 1) {
+    if (MODE <= 1 || MODE == kModeWindow) {
         double *r = A.v64[0], *z = A.v64[1], *pa = A.v64[2], *pb = A.v64[3], *q = A.v64[4], *dinv = A.v64[5];
         if (MODE == 0) {
             CsrS<DIM, double> op{A.rp, (const double*)A.kval, g.nx, g.ny, g.nz};
@@ -567,7 +723,7 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
                         const int64_t i = DIM * nd + c;
                         const int64_t k = A.rp[i + 1] - 1;
                         const double dg = A.kdiag64 ? A.kdiag64[k] : (double)A.kdiag32[k];
-                        dinv[i] = A.freem[i] && dg != 0.0 ? 1.0 / dg : 0.0;
+                        o.st(dinv, nd, i, A.freem[i] && dg != 0.0 ? 1.0 / dg : 0.0);
                     }
             } else {
                 jacobi<DIM, double>(mf64, g, C.o, A.freem, dinv);
@@ -580,7 +736,12 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
                 cg.wn = whi - cg.wlo;
                 if (cg.wn <= A.stage) cg.win = solve_win;     // else (never, by the launch's sizing) gather
             }
-            iters = cg.run(A.f, u, false, dinv, r, z, pa, pb, q, tol, A.maxit, restarts);
+            if constexpr (DIM == 2 && MODE == kModeWindow) {
+                if (cg.win) iters = cg.run1(A.f, u, dinv, r, z, pb, q, A.v64[6], A.v64[7], pa, tol, A.maxit, restarts);
+                else C.alive = false;      // the launch sizes the window; a kernel without one reports failure
+            } else {
+                iters = cg.run(A.f, u, false, dinv, r, z, pa, pb, q, tol, A.maxit, restarts);
+            }
         }
         resid = sqrt(C.res[1]) / (bnorm > 0 ? bnorm : 1.0);
     } else {
@@ -630,7 +791,7 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
 // Threads per block of the persistent solve: 2D FP64 kernels fit in 128
 // registers, so a block of 16 waves (one block per CU) hides the gather
 // latency without adding blocks to every grid reduction; the others use 4.
-constexpr int solve_block(int dim, int mode) { return dim == 2 && mode <= 1 ? 1024 : 256; }
+constexpr int solve_block(int dim, int mode) { return dim == 2 && (mode <= 1 || mode == 4) ? 1024 : 256; }
 constexpr size_t kSolveWindowBytes = 96 * 1024;
 
 template <int DIM, int MODE>
@@ -657,21 +818,24 @@ static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream
     int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(maxb, p->num_cu), want));
     if (req_blocks > 0) blocks = std::min(req_blocks, maxb);
     blocks = std::min(blocks, kMaxCoopBlocks);
-    // 2D matrix-free FP64: the direction's window (own nodes and the band on
-    // either side) in LDS when it fits beside one block per CU
-    size_t lds = 0;
     A.stage = 0;
-    if (DIM == 2 && MODE == 1) {
+    if constexpr (DIM == 2 && MODE == 1) {
+        // 2D matrix-free FP64: when the block's window (own nodes and the band
+        // on either side) fits in LDS beside one block per CU, the kernel
+        // with the window and one grid sum per iteration
+        auto kw = solve_kernel<2, kModeWindow>;
         const int64_t chunk = (A.geo.nnode + blocks - 1) / blocks;
         const int64_t wn = std::min<int64_t>(A.geo.nnode, chunk + 2 * ((int64_t)A.geo.ny + 2));
         const size_t bytes = (size_t)wn * 2 * sizeof(double);
-        if (bytes <= kSolveWindowBytes && coop_blocks_for((const void*)k, SB, bytes, p->num_cu) >= blocks) {
+        if (bytes <= kSolveWindowBytes && coop_blocks_for((const void*)kw, SB, bytes, p->num_cu) >= blocks) {
             A.stage = (int)wn;
-            lds = bytes;
+            void* args[] = {&A};
+            TO_HIP(hipLaunchCooperativeKernel((const void*)kw, dim3(blocks), dim3(SB), args, bytes, s));
+            return TO_OK;
         }
     }
     void* args[] = {&A};
-    TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(SB), args, lds, s));
+    TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(SB), args, 0, s));
     return TO_OK;
 }
 
