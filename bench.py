@@ -105,11 +105,16 @@ def stage_bytes(cfg, info, dt_bytes, op, solve):
     opk, vp = solve_path(cfg, op, solve)
     V = 4 if vp == "f32" else 8
     mat = (F * nnz + 4 * (n + 1)) if opk == "assembled" else V * m   # K^(s) values + row_ptr | moduli
-    phase_a = mat + 2 * V * n + 2 * V * n + n                 # z, p_old in; p_new, q out; free mask
-    phase_b = 5 * V * n + 3 * V * n                           # x, p, r, q, dinv in; x, r, z out
-    if vp == "f32":
-        phase_b += 2 * 4 * n                                  # the iterate u stays FP64
-    b["solve_per_iter_kernel_model"] = phase_a + phase_b
+    if info.dim == 2 and opk == "matfree" and vp == "f64":
+        # one sweep per iteration (single grid sum): dinv, r, w, s_old, p, x in;
+        # p, s, x, r, w out; moduli and free mask
+        b["solve_per_iter_kernel_model"] = mat + 6 * V * n + 5 * V * n + n
+    else:
+        phase_a = mat + 2 * V * n + 2 * V * n + n             # z, p_old in; p_new, q out; free mask
+        phase_b = 5 * V * n + 3 * V * n                       # x, p, r, q, dinv in; x, r, z out
+        if vp == "f32":
+            phase_b += 2 * 4 * n                              # the iterate u stays FP64
+        b["solve_per_iter_kernel_model"] = phase_a + phase_b
     b["solve_kernel"] = {"operator": opk, "vectors": vp}
     return b
 
@@ -907,7 +912,7 @@ def main():
     I = g.plan.info
     K = args.steps
     sol = rec["solve"]
-    tpi = measured_traffic("solve_kernel<2, 1>") if I.dim == 2 else None
+    tpi = measured_traffic("solve_kernel<2, 4>") if I.dim == 2 else None
     roof = {"kernel": sol["kernel"], "bound": "hbm", "achieved": sol["gbps"], "peak": HBM_PEAK / 1e9,
             "unit": "GB/s", "frac": round(sol["gbps"] * 1e9 / HBM_PEAK, 4),
             "traffic": None if tpi is None else round(tpi * sol["cg_iterations_per_launch"]),
