@@ -185,7 +185,7 @@ struct SolveArgs {
     double rtol, inner_rtol;
     int maxit, zero_x0;
     int stage;                  // 2D FP64 matrix-free: nodes of the LDS window of the SpMV source (0: off)
-    int pad;
+    int stage_own;              // with the window: own-node capacity of the LDS copies of dinv, x, p (0: off)
     double* partial; unsigned* bar;
     unsigned long long* ll;
     to_solve_stats* st;
@@ -227,6 +227,7 @@ struct Pcg {
     Ctx& C;
     T* win = nullptr;            // LDS window of the direction (2D; nullptr: gather from memory)
     int64_t wlo = 0, wn = 0;
+    T* own = nullptr;            // run1: LDS copies of dinv, x and p on the own nodes (nullptr: in memory)
 
     // r = b - A x (x = 0: r = b), z = dinv r; returns (r.z, r.r) in C.res
     __device__ void residual(const T* b, const T* x, bool x_zero, const T* dinv, T* r, T* z) {
@@ -373,11 +374,33 @@ struct Pcg {
     // operations are those of the owner, so every block sees the same u.
     // Convergence is confirmed on the recomputed residual b - A x, and a
     // failed confirmation restarts from x, as in run.
-    __device__ int run1(const T* b, T* x, const T* dinv, T* R0, T* R1, T* W0, T* W1, T* S0, T* S1, T* P, double tol,
+    __device__ int run1(const T* b, T* x, const T* dinv, T* R0, T* R1, T* W0, T* W1, T* S0, T* S1, double tol,
                         int maxit, int& restarts) {
         const Own& o = C.o;
         const int64_t whi = wlo + wn;
         const int64_t nlo = 2 * (o.lo - wlo), nh = nlo + 2 * (whi - o.hi);   // band values below / in total
+        // dinv, x and p of the own nodes can live in LDS for the whole solve
+        // (read and written by this block only; x goes back to memory before
+        // every true residual and at the end)
+        const int64_t nown = 2 * (o.hi - o.lo), i0 = 2 * o.lo;
+        T* const dl = own;
+        T* const xl = own + nown;
+        T* const pl = own + 2 * nown;
+        // each own value is moved by the thread that wrote it (the node loop's
+        // thread mapping), so no barrier is needed before these reads
+        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int64_t i = 2 * nd + c;
+                dl[i - i0] = dinv[i];
+                xl[i - i0] = x[i];
+            }
+        auto flush_x = [&]() {
+            for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) o.st(x, nd, 2 * nd + c, xl[2 * nd + c - i0]);
+            C.alive = C.gb.sync() && C.alive;       // the band of x is read by the neighbours' residual
+        };
         int it = 0;
         while (C.alive) {
             // (re)start: r = b - A x (the true residual), then u, w = A u
@@ -449,15 +472,15 @@ struct Pcg {
                 for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
-                        const int64_t i = 2 * nd + c;
-                        const T di = dinv[i], rk = Rk[i], wk = Wk[i];
+                        const int64_t i = 2 * nd + c, j = i - i0;
+                        const T di = dl[j], rk = Rk[i], wk = Wk[i];
                         const T ui = di * rk;
-                        const T pi = k == 0 ? ui : fma(bt, P[i], ui);
+                        const T pi = k == 0 ? ui : fma(bt, pl[j], ui);
                         const T si = k == 0 ? wk : fma(bt, So[i], wk);
                         const T rn = fma(-a, si, rk);
                         const T un = di * rn;
-                        P[i] = pi;
-                        o.st(x, nd, i, fma(a, pi, x[i]));
+                        pl[j] = pi;
+                        xl[j] = fma(a, pi, xl[j]);
                         o.st(Sk, nd, i, si);
                         o.st(Rn, nd, i, rn);
                         win[2 * (nd - wlo) + c] = un;
@@ -498,6 +521,7 @@ struct Pcg {
                 ++it;
             }
             if (!C.alive) break;
+            flush_x();
             if (ok && rr <= tol * tol) {
                 // confirm on the recomputed residual; a failure restarts
                 residual(b, x, false, dinv, R0, S1);
@@ -734,11 +758,14 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
                 cg.wlo = o.lo - o.band > 0 ? o.lo - o.band : 0;
                 const int64_t whi = o.hi + o.band < g.nnode ? o.hi + o.band : g.nnode;
                 cg.wn = whi - cg.wlo;
-                if (cg.wn <= A.stage) cg.win = solve_win;     // else (never, by the launch's sizing) gather
+                if (cg.wn <= A.stage) {                      // else (never, by the launch's sizing) gather
+                    cg.win = solve_win;
+                    if (A.stage_own > 0 && o.hi - o.lo <= A.stage_own) cg.own = solve_win + 2 * (int64_t)A.stage;
+                }
             }
             if constexpr (DIM == 2 && MODE == kModeWindow) {
-                if (cg.win) iters = cg.run1(A.f, u, dinv, r, z, pb, q, A.v64[6], A.v64[7], pa, tol, A.maxit, restarts);
-                else C.alive = false;      // the launch sizes the window; a kernel without one reports failure
+                if (cg.win && cg.own) iters = cg.run1(A.f, u, dinv, r, z, pb, q, A.v64[6], A.v64[7], tol, A.maxit, restarts);
+                else C.alive = false;      // the launch sizes the LDS; a kernel without it reports failure
             } else {
                 iters = cg.run(A.f, u, false, dinv, r, z, pa, pb, q, tol, A.maxit, restarts);
             }
@@ -792,7 +819,7 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
 // registers, so a block of 16 waves (one block per CU) hides the gather
 // latency without adding blocks to every grid reduction; the others use 4.
 constexpr int solve_block(int dim, int mode) { return dim == 2 && (mode <= 1 || mode == 4) ? 1024 : 256; }
-constexpr size_t kSolveWindowBytes = 96 * 1024;
+constexpr size_t kSolveLdsBytes = 150 * 1024;     // dynamic LDS of the windowed kernel (one block per CU)
 
 template <int DIM, int MODE>
 __global__ __launch_bounds__(solve_block(DIM, MODE)) void solve_kernel(SolveArgs A) {
@@ -819,6 +846,7 @@ static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream
     if (req_blocks > 0) blocks = std::min(req_blocks, maxb);
     blocks = std::min(blocks, kMaxCoopBlocks);
     A.stage = 0;
+    A.stage_own = 0;
     if constexpr (DIM == 2 && MODE == 1) {
         // 2D matrix-free FP64: when the block's window (own nodes and the band
         // on either side) fits in LDS beside one block per CU, the kernel
@@ -826,11 +854,23 @@ static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream
         auto kw = solve_kernel<2, kModeWindow>;
         const int64_t chunk = (A.geo.nnode + blocks - 1) / blocks;
         const int64_t wn = std::min<int64_t>(A.geo.nnode, chunk + 2 * ((int64_t)A.geo.ny + 2));
-        const size_t bytes = (size_t)wn * 2 * sizeof(double);
-        if (bytes <= kSolveWindowBytes && coop_blocks_for((const void*)kw, SB, bytes, p->num_cu) >= blocks) {
+        const size_t win_bytes = (size_t)wn * 2 * sizeof(double);
+        const size_t own_bytes = (size_t)chunk * 6 * sizeof(double);     // dinv, x, p of the own nodes
+        auto fits = [&](size_t b) {
+            return b <= kSolveLdsBytes && coop_blocks_for((const void*)kw, SB, b, p->num_cu) >= blocks;
+        };
+        if (fits(win_bytes + own_bytes)) {
+            A.stage = (int)wn;
+            A.stage_own = (int)chunk;
+            void* args[] = {&A};
+            TO_HIP(hipLaunchCooperativeKernel((const void*)kw, dim3(blocks), dim3(SB), args, win_bytes + own_bytes, s));
+            return TO_OK;
+        }
+        if (win_bytes <= kSolveLdsBytes && coop_blocks_for((const void*)k, SB, win_bytes, p->num_cu) >= blocks) {
+            // the window alone: the two-sum iteration with the SpMV from LDS
             A.stage = (int)wn;
             void* args[] = {&A};
-            TO_HIP(hipLaunchCooperativeKernel((const void*)kw, dim3(blocks), dim3(SB), args, bytes, s));
+            TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(SB), args, win_bytes, s));
             return TO_OK;
         }
     }
