@@ -125,6 +125,7 @@ struct MatFree<2, T> {
     const T* __restrict__ E;
     const T* __restrict__ ke;
     int nx, ny, nz;
+    int64_t e0 = 0;              // E holds the moduli from element e0 on (a window of them)
     static constexpr int D = 8;
 
     template <class S>
@@ -148,7 +149,7 @@ struct MatFree<2, T> {
         for (int a = 0; a < 4; ++a) {
             const int ey = iy - CY[a], ex = ix - CX[a];
             if (ey < 0 || ey >= ny || ex < 0 || ex >= nx) continue;
-            const T Ee = E[ey + (int64_t)ny * ex];
+            const T Ee = E[ey + (int64_t)ny * ex - e0];
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const T* kr = ke + (a * 2 + c) * D;
@@ -171,7 +172,7 @@ struct MatFree<2, T> {
         for (int a = 0; a < 4; ++a) {
             const int ey = iy - CY[a], ex = ix - CX[a];
             if (ey < 0 || ey >= ny || ex < 0 || ex >= nx) continue;
-            const T Ee = E[ey + (int64_t)ny * ex];
+            const T Ee = E[ey + (int64_t)ny * ex - e0];
 #pragma unroll
             for (int c = 0; c < 2; ++c) out[c] += Ee * ke[(a * 2 + c) * D + a * 2 + c];
         }

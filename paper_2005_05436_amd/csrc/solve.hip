@@ -186,6 +186,8 @@ struct SolveArgs {
     int maxit, zero_x0;
     int stage;                  // 2D FP64 matrix-free: nodes of the LDS window of the SpMV source (0: off)
     int stage_own;              // with the window: own-node capacity of the LDS copies of dinv, x, p (0: off)
+    int stage_e;                // with them: capacity of the LDS copy of the moduli the own nodes touch
+    int pad;
     double* partial; unsigned* bar;
     unsigned long long* ll;
     to_solve_stats* st;
@@ -386,6 +388,19 @@ struct Pcg {
         T* const dl = own;
         T* const xl = own + nown;
         T* const pl = own + 2 * nown;
+        // the moduli of the elements around the own nodes (columns ix_lo - 1 ..
+        // ix_hi) and the free-DOF flags of the own nodes, also in LDS: the
+        // SpMV then reads only LDS and the scalar-cached Ke
+        const int ny1 = g.ny + 1;
+        const int64_t exl = o.lo / ny1 > 0 ? o.lo / ny1 - 1 : 0;
+        const int64_t exh = (o.hi - 1) / ny1 < g.nx - 1 ? (o.hi - 1) / ny1 : g.nx - 1;
+        const int64_t elo = exl * g.ny, ne = (exh + 1) * g.ny - elo;
+        T* const el = own + 3 * nown;
+        uint8_t* const fl = reinterpret_cast<uint8_t*>(el + ne);
+        for (int64_t t = threadIdx.x; t < ne; t += (int64_t)blockDim.x) el[t] = op.E[elo + t];
+        Op opl = op;
+        opl.E = el;
+        opl.e0 = elo;
         // each own value is moved by the thread that wrote it (the node loop's
         // thread mapping), so no barrier is needed before these reads
         for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x)
@@ -394,7 +409,9 @@ struct Pcg {
                 const int64_t i = 2 * nd + c;
                 dl[i - i0] = dinv[i];
                 xl[i - i0] = x[i];
+                if (c == 1) fl[nd - o.lo] = (uint8_t)((fm[i - 1] ? 1 : 0) | (fm[i] ? 2 : 0));
             }
+        __syncthreads();
         auto flush_x = [&]() {
             for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x)
 #pragma unroll
@@ -502,11 +519,12 @@ struct Pcg {
                     int iy, ix, iz;
                     g.coords(nd, iy, ix, iz, 2);
                     T aw[2];
-                    op.apply(nd, iy, ix, iz, sl, aw);
+                    opl.apply(nd, iy, ix, iz, sl, aw);
+                    const int f2 = fl[nd - o.lo];
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
                         const int64_t i = 2 * nd + c;
-                        const T wi = fm[i] ? aw[c] : T(0);
+                        const T wi = (f2 >> c) & 1 ? aw[c] : T(0);
                         o.st(Wn, nd, i, wi);
                         v[1] += (double)wi * (double)sl(nd, c);
                     }
@@ -819,7 +837,7 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
 // registers, so a block of 16 waves (one block per CU) hides the gather
 // latency without adding blocks to every grid reduction; the others use 4.
 constexpr int solve_block(int dim, int mode) { return dim == 2 && (mode <= 1 || mode == 4) ? 1024 : 256; }
-constexpr size_t kSolveLdsBytes = 150 * 1024;     // dynamic LDS of the windowed kernel (one block per CU)
+constexpr size_t kSolveLdsBytes = 158 * 1024;     // dynamic LDS of the windowed kernel (one block per CU)
 
 template <int DIM, int MODE>
 __global__ __launch_bounds__(solve_block(DIM, MODE)) void solve_kernel(SolveArgs A) {
@@ -847,6 +865,7 @@ static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream
     blocks = std::min(blocks, kMaxCoopBlocks);
     A.stage = 0;
     A.stage_own = 0;
+    A.stage_e = 0;
     if constexpr (DIM == 2 && MODE == 1) {
         // 2D matrix-free FP64: when the block's window (own nodes and the band
         // on either side) fits in LDS beside one block per CU, the kernel
@@ -855,13 +874,18 @@ static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream
         const int64_t chunk = (A.geo.nnode + blocks - 1) / blocks;
         const int64_t wn = std::min<int64_t>(A.geo.nnode, chunk + 2 * ((int64_t)A.geo.ny + 2));
         const size_t win_bytes = (size_t)wn * 2 * sizeof(double);
-        const size_t own_bytes = (size_t)chunk * 6 * sizeof(double);     // dinv, x, p of the own nodes
+        // dinv, x, p of the own nodes; the moduli of the element columns they
+        // touch (at most chunk / (ny + 1) + 3 columns); a flag byte per node
+        const int64_t ecap = (int64_t)A.geo.ny * (chunk / ((int64_t)A.geo.ny + 1) + 3);
+        const size_t own_bytes = (size_t)chunk * 6 * sizeof(double) + (size_t)ecap * sizeof(double) +
+                                 (size_t)(chunk + 7) / 8 * 8;
         auto fits = [&](size_t b) {
             return b <= kSolveLdsBytes && coop_blocks_for((const void*)kw, SB, b, p->num_cu) >= blocks;
         };
         if (fits(win_bytes + own_bytes)) {
             A.stage = (int)wn;
             A.stage_own = (int)chunk;
+            A.stage_e = (int)ecap;
             void* args[] = {&A};
             TO_HIP(hipLaunchCooperativeKernel((const void*)kw, dim3(blocks), dim3(SB), args, win_bytes + own_bytes, s));
             return TO_OK;
