@@ -106,9 +106,10 @@ def stage_bytes(cfg, info, dt_bytes, op, solve):
     V = 4 if vp == "f32" else 8
     mat = (F * nnz + 4 * (n + 1)) if opk == "assembled" else V * m   # K^(s) values + row_ptr | moduli
     if info.dim == 2 and opk == "matfree" and vp == "f64":
-        # one sweep per iteration (single grid sum): dinv, r, w, s_old, p, x in;
-        # p, s, x, r, w out; moduli and free mask
-        b["solve_per_iter_kernel_model"] = mat + 6 * V * n + 5 * V * n + n
+        # one sweep per iteration (single grid sum) with dinv, x, p, the moduli
+        # and the free flags held in LDS for the whole solve: r, w, s_old in;
+        # s, r, w out
+        b["solve_per_iter_kernel_model"] = 6 * V * n
     else:
         phase_a = mat + 2 * V * n + 2 * V * n + n             # z, p_old in; p_new, q out; free mask
         phase_b = 5 * V * n + 3 * V * n                       # x, p, r, q, dinv in; x, r, z out
@@ -279,7 +280,7 @@ def batch_run(args):
     cfgs = W.batch_configs(64, 0)
     m_total = sum(c.m for c in cfgs)
     out = {"designs": len(cfgs), "elements": m_total, "steps": args.batch_steps}
-    for name, kw in (("jacobi", {}), ("gmg", {"precond": L.TO_PREC_GMG, "budget": 32, "op": L.TO_OP_HYBRID})):
+    for name, kw in (("jacobi", {}), ("gmg", {"precond": L.TO_PREC_GMG, "budget": 64, "op": L.TO_OP_HYBRID})):
         b = Batch(cfgs, autotune=True, **kw)
         b.step(use_graph=True)                       # warm-up: capture
         torch.cuda.synchronize()
@@ -599,7 +600,8 @@ def c3d_run(args):
     for name, prec, op, solve, pc in (("jacobi_f64", "f64", "hybrid", "auto", L.TO_PREC_JACOBI),
                                       ("jacobi_f32_mixed", "f32", "matfree", "mixed", L.TO_PREC_JACOBI),
                                       ("gmg_f64", "f64", "hybrid", "auto", L.TO_PREC_GMG)):
-        rec, g, sb = run_leg(a3, replace(W.C2, precision=prec), op, solve, precond=pc, budget=64)
+        # multigrid: the host-checked form (runs to convergence at every step)
+        rec, g, sb = run_leg(a3, replace(W.C2, precision=prec), op, solve, precond=pc, budget=0)
         c = g.stats()["c"]
         comp[name] = c
         lc = rec["loop_counts"]
@@ -618,7 +620,7 @@ def c3d_run(args):
     chk = {}
     for bc, paper_c in (("N", 3993.7), ("D", 4074.3)):
         cfg = replace(W.C2, name="cantilever48x24x24", nelx=48, nely=24, nelz=24, bc=bc, iterations=100)
-        g = TopOpt(cfg, precond=L.TO_PREC_GMG, budget=64)
+        g = TopOpt(cfg, precond=L.TO_PREC_GMG, budget=0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(100):
@@ -646,7 +648,7 @@ def run_leg(args, cfg, op_name, solve="auto", precond=0, budget=None):
     op = OPS[op_name]
     sp = {"auto": L.TO_SOLVE_AUTO, "f64": L.TO_SOLVE_F64, "mixed": L.TO_SOLVE_MIXED}[solve]
     g = TopOpt(cfg, op=op, solve_precision=sp, autotune=True, precond=precond,
-               budget=(budget or args.gmg_budget) if precond == L.TO_PREC_GMG else 0)
+               budget=(args.gmg_budget if budget is None else budget) if precond == L.TO_PREC_GMG else 0)
     I = g.plan.info
     stream = torch.cuda.current_stream()
     t = g.tuning
@@ -741,7 +743,6 @@ def run_leg(args, cfg, op_name, solve="auto", precond=0, budget=None):
         fc = {}
         for stage, nf, shape in (("filter", 1, t.filt_mfma), ("backfilter", 2, t.filt_mfma2)):
             sec = avg_ms[stage] * 1e-3
-            shape = shape if cfg.precision == "f32" else 0
             d = {"kernel": f"filter2d_mfma_kernel, tile shape {shape}" if shape else "filter2d_kernel (stencil)",
                  "useful_tflops": round(nf * useful * I.m / sec / 1e12, 1)}
             peak = FP32_PEAK if cfg.precision == "f32" else FP64_PEAK
@@ -922,7 +923,10 @@ def main():
             "us_per_cg_iteration": sol["us_per_cg_iteration"],
             "kernel_model": {"bytes_per_cg_iteration": sol["bytes_per_cg_iteration_kernel_model"],
                              "gbps": sol["gbps_kernel_model"],
-                             "frac": round(sol["gbps_kernel_model"] * 1e9 / HBM_PEAK, 4)}}
+                             "frac": round(sol["gbps_kernel_model"] * 1e9 / HBM_PEAK, 4)},
+            "note": ("achieved prices a CG iteration at the survey's CG row (the full FP64 CSR K); the kernel "
+                     "applies the matrix-free operator and never reads K, so that rate can pass the HBM peak; "
+                     "kernel_model counts the arrays this kernel reads and writes, traffic the counted bytes")}
     line = {
         "metric": METRIC, "value": rec["value"], "unit": "elem/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": rec["ms_per_step"], "higher_is_better": True,
