@@ -211,14 +211,14 @@ struct Ctx {
     }
 };
 
-// Source of the 2D SpMV read from the block's LDS window: nodes wlo ..
-// wlo + wn - 1 (the block's own range and the band on either side), two
+// Source of the SpMV read from the block's LDS window: nodes wlo ..
+// wlo + wn - 1 (the block's own range and the band on either side), DIM
 // values per node.
-template <typename T>
+template <int DIM, typename T>
 struct SrcLds {
     const T* w;
     int64_t wlo;
-    __device__ __forceinline__ T operator()(int64_t q, int c) const { return w[2 * (q - wlo) + c]; }
+    __device__ __forceinline__ T operator()(int64_t q, int c) const { return w[DIM * (q - wlo) + c]; }
 };
 
 template <int DIM, typename T, class Op>
@@ -260,6 +260,7 @@ struct Pcg {
     // scheme stops on the recursive residual: at high stiffness contrast the
     // FP32 recomputation of b - A x is dominated by cancellation, and the
     // outer FP64 residual is the judge anyway.
+    template <bool WIN = true>
     __device__ int run(const T* b, T* x, bool x_zero, const T* dinv, T* r, T* z, T* pa, T* pb, T* q,
                        double tol, int maxit, int& restarts, bool confirm = true) {
         const Own& o = C.o;
@@ -288,14 +289,29 @@ struct Pcg {
             // phase A: pnew = z + beta pold; q = A pnew
             double v1[1] = {0.0};
             const SrcZP<DIM, T> src{z, pold, (T)beta, o};
-            if (DIM == 2 && win) {
+            if (WIN && win) {
                 // the direction over the window, staged once with coalesced
                 // loads (the band from the neighbouring blocks' stores), then
                 // the SpMV gathers from LDS
-                for (int64_t i = threadIdx.x; i < 2 * wn; i += (int64_t)blockDim.x)
-                    win[i] = src(wlo + (i >> 1), (int)(i & 1));
+                // several values per thread and pass, their loads issued together
+                // (one memory latency per pass, not per value)
+                constexpr int U = DIM == 3 ? 8 : 2;
+                const int64_t nwin = DIM * wn, bd = blockDim.x;
+                for (int64_t i0 = threadIdx.x; i0 < nwin; i0 += U * bd) {
+                    T val[U];
+#pragma unroll
+                    for (int k2 = 0; k2 < U; ++k2) {
+                        const int64_t i = i0 + k2 * bd;
+                        val[k2] = i < nwin ? src(wlo + i / DIM, (int)(i % DIM)) : T(0);
+                    }
+#pragma unroll
+                    for (int k2 = 0; k2 < U; ++k2) {
+                        const int64_t i = i0 + k2 * bd;
+                        if (i < nwin) win[i] = val[k2];
+                    }
+                }
                 __syncthreads();
-                const SrcLds<T> sl{win, wlo};
+                const SrcLds<DIM, T> sl{win, wlo};
                 for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
                     int iy, ix, iz;
                     g.coords(nd, iy, ix, iz, DIM);
@@ -447,7 +463,7 @@ struct Pcg {
                     win[t] = o.ld(dinv, q, i) * o.ld(R0, q, i);
                 }
                 __syncthreads();
-                const SrcLds<T> sl{win, wlo};
+                const SrcLds<2, T> sl{win, wlo};
                 double v[2] = {0.0, 0.0};
                 for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
                     int iy, ix, iz;
@@ -514,7 +530,7 @@ struct Pcg {
                     win[j] = di * rn;
                 }
                 __syncthreads();
-                const SrcLds<T> sl{win, wlo};
+                const SrcLds<2, T> sl{win, wlo};
                 for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
                     int iy, ix, iz;
                     g.coords(nd, iy, ix, iz, 2);
@@ -708,8 +724,17 @@ __device__ bool mixed_cg(Ctx& C, const Geo& g, const SolveArgs& A, const Op32& o
 //      kModeWindow: 2D FP64 matrix-free with the SpMV source in an LDS window
 //      and one grid sum per iteration (Pcg::run1).
 constexpr int kModeWindow = 4;
+// kModeFallback: the FP64 PCG that finishes a mixed-precision solve which
+// stalled (its own launch after the mixed kernel, so the two solvers do not
+// share one kernel's registers); it returns at once when the mixed solve
+// converged.
+constexpr int kModeFallback = 5;
+// kModeWindow3: 3D FP64 matrix-free with the SpMV source in an LDS window
+// (the two-sum iteration of Pcg::run; 512-thread blocks, one per CU).
+constexpr int kModeWindow3 = 6;
 template <int DIM, int MODE>
 __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
+    if (MODE == kModeFallback && !(A.st->fallback == 1 && A.st->converged == 0)) return;   // uniform over the grid
     __shared__ double sh[16];
     __shared__ double res[4];
     Ctx C{A.partial, GridBar{}, sh, res, 0, true, Own{}, FlagReduce{}};
@@ -730,6 +755,30 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
     const int64_t n = g.nnode * DIM;
     double* u = A.u;
 
+    if constexpr (MODE == kModeFallback) {
+        // FP64 PCG from the restored iterate, with the mixed solve's Jacobi
+        // diagonal, norm and remaining budget
+        const to_solve_stats prev = *A.st;
+        const double tol = A.rtol * prev.bnorm;
+        MatFree<DIM, double> mf64{A.E64, A.kf64, A.geo.nx, A.geo.ny, A.geo.nz};
+        Pcg<DIM, double, MatFree<DIM, double>> cg64{mf64, A.geo, A.freem, C};
+        int restarts = prev.restarts;
+        const int left = A.maxit - prev.iterations;
+        const int it = cg64.run(A.f, A.u, false, A.v64[5], A.v64[0], A.v64[1], A.v64[2], A.v64[3], A.v64[4], tol,
+                                left > 0 ? left : 0, restarts);
+        const double resid = sqrt(C.res[1]) / (prev.bnorm > 0 ? prev.bnorm : 1.0);
+        C.fr.finish();
+        if (bid == 0 && threadIdx.x == 0) {
+            to_solve_stats st2 = prev;
+            st2.residual = resid;
+            st2.iterations = prev.iterations + it;
+            st2.converged = (resid <= A.rtol && C.alive) ? 1 : 0;
+            st2.restarts = restarts;
+            st2.pad = C.alive ? 0 : 1;
+            *A.st = st2;
+        }
+        return;
+    }
     // |f_free|, and u = 0 on fixed DOFs (or everywhere when asked)
     {
         double v[1] = {0.0};
@@ -750,7 +799,7 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
     double resid = 0.0;
 
     MatFree<DIM, double> mf64{A.E64, A.kf64, g.nx, g.ny, g.nz};
-    if (MODE <= 1 || MODE == kModeWindow) {
+    if (MODE <= 1 || MODE == kModeWindow || MODE == kModeWindow3) {
         double *r = A.v64[0], *z = A.v64[1], *pa = A.v64[2], *pb = A.v64[3], *q = A.v64[4], *dinv = A.v64[5];
         if (MODE == 0) {
             CsrS<DIM, double> op{A.rp, (const double*)A.kval, g.nx, g.ny, g.nz};
@@ -771,19 +820,23 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
                 jacobi<DIM, double>(mf64, g, C.o, A.freem, dinv);
             }
             Pcg<DIM, double, MatFree<DIM, double>> cg{mf64, g, A.freem, C};
-            if (DIM == 2 && A.stage > 0) {
+            if (A.stage > 0) {
                 extern __shared__ double solve_win[];
                 cg.wlo = o.lo - o.band > 0 ? o.lo - o.band : 0;
                 const int64_t whi = o.hi + o.band < g.nnode ? o.hi + o.band : g.nnode;
                 cg.wn = whi - cg.wlo;
                 if (cg.wn <= A.stage) {                      // else (never, by the launch's sizing) gather
                     cg.win = solve_win;
-                    if (A.stage_own > 0 && o.hi - o.lo <= A.stage_own) cg.own = solve_win + 2 * (int64_t)A.stage;
+                    if (DIM == 2 && A.stage_own > 0 && o.hi - o.lo <= A.stage_own)
+                        cg.own = solve_win + 2 * (int64_t)A.stage;
                 }
             }
             if constexpr (DIM == 2 && MODE == kModeWindow) {
                 if (cg.win && cg.own) iters = cg.run1(A.f, u, dinv, r, z, pb, q, A.v64[6], A.v64[7], tol, A.maxit, restarts);
                 else C.alive = false;      // the launch sizes the LDS; a kernel without it reports failure
+            } else if constexpr (DIM == 3 && MODE == 1) {
+                // the gather kernel (the window kernel is kModeWindow3): no LDS path compiled in
+                iters = cg.template run<false>(A.f, u, false, dinv, r, z, pa, pb, q, tol, A.maxit, restarts);
             } else {
                 iters = cg.run(A.f, u, false, dinv, r, z, pa, pb, q, tol, A.maxit, restarts);
             }
@@ -805,16 +858,12 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
             converged = mixed_cg<DIM>(C, g, A, mf32, mf64, tol, iters, outer, resid, ubest);
         }
         if (!converged && C.alive) {
+            // the iterate with the smallest FP64 residual goes back into u;
+            // the FP64 PCG of the next launch (kModeFallback) finishes from it
             fallback = 1;
-            // restart from the iterate with the smallest FP64 residual
             for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x)
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) o.st(u, nd, DIM * nd + c, ubest[DIM * nd + c]);
-            C.alive = C.gb.sync() && C.alive;
-            const int left = A.maxit - iters;
-            Pcg<DIM, double, MatFree<DIM, double>> cg64{mf64, g, A.freem, C};
-            iters += cg64.run(A.f, u, false, dinv64, r64, z64, pa64, pb64, q64, tol, left > 0 ? left : 0, restarts);
-            resid = sqrt(C.res[1]);
         }
         resid /= (bnorm > 0 ? bnorm : 1.0);
     }
@@ -836,8 +885,13 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
 // Threads per block of the persistent solve: 2D FP64 kernels fit in 128
 // registers, so a block of 16 waves (one block per CU) hides the gather
 // latency without adding blocks to every grid reduction; the others use 4.
-constexpr int solve_block(int dim, int mode) { return dim == 2 && (mode <= 1 || mode == 4) ? 1024 : 256; }
+constexpr int solve_block(int dim, int mode) {
+    return dim == 2 && (mode <= 1 || mode == 4) ? 1024 : mode == 6 ? 512 : 256;
+}
+static_assert(solve_block(2, kModeFallback) == solve_block(2, 3) && solve_block(3, kModeFallback) == solve_block(3, 3),
+              "a batch launches the fallback kernel with the mixed kernel's grid");
 constexpr size_t kSolveLdsBytes = 158 * 1024;     // dynamic LDS of the windowed kernel (one block per CU)
+constexpr bool kSolveWindow3 = true;              // the 3D windowed kernel where its window fits
 
 template <int DIM, int MODE>
 __global__ __launch_bounds__(solve_block(DIM, MODE)) void solve_kernel(SolveArgs A) {
@@ -895,6 +949,25 @@ static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream
             A.stage = (int)wn;
             void* args[] = {&A};
             TO_HIP(hipLaunchCooperativeKernel((const void*)k, dim3(blocks), dim3(SB), args, win_bytes, s));
+            return TO_OK;
+        }
+    }
+    if constexpr (DIM == 3 && MODE == 1) {
+        // 3D matrix-free FP64: one 512-thread block per CU with the window of
+        // the SpMV source (own nodes and one band of (ny+1)(nz+1) + ny + 2
+        // nodes on either side) in LDS, when it fits
+        auto kw = solve_kernel<3, kModeWindow3>;
+        constexpr int SBW = solve_block(3, kModeWindow3);
+        const int bw = req_blocks > 0 ? std::min(req_blocks, p->num_cu) : p->num_cu;
+        const int64_t band = ((int64_t)A.geo.ny + 1) * ((int64_t)A.geo.nz + 1) + A.geo.ny + 2;
+        const int64_t chunk = (A.geo.nnode + bw - 1) / bw;
+        const int64_t wn = std::min<int64_t>(A.geo.nnode, chunk + 2 * band);
+        const size_t bytes = (size_t)wn * 3 * sizeof(double);
+        if (kSolveWindow3 && bytes <= kSolveLdsBytes &&
+            coop_blocks_for((const void*)kw, SBW, bytes, p->num_cu) >= bw) {
+            A.stage = (int)wn;
+            void* args[] = {&A};
+            TO_HIP(hipLaunchCooperativeKernel((const void*)kw, dim3(bw), dim3(SBW), args, bytes, s));
             return TO_OK;
         }
     }
@@ -1054,16 +1127,19 @@ to_status launch_solve(Plan* p, to_dtype dt, const void* kval, const void* xphys
         switch (mode) {
         case 0: return launch_solve_t<2, 0>(p, A, o.grid_blocks, s);
         case 1: return launch_solve_t<2, 1>(p, A, o.grid_blocks, s);
-        case 2: return launch_solve_t<2, 2>(p, A, o.grid_blocks, s);
-        default: return launch_solve_t<2, 3>(p, A, o.grid_blocks, s);
+        case 2: r = launch_solve_t<2, 2>(p, A, o.grid_blocks, s); break;
+        default: r = launch_solve_t<2, 3>(p, A, o.grid_blocks, s); break;
         }
+        // the mixed solve's FP64 fallback (returns at once unless it stalled)
+        return r != TO_OK ? r : launch_solve_t<2, kModeFallback>(p, A, o.grid_blocks, s);
     }
     switch (mode) {
     case 0: return launch_solve_t<3, 0>(p, A, o.grid_blocks, s);
     case 1: return launch_solve_t<3, 1>(p, A, o.grid_blocks, s);
-    case 2: return launch_solve_t<3, 2>(p, A, o.grid_blocks, s);
-    default: return launch_solve_t<3, 3>(p, A, o.grid_blocks, s);
+    case 2: r = launch_solve_t<3, 2>(p, A, o.grid_blocks, s); break;
+    default: r = launch_solve_t<3, 3>(p, A, o.grid_blocks, s); break;
     }
+    return r != TO_OK ? r : launch_solve_t<3, kModeFallback>(p, A, o.grid_blocks, s);
 }
 
 static const void* solve_batch_fn(int dim, int mode) {
@@ -1085,14 +1161,23 @@ static const void* solve_batch_fn(int dim, int mode) {
 
 int solve_block_size(int dim, int mode) { return solve_block(dim, mode); }
 
+static const void* solve_batch_fallback_fn(int dim) {
+    return dim == 2 ? (const void*)solve_batch_kernel<2, kModeFallback> : (const void*)solve_batch_kernel<3, kModeFallback>;
+}
+
 int solve_batch_capacity(int dim, int mode, int num_cu) {
-    return coop_blocks_for(solve_batch_fn(dim, mode), solve_block(dim, mode), 0, num_cu);
+    int c = coop_blocks_for(solve_batch_fn(dim, mode), solve_block(dim, mode), 0, num_cu);
+    if (mode >= 2) c = std::min(c, coop_blocks_for(solve_batch_fallback_fn(dim), solve_block(dim, mode), 0, num_cu));
+    return c;
 }
 
 to_status launch_solve_batch(int dim, int mode, const void* tab, const BatchMap& mp, hipStream_t s) {
     void* args[] = {(void*)&tab, (void*)&mp.inst, (void*)&mp.first, (void*)&mp.count};
     TO_HIP(hipLaunchCooperativeKernel(solve_batch_fn(dim, mode), dim3(mp.blocks), dim3(solve_block(dim, mode)), args,
                                       0, s));
+    if (mode >= 2)        // the mixed solves' FP64 fallbacks, per design (each returns at once unless it stalled)
+        TO_HIP(hipLaunchCooperativeKernel(solve_batch_fallback_fn(dim), dim3(mp.blocks), dim3(solve_block(dim, mode)),
+                                          args, 0, s));
     return TO_OK;
 }
 

@@ -380,6 +380,54 @@ def test_solve(case):
     assert res <= 1.05e-8, res
     assert abs(s.residual - res) <= 1e-9
     assert np.all(uh[prob.fixed] == 0.0)
+
+
+@pytest.mark.parametrize("cfgname", ["c0", "c2s"])
+def test_mixed_solve_fallback(cfgname):
+    """The FP64 fallback of the mixed-precision CG, its own launch after the
+    mixed kernel: with an iteration cap that stops the mixed iteration
+    (its budget is half the cap) before it converges, the fallback starts
+    from the mixed iterate with the smallest FP64 residual and reaches the
+    true residual 1e-8 (judged with the oracle's K).  With a large cap the
+    solve converges too (at this stiffness contrast the mixed iteration can
+    stall and hand over to the fallback by itself)."""
+    from paper_2005_05436_amd import _lib as L
+    from paper_2005_05436_amd.driver import plan_for_config, read_struct
+    cfg = {"c0": W.C0, "c2s": W.C2_SMALL}[cfgname]
+    prob, x, K = _solve_case(cfg, 31)
+    P, f, _ = plan_for_config(cfg)
+    dt = L.TO_F32
+    xd = dev(x, torch.float32)
+    kval = torch.zeros(P.info.nnz_lower, dtype=torch.float32, device="cuda")
+    L.to_assemble(P.handle, dt, xd, cfg.penal, kval)
+    fd = dev(f, torch.float64)
+    xin = host(xd)
+    kv = osp.assemble(xin, prob.ke_lower, prob.perm, prob.seg_ptr, cfg.penal, 1.0, 1e-9)
+    Ko = osp.lower_to_full(prob.row_ptr, prob.col_idx, kv, prob.mesh.n)
+
+    def run(maxit, prec=L.TO_SOLVE_MIXED):
+        u = torch.zeros(P.info.n, dtype=torch.float64, device="cuda")
+        st = torch.zeros(40, dtype=torch.uint8, device="cuda")
+        opts = L.SolveOpts(1e-8, 0.1, maxit, L.TO_OP_MATFREE, prec, 1, 0, 0)
+        L.to_solve(P.handle, dt, kval, xd, cfg.penal, fd, u, opts, st)
+        return read_struct(st, L.SolveStats), host(u)
+
+    s64, _ = run(200000, L.TO_SOLVE_F64)
+    s_free, u_free = run(200000)
+    res_free = osolve.true_residual(Ko, prob.f, prob.free, u_free)
+    assert s_free.converged == 1 and res_free <= 1.05e-8, (s_free.iterations, s_free.fallback, res_free)
+    # the mixed budget (half the cap) ends before the mixed iteration
+    # converges, and the rest of the cap leaves the FP64 PCG more than it
+    # needs from zero
+    half = min(s64.iterations + 100, s_free.iterations - 1)
+    s, uh = run(2 * half)
+    res = osolve.true_residual(Ko, prob.f, prob.free, uh)
+    print(f"{cfgname}: uncapped {s_free.iterations} iterations (fallback {s_free.fallback}); capped: "
+          f"{s.iterations} iterations, fallback {s.fallback}, residual {res:.3e}")
+    assert s.fallback == 1
+    assert s.converged == 1 and res <= 1.05e-8, (s.iterations, s.residual, res)
+    assert abs(s.residual - res) <= 1e-9
+    assert s.iterations <= 2 * half
     if prob.mesh.n <= 3000:
         ud = osolve.solve_dense(K.toarray(), prob.f, prob.free)
         assert abs(prob.f @ uh - prob.f @ ud) <= 1e-7 * abs(prob.f @ ud)
