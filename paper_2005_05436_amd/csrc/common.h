@@ -411,27 +411,35 @@ struct FlagReduce {
         double acc[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) acc[k] = 0.0;
+        // a block's 2K words are loaded together (one memory round trip, not
+        // one per value) and only the words without the current tag reloaded
         for (int b = threadIdx.x; b < (int)nblk; b += NB) {
+            const unsigned long long* wd = region + (size_t)b * kLLVals * 2;
+            unsigned long long wv[2 * K];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const unsigned long long* wd = region + ((size_t)b * kLLVals + k) * 2;
-                unsigned long long lo = ld_dev(wd), hi = ld_dev(wd + 1);
-                unsigned spins = 0;
-                while (ok && ((unsigned)(lo >> 32) != tag || (unsigned)(hi >> 32) != tag)) {
-                    if ((++spins & 255u) == 0u) {
-                        if (ld_dev(&bar[2]) != 0u) ok = false;
-                        else if (spins > kSpinLimit) {
-                            atomicOr(&bar[3], FLAG_BARRIER_TIMEOUT);
-                            atomicExch(&bar[2], 1u);
-                            ok = false;
-                        }
+            for (int h = 0; h < 2 * K; ++h) wv[h] = ld_dev(wd + h);
+            unsigned spins = 0;
+            while (ok) {
+                bool ready = true;
+#pragma unroll
+                for (int h = 0; h < 2 * K; ++h) ready = ready && (unsigned)(wv[h] >> 32) == tag;
+                if (ready) break;
+                if ((++spins & 255u) == 0u) {
+                    if (ld_dev(&bar[2]) != 0u) ok = false;
+                    else if (spins > kSpinLimit) {
+                        atomicOr(&bar[3], FLAG_BARRIER_TIMEOUT);
+                        atomicExch(&bar[2], 1u);
+                        ok = false;
                     }
-                    __builtin_amdgcn_s_sleep(1);
-                    lo = ld_dev(wd);
-                    hi = ld_dev(wd + 1);
                 }
-                acc[k] += __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
+                __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                for (int h = 0; h < 2 * K; ++h)
+                    if ((unsigned)(wv[h] >> 32) != tag) wv[h] = ld_dev(wd + h);
             }
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                acc[k] += __longlong_as_double((long long)((wv[2 * k + 1] << 32) | (wv[2 * k] & 0xFFFFFFFFull)));
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {

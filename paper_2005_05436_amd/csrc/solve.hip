@@ -221,6 +221,14 @@ struct SrcLds {
     __device__ __forceinline__ T operator()(int64_t q, int c) const { return w[DIM * (q - wlo) + c]; }
 };
 
+// Hides per-node values from loop-invariant code motion: the neighbour
+// masks and addresses derived from them are then recomputed where they are
+// used, instead of being held in registers across the whole CG loop for
+// every node a thread owns.
+__device__ __forceinline__ void opaque(int& a, int& b, int& c, uint32_t& d) {
+    asm volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
+}
+
 template <int DIM, typename T, class Op>
 struct Pcg {
     const Op& op;
@@ -229,10 +237,10 @@ struct Pcg {
     Ctx& C;
     T* win = nullptr;            // LDS window of the direction (2D; nullptr: gather from memory)
     int64_t wlo = 0, wn = 0;
-    T* own = nullptr;            // run1: LDS copies of dinv, x and p on the own nodes (nullptr: in memory)
+    T* own = nullptr;            // run1: LDS for x and p of the own nodes, their moduli and the band's dinv
 
     // r = b - A x (x = 0: r = b), z = dinv r; returns (r.z, r.r) in C.res
-    __device__ void residual(const T* b, const T* x, bool x_zero, const T* dinv, T* r, T* z) {
+    __device__ __forceinline__ void residual(const T* b, const T* x, bool x_zero, const T* dinv, T* r, T* z) {
         double v[2] = {0.0, 0.0};
         const Own& o = C.o;
         for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
@@ -390,92 +398,144 @@ struct Pcg {
     // their new r and s meanwhile) is formed here from their previous r, w
     // and s, so r, w and s are double-buffered by iteration parity; the
     // operations are those of the owner, so every block sees the same u.
-    // Convergence is confirmed on the recomputed residual b - A x, and a
-    // failed confirmation restarts from x, as in run.
-    __device__ int run1(const T* b, T* x, const T* dinv, T* R0, T* R1, T* W0, T* W1, T* S0, T* S1, double tol,
-                        int maxit, int& restarts) {
+    //
+    // Residency: thread t owns the nodes lo + t + j blockDim.x (j < J) for
+    // the whole solve and keeps their coordinates, free flags, Jacobi
+    // diagonal and r, w, s in registers, their x and p in LDS; the moduli of
+    // the element columns around the own nodes and the band nodes' Jacobi
+    // diagonal are staged in LDS once.  Only the own nodes within one band of
+    // the range ends (those in a neighbour's window) publish r, w and s to
+    // memory; the others never leave the CU.  x goes back to memory before
+    // every true residual and at the end.  Convergence is confirmed on the
+    // recomputed residual b - A x, and a failed confirmation restarts from x.
+    template <int J>
+    __device__ __forceinline__ int run1(const T* b, T* x, const T* dinv, T* R0, T* R1, T* W0, T* W1, T* S0, T* S1,
+                                        double tol, int maxit, int& restarts) {
         const Own& o = C.o;
+        const int bd = (int)blockDim.x;
         const int64_t whi = wlo + wn;
-        const int64_t nlo = 2 * (o.lo - wlo), nh = nlo + 2 * (whi - o.hi);   // band values below / in total
-        // dinv, x and p of the own nodes can live in LDS for the whole solve
-        // (read and written by this block only; x goes back to memory before
-        // every true residual and at the end)
-        const int64_t nown = 2 * (o.hi - o.lo), i0 = 2 * o.lo;
-        T* const dl = own;
-        T* const xl = own + nown;
-        T* const pl = own + 2 * nown;
-        // the moduli of the elements around the own nodes (columns ix_lo - 1 ..
-        // ix_hi) and the free-DOF flags of the own nodes, also in LDS: the
-        // SpMV then reads only LDS and the scalar-cached Ke
+        const int nlo = (int)(2 * (o.lo - wlo)), nh = nlo + (int)(2 * (whi - o.hi));   // band values below / in total
+        const int nown = (int)(2 * (o.hi - o.lo)), ohi = (int)(2 * (o.hi - wlo));
+        // 32-bit value indices (the launch checks 2 nnode < 2^31)
+        const uint32_t i0 = (uint32_t)(2 * o.lo), w0 = (uint32_t)(2 * wlo);
+        T* const xl = own;
+        T* const pl = own + nown;
         const int ny1 = g.ny + 1;
         const int64_t exl = o.lo / ny1 > 0 ? o.lo / ny1 - 1 : 0;
         const int64_t exh = (o.hi - 1) / ny1 < g.nx - 1 ? (o.hi - 1) / ny1 : g.nx - 1;
-        const int64_t elo = exl * g.ny, ne = (exh + 1) * g.ny - elo;
-        T* const el = own + 3 * nown;
-        uint8_t* const fl = reinterpret_cast<uint8_t*>(el + ne);
-        for (int64_t t = threadIdx.x; t < ne; t += (int64_t)blockDim.x) el[t] = op.E[elo + t];
+        const int64_t elo = exl * g.ny;
+        const int ne = (int)((exh + 1) * g.ny - elo);
+        T* const el = own + 2 * nown;
+        T* const dband = el + ne;                 // filled after the first grid sum (below)
+        for (int t = threadIdx.x; t < ne; t += bd) el[t] = op.E[elo + t];
         Op opl = op;
         opl.E = el;
         opl.e0 = elo;
-        // each own value is moved by the thread that wrote it (the node loop's
-        // thread mapping), so no barrier is needed before these reads
-        for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x)
+        // per node: 2 nd, coordinates, and flags (bits 0, 1: free DOFs;
+        // kPub: within one band of the range ends; kOn: an own node)
+        constexpr int kPub = 4, kOn = 8;
+        uint32_t gi[J];
+        int iy[J], ix[J], fl[J];
+        T d[J][2], r[J][2], w[J][2], s[J][2];
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const int64_t i = 2 * nd + c;
-                dl[i - i0] = dinv[i];
-                xl[i - i0] = x[i];
-                if (c == 1) fl[nd - o.lo] = (uint8_t)((fm[i - 1] ? 1 : 0) | (fm[i] ? 2 : 0));
+        for (int j = 0; j < J; ++j) {
+            const int64_t ndj = o.lo + threadIdx.x + (int64_t)j * bd;
+            gi[j] = (uint32_t)(2 * ndj);
+            iy[j] = ix[j] = fl[j] = 0;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) d[j][c] = r[j][c] = w[j][c] = s[j][c] = T(0);
+            if (ndj < o.hi) {
+                int iz;
+                g.coords(ndj, iy[j], ix[j], iz, 2);
+                fl[j] = kOn | (o.edge(ndj) ? kPub : 0);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const uint32_t i = gi[j] + c;
+                    fl[j] |= fm[i] ? 1 << c : 0;
+                    d[j][c] = dinv[i];                // written by this thread (same node mapping)
+                    xl[i - i0] = x[i];
+                }
             }
+        }
         __syncthreads();
         auto flush_x = [&]() {
-            for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x)
 #pragma unroll
-                for (int c = 0; c < 2; ++c) o.st(x, nd, 2 * nd + c, xl[2 * nd + c - i0]);
+            for (int j = 0; j < J; ++j) {
+                if (!(fl[j] & kOn)) continue;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const uint32_t i = gi[j] + c;
+                    if (fl[j] & kPub) st_dev(x + i, xl[i - i0]);
+                    else x[i] = xl[i - i0];
+                }
+            }
             C.alive = C.gb.sync() && C.alive;       // the band of x is read by the neighbours' residual
         };
         int it = 0;
+        bool confirming = false, stop = false;
         while (C.alive) {
-            // (re)start: r = b - A x (the true residual), then u, w = A u
+            // (re)start: r = b - A x (the true residual: it confirms the
+            // previous pass's convergence, or is the one reported after a
+            // breakdown or a spent budget), then u, w = A u
             {
                 double v[2] = {0.0, 0.0};
-                for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
-                    int iy, ix, iz;
-                    g.coords(nd, iy, ix, iz, 2);
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    int f = fl[j], yy = iy[j], xx = ix[j];
+                    uint32_t gg = gi[j];
+                    opaque(f, yy, xx, gg);
+                    if (!(f & kOn)) continue;
                     T ax[2];
-                    op.apply(nd, iy, ix, iz, Src1<2, T>{x, o}, ax);
+                    opl.apply((int64_t)(gg >> 1), yy, xx, 0, Src1<2, T>{x, o}, ax);
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
-                        const int64_t i = 2 * nd + c;
-                        const T ri = fm[i] ? b[i] - ax[c] : T(0);
-                        o.st(R0, nd, i, ri);
-                        v[0] += (double)ri * (double)(dinv[i] * ri);
+                        const uint32_t i = gg + c;
+                        const T ri = (f >> c) & 1 ? b[i] - ax[c] : T(0);
+                        r[j][c] = ri;
+                        if (f & kPub) st_dev(R0 + i, ri);
+                        v[0] += (double)ri * (double)(d[j][c] * ri);
                         v[1] += (double)ri * (double)ri;
                     }
                 }
                 C.reduce<2>(v);
             }
             double rr = C.res[1];
-            if (rr <= tol * tol || !C.alive) break;       // a fresh residual needs no confirmation
+            if (rr <= tol * tol || !C.alive || stop) break;   // a fresh residual needs no confirmation
+            if (confirming) ++restarts;                        // the recursive residual had met tol
+            // the band's Jacobi diagonal, written by the neighbouring blocks
+            // before the grid sum just taken (band nodes are never this
+            // block's own); each value is read back by the thread that wrote it
+            for (int t = threadIdx.x; t < nh; t += bd) {
+                const int j = t < nlo ? t : t - nlo + ohi;
+                dband[t] = ld_dev(dinv + w0 + j);
+            }
             {
-                for (int64_t t = threadIdx.x; t < 2 * wn; t += (int64_t)blockDim.x) {
-                    const int64_t q = wlo + (t >> 1), i = 2 * q + (t & 1);
-                    win[t] = o.ld(dinv, q, i) * o.ld(R0, q, i);
+#pragma unroll
+                for (int j = 0; j < J; ++j)
+                    if (fl[j] & kOn)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) win[gi[j] + c - w0] = d[j][c] * r[j][c];
+                for (int t = threadIdx.x; t < nh; t += bd) {
+                    const int j = t < nlo ? t : t - nlo + ohi;
+                    win[j] = dband[t] * ld_dev(R0 + w0 + j);
                 }
                 __syncthreads();
                 const SrcLds<2, T> sl{win, wlo};
                 double v[2] = {0.0, 0.0};
-                for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
-                    int iy, ix, iz;
-                    g.coords(nd, iy, ix, iz, 2);
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    int f = fl[j], yy = iy[j], xx = ix[j];
+                    uint32_t gg = gi[j];
+                    opaque(f, yy, xx, gg);
+                    if (!(f & kOn)) continue;
                     T aw[2];
-                    op.apply(nd, iy, ix, iz, sl, aw);
+                    opl.apply((int64_t)(gg >> 1), yy, xx, 0, sl, aw);
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
-                        const int64_t i = 2 * nd + c;
-                        const T ui = sl(nd, c), wi = fm[i] ? aw[c] : T(0);
-                        o.st(W0, nd, i, wi);
-                        v[0] += (double)R0[i] * (double)ui;
+                        const T ui = d[j][c] * r[j][c], wi = (f >> c) & 1 ? aw[c] : T(0);
+                        w[j][c] = wi;
+                        if (f & kPub) st_dev(W0 + gg + c, wi);
+                        v[0] += (double)r[j][c] * (double)ui;
                         v[1] += (double)wi * (double)ui;
                     }
                 }
@@ -502,47 +562,57 @@ struct Pcg {
                 const T* So = odd ? S0 : S1;
                 const T a = (T)alpha, bt = (T)beta;
                 double v[3] = {0.0, 0.0, 0.0};        // gamma, delta, |r|^2
-                for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    int f = fl[j], yy = iy[j], xx = ix[j];
+                    uint32_t gg = gi[j];
+                    opaque(f, yy, xx, gg);
+                    if (!(f & kOn)) continue;
+                    const uint32_t l = gg - i0;
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
-                        const int64_t i = 2 * nd + c, j = i - i0;
-                        const T di = dl[j], rk = Rk[i], wk = Wk[i];
-                        const T ui = di * rk;
-                        const T pi = k == 0 ? ui : fma(bt, pl[j], ui);
-                        const T si = k == 0 ? wk : fma(bt, So[i], wk);
-                        const T rn = fma(-a, si, rk);
-                        const T un = di * rn;
-                        pl[j] = pi;
-                        xl[j] = fma(a, pi, xl[j]);
-                        o.st(Sk, nd, i, si);
-                        o.st(Rn, nd, i, rn);
-                        win[2 * (nd - wlo) + c] = un;
+                        const T ui = d[j][c] * r[j][c];
+                        const T pi = k == 0 ? ui : fma(bt, pl[l + c], ui);
+                        const T si = k == 0 ? w[j][c] : fma(bt, s[j][c], w[j][c]);
+                        const T rn = fma(-a, si, r[j][c]);
+                        const T un = d[j][c] * rn;
+                        pl[l + c] = pi;
+                        xl[l + c] = fma(a, pi, xl[l + c]);
+                        s[j][c] = si;
+                        r[j][c] = rn;
+                        if (f & kPub) {
+                            st_dev(Sk + gg + c, si);
+                            st_dev(Rn + gg + c, rn);
+                        }
+                        win[gg + c - w0] = un;
                         v[0] += (double)rn * (double)un;
                         v[2] += (double)rn * (double)rn;
                     }
                 }
-                for (int64_t t = threadIdx.x; t < nh; t += (int64_t)blockDim.x) {
-                    const int64_t j = t < nlo ? t : t - nlo + 2 * (o.hi - wlo);   // window value index
-                    const int64_t q = wlo + (j >> 1), i = 2 * q + (j & 1);
-                    const T di = o.ld(dinv, q, i), rk = o.ld(Rk, q, i), wk = o.ld(Wk, q, i);
-                    const T si = k == 0 ? wk : fma(bt, o.ld(So, q, i), wk);
+                for (int t = threadIdx.x; t < nh; t += bd) {
+                    const int j = t < nlo ? t : t - nlo + ohi;
+                    const uint32_t i = w0 + (uint32_t)j;
+                    const T rk = ld_dev(Rk + i), wk = ld_dev(Wk + i);
+                    const T si = k == 0 ? wk : fma(bt, ld_dev(So + i), wk);
                     const T rn = fma(-a, si, rk);
-                    win[j] = di * rn;
+                    win[j] = dband[t] * rn;
                 }
                 __syncthreads();
                 const SrcLds<2, T> sl{win, wlo};
-                for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
-                    int iy, ix, iz;
-                    g.coords(nd, iy, ix, iz, 2);
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    int f = fl[j], yy = iy[j], xx = ix[j];
+                    uint32_t gg = gi[j];
+                    opaque(f, yy, xx, gg);
+                    if (!(f & kOn)) continue;
                     T aw[2];
-                    opl.apply(nd, iy, ix, iz, sl, aw);
-                    const int f2 = fl[nd - o.lo];
+                    opl.apply((int64_t)(gg >> 1), yy, xx, 0, sl, aw);
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
-                        const int64_t i = 2 * nd + c;
-                        const T wi = (f2 >> c) & 1 ? aw[c] : T(0);
-                        o.st(Wn, nd, i, wi);
-                        v[1] += (double)wi * (double)sl(nd, c);
+                        const T wi = (f >> c) & 1 ? aw[c] : T(0);
+                        w[j][c] = wi;
+                        if (f & kPub) st_dev(Wn + gg + c, wi);
+                        v[1] += (double)wi * (double)(d[j][c] * r[j][c]);
                     }
                 }
                 C.reduce<3>(v);
@@ -556,22 +626,15 @@ struct Pcg {
             }
             if (!C.alive) break;
             flush_x();
-            if (ok && rr <= tol * tol) {
-                // confirm on the recomputed residual; a failure restarts
-                residual(b, x, false, dinv, R0, S1);
-                if (C.res[1] <= tol * tol) break;
-                ++restarts;
-                continue;
-            }
-            residual(b, x, false, dinv, R0, S1);          // breakdown or budget spent: report the true residual
-            break;
+            confirming = ok && rr <= tol * tol;
+            stop = !confirming;                                // breakdown or budget spent
         }
         return it;
     }
 };
 
 template <int DIM, typename T, class Op>
-__device__ void jacobi(const Op& op, const Geo& g, const Own& o, const uint8_t* fm, T* dinv) {
+__device__ __forceinline__ void jacobi(const Op& op, const Geo& g, const Own& o, const uint8_t* fm, T* dinv) {
     for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
         int iy, ix, iz;
         g.coords(nd, iy, ix, iz, DIM);
@@ -722,8 +785,10 @@ __device__ bool mixed_cg(Ctx& C, const Geo& g, const SolveArgs& A, const Op32& o
 // MODE 0: FP64, assembled operator; 1: FP64, matrix-free;
 //      2: mixed, FP32 assembled inner; 3: mixed, FP32 matrix-free inner;
 //      kModeWindow: 2D FP64 matrix-free with the SpMV source in an LDS window
-//      and one grid sum per iteration (Pcg::run1).
+//      and one grid sum per iteration (Pcg::run1), the own nodes' vectors
+//      held on chip (at most kRegNodes nodes per thread).
 constexpr int kModeWindow = 4;
+constexpr int kRegNodes = 4;
 // kModeFallback: the FP64 PCG that finishes a mixed-precision solve which
 // stalled (its own launch after the mixed kernel, so the two solvers do not
 // share one kernel's registers); it returns at once when the mixed solve
@@ -733,7 +798,7 @@ constexpr int kModeFallback = 5;
 // (the two-sum iteration of Pcg::run; 512-thread blocks, one per CU).
 constexpr int kModeWindow3 = 6;
 template <int DIM, int MODE>
-__device__ void solve_body(const SolveArgs& A, int bid, int nb) {
+__device__ __forceinline__ void solve_body(const SolveArgs& A, int bid, int nb) {
     if (MODE == kModeFallback && !(A.st->fallback == 1 && A.st->converged == 0)) return;   // uniform over the grid
     __shared__ double sh[16];
     __shared__ double res[4];
@@ -832,7 +897,9 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
                 }
             }
             if constexpr (DIM == 2 && MODE == kModeWindow) {
-                if (cg.win && cg.own) iters = cg.run1(A.f, u, dinv, r, z, pb, q, A.v64[6], A.v64[7], tol, A.maxit, restarts);
+                if (cg.win && cg.own && o.hi - o.lo <= (int64_t)kRegNodes * blockDim.x)
+                    iters = cg.template run1<kRegNodes>(A.f, u, dinv, r, z, pb, q, A.v64[6], A.v64[7], tol, A.maxit,
+                                                        restarts);
                 else C.alive = false;      // the launch sizes the LDS; a kernel without it reports failure
             } else if constexpr (DIM == 3 && MODE == 1) {
                 // the gather kernel (the window kernel is kModeWindow3): no LDS path compiled in
@@ -886,7 +953,7 @@ __device__ void solve_body(const SolveArgs& A, int bid, int nb) {
 // registers, so a block of 16 waves (one block per CU) hides the gather
 // latency without adding blocks to every grid reduction; the others use 4.
 constexpr int solve_block(int dim, int mode) {
-    return dim == 2 && (mode <= 1 || mode == 4) ? 1024 : mode == 6 ? 512 : 256;
+    return dim == 2 && mode <= 1 ? 1024 : mode == 4 || mode == 6 ? 512 : 256;
 }
 static_assert(solve_block(2, kModeFallback) == solve_block(2, 3) && solve_block(3, kModeFallback) == solve_block(3, 3),
               "a batch launches the fallback kernel with the mixed kernel's grid");
@@ -928,20 +995,25 @@ static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream
         const int64_t chunk = (A.geo.nnode + blocks - 1) / blocks;
         const int64_t wn = std::min<int64_t>(A.geo.nnode, chunk + 2 * ((int64_t)A.geo.ny + 2));
         const size_t win_bytes = (size_t)wn * 2 * sizeof(double);
-        // dinv, x, p of the own nodes; the moduli of the element columns they
-        // touch (at most chunk / (ny + 1) + 3 columns); a flag byte per node
+        // x, p of the own nodes; the moduli of the element columns they touch
+        // (at most chunk / (ny + 1) + 3 columns); the Jacobi diagonal of the
+        // two bands
         const int64_t ecap = (int64_t)A.geo.ny * (chunk / ((int64_t)A.geo.ny + 1) + 3);
-        const size_t own_bytes = (size_t)chunk * 6 * sizeof(double) + (size_t)ecap * sizeof(double) +
-                                 (size_t)(chunk + 7) / 8 * 8;
+        const size_t own_bytes = (size_t)chunk * 4 * sizeof(double) + (size_t)ecap * sizeof(double) +
+                                 (size_t)4 * ((size_t)A.geo.ny + 2) * sizeof(double);
+        constexpr int SBW = solve_block(2, kModeWindow);
         auto fits = [&](size_t b) {
-            return b <= kSolveLdsBytes && coop_blocks_for((const void*)kw, SB, b, p->num_cu) >= blocks;
+            return b <= kSolveLdsBytes && coop_blocks_for((const void*)kw, SBW, b, p->num_cu) >= blocks;
         };
-        if (fits(win_bytes + own_bytes)) {
+        // the kernel keeps up to kRegNodes own nodes per thread on chip and
+        // indexes vectors with 32-bit offsets
+        if (chunk <= (int64_t)kRegNodes * SBW && 2 * A.geo.nnode < ((int64_t)1 << 31) &&
+            fits(win_bytes + own_bytes)) {
             A.stage = (int)wn;
             A.stage_own = (int)chunk;
             A.stage_e = (int)ecap;
             void* args[] = {&A};
-            TO_HIP(hipLaunchCooperativeKernel((const void*)kw, dim3(blocks), dim3(SB), args, win_bytes + own_bytes, s));
+            TO_HIP(hipLaunchCooperativeKernel((const void*)kw, dim3(blocks), dim3(SBW), args, win_bytes + own_bytes, s));
             return TO_OK;
         }
         if (win_bytes <= kSolveLdsBytes && coop_blocks_for((const void*)k, SB, win_bytes, p->num_cu) >= blocks) {

@@ -382,6 +382,53 @@ def test_solve(case):
     assert np.all(uh[prob.fixed] == 0.0)
 
 
+def _mbb_true_residual(cfg, x, u):
+    """|f - K u| / |f| over the free DOFs of the MBB problem, with
+    K = sum_e E(x_e) C_e^T Ke C_e (eqs. (3)-(5)) applied element by element
+    from the oracle's mesh, supports, Q4 element matrix and SIMP modulus (no
+    global matrix: fast at 480,000 elements)."""
+    M = omesh.Mesh(cfg.nelx, cfg.nely)
+    f, fixed = omesh.mbb(M, cfg.load)
+    free = omesh.free_dofs(M, fixed)
+    C = M.cmat()
+    E = osp.simp_modulus(x, cfg.penal, cfg.E0, cfg.Emin)
+    uf = np.zeros(M.n)
+    uf[free] = u[free]
+    fe = (uf[C] @ oel.ke_q4(cfg.nu)) * E[:, None]        # Ke is symmetric
+    Ku = np.bincount(C.ravel(), weights=fe.ravel(), minlength=M.n)
+    return np.linalg.norm((f - Ku)[free]) / np.linalg.norm(f[free])
+
+
+@pytest.mark.parametrize("nelx", [600, 1200])
+def test_solve_window_kernel_two_designs(nelx):
+    """The default 2D FP64 solve (matrix-free operator, Jacobi diagonal from
+    the assembled K) at the MBB sizes where its persistent kernel keeps 2 and
+    4 own nodes per thread on chip over 118 and 256 blocks: two different
+    designs solved one after the other on one plan (the second solve must use
+    only its own Jacobi diagonal, also in the bands the blocks exchange), each
+    judged by its true residual."""
+    from dataclasses import replace
+    from paper_2005_05436_amd import _lib as L
+    from paper_2005_05436_amd.driver import plan_for_config, read_struct
+    cfg = replace(W.C1[nelx], penal=3.0)
+    P, f, _ = plan_for_config(cfg)
+    fd = dev(f, torch.float64)
+    kval = torch.zeros(P.info.nnz_lower, dtype=torch.float64, device="cuda")
+    opts = L.SolveOpts(1e-8, 0.1, 200000, L.TO_OP_HYBRID, L.TO_SOLVE_AUTO, 1, 0, 0)
+    for seed in (5, 6):
+        xd = dev(W.smooth_design(cfg, seed), torch.float64)
+        L.to_assemble(P.handle, L.TO_F64, xd, cfg.penal, kval)
+        u = torch.zeros(P.info.n, dtype=torch.float64, device="cuda")
+        st = torch.zeros(40, dtype=torch.uint8, device="cuda")
+        L.to_solve(P.handle, L.TO_F64, kval, xd, cfg.penal, fd, u, opts, st)
+        s = read_struct(st, L.SolveStats)
+        res = _mbb_true_residual(cfg, host(xd), host(u))
+        print(f"{nelx} seed {seed}: iterations={s.iterations} restarts={s.restarts} residual={res:.3e}")
+        assert s.converged == 1, (s.iterations, s.residual)
+        assert res <= 1.05e-8, res
+        assert abs(s.residual - res) <= 1e-9
+
+
 @pytest.mark.parametrize("cfgname", ["c0", "c2s"])
 def test_mixed_solve_fallback(cfgname):
     """The FP64 fallback of the mixed-precision CG, its own launch after the
