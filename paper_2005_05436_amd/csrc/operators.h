@@ -8,6 +8,15 @@
 
 namespace topt {
 
+// Reads a value that nothing writes while the kernel runs (the element
+// matrix) through the constant address space: a wave-uniform address then
+// becomes a scalar load even in kernels that also store to global memory,
+// where the compiler cannot otherwise rule out that a store changed it.
+template <typename T>
+__device__ __forceinline__ T ld_const(const T* p) {
+    return *(const __attribute__((address_space(4))) T*)p;
+}
+
 struct Geo {
     int nx, ny, nz;
     int64_t nnode;
@@ -91,7 +100,7 @@ struct MatFree {
             for (int c = 0; c < DIM; ++c) {
                 T acc = T(0);
 #pragma unroll
-                for (int j = 0; j < D; ++j) acc += kr[c * D + j] * sv[j];
+                for (int j = 0; j < D; ++j) acc += ld_const(kr + c * D + j) * sv[j];
                 out[c] += Ee * acc;
             }
         }
@@ -157,7 +166,7 @@ struct MatFree<2, T> {
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const int dy = CY[b] - CY[a], dx = CX[b] - CX[a];
-                    acc += kr[2 * b] * pv[dx + 1][dy + 1][0] + kr[2 * b + 1] * pv[dx + 1][dy + 1][1];
+                    acc += ld_const(kr + 2 * b) * pv[dx + 1][dy + 1][0] + ld_const(kr + 2 * b + 1) * pv[dx + 1][dy + 1][1];
                 }
                 out[c] += Ee * acc;
             }
