@@ -252,6 +252,15 @@ __device__ __forceinline__ void st_dev(T* p, T v) {
 }
 __device__ __forceinline__ double ld_acq(const double* p) { return ld_dev(p); }
 
+// Reads a value that nothing writes while the kernel runs (the element
+// matrix) through the constant address space: a wave-uniform address then
+// becomes a scalar load even in kernels that also store to global memory,
+// where the compiler cannot otherwise rule out that a store changed it.
+template <typename T>
+__device__ __forceinline__ T ld_const(const T* p) {
+    return *(const __attribute__((address_space(4))) T*)p;
+}
+
 // Wait until every global access this wave has issued has completed.  On gfx9
 // the vector memory counter covers stores as well as loads, and a completed
 // device-scope store (st_dev) is visible at the device coherence point.  A
@@ -411,14 +420,28 @@ struct FlagReduce {
         double acc[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) acc[k] = 0.0;
-        // a block's 2K words are loaded together (one memory round trip, not
-        // one per value) and only the words without the current tag reloaded
+        // each polling thread first spins on one word of its block's record
+        // (the last one the publisher writes; every block polls every record,
+        // so the poll's request rate is what costs), then loads the record's
+        // 2K words together and reloads any without the current tag
         for (int b = threadIdx.x; b < (int)nblk; b += NB) {
             const unsigned long long* wd = region + (size_t)b * kLLVals * 2;
+            unsigned spins = 0;
+            for (unsigned long long sent = ld_dev(wd + 2 * K - 1); ok && (unsigned)(sent >> 32) != tag;
+                 sent = ld_dev(wd + 2 * K - 1)) {
+                if ((++spins & 255u) == 0u) {
+                    if (ld_dev(&bar[2]) != 0u) ok = false;
+                    else if (spins > kSpinLimit) {
+                        atomicOr(&bar[3], FLAG_BARRIER_TIMEOUT);
+                        atomicExch(&bar[2], 1u);
+                        ok = false;
+                    }
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
             unsigned long long wv[2 * K];
 #pragma unroll
             for (int h = 0; h < 2 * K; ++h) wv[h] = ld_dev(wd + h);
-            unsigned spins = 0;
             while (ok) {
                 bool ready = true;
 #pragma unroll

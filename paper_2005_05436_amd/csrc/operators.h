@@ -8,15 +8,6 @@
 
 namespace topt {
 
-// Reads a value that nothing writes while the kernel runs (the element
-// matrix) through the constant address space: a wave-uniform address then
-// becomes a scalar load even in kernels that also store to global memory,
-// where the compiler cannot otherwise rule out that a store changed it.
-template <typename T>
-__device__ __forceinline__ T ld_const(const T* p) {
-    return *(const __attribute__((address_space(4))) T*)p;
-}
-
 struct Geo {
     int nx, ny, nz;
     int64_t nnode;

@@ -77,7 +77,7 @@ __device__ __forceinline__ void sens_body(const SensArgs<T>& A, double penal, in
         for (int i = 0; i < D; ++i) {
             double k_u = 0.0;
 #pragma unroll
-            for (int j = 0; j < D; ++j) k_u += ke[i * D + j] * ue[j];
+            for (int j = 0; j < D; ++j) k_u += ld_const(ke + i * D + j) * ue[j];
             ce += ue[i] * k_u;
         }
         double out = 0.0;

@@ -589,13 +589,30 @@ struct Pcg {
                         v[2] += (double)rn * (double)rn;
                     }
                 }
-                for (int t = threadIdx.x; t < nh; t += bd) {
-                    const int j = t < nlo ? t : t - nlo + ohi;
-                    const uint32_t i = w0 + (uint32_t)j;
-                    const T rk = ld_dev(Rk + i), wk = ld_dev(Wk + i);
-                    const T si = k == 0 ? wk : fma(bt, ld_dev(So + i), wk);
-                    const T rn = fma(-a, si, rk);
-                    win[j] = dband[t] * rn;
+                // the band: a thread's loads (up to UB values) are all issued
+                // before the first is used, one memory latency per pass
+                constexpr int UB = 4;
+                for (int t0 = threadIdx.x; t0 < nh; t0 += UB * bd) {
+                    T rk[UB], wk[UB], so[UB];
+#pragma unroll
+                    for (int ub = 0; ub < UB; ++ub) {
+                        const int t = t0 + ub * bd;
+                        rk[ub] = wk[ub] = so[ub] = T(0);
+                        if (t < nh) {
+                            const uint32_t i = w0 + (uint32_t)(t < nlo ? t : t - nlo + ohi);
+                            rk[ub] = ld_dev(Rk + i);
+                            wk[ub] = ld_dev(Wk + i);
+                            if (k > 0) so[ub] = ld_dev(So + i);
+                        }
+                    }
+#pragma unroll
+                    for (int ub = 0; ub < UB; ++ub) {
+                        const int t = t0 + ub * bd;
+                        if (t < nh) {
+                            const T si = k == 0 ? wk[ub] : fma(bt, so[ub], wk[ub]);
+                            win[t < nlo ? t : t - nlo + ohi] = dband[t] * fma(-a, si, rk[ub]);
+                        }
+                    }
                 }
                 __syncthreads();
                 const SrcLds<2, T> sl{win, wlo};
