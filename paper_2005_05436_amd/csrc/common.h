@@ -388,7 +388,7 @@ struct FlagReduce {
     // the wait timed out or another block aborted.  Two block barriers: one
     // after the waves' partial sums, one after the waves' shares of the poll.
     template <int K>
-    __device__ bool reduce(const double (&v)[K], double* out_sh, double* /*unused*/) {
+    __device__ __forceinline__ bool reduce(const double (&v)[K], double* out_sh, double* /*unused*/) {
         constexpr int NWMAX = 16;                      // up to 1024 threads
         __shared__ double shA[NWMAX][K];
         __shared__ double shB[NWMAX][K + 1];

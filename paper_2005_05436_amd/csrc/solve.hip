@@ -269,7 +269,7 @@ struct Pcg {
     // FP32 recomputation of b - A x is dominated by cancellation, and the
     // outer FP64 residual is the judge anyway.
     template <bool WIN = true>
-    __device__ int run(const T* b, T* x, bool x_zero, const T* dinv, T* r, T* z, T* pa, T* pb, T* q,
+    __device__ __forceinline__ int run(const T* b, T* x, bool x_zero, const T* dinv, T* r, T* z, T* pa, T* pb, T* q,
                        double tol, int maxit, int& restarts, bool confirm = true) {
         const Own& o = C.o;
         if (x_zero)
@@ -616,8 +616,12 @@ struct Pcg {
                 }
                 __syncthreads();
                 const SrcLds<2, T> sl{win, wlo};
+                // the first and last node slots hold the band nodes, whose w
+                // is stored for the neighbours: those go first, so that their
+                // stores complete while the other nodes are computed
 #pragma unroll
-                for (int j = 0; j < J; ++j) {
+                for (int jj = 0; jj < J; ++jj) {
+                    const int j = jj == 0 ? 0 : J - jj;
                     int f = fl[j], yy = iy[j], xx = ix[j];
                     uint32_t gg = gi[j];
                     opaque(f, yy, xx, gg);
