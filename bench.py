@@ -106,10 +106,23 @@ def stage_bytes(cfg, info, dt_bytes, op, solve):
     V = 4 if vp == "f32" else 8
     mat = (F * nnz + 4 * (n + 1)) if opk == "assembled" else V * m   # K^(s) values + row_ptr | moduli
     if info.dim == 2 and opk == "matfree" and vp == "f64":
-        # one sweep per iteration (single grid sum) with dinv, x, p, the moduli
-        # and the free flags held in LDS for the whole solve: r, w, s_old in;
-        # s, r, w out
-        b["solve_per_iter_kernel_model"] = 6 * V * n
+        # one sweep per iteration (single grid sum); the own nodes' dinv, r, w,
+        # s in registers and x, p, the moduli and the free flags in LDS for the
+        # whole solve, so only the band moves through memory: each block
+        # stores r, w, s of its nodes within one band (ny + 2 nodes) of its
+        # range ends and loads those of the band on either side of its range
+        import torch
+        nnode, band = n // 2, cfg.nely + 2
+        num_cu = torch.cuda.get_device_properties(0).multi_processor_count if torch.cuda.is_available() else 256
+        nb = min(num_cu, -(-nnode // 1024))
+        chunk = -(-nnode // nb)
+        pub = rd = 0
+        for bb in range(nb):
+            lo = min(nnode, bb * chunk)
+            hi = min(nnode, lo + chunk)
+            pub += min(hi - lo, 2 * band)
+            rd += (lo - max(0, lo - band)) + (min(nnode, hi + band) - hi)
+        b["solve_per_iter_kernel_model"] = 3 * V * 2 * (pub + rd)
     else:
         phase_a = mat + 2 * V * n + 2 * V * n + n             # z, p_old in; p_new, q out; free mask
         phase_b = 5 * V * n + 3 * V * n                       # x, p, r, q, dinv in; x, r, z out
