@@ -384,18 +384,44 @@ struct FlagReduce {
         ll = l; bar = b; bid = block; nblk = nblocks; red = 0;
         epoch = ld_dev(&b[4]);
     }
-    // K <= kLLVals; results in out_sh[0..K) (valid in every thread); false if
-    // the wait timed out or another block aborted.  Two block barriers: one
-    // after the waves' partial sums, one after the waves' shares of the poll.
+    __device__ __forceinline__ unsigned long long* region() const {
+        return ll + (size_t)(red & 1) * kMaxCoopBlocks * kLLVals * 2;
+    }
+    __device__ __forceinline__ unsigned tag() const { return epoch + (unsigned)red + 1u; }
+    __device__ __forceinline__ void waited(unsigned& spins, bool& ok) const {
+        if ((++spins & 255u) == 0u) {
+            if (ld_dev(&bar[2]) != 0u) ok = false;
+            else if (spins > kSpinLimit) {
+                atomicOr(&bar[3], FLAG_BARRIER_TIMEOUT);
+                atomicExch(&bar[2], 1u);
+                ok = false;
+            }
+        }
+    }
+    // Spins (one thread) until block b's record of the current grid sum
+    // carries its tag: one word, the last its publisher writes (every block
+    // polls every record, so the poll's request rate is what costs).
     template <int K>
-    __device__ __forceinline__ bool reduce(const double (&v)[K], double* out_sh, double* /*unused*/) {
+    __device__ __forceinline__ void wait_record(unsigned b, bool& ok) const {
+        const unsigned long long* wd = region() + (size_t)b * kLLVals * 2;
+        const unsigned tg = tag();
+        unsigned spins = 0;
+        for (unsigned long long sent = ld_dev(wd + 2 * K - 1); ok && (unsigned)(sent >> 32) != tg;
+             sent = ld_dev(wd + 2 * K - 1)) {
+            waited(spins, ok);
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    // First half of a grid sum: the block's K partial sums (wave sums, then
+    // waves in order) published as its flagged record, after every wave's
+    // stores for other blocks completed (so a record also certifies them).
+    // Every thread of the block calls it.
+    template <int K>
+    __device__ __forceinline__ void publish(const double (&v)[K]) {
         constexpr int NWMAX = 16;                      // up to 1024 threads
         __shared__ double shA[NWMAX][K];
-        __shared__ double shB[NWMAX][K + 1];
-        const int NW = (int)(blockDim.x >> 6), NB = (int)blockDim.x;
+        const int NW = (int)(blockDim.x >> 6);
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        unsigned long long* region = ll + (size_t)(red & 1) * kMaxCoopBlocks * kLLVals * 2;
-        const unsigned tag = epoch + (unsigned)red + 1u;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const double s = wave_sum(v[k]);
@@ -406,59 +432,53 @@ struct FlagReduce {
         wait_stores();
         __syncthreads();
         if (threadIdx.x == 0) {
+            unsigned long long* reg = region();
+            const unsigned tg = tag();
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 double s = shA[0][k];
                 for (int i = 1; i < NW; ++i) s += shA[i][k];
                 const unsigned long long bits = (unsigned long long)__double_as_longlong(s);
-                unsigned long long* wd = region + ((size_t)bid * kLLVals + k) * 2;
-                st_dev(wd, ((unsigned long long)tag << 32) | (bits & 0xFFFFFFFFull));
-                st_dev(wd + 1, ((unsigned long long)tag << 32) | (bits >> 32));
+                unsigned long long* wd = reg + ((size_t)bid * kLLVals + k) * 2;
+                st_dev(wd, ((unsigned long long)tg << 32) | (bits & 0xFFFFFFFFull));
+                st_dev(wd + 1, ((unsigned long long)tg << 32) | (bits >> 32));
             }
         }
-        bool ok = true;
+    }
+    // Second half: every block's record of the current grid sum, summed in
+    // block order; results in out_sh[0..K) (valid in every thread); false if
+    // the wait timed out or another block aborted.  A polling thread spins on
+    // one word of its record, then loads the record's 2K words together and
+    // reloads any without the tag.
+    template <int K>
+    __device__ __forceinline__ bool collect(double* out_sh, bool ok0 = true) {
+        constexpr int NWMAX = 16;
+        __shared__ double shB[NWMAX][K + 1];
+        const int NW = (int)(blockDim.x >> 6), NB = (int)blockDim.x;
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const unsigned long long* reg = region();
+        const unsigned tg = tag();
+        bool ok = ok0;                                 // a caller's failed wait joins the verdict
         double acc[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) acc[k] = 0.0;
-        // each polling thread first spins on one word of its block's record
-        // (the last one the publisher writes; every block polls every record,
-        // so the poll's request rate is what costs), then loads the record's
-        // 2K words together and reloads any without the current tag
         for (int b = threadIdx.x; b < (int)nblk; b += NB) {
-            const unsigned long long* wd = region + (size_t)b * kLLVals * 2;
+            wait_record<K>((unsigned)b, ok);
+            const unsigned long long* wd = reg + (size_t)b * kLLVals * 2;
             unsigned spins = 0;
-            for (unsigned long long sent = ld_dev(wd + 2 * K - 1); ok && (unsigned)(sent >> 32) != tag;
-                 sent = ld_dev(wd + 2 * K - 1)) {
-                if ((++spins & 255u) == 0u) {
-                    if (ld_dev(&bar[2]) != 0u) ok = false;
-                    else if (spins > kSpinLimit) {
-                        atomicOr(&bar[3], FLAG_BARRIER_TIMEOUT);
-                        atomicExch(&bar[2], 1u);
-                        ok = false;
-                    }
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
             unsigned long long wv[2 * K];
 #pragma unroll
             for (int h = 0; h < 2 * K; ++h) wv[h] = ld_dev(wd + h);
             while (ok) {
                 bool ready = true;
 #pragma unroll
-                for (int h = 0; h < 2 * K; ++h) ready = ready && (unsigned)(wv[h] >> 32) == tag;
+                for (int h = 0; h < 2 * K; ++h) ready = ready && (unsigned)(wv[h] >> 32) == tg;
                 if (ready) break;
-                if ((++spins & 255u) == 0u) {
-                    if (ld_dev(&bar[2]) != 0u) ok = false;
-                    else if (spins > kSpinLimit) {
-                        atomicOr(&bar[3], FLAG_BARRIER_TIMEOUT);
-                        atomicExch(&bar[2], 1u);
-                        ok = false;
-                    }
-                }
+                waited(spins, ok);
                 __builtin_amdgcn_s_sleep(1);
 #pragma unroll
                 for (int h = 0; h < 2 * K; ++h)
-                    if ((unsigned)(wv[h] >> 32) != tag) wv[h] = ld_dev(wd + h);
+                    if ((unsigned)(wv[h] >> 32) != tg) wv[h] = ld_dev(wd + h);
             }
 #pragma unroll
             for (int k = 0; k < K; ++k)
@@ -482,6 +502,13 @@ struct FlagReduce {
         for (int i = 0; i < NW; ++i) all_ok = all_ok && shB[i][K] != 0.0;
         ++red;
         return all_ok;
+    }
+    // K <= kLLVals; a whole grid sum: publish, then collect (two block
+    // barriers).
+    template <int K>
+    __device__ __forceinline__ bool reduce(const double (&v)[K], double* out_sh, double* /*unused*/) {
+        publish<K>(v);
+        return collect<K>(out_sh);
     }
     // block 0 advances the epoch once every block has published its last sums
     __device__ __forceinline__ void finish() {

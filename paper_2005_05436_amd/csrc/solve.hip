@@ -229,6 +229,11 @@ __device__ __forceinline__ void opaque(int& a, int& b, int& c, uint32_t& d) {
     asm volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
 }
 
+// Iterations between the pipelined PCG's recomputations of its recurrences
+// (every 100 keeps the iteration count of PCG on the SIMP test meshes; every
+// 400 lost 60%).
+constexpr int kPipeReplace = 100;
+
 template <int DIM, typename T, class Op>
 struct Pcg {
     const Op& op;
@@ -652,6 +657,279 @@ struct Pcg {
         }
         return it;
     }
+
+    // Pipelined PCG (the arrangement of Ghysels and Vanroose, 2014) of the
+    // single-sum iteration above, with the same on-chip residency.  With
+    // u = M^-1 r, w = A u, m = M^-1 w, n = A m and the extra recurrence
+    // z = n + beta z (z = A M^-1 s):
+    //   s = w + beta s,  p = u + beta p,  x += alpha p,  r -= alpha s,
+    //   w -= alpha z,    u = M^-1 r,
+    // the SpMV of an iteration (n = A m) no longer comes before its grid sum:
+    // a block publishes its partial gamma = (r, u), delta = (w, u) and |r|^2,
+    // applies A to m while the sums travel, and collects them afterwards.
+    // The SpMV needs the neighbours' new w on the band, so a block first
+    // waits only for the blocks whose nodes its window holds: their records
+    // of the same grid sum, written after their band stores completed.  At
+    // SIMP's stiffness contrast the recurrences for w, s and z drift from
+    // A u, A p and A M^-1 s; every kPipeReplace iterations, and to confirm
+    // convergence, r = b - A x, w, s and z are recomputed (four SpMVs with
+    // their band exchanges), which keeps the iteration count that of PCG.
+    // The w of the band nodes goes through memory double-buffered by the
+    // parity of its publication (a block cannot publish twice more before
+    // every reader has loaded it: that needs the readers' next grid sums).
+    template <int J>
+    __device__ __forceinline__ int run_pipe(const T* b, T* x, const T* dinv, T* WB0, T* WB1, T* EX0, T* EX1,
+                                            double tol, int maxit, int& restarts) {
+        const Own& o = C.o;
+        const int bd = (int)blockDim.x;
+        const int64_t whi = wlo + wn;
+        const int nlo = (int)(2 * (o.lo - wlo)), nh = nlo + (int)(2 * (whi - o.hi));
+        const int nown = (int)(2 * (o.hi - o.lo)), ohi = (int)(2 * (o.hi - wlo));
+        const uint32_t i0 = (uint32_t)(2 * o.lo), w0 = (uint32_t)(2 * wlo);
+        T* const xl = own;
+        T* const pl = own + nown;
+        const int ny1 = g.ny + 1;
+        const int64_t exl = o.lo / ny1 > 0 ? o.lo / ny1 - 1 : 0;
+        const int64_t exh = (o.hi - 1) / ny1 < g.nx - 1 ? (o.hi - 1) / ny1 : g.nx - 1;
+        const int64_t elo = exl * g.ny;
+        const int ne = (int)((exh + 1) * g.ny - elo);
+        T* const el = own + 2 * nown;
+        T* const dband = el + ne;
+        for (int t = threadIdx.x; t < ne; t += bd) el[t] = op.E[elo + t];
+        Op opl = op;
+        opl.E = el;
+        opl.e0 = elo;
+        // the blocks whose nodes the window's bands hold (ranges of `chunk`
+        // nodes, as the kernel deals them)
+        const int64_t chunk = (g.nnode + C.fr.nblk - 1) / C.fr.nblk;
+        const int nb_lo0 = (int)(wlo / chunk), nb_lo1 = o.lo > wlo ? (int)((o.lo - 1) / chunk) : -1;
+        const int nb_hi0 = (int)(o.hi / chunk), nb_hi1 = whi > o.hi ? (int)((whi - 1) / chunk) : -1;
+        const int n_lo = nb_lo1 >= nb_lo0 ? nb_lo1 - nb_lo0 + 1 : 0;
+        const int n_nb = n_lo + (nb_hi1 >= nb_hi0 ? nb_hi1 - nb_hi0 + 1 : 0);
+        constexpr int kPub = 4, kOn = 8;
+        uint32_t gi[J];
+        int iy[J], ix[J], fl[J];
+        T d[J][2], r[J][2], w[J][2], s[J][2], z[J][2], nv[J][2];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int64_t ndj = o.lo + threadIdx.x + (int64_t)j * bd;
+            gi[j] = (uint32_t)(2 * ndj);
+            iy[j] = ix[j] = fl[j] = 0;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) d[j][c] = r[j][c] = w[j][c] = s[j][c] = z[j][c] = nv[j][c] = T(0);
+            if (ndj < o.hi) {
+                int iz;
+                g.coords(ndj, iy[j], ix[j], iz, 2);
+                fl[j] = kOn | (o.edge(ndj) ? kPub : 0);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const uint32_t i = gi[j] + c;
+                    fl[j] |= fm[i] ? 1 << c : 0;
+                    d[j][c] = dinv[i];                // written by this thread (same node mapping)
+                    xl[i - i0] = x[i];
+                    pl[i - i0] = T(0);
+                }
+            }
+        }
+        __syncthreads();
+        const SrcLds<2, T> sl{win, wlo};
+        // the own values of a vector into the window (after the block's
+        // previous SpMV: callers place a barrier before)
+        auto own_to_window = [&](auto&& val) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                int f = fl[j], yy = 0, xx = 0;
+                uint32_t gg = gi[j];
+                opaque(f, yy, xx, gg);
+                if (f & kOn)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) win[gg + c - w0] = val(j, c);
+            }
+        };
+        auto publish_band = [&](T* buf, auto&& val) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                int f = fl[j], yy = 0, xx = 0;
+                uint32_t gg = gi[j];
+                opaque(f, yy, xx, gg);
+                if (f & kPub)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) st_dev(buf + gg + c, val(j, c));
+            }
+        };
+        // the band of the window from the neighbours' published values,
+        // times their Jacobi diagonal when `scaled`; a thread's loads (UB per
+        // pass) are issued together
+        auto band_to_window = [&](const T* buf, bool scaled) {
+            constexpr int UB = 4;
+            for (int t0 = threadIdx.x; t0 < nh; t0 += UB * bd) {
+                T bv[UB];
+#pragma unroll
+                for (int ub = 0; ub < UB; ++ub) {
+                    const int t = t0 + ub * bd;
+                    bv[ub] = T(0);
+                    if (t < nh) bv[ub] = ld_dev(buf + w0 + (uint32_t)(t < nlo ? t : t - nlo + ohi));
+                }
+#pragma unroll
+                for (int ub = 0; ub < UB; ++ub) {
+                    const int t = t0 + ub * bd;
+                    if (t < nh) win[t < nlo ? t : t - nlo + ohi] = scaled ? dband[t] * bv[ub] : bv[ub];
+                }
+            }
+        };
+        // out = A (window) on the own free DOFs; the band node slots first
+        auto spmv = [&](T (&out)[J][2]) {
+#pragma unroll
+            for (int jj = 0; jj < J; ++jj) {
+                const int j = jj == 0 ? 0 : J - jj;
+                int f = fl[j], yy = iy[j], xx = ix[j];
+                uint32_t gg = gi[j];
+                opaque(f, yy, xx, gg);
+                if (!(f & kOn)) continue;
+                T a2[2];
+                opl.apply((int64_t)(gg >> 1), yy, xx, 0, sl, a2);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) out[j][c] = (f >> c) & 1 ? a2[c] : T(0);
+            }
+        };
+        // one exchange and SpMV: out = A (M^-1 raw) when scaled, else A raw;
+        // the band nodes' raw values go through buf
+        auto exchange_spmv = [&](auto&& raw, T* buf, bool scaled, T (&out)[J][2]) {
+            __syncthreads();                        // the previous SpMV's window reads are done
+            own_to_window([&](int j, int c) { return scaled ? d[j][c] * raw(j, c) : raw(j, c); });
+            publish_band(buf, raw);
+            C.alive = C.gb.sync() && C.alive;       // the neighbours' band stores are complete
+            band_to_window(buf, scaled);
+            __syncthreads();
+            spmv(out);
+        };
+        // r = b - A x, w = A M^-1 r, s = A p and z = A M^-1 s recomputed from
+        // x and p (x and p through the window like the other sources)
+        auto replace_all = [&]() {
+            exchange_spmv([&](int j, int c) { return xl[gi[j] + c - i0]; }, EX0, false, nv);
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                int f = fl[j], yy = 0, xx = 0;
+                uint32_t gg = gi[j];
+                opaque(f, yy, xx, gg);
+                if (f & kOn)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) r[j][c] = (f >> c) & 1 ? b[gg + c] - nv[j][c] : T(0);
+            }
+            exchange_spmv([&](int j, int c) { return r[j][c]; }, EX1, true, w);
+            exchange_spmv([&](int j, int c) { return pl[gi[j] + c - i0]; }, EX0, false, s);
+            exchange_spmv([&](int j, int c) { return s[j][c]; }, EX1, true, z);
+        };
+        auto partials = [&](double (&v)[3]) {
+            v[0] = v[1] = v[2] = 0.0;
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+                if (fl[j] & kOn)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const T ui = d[j][c] * r[j][c];
+                        v[0] += (double)r[j][c] * (double)ui;
+                        v[1] += (double)w[j][c] * (double)ui;
+                        v[2] += (double)r[j][c] * (double)r[j][c];
+                    }
+        };
+        int it = 0, since = 0, pub = 0;
+        bool fresh = false, stop = false, confirming = false, replace = true;
+        double gamma_old = 1.0, alpha_old = 1.0, beta = 0.0, alpha = 0.0;
+        double v[3];
+        // the band's Jacobi diagonal, written by the neighbouring blocks
+        // before this barrier (each value read back by the thread that loads it)
+        C.alive = C.gb.sync() && C.alive;
+        for (int t = threadIdx.x; t < nh; t += bd) dband[t] = ld_dev(dinv + w0 + (uint32_t)(t < nlo ? t : t - nlo + ohi));
+        while (C.alive) {
+            if (replace) {
+                // the recurrences' vectors recomputed (the true residual: it
+                // confirms convergence, or is the one a spent budget or a
+                // breakdown reports); p = s = z = 0 at the start
+                replace_all();
+                replace = false;
+                fresh = true;
+                since = 0;
+            } else {
+                const T a = (T)alpha, bt = (T)beta;
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    int f = fl[j], yy = 0, xx = 0;
+                    uint32_t gg = gi[j];
+                    opaque(f, yy, xx, gg);
+                    if (!(f & kOn)) continue;
+                    const uint32_t l = gg - i0;
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const T ui = d[j][c] * r[j][c];
+                        z[j][c] = fma(bt, z[j][c], nv[j][c]);
+                        s[j][c] = fma(bt, s[j][c], w[j][c]);
+                        const T pi = fma(bt, pl[l + c], ui);
+                        pl[l + c] = pi;
+                        xl[l + c] = fma(a, pi, xl[l + c]);
+                        r[j][c] = fma(-a, s[j][c], r[j][c]);
+                        w[j][c] = fma(-a, z[j][c], w[j][c]);
+                    }
+                }
+                fresh = false;
+                ++it;
+                ++since;
+            }
+            partials(v);
+            publish_band(pub & 1 ? WB1 : WB0, [&](int j, int c) { return w[j][c]; });
+            // m = M^-1 w into the window (own part), the partial sums out
+            __syncthreads();
+            own_to_window([&](int j, int c) { return d[j][c] * w[j][c]; });
+            C.fr.template publish<3>(v);
+            // the band of m: wait for the blocks that own it (a failed wait
+            // enters the grid sum's verdict), then load
+            bool nb_ok = true;
+            if ((int)threadIdx.x < n_nb) {
+                const int t = threadIdx.x;
+                C.fr.template wait_record<3>((unsigned)(t < n_lo ? nb_lo0 + t : nb_hi0 + t - n_lo), nb_ok);
+            }
+            __syncthreads();
+            band_to_window(pub & 1 ? WB1 : WB0, true);
+            ++pub;
+            __syncthreads();
+            spmv(nv);                                   // n = A m, while the sums travel
+            C.alive = C.fr.template collect<3>(C.res, nb_ok) && C.alive;
+            if (!C.alive) break;
+            const double gamma = C.res[0], delta = C.res[1], rr = C.res[2];
+            if (stop || (fresh && rr <= tol * tol)) break;
+            if (fresh && confirming) ++restarts;        // the true residual missed tol
+            confirming = rr <= tol * tol;
+            if (confirming || it >= maxit || since >= kPipeReplace) {
+                stop = it >= maxit;
+                replace = true;
+                continue;
+            }
+            if (it == 0) {
+                beta = 0.0;
+                alpha = gamma / delta;
+            } else {
+                beta = gamma / gamma_old;
+                alpha = gamma / (delta - beta * gamma / alpha_old);
+            }
+            if (!(alpha > 0.0) || !(alpha < INFINITY)) {   // breakdown: report the true residual
+                stop = true;
+                replace = true;
+                continue;
+            }
+            gamma_old = gamma;
+            alpha_old = alpha;
+        }
+        // x of the own nodes back to memory
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            if (!(fl[j] & kOn)) continue;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) x[gi[j] + c] = xl[gi[j] + c - i0];
+        }
+        if (threadIdx.x == 0) C.res[1] = C.res[2];      // the caller reads |r|^2 there
+        __syncthreads();
+        return it;
+    }
 };
 
 template <int DIM, typename T, class Op>
@@ -810,6 +1088,8 @@ __device__ bool mixed_cg(Ctx& C, const Geo& g, const SolveArgs& A, const Op32& o
 //      held on chip (at most kRegNodes nodes per thread).
 constexpr int kModeWindow = 4;
 constexpr int kRegNodes = 4;
+// kModePipe: the same residency with the pipelined iteration (Pcg::run_pipe).
+constexpr int kModePipe = 7;
 // kModeFallback: the FP64 PCG that finishes a mixed-precision solve which
 // stalled (its own launch after the mixed kernel, so the two solvers do not
 // share one kernel's registers); it returns at once when the mixed solve
@@ -885,7 +1165,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& A, int bid, int nb) 
     double resid = 0.0;
 
     MatFree<DIM, double> mf64{A.E64, A.kf64, g.nx, g.ny, g.nz};
-    if (MODE <= 1 || MODE == kModeWindow || MODE == kModeWindow3) {
+    if (MODE <= 1 || MODE == kModeWindow || MODE == kModeWindow3 || MODE == kModePipe) {
         double *r = A.v64[0], *z = A.v64[1], *pa = A.v64[2], *pb = A.v64[3], *q = A.v64[4], *dinv = A.v64[5];
         if (MODE == 0) {
             CsrS<DIM, double> op{A.rp, (const double*)A.kval, g.nx, g.ny, g.nz};
@@ -917,7 +1197,11 @@ __device__ __forceinline__ void solve_body(const SolveArgs& A, int bid, int nb) 
                         cg.own = solve_win + 2 * (int64_t)A.stage;
                 }
             }
-            if constexpr (DIM == 2 && MODE == kModeWindow) {
+            if constexpr (DIM == 2 && MODE == kModePipe) {
+                if (cg.win && cg.own && o.hi - o.lo <= (int64_t)kRegNodes * blockDim.x)
+                    iters = cg.template run_pipe<kRegNodes>(A.f, u, dinv, r, z, pb, q, tol, A.maxit, restarts);
+                else C.alive = false;      // the launch sizes the LDS; a kernel without it reports failure
+            } else if constexpr (DIM == 2 && MODE == kModeWindow) {
                 if (cg.win && cg.own && o.hi - o.lo <= (int64_t)kRegNodes * blockDim.x)
                     iters = cg.template run1<kRegNodes>(A.f, u, dinv, r, z, pb, q, A.v64[6], A.v64[7], tol, A.maxit,
                                                         restarts);
@@ -974,12 +1258,13 @@ __device__ __forceinline__ void solve_body(const SolveArgs& A, int bid, int nb) 
 // registers, so a block of 16 waves (one block per CU) hides the gather
 // latency without adding blocks to every grid reduction; the others use 4.
 constexpr int solve_block(int dim, int mode) {
-    return dim == 2 && mode <= 1 ? 1024 : mode == 4 || mode == 6 ? 512 : 256;
+    return dim == 2 && mode <= 1 ? 1024 : mode == 4 || mode == 6 || mode == 7 ? 512 : 256;
 }
 static_assert(solve_block(2, kModeFallback) == solve_block(2, 3) && solve_block(3, kModeFallback) == solve_block(3, 3),
               "a batch launches the fallback kernel with the mixed kernel's grid");
 constexpr size_t kSolveLdsBytes = 158 * 1024;     // dynamic LDS of the windowed kernel (one block per CU)
 constexpr bool kSolveWindow3 = true;              // the 3D windowed kernel where its window fits
+constexpr bool kSolvePipe = true;                 // 2D on-chip kernel: the pipelined iteration
 
 template <int DIM, int MODE>
 __global__ __launch_bounds__(solve_block(DIM, MODE)) void solve_kernel(SolveArgs A) {
@@ -1012,7 +1297,7 @@ static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream
         // 2D matrix-free FP64: when the block's window (own nodes and the band
         // on either side) fits in LDS beside one block per CU, the kernel
         // with the window and one grid sum per iteration
-        auto kw = solve_kernel<2, kModeWindow>;
+        auto kw = kSolvePipe ? solve_kernel<2, kModePipe> : solve_kernel<2, kModeWindow>;
         const int64_t chunk = (A.geo.nnode + blocks - 1) / blocks;
         const int64_t wn = std::min<int64_t>(A.geo.nnode, chunk + 2 * ((int64_t)A.geo.ny + 2));
         const size_t win_bytes = (size_t)wn * 2 * sizeof(double);
