@@ -251,7 +251,9 @@ typedef struct {
     int32_t iterations;          /* CG iterations (inner + fallback) */
     int32_t outer;               /* FP64 residual replacements (mixed) */
     int32_t converged;           /* 1 if residual <= rtol */
-    int32_t fallback;            /* 1 if the FP64 fallback ran */
+    int32_t fallback;            /* 1 if a fallback ran: the FP64 PCG after a mixed-precision solve
+                                    that stalled, or the single-sum PCG after a pipelined one whose
+                                    recurrences ran away (it continues from the best iterate) */
     int32_t restarts;            /* residual-replacement restarts */
     int32_t pad;
 } to_solve_stats;

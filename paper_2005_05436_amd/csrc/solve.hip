@@ -187,7 +187,7 @@ struct SolveArgs {
     int stage;                  // 2D FP64 matrix-free: nodes of the LDS window of the SpMV source (0: off)
     int stage_own;              // with the window: own-node capacity of the LDS copies of dinv, x, p (0: off)
     int stage_e;                // with them: capacity of the LDS copy of the moduli the own nodes touch
-    int pad;
+    int follow;                 // 2D single-sum launch that continues a pipelined solve which handed over
     double* partial; unsigned* bar;
     unsigned long long* ll;
     to_solve_stats* st;
@@ -679,7 +679,7 @@ struct Pcg {
     // every reader has loaded it: that needs the readers' next grid sums).
     template <int J>
     __device__ __forceinline__ int run_pipe(const T* b, T* x, const T* dinv, T* WB0, T* WB1, T* EX0, T* EX1,
-                                            double tol, int maxit, int& restarts) {
+                                            double tol, int maxit, int& restarts, bool& handover) {
         const Own& o = C.o;
         const int bd = (int)blockDim.x;
         const int64_t whi = wlo + wn;
@@ -836,6 +836,9 @@ struct Pcg {
         int it = 0, since = 0, pub = 0;
         bool fresh = false, stop = false, confirming = false, replace = true;
         double gamma_old = 1.0, alpha_old = 1.0, beta = 0.0, alpha = 0.0;
+        // the smallest true residual so far; its x is kept in memory (x)
+        double rr_best = INFINITY;
+        handover = false;
         double v[3];
         // the band's Jacobi diagonal, written by the neighbouring blocks
         // before this barrier (each value read back by the thread that loads it)
@@ -896,6 +899,21 @@ struct Pcg {
             C.alive = C.fr.template collect<3>(C.res, nb_ok) && C.alive;
             if (!C.alive) break;
             const double gamma = C.res[0], delta = C.res[1], rr = C.res[2];
+            if (fresh) {
+                // near the attainable accuracy the recurrences can run away
+                // (the true residual grows by orders of magnitude): hand the
+                // solve over, from the best iterate, to the single-sum kernel
+                if (!(rr <= 1e6 * rr_best)) { handover = true; break; }
+                if (rr < rr_best) {
+                    rr_best = rr;
+#pragma unroll
+                    for (int j = 0; j < J; ++j) {
+                        if (!(fl[j] & kOn)) continue;
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) x[gi[j] + c] = xl[gi[j] + c - i0];
+                    }
+                }
+            }
             if (stop || (fresh && rr <= tol * tol)) break;
             if (fresh && confirming) ++restarts;        // the true residual missed tol
             confirming = rr <= tol * tol;
@@ -911,22 +929,23 @@ struct Pcg {
                 beta = gamma / gamma_old;
                 alpha = gamma / (delta - beta * gamma / alpha_old);
             }
-            if (!(alpha > 0.0) || !(alpha < INFINITY)) {   // breakdown: report the true residual
-                stop = true;
-                replace = true;
-                continue;
+            if (!(alpha > 0.0) || !(alpha < INFINITY)) {   // breakdown: hand over from the best iterate
+                handover = true;
+                break;
             }
             gamma_old = gamma;
             alpha_old = alpha;
         }
-        // x of the own nodes back to memory
+        // x of the own nodes back to memory (a hand-over leaves the best one)
+        if (!handover)
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            if (!(fl[j] & kOn)) continue;
+            for (int j = 0; j < J; ++j) {
+                if (!(fl[j] & kOn)) continue;
 #pragma unroll
-            for (int c = 0; c < 2; ++c) x[gi[j] + c] = xl[gi[j] + c - i0];
-        }
-        if (threadIdx.x == 0) C.res[1] = C.res[2];      // the caller reads |r|^2 there
+                for (int c = 0; c < 2; ++c) x[gi[j] + c] = xl[gi[j] + c - i0];
+            }
+        __syncthreads();
+        if (threadIdx.x == 0) C.res[1] = handover ? rr_best : C.res[2];   // the caller reads |r|^2 there
         __syncthreads();
         return it;
     }
@@ -1101,6 +1120,8 @@ constexpr int kModeWindow3 = 6;
 template <int DIM, int MODE>
 __device__ __forceinline__ void solve_body(const SolveArgs& A, int bid, int nb) {
     if (MODE == kModeFallback && !(A.st->fallback == 1 && A.st->converged == 0)) return;   // uniform over the grid
+    if (MODE == kModeWindow && A.follow && !(A.st->fallback == 1 && A.st->converged == 0)) return;
+    const to_solve_stats prev_st = MODE == kModeWindow && A.follow ? *A.st : to_solve_stats{};
     __shared__ double sh[16];
     __shared__ double res[4];
     Ctx C{A.partial, GridBar{}, sh, res, 0, true, Own{}, FlagReduce{}};
@@ -1153,7 +1174,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& A, int bid, int nb) 
             for (int c = 0; c < DIM; ++c) {
                 const int64_t i = DIM * nd + c;
                 const bool fr = A.freem[i] != 0;
-                if (!fr || A.zero_x0) o.st(u, nd, i, 0.0);
+                if (!fr || (A.zero_x0 && !A.follow)) o.st(u, nd, i, 0.0);
                 const double fi = fr ? A.f[i] : 0.0;
                 v[0] += fi * fi;
             }
@@ -1198,14 +1219,23 @@ __device__ __forceinline__ void solve_body(const SolveArgs& A, int bid, int nb) 
                 }
             }
             if constexpr (DIM == 2 && MODE == kModePipe) {
+                bool handover = false;
                 if (cg.win && cg.own && o.hi - o.lo <= (int64_t)kRegNodes * blockDim.x)
-                    iters = cg.template run_pipe<kRegNodes>(A.f, u, dinv, r, z, pb, q, tol, A.maxit, restarts);
+                    iters = cg.template run_pipe<kRegNodes>(A.f, u, dinv, r, z, pb, q, tol, A.maxit, restarts, handover);
                 else C.alive = false;      // the launch sizes the LDS; a kernel without it reports failure
+                fallback = handover ? 1 : 0;
             } else if constexpr (DIM == 2 && MODE == kModeWindow) {
+                // as the follow-up of a pipelined solve: the remaining budget
+                const int left = A.follow ? A.maxit - prev_st.iterations : A.maxit;
                 if (cg.win && cg.own && o.hi - o.lo <= (int64_t)kRegNodes * blockDim.x)
-                    iters = cg.template run1<kRegNodes>(A.f, u, dinv, r, z, pb, q, A.v64[6], A.v64[7], tol, A.maxit,
-                                                        restarts);
+                    iters = cg.template run1<kRegNodes>(A.f, u, dinv, r, z, pb, q, A.v64[6], A.v64[7], tol,
+                                                        left > 0 ? left : 0, restarts);
                 else C.alive = false;      // the launch sizes the LDS; a kernel without it reports failure
+                if (A.follow) {
+                    iters += prev_st.iterations;
+                    restarts += prev_st.restarts;
+                    fallback = 1;
+                }
             } else if constexpr (DIM == 3 && MODE == 1) {
                 // the gather kernel (the window kernel is kModeWindow3): no LDS path compiled in
                 iters = cg.template run<false>(A.f, u, false, dinv, r, z, pa, pb, q, tol, A.maxit, restarts);
@@ -1293,6 +1323,7 @@ static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream
     A.stage = 0;
     A.stage_own = 0;
     A.stage_e = 0;
+    A.follow = 0;
     if constexpr (DIM == 2 && MODE == 1) {
         // 2D matrix-free FP64: when the block's window (own nodes and the band
         // on either side) fits in LDS beside one block per CU, the kernel
@@ -1320,6 +1351,14 @@ static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream
             A.stage_e = (int)ecap;
             void* args[] = {&A};
             TO_HIP(hipLaunchCooperativeKernel((const void*)kw, dim3(blocks), dim3(SBW), args, win_bytes + own_bytes, s));
+            if (kSolvePipe) {
+                // the single-sum kernel continues a pipelined solve that handed
+                // over (it returns at once otherwise)
+                A.follow = 1;
+                TO_HIP(hipLaunchCooperativeKernel((const void*)solve_kernel<2, kModeWindow>, dim3(blocks), dim3(SBW), args,
+                                                  win_bytes + own_bytes, s));
+                A.follow = 0;
+            }
             return TO_OK;
         }
         if (win_bytes <= kSolveLdsBytes && coop_blocks_for((const void*)k, SB, win_bytes, p->num_cu) >= blocks) {

@@ -429,6 +429,65 @@ def test_solve_window_kernel_two_designs(nelx):
         assert abs(s.residual - res) <= 1e-9
 
 
+@pytest.mark.parametrize("dims", [(100, 1100), (1600, 100)])
+def test_solve_window_kernel_tall_and_flat_meshes(dims):
+    """The default 2D FP64 solve on an MBB mesh taller than a block's node
+    range (100 x 1100: 109 blocks of 1,021 nodes, each window band of 1,102
+    nodes spans two neighbouring blocks on either side, and the band is
+    loaded in several passes) and on a flat one (1600 x 100: 158 blocks of
+    1,024 nodes, about 10 node columns each), judged by the true residual."""
+    from dataclasses import replace
+    from paper_2005_05436_amd import _lib as L
+    from paper_2005_05436_amd.driver import plan_for_config, read_struct
+    nelx, nely = dims
+    cfg = replace(W.C0, nelx=nelx, nely=nely, penal=3.0, rmin=1.5)
+    P, f, _ = plan_for_config(cfg)
+    fd = dev(f, torch.float64)
+    kval = torch.zeros(P.info.nnz_lower, dtype=torch.float64, device="cuda")
+    opts = L.SolveOpts(1e-8, 0.1, 200000, L.TO_OP_HYBRID, L.TO_SOLVE_AUTO, 1, 0, 0)
+    xd = dev(W.smooth_design(cfg, 9), torch.float64)
+    L.to_assemble(P.handle, L.TO_F64, xd, cfg.penal, kval)
+    u = torch.zeros(P.info.n, dtype=torch.float64, device="cuda")
+    st = torch.zeros(40, dtype=torch.uint8, device="cuda")
+    L.to_solve(P.handle, L.TO_F64, kval, xd, cfg.penal, fd, u, opts, st)
+    s = read_struct(st, L.SolveStats)
+    res = _mbb_true_residual(cfg, host(xd), host(u))
+    print(f"{dims}: iterations={s.iterations} restarts={s.restarts} fallback={s.fallback} residual={res:.3e}")
+    assert s.converged == 1, (s.iterations, s.residual)
+    assert res <= 1.05e-8, res
+    assert abs(s.residual - res) <= 1e-9
+
+
+def test_solve_pipelined_runaway_hands_over():
+    """A slender MBB beam (2400 x 60, SIMP contrast at penal 3) whose rtol
+    1e-8 lies below what FP64 CG attains (the oracle's PCG stops on its
+    recursive residual with a true one of 1.4e-6): the pipelined kernel's
+    recurrences run away near that floor, and the solve must hand over from
+    its best iterate to the single-sum kernel instead of returning a
+    diverged one.  Judged by the true residual (small, and the one
+    reported), not by convergence."""
+    from dataclasses import replace
+    from paper_2005_05436_amd import _lib as L
+    from paper_2005_05436_amd.driver import plan_for_config, read_struct
+    cfg = replace(W.C0, nelx=2400, nely=60, penal=3.0, rmin=1.5)
+    P, f, _ = plan_for_config(cfg)
+    fd = dev(f, torch.float64)
+    kval = torch.zeros(P.info.nnz_lower, dtype=torch.float64, device="cuda")
+    opts = L.SolveOpts(1e-8, 0.1, 80000, L.TO_OP_HYBRID, L.TO_SOLVE_AUTO, 1, 0, 0)
+    xd = dev(W.smooth_design(cfg, 9), torch.float64)
+    L.to_assemble(P.handle, L.TO_F64, xd, cfg.penal, kval)
+    u = torch.zeros(P.info.n, dtype=torch.float64, device="cuda")
+    st = torch.zeros(40, dtype=torch.uint8, device="cuda")
+    L.to_solve(P.handle, L.TO_F64, kval, xd, cfg.penal, fd, u, opts, st)
+    s = read_struct(st, L.SolveStats)
+    res = _mbb_true_residual(cfg, host(xd), host(u))
+    print(f"iterations={s.iterations} converged={s.converged} fallback={s.fallback} restarts={s.restarts} "
+          f"reported={s.residual:.3e} true={res:.3e}")
+    assert s.iterations <= 80000
+    assert res <= 1e-6, res
+    assert abs(s.residual - res) <= 1e-7
+
+
 @pytest.mark.parametrize("cfgname", ["c0", "c2s"])
 def test_mixed_solve_fallback(cfgname):
     """The FP64 fallback of the mixed-precision CG, its own launch after the
