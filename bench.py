@@ -65,9 +65,11 @@ FP64_PEAK = 78.6e12           # flop/s, MI355X FP64 (vector)
 
 def filter_flops(rmin):
     """2D cone filter work per element: (useful flops = 2 per non-zero tap,
-    flops the matrix-core kernel issues = 2,048 per v_mfma_f32_16x16x4_f32,
-    sum over the tap columns dx of ceil((16 + 2 lim(dx)) / 4) of them per
-    16 x 16 outputs, lim(dx) = the largest |dy| with a non-zero weight)."""
+    flops the matrix-core kernel issues = 2,048 per 16 x 16 x 4 product,
+    sum over the tap columns dx >= 0 of ceil((16 + 2 lim(dx)) / 4) of them
+    per 16 x 16 outputs, lim(dx) = the largest |dy| with a non-zero weight;
+    the columns dx and -dx share one product, their window values added
+    first, so the useful rate counts taps the kernel did not multiply)."""
     import math
     R = math.ceil(rmin) - 1
     taps, steps = 0, 0
@@ -77,7 +79,7 @@ def filter_flops(rmin):
             if rmin - math.sqrt(dx * dx + dy * dy) > 0.0:
                 taps += 1
                 lim = max(lim, abs(dy))
-        if lim >= 0:
+        if lim >= 0 and dx >= 0:
             steps += (16 + 2 * lim + 3) // 4
     return 2.0 * taps, steps * 2048.0 / 256.0
 

@@ -15,6 +15,7 @@
 //        ADJ  out = h * (in . s / Hs)
 //        ADJ2 out = h * (in . s / Hs), out2 = h * (in2 . s / Hs)  (one pass)
 #include <cstring>
+#include <type_traits>
 
 #include "common.h"
 
@@ -411,31 +412,46 @@ __global__ __launch_bounds__(512) void filter2d_mfma_kernel(
         for (int f = 0; f < NF; ++f)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) acc[f][nb] = Acc{T(0), T(0), T(0), T(0)};
-        for (int dxi = part; dxi <= 2 * R; dxi += NP) {
-            const int lim = hlim[dxi];
+        // h is even in dx: the columns +dx and -dx share their weights, so
+        // their window values are added first and one product serves both
+        // (half the matrix-core work; column dx = 0 alone)
+        for (int dxa = part; dxa <= R; dxa += NP) {
+            const int lim = hlim[R + dxa];
             if (lim < 0) continue;
             const int S = (16 + 2 * lim + 3) >> 2;
-            const T* ap = wtab + (size_t)min(dxi, 2 * R - dxi) * hms + (R + 16 - lim) + kq * S - i16;
-            const size_t b0 = (size_t)(dxi + i16) * ls + mt * 16 + R - lim + kq * S;
-            const T* bp = tile + b0;
-            const T* bp2 = tile2 + b0;
+            const T* ap = wtab + (size_t)(R - dxa) * hms + (R + 16 - lim) + kq * S - i16;
+            const size_t r0 = (size_t)mt * 16 + R - lim + kq * S;
+            const size_t bpo = (size_t)(R + dxa + i16) * ls + r0, bmo = (size_t)(R - dxa + i16) * ls + r0;
+            const T* bp = tile + bpo;
+            const T* bm = tile + bmo;
+            const T* bp2 = tile2 + bpo;
+            const T* bm2 = tile2 + bmo;
             // MFMA is convergent, so the compiler will not unroll a loop of
             // unknown trip count: groups of kFmUnroll steps by hand (their
             // LDS reads issue together), then the rest one by one
-            auto step = [&](int s) {
+            auto step = [&](int s, auto pair) {
                 const T a = ap[s];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    acc[0][nb] = Mfma<T>::step(a, bp[(size_t)nb * 16 * ls + s], acc[0][nb]);
-                    if (NF == 2) acc[NF - 1][nb] = Mfma<T>::step(a, bp2[(size_t)nb * 16 * ls + s], acc[NF - 1][nb]);
+                    const size_t o = (size_t)nb * 16 * ls + s;
+                    const T b1 = decltype(pair)::value ? bp[o] + bm[o] : bp[o];
+                    acc[0][nb] = Mfma<T>::step(a, b1, acc[0][nb]);
+                    if (NF == 2) {
+                        const T b2 = decltype(pair)::value ? bp2[o] + bm2[o] : bp2[o];
+                        acc[NF - 1][nb] = Mfma<T>::step(a, b2, acc[NF - 1][nb]);
+                    }
                 }
             };
-            int s = 0;
-            for (; s + kFmUnroll <= S; s += kFmUnroll) {
+            auto steps = [&](auto pair) {
+                int s = 0;
+                for (; s + kFmUnroll <= S; s += kFmUnroll) {
 #pragma unroll
-                for (int u = 0; u < kFmUnroll; ++u) step(s + u);
-            }
-            for (; s < S; ++s) step(s);
+                    for (int u = 0; u < kFmUnroll; ++u) step(s + u, pair);
+                }
+                for (; s < S; ++s) step(s, pair);
+            };
+            if (dxa > 0) steps(std::true_type{});
+            else steps(std::false_type{});
         }
         __syncthreads();                 // the window is no longer needed
         T* red = tile;                   // [part][field][column][row], TX x TY per slab
