@@ -792,6 +792,22 @@ struct Pcg {
                 for (int c = 0; c < 2; ++c) out[j][c] = (f >> c) & 1 ? a2[c] : T(0);
             }
         };
+        // the same on the nodes within one band of the range ends (near) or
+        // on the others, whose stencils stay within the own range (!near)
+        auto spmv_part = [&](T (&out)[J][2], bool near) {
+#pragma unroll
+            for (int jj = 0; jj < J; ++jj) {
+                const int j = jj == 0 ? 0 : J - jj;
+                int f = fl[j], yy = iy[j], xx = ix[j];
+                uint32_t gg = gi[j];
+                opaque(f, yy, xx, gg);
+                if (!(f & kOn) || ((f & kPub) != 0) != near) continue;
+                T a2[2];
+                opl.apply((int64_t)(gg >> 1), yy, xx, 0, sl, a2);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) out[j][c] = (f >> c) & 1 ? a2[c] : T(0);
+            }
+        };
         // one exchange and SpMV: out = A (M^-1 raw) when scaled, else A raw;
         // the band nodes' raw values go through buf
         auto exchange_spmv = [&](auto&& raw, T* buf, bool scaled, T (&out)[J][2]) {
@@ -884,8 +900,13 @@ struct Pcg {
             __syncthreads();
             own_to_window([&](int j, int c) { return d[j][c] * w[j][c]; });
             C.fr.template publish<3>(v);
-            // the band of m: wait for the blocks that own it (a failed wait
-            // enters the grid sum's verdict), then load
+            // n = A m while the sums travel: first on the nodes whose
+            // stencils stay within the own range (the window's own part is
+            // complete after the publication's barrier), while the
+            // neighbours publish; then the band of m (wait for the blocks
+            // that own it: a failed wait enters the grid sum's verdict) and
+            // the nodes near the range ends
+            spmv_part(nv, false);
             bool nb_ok = true;
             if ((int)threadIdx.x < n_nb) {
                 const int t = threadIdx.x;
@@ -895,7 +916,7 @@ struct Pcg {
             band_to_window(pub & 1 ? WB1 : WB0, true);
             ++pub;
             __syncthreads();
-            spmv(nv);                                   // n = A m, while the sums travel
+            spmv_part(nv, true);
             C.alive = C.fr.template collect<3>(C.res, nb_ok) && C.alive;
             if (!C.alive) break;
             const double gamma = C.res[0], delta = C.res[1], rr = C.res[2];
