@@ -25,6 +25,7 @@
 // the FP64 matrix-free operator; FP64 PCG fallback when it stalls.
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "common.h"
 #include "operators.h"
@@ -221,6 +222,24 @@ struct SrcLds {
     __device__ __forceinline__ T operator()(int64_t q, int c) const { return w[DIM * (q - wlo) + c]; }
 };
 
+// 3D: the SpMV of nodes lo .. hi - 1 reads, in each of the x-planes ix - 1,
+// ix, ix + 1, only the nodes within ny + 2 of the range shifted by one
+// plane (P = (ny+1)(nz+1) nodes), so the window holds three segments of
+// L = hi - lo + 2 (ny + 2) nodes: segment k starts at node wlo + k P
+// (wlo = lo - (ny + 2) - P) and at slot k L.  Node q lies at rel = q - wlo
+// in [k P, k P + L) for the k it is read with, k = [rel >= P] + [rel >= 2P];
+// where segments overlap (L > P) both copies hold the same value.
+template <typename T>
+struct SrcSeg3 {
+    const T* w;
+    int64_t wlo;
+    int P, S;                // S = P - L
+    __device__ __forceinline__ T operator()(int64_t q, int c) const {
+        const int rel = (int)(q - wlo);
+        return w[3 * (rel - ((rel >= P) + (rel >= 2 * P)) * S) + c];
+    }
+};
+
 // Hides per-node values from loop-invariant code motion: the neighbour
 // masks and addresses derived from them are then recomputed where they are
 // used, instead of being held in registers across the whole CG loop for
@@ -242,6 +261,7 @@ struct Pcg {
     Ctx& C;
     T* win = nullptr;            // LDS window of the direction (2D; nullptr: gather from memory)
     int64_t wlo = 0, wn = 0;
+    int wP = 0, wS = 0;          // 3D: the window's segment shift P and P - L (SrcSeg3)
     T* own = nullptr;            // run1: LDS for x and p of the own nodes, their moduli and the band's dinv
 
     // r = b - A x (x = 0: r = b), z = dinv r; returns (r.z, r.r) in C.res
@@ -310,12 +330,21 @@ struct Pcg {
                 // (one memory latency per pass, not per value)
                 constexpr int U = DIM == 3 ? 8 : 2;
                 const int64_t nwin = DIM * wn, bd = blockDim.x;
+                const int L = (int)(wn / 3);     // 3D: the segment length
                 for (int64_t i0 = threadIdx.x; i0 < nwin; i0 += U * bd) {
                     T val[U];
 #pragma unroll
                     for (int k2 = 0; k2 < U; ++k2) {
                         const int64_t i = i0 + k2 * bd;
-                        val[k2] = i < nwin ? src(wlo + i / DIM, (int)(i % DIM)) : T(0);
+                        if constexpr (DIM == 3) {
+                            // slot j of segment k holds node wlo + j + k (P - L); nodes
+                            // outside the mesh (the first and last blocks) are never read
+                            const int j = (int)(i / 3);
+                            const int64_t nd = wlo + j + ((j >= L) + (j >= 2 * L)) * (int64_t)wS;
+                            val[k2] = i < nwin && nd >= 0 && nd < g.nnode ? src(nd, (int)(i - 3 * j)) : T(0);
+                        } else {
+                            val[k2] = i < nwin ? src(wlo + i / DIM, (int)(i % DIM)) : T(0);
+                        }
                     }
 #pragma unroll
                     for (int k2 = 0; k2 < U; ++k2) {
@@ -324,7 +353,11 @@ struct Pcg {
                     }
                 }
                 __syncthreads();
-                const SrcLds<DIM, T> sl{win, wlo};
+                using SL = std::conditional_t<DIM == 3, SrcSeg3<T>, SrcLds<DIM, T>>;
+                const SL sl = [&] {
+                    if constexpr (DIM == 3) return SrcSeg3<T>{win, wlo, wP, wS};
+                    else return SrcLds<DIM, T>{win, wlo};
+                }();
                 for (int64_t nd = o.lo + threadIdx.x; nd < o.hi; nd += (int64_t)blockDim.x) {
                     int iy, ix, iz;
                     g.coords(nd, iy, ix, iz, DIM);
@@ -1228,7 +1261,15 @@ __device__ __forceinline__ void solve_body(const SolveArgs& A, int bid, int nb) 
                 jacobi<DIM, double>(mf64, g, C.o, A.freem, dinv);
             }
             Pcg<DIM, double, MatFree<DIM, double>> cg{mf64, g, A.freem, C};
-            if (A.stage > 0) {
+            if (DIM == 3 && A.stage > 0) {
+                extern __shared__ double solve_win[];
+                const int64_t P = ((int64_t)g.ny + 1) * (g.nz + 1), L = o.hi - o.lo + 2 * ((int64_t)g.ny + 2);
+                cg.wlo = o.lo - (g.ny + 2) - P;
+                cg.wn = 3 * L;
+                cg.wP = (int)P;
+                cg.wS = (int)(P - L);
+                if (cg.wn <= A.stage) cg.win = solve_win;   // else (never, by the launch's sizing) gather
+            } else if (A.stage > 0) {
                 extern __shared__ double solve_win[];
                 cg.wlo = o.lo - o.band > 0 ? o.lo - o.band : 0;
                 const int64_t whi = o.hi + o.band < g.nnode ? o.hi + o.band : g.nnode;
@@ -1392,16 +1433,16 @@ static to_status launch_solve_t(Plan* p, SolveArgs& A, int req_blocks, hipStream
     }
     if constexpr (DIM == 3 && MODE == 1) {
         // 3D matrix-free FP64: one 512-thread block per CU with the window of
-        // the SpMV source (own nodes and one band of (ny+1)(nz+1) + ny + 2
-        // nodes on either side) in LDS, when it fits
+        // the SpMV source in LDS, when it fits: the three segments of the own
+        // range widened by ny + 2 nodes, in the planes ix - 1, ix, ix + 1
         auto kw = solve_kernel<3, kModeWindow3>;
         constexpr int SBW = solve_block(3, kModeWindow3);
         const int bw = req_blocks > 0 ? std::min(req_blocks, p->num_cu) : p->num_cu;
-        const int64_t band = ((int64_t)A.geo.ny + 1) * ((int64_t)A.geo.nz + 1) + A.geo.ny + 2;
+        const int64_t plane = ((int64_t)A.geo.ny + 1) * ((int64_t)A.geo.nz + 1);
         const int64_t chunk = (A.geo.nnode + bw - 1) / bw;
-        const int64_t wn = std::min<int64_t>(A.geo.nnode, chunk + 2 * band);
+        const int64_t wn = 3 * (chunk + 2 * ((int64_t)A.geo.ny + 2));
         const size_t bytes = (size_t)wn * 3 * sizeof(double);
-        if (kSolveWindow3 && bytes <= kSolveLdsBytes &&
+        if (kSolveWindow3 && bytes <= kSolveLdsBytes && 3 * plane < ((int64_t)1 << 30) &&
             coop_blocks_for((const void*)kw, SBW, bytes, p->num_cu) >= bw) {
             A.stage = (int)wn;
             void* args[] = {&A};
