@@ -382,6 +382,41 @@ def test_solve(case):
     assert np.all(uh[prob.fixed] == 0.0)
 
 
+@pytest.mark.parametrize("dims", [(40, 20, 1), (60, 30, 10)])
+def test_solve_window3_plane_segments(dims):
+    """The 3D FP64 matrix-free solve, whose window holds the three plane
+    segments of each block's SpMV reads, on a mesh one element thick (40 x
+    20 x 1: 7 nodes per block, segments of 51 nodes longer than a plane of
+    42, so they overlap) and on one whose segments are disjoint (60 x 30 x
+    10: 82 nodes per block, 146-node segments in 341-node planes), judged by
+    the true residual with the oracle's K."""
+    from dataclasses import replace
+    from paper_2005_05436_amd import _lib as L
+    from paper_2005_05436_amd.driver import plan_for_config, read_struct
+    nelx, nely, nelz = dims
+    cfg = replace(W.C2_SMALL, nelx=nelx, nely=nely, nelz=nelz, penal=3.0)
+    prob, x, _ = _solve_case(cfg, 41)
+    P, f, _ = plan_for_config(cfg)
+    xd = dev(x, torch.float64)
+    kval = torch.zeros(P.info.nnz_lower, dtype=torch.float64, device="cuda")
+    L.to_assemble(P.handle, L.TO_F64, xd, cfg.penal, kval)
+    fd = dev(f, torch.float64)
+    u = torch.zeros(P.info.n, dtype=torch.float64, device="cuda")
+    st = torch.zeros(40, dtype=torch.uint8, device="cuda")
+    opts = L.SolveOpts(1e-8, 0.1, 200000, L.TO_OP_MATFREE, L.TO_SOLVE_AUTO, 1, 0, 0)
+    L.to_solve(P.handle, L.TO_F64, kval, xd, cfg.penal, fd, u, opts, st)
+    s = read_struct(st, L.SolveStats)
+    uh = host(u)
+    kv = osp.assemble(host(xd), prob.ke_lower, prob.perm, prob.seg_ptr, cfg.penal, 1.0, 1e-9)
+    K = osp.lower_to_full(prob.row_ptr, prob.col_idx, kv, prob.mesh.n)
+    res = osolve.true_residual(K, prob.f, prob.free, uh)
+    print(f"{dims}: iterations={s.iterations} restarts={s.restarts} residual={res:.3e}")
+    assert s.converged == 1, (s.iterations, s.residual)
+    assert res <= 1.05e-8, res
+    assert abs(s.residual - res) <= 1e-9
+    assert np.all(uh[prob.fixed] == 0.0)
+
+
 def _mbb_true_residual(cfg, x, u):
     """|f - K u| / |f| over the free DOFs of the MBB problem, with
     K = sum_e E(x_e) C_e^T Ke C_e (eqs. (3)-(5)) applied element by element
